@@ -1,0 +1,144 @@
+"""Seeded synthetic inputs shaped like the paper's graph classes.
+
+This module only synthesises graphs (Appendix C lists the paper's classes:
+meshes as the local control, R-MAT, Erdos-Renyi and geometric graphs as the
+non-local / weighted cases).  It contains none of the partitioning method's
+arithmetic and is the one module shared by the GPU library's tests and
+benchmark and by the CPU oracle's tests.
+
+Graphs are returned as :class:`Graph` holding a canonical symmetric CSR
+(numpy arrays): ``xadj`` uint64[n+1], ``adjncy`` uint32[M] with sorted rows,
+no self-loops and no duplicates; ``adjwgt`` int32[M] or ``None`` (unit);
+``vwgt`` is always ``None`` (unit node weights).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgraphgen.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from paper_2504_17615_amd.build import build_graphgen
+
+        build_graphgen()
+    lib = ctypes.CDLL(_LIB_PATH)
+    u64, u32, dbl, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+    lib.gg_grid.argtypes = [u64, u64]
+    lib.gg_grid.restype = vp
+    lib.gg_rmat.argtypes = [u32, u64, dbl, dbl, dbl, u64]
+    lib.gg_rmat.restype = vp
+    lib.gg_er.argtypes = [u64, u64, u64]
+    lib.gg_er.restype = vp
+    lib.gg_rgg.argtypes = [u64, dbl, u64]
+    lib.gg_rgg.restype = vp
+    lib.gg_n.argtypes = [vp]
+    lib.gg_n.restype = u64
+    lib.gg_nnz.argtypes = [vp]
+    lib.gg_nnz.restype = u64
+    lib.gg_weighted.argtypes = [vp]
+    lib.gg_weighted.restype = ctypes.c_int
+    lib.gg_copy.argtypes = [vp, vp, vp, vp]
+    lib.gg_copy.restype = None
+    lib.gg_free.argtypes = [vp]
+    lib.gg_free.restype = None
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Graph:
+    n: int
+    xadj: np.ndarray
+    adjncy: np.ndarray
+    adjwgt: Optional[np.ndarray] = None
+    vwgt: Optional[np.ndarray] = None
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.adjncy.shape[0])
+
+    @property
+    def m(self) -> int:
+        return self.nnz // 2
+
+
+def _collect(h, name) -> Graph:
+    lib = _load()
+    try:
+        n = int(lib.gg_n(h))
+        nnz = int(lib.gg_nnz(h))
+        xadj = np.empty(n + 1, dtype=np.uint64)
+        adj = np.empty(nnz, dtype=np.uint32)
+        w = np.empty(nnz, dtype=np.int32) if lib.gg_weighted(h) else None
+        lib.gg_copy(h, xadj.ctypes.data, adj.ctypes.data, None if w is None else w.ctypes.data)
+    finally:
+        lib.gg_free(h)
+    return Graph(n=n, xadj=xadj, adjncy=adj, adjwgt=w, name=name)
+
+
+def grid(rows: int, cols: int) -> Graph:
+    return _collect(_load().gg_grid(rows, cols), f"grid{rows}x{cols}")
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         seed: int = 22) -> Graph:
+    return _collect(_load().gg_rmat(scale, edge_factor, a, b, c, seed), f"rmat{scale}")
+
+
+def er(n: int, m: int, seed: int = 23) -> Graph:
+    if m > n * (n - 1) // 2:
+        raise ValueError("more edges than pairs")
+    return _collect(_load().gg_er(n, m, seed), f"er{n}_{m}")
+
+
+def rgg_radius(n: int, avg_degree: float = 12.0) -> float:
+    # expected degree of a point away from the border is pi r^2 n
+    return math.sqrt(avg_degree / (math.pi * n))
+
+
+def rgg(n: int, r: Optional[float] = None, seed: int = 24) -> Graph:
+    if r is None:
+        r = rgg_radius(n)
+    return _collect(_load().gg_rgg(n, r, seed), f"rgg{n}")
+
+
+# The workloads: (graph factory, k, eps, seed).  Full sizes plus reduced
+# shapes of the same recipes that the CPU oracle finishes in seconds.
+def workload(name: str):
+    """Return (graph, k, eps, seed) for a named workload."""
+    if name == "grid128":
+        return grid(128, 128), 4, 0.03, 1
+    if name == "rmat22":
+        return rmat(22), 64, 0.03, 1
+    if name == "er22":
+        return er(1 << 22, 1 << 26), 128, 0.03, 1
+    if name == "rgg24":
+        return rgg(1 << 24), 256, 0.03, 1
+    # reduced shapes (same recipes)
+    if name.startswith("rmat"):
+        s = int(name[4:])
+        return rmat(s), 64, 0.03, 1
+    if name.startswith("er"):
+        s = int(name[2:])
+        return er(1 << s, 1 << (s + 4)), 128, 0.03, 1
+    if name.startswith("rgg"):
+        s = int(name[3:])
+        return rgg(1 << s), 256, 0.03, 1
+    if name.startswith("grid"):
+        s = int(name[4:])
+        return grid(s, s), 4, 0.03, 1
+    raise KeyError(name)
