@@ -1,0 +1,204 @@
+/*
+ * lmgp.h -- C ABI of the MI355X (gfx950) multilevel graph partitioner with
+ * edge sparsification (Linear-Time Multilevel Graph Partitioning via Edge
+ * Sparsification, arXiv 2504.17615).
+ *
+ * The library computes, on one GPU:
+ *   - the coarsening hierarchy of Algorithm 1: size-constrained label
+ *     propagation clustering with 2-hop clustering (Sec. 3, Sec. 4.1),
+ *     contraction (Sec. 2), the edge budget m_hat and weighted threshold
+ *     sampling (Sec. 4.2), termination rules (Sec. 4.3);
+ *   - a k-way partition: recursive bipartitioning of the coarsest graph
+ *     (Sec. 4.3) and size-constrained label propagation refinement on every
+ *     level on the way back up (Sec. 2, Sec. 3);
+ * every step running in the library's own HIP kernels.
+ *
+ * Graphs (Sec. 2): undirected, node weights c > 0, edge weights omega > 0,
+ * stored as a canonical symmetric CSR: xadj[n+1] (uint64, xadj[0] = 0,
+ * non-decreasing), adjncy[nnz] (uint32 node ids < n), every undirected edge
+ * {u,v} present as both entries (u,v) and (v,u) with equal weight, rows sorted
+ * strictly ascending (no duplicates), no self-loops.  nnz = 2|E|.
+ * Limits: n < 2^31, nnz < 2^40.
+ *
+ * Conventions for every call:
+ *   - returns an lmgp_status; output parameters are written only on LMGP_OK;
+ *   - no C++ exception crosses the ABI; lmgp_last_error() returns a message for
+ *     the calling thread's most recent failure (valid until its next call);
+ *   - `stream` is a hipStream_t (NULL = the default stream); all device work is
+ *     ordered on it; calls return after the result is complete unless stated;
+ *   - results are a pure function of (graph, k, eps, seed, params): bit-exact
+ *     across runs, batch compositions and the serving loop.
+ */
+#ifndef LMGP_H
+#define LMGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LMGP_OK = 0,
+  LMGP_EINVAL = 1,      /* invalid argument or malformed graph                 */
+  LMGP_ENOMEM = 2,      /* device allocation failed (or caller allocator NULL) */
+  LMGP_EDEVICE = 3,     /* HIP runtime / kernel error                          */
+  LMGP_ENOTREADY = 4,   /* serving: request not finished yet                   */
+  LMGP_EBUSY = 5,       /* serving: request can never be admitted              */
+  LMGP_ECANCELLED = 6   /* serving: server shut down before completion         */
+} lmgp_status;
+
+/* Optional device allocator.  alloc returns device memory of at least
+ * `bytes` bytes usable in stream order on `stream` (NULL on failure); free
+ * releases it in stream order.  When no allocator is given the library uses
+ * its own stream-ordered caching pool of hipMalloc'd memory. */
+typedef struct {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*free)(void *ctx, void *ptr, void *stream);
+} lmgp_allocator;
+
+/* A CSR graph handed to lmgp_graph_create.  Pointers are host memory
+ * (on_device = 0) or device memory (on_device = 1).  vwgt / adjwgt may be
+ * NULL for unit weights; otherwise their element width is given by
+ * vwgt_bits / adjwgt_bits (32 or 64, signed).  validate = 1 runs the full
+ * canonical-form check (sorted rows, no duplicates, symmetry with equal
+ * weights) in addition to the always-on checks. */
+typedef struct {
+  uint64_t n;
+  uint64_t nnz;
+  const uint64_t *xadj;
+  const uint32_t *adjncy;
+  const void *vwgt;
+  const void *adjwgt;
+  uint32_t vwgt_bits;
+  uint32_t adjwgt_bits;
+  uint32_t on_device;
+  uint32_t validate;
+} lmgp_csr_view;
+
+/* Parameters (defaults from lmgp_default_params).  Rational thresholds make
+ * every decision exact integer arithmetic. */
+typedef struct {
+  uint32_t tau_e_num, tau_e_den; /* edge threshold tau_e = 1/2 (Sec. 4.2, Sec. 5.1)  */
+  uint32_t tau_d_num, tau_d_den; /* density threshold tau_d = 1/2                   */
+  uint32_t rho_num, rho_den;     /* minimum reduction factor rho = 4               */
+  uint32_t sampler;              /* 0 = weighted threshold sampling, 2 = off       */
+  uint32_t clim;                 /* C = 160: U = c(V)/(C k), stop at C k nodes     */
+  uint32_t shrink_num, shrink_den; /* node reduction cap 5/2 = 2.5x (Sec. 4.3)     */
+  uint32_t lp_rounds;            /* LP clustering rounds, 5                        */
+  uint32_t ref_rounds;           /* LP refinement rounds per level, 5              */
+  uint32_t subrounds;            /* synchronous sub-rounds per LP round, 4         */
+  uint32_t max_levels;           /* hierarchy depth cap, 64                        */
+  uint32_t stop_num, stop_den;   /* stop when stop_den*n' > stop_num*n (19/20)     */
+} lmgp_params;
+
+typedef struct lmgp_graph lmgp_graph;
+typedef struct lmgp_hierarchy lmgp_hierarchy;
+typedef struct lmgp_server lmgp_server;
+
+/* Per-level statistics; level 0 is the input graph. */
+typedef struct {
+  uint64_t n, m;        /* nodes and undirected edges of this level           */
+  uint64_t m_prime;     /* |E'| before sparsification (= m if not triggered)  */
+  uint64_t m_hat;       /* edge budget of Algorithm 1                          */
+  uint32_t triggered;   /* 1 if sparsification ran                             */
+  uint32_t lp_rounds;   /* LP rounds run when clustering the previous level   */
+  uint32_t twohop;      /* 1 if 2-hop clustering ran on the previous level    */
+  uint32_t pad;
+  int64_t w_t;          /* threshold weight omega_t (0 if not triggered)      */
+  uint64_t n_gt, n_eq;  /* |E'^>| and |E'^=| (undirected)                     */
+  uint64_t nclusters_lp;/* clusters after LP, before 2-hop                    */
+} lmgp_level_info;
+
+typedef struct {
+  int64_t cut;               /* cut(Pi) on the input graph (Sec. 2)              */
+  int64_t max_block_weight;  /* max_i c(V_i)                                     */
+  int64_t lmax;              /* L_max = floor((1+eps) * ceil(c(V)/k))            */
+  uint32_t levels;           /* hierarchy depth l                                */
+  uint32_t pad;
+  int64_t t_coarsen_ns;      /* phase times measured with events on the stream  */
+  int64_t t_initial_ns;
+  int64_t t_refine_ns;
+  int64_t t_total_ns;
+} lmgp_result;
+
+/* Serving configuration. */
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* admission limit on the summed estimated footprint */
+  uint32_t max_slots;         /* requests resident at once                          */
+  uint32_t max_batch;         /* requests fused into one batched run                */
+  uint32_t streams;           /* concurrent device streams (worker threads)         */
+  uint32_t pad;
+} lmgp_server_cfg;
+
+void lmgp_default_params(lmgp_params *out);
+
+/* Last error message of the calling thread ("" if none). */
+const char *lmgp_last_error(void);
+
+/* Copies and validates a graph into library-owned device memory (allocated
+ * with `alloc` if given).  Always checked: n, nnz, xadj monotone with
+ * xadj[0] = 0 and xadj[n] = nnz, adjncy < n, no self-loops, weights > 0.
+ * EINVAL on any violation. The caller keeps ownership of the view's buffers.
+ * Definitions: Sec. 2 (graph, weights). */
+lmgp_status lmgp_graph_create(const lmgp_csr_view *view, const lmgp_allocator *alloc,
+                              void *stream, lmgp_graph **out);
+void lmgp_graph_destroy(lmgp_graph *g);
+/* n, nnz and the total node weight c(V) of a created graph. */
+lmgp_status lmgp_graph_info(const lmgp_graph *g, uint64_t *n, uint64_t *nnz, int64_t *total_weight);
+
+/* Builds the coarsening hierarchy of Algorithm 1 for k blocks (k >= 1,
+ * k <= n) and keeps it device-resident.  params NULL = defaults. */
+lmgp_status lmgp_coarsen(lmgp_graph *g, uint32_t k, uint64_t seed, const lmgp_params *params,
+                         void *stream, lmgp_hierarchy **out);
+lmgp_status lmgp_hierarchy_levels(const lmgp_hierarchy *h, uint32_t *num_levels);
+lmgp_status lmgp_hierarchy_level_info(const lmgp_hierarchy *h, uint32_t level,
+                                      lmgp_level_info *out);
+/* Copies level `level` (0 = input) into host buffers sized from its info:
+ * xadj[n+1], adjncy[2m], vwgt[n] (int64), adjwgt[2m] (int64), map[n] (node
+ * of level+1 for each node; not written for the last level).  Any pointer may
+ * be NULL to skip that array. */
+lmgp_status lmgp_hierarchy_copy_level(const lmgp_hierarchy *h, uint32_t level, uint64_t *xadj,
+                                      uint32_t *adjncy, int64_t *vwgt, int64_t *adjwgt,
+                                      uint32_t *map);
+void lmgp_hierarchy_destroy(lmgp_hierarchy *h);
+
+/* Full partition into k blocks with imbalance eps > 0 (Sec. 2: balance
+ * constraint c(V_i) <= L_max).  block_out[n] receives block ids in [0, k);
+ * it is device memory if block_on_device = 1, else host memory.  res may be
+ * NULL. */
+lmgp_status lmgp_partition(lmgp_graph *g, uint32_t k, double eps, uint64_t seed,
+                           const lmgp_params *params, void *stream, uint32_t *block_out,
+                           uint32_t block_on_device, lmgp_result *res);
+
+/* Partitions `count` graphs as one batched run: every kernel launch covers
+ * all graphs of the batch.  Outputs are identical to `count` separate
+ * lmgp_partition calls.  k, eps, seed, block_out and res are arrays of
+ * `count` entries (res may be NULL). */
+lmgp_status lmgp_partition_batch(lmgp_graph *const *graphs, const uint32_t *k, const double *eps,
+                                 const uint64_t *seed, uint32_t count, const lmgp_params *params,
+                                 void *stream, uint32_t *const *block_out,
+                                 uint32_t block_on_device, lmgp_result *res);
+
+/* Serving loop: requests are admitted while their estimated device footprint
+ * fits hbm_budget_bytes and a slot is free; admitted requests that wait
+ * together are fused into batched runs on `streams` device streams. */
+lmgp_status lmgp_server_create(const lmgp_server_cfg *cfg, const lmgp_allocator *alloc,
+                               lmgp_server **out);
+/* Submits a request; the graph must stay alive until the request finishes.
+ * block_out is host memory of n entries.  EBUSY if the request's footprint
+ * exceeds the whole budget. */
+lmgp_status lmgp_server_submit(lmgp_server *s, lmgp_graph *g, uint32_t k, double eps,
+                               uint64_t seed, uint32_t *block_out, uint64_t *ticket);
+/* ENOTREADY until the request is done; then fills res (latency fields:
+ * t_total_ns = submit-to-completion). */
+lmgp_status lmgp_server_poll(lmgp_server *s, uint64_t ticket, lmgp_result *res);
+lmgp_status lmgp_server_wait(lmgp_server *s, uint64_t ticket, lmgp_result *res);
+void lmgp_server_destroy(lmgp_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMGP_H */

@@ -1,0 +1,87 @@
+// Contraction, sparsification and uncoarsening helpers (host interfaces).
+#pragma once
+#include <vector>
+
+#include "kernels.h"
+
+namespace lmgp {
+
+struct ContractIn {
+  uint64_t n = 0;
+  const uint64_t* xadj = nullptr;
+  const uint32_t* adj = nullptr;
+  const void* ew = nullptr;
+  int ew_kind = EW_UNIT;
+  const uint32_t* label = nullptr;
+  const int64_t* W = nullptr;       // cluster weights indexed by label
+  const uint32_t* csize = nullptr;  // cluster member counts indexed by label
+  const uint32_t* gid = nullptr;
+  const uint8_t* keep = nullptr;    // device, per graph: contract this graph
+  std::vector<uint64_t> bounds;     // node boundaries of the graphs (B + 1 values)
+};
+
+struct ContractOut {
+  uint64_t nc = 0, nnz = 0;
+  DBuf<uint32_t> map;  // fine node -> coarse node (EMPTY_KEY for graphs not kept)
+  DBuf<int64_t> nw;
+  DBuf<uint32_t> gid;
+  DBuf<uint64_t> xadj;
+  DBuf<uint32_t> adj;
+  DBuf<int64_t> ew;
+  DBuf<uint32_t> src;
+  std::vector<uint32_t> cid_at_bounds;  // coarse node boundaries of the graphs
+};
+
+struct ContractArgs {
+  const uint64_t* xadj;
+  const uint32_t* adj;
+  const void* ew;
+  const uint32_t* map;
+  const uint64_t* mstart;
+  const uint32_t* members;
+  const unsigned long long* degsum;
+  const uint64_t* tmpoff;
+  uint32_t* tkey;
+  int64_t* tw;
+  uint32_t* tsrc;
+  uint32_t* ndist;
+};
+
+void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStream_t s);
+
+// ---------------------------------------------------------- sparsification --
+struct SparsGraph {
+  uint64_t node_base = 0;
+  uint64_t e0 = 0, e1 = 0;   // entry range of the graph
+  uint64_t m_hat = 0;
+  bool triggered = false;
+  uint64_t pre = 0;          // H(seed, SPARS, level) prefix
+  // outputs
+  int64_t w_t = 0;
+  uint64_t n_gt = 0, n_eq = 0;
+};
+
+struct SparsOut {
+  uint64_t nnz = 0;
+  DBuf<uint64_t> xadj;
+  DBuf<uint32_t> adj;
+  DBuf<int64_t> ew;
+  DBuf<uint32_t> src;
+};
+
+// Sparsify the triggered graphs of a union level in place of a new CSR.
+void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
+                    const int64_t* ew, const uint32_t* src, const uint32_t* gid,
+                    std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s);
+
+// --------------------------------------------------------------- refinement --
+void project_blocks(const uint32_t* map, const uint32_t* cblock, uint64_t n, uint32_t* block,
+                    hipStream_t s);
+void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t* BW,
+                   hipStream_t s);
+// cut per graph over entries with src < adj (int64 atomics into cut[g])
+void edge_cut(const uint32_t* src, const uint32_t* adj, const void* ew, int ew_kind,
+              const uint32_t* block, const uint32_t* gid, uint64_t nnz, int64_t* cut,
+              hipStream_t s);
+
+}  // namespace lmgp

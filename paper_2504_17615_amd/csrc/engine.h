@@ -1,0 +1,118 @@
+// Host orchestration of the multilevel pipeline on one GPU.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "contract.h"
+#include "lmgp.h"
+
+namespace lmgp {
+
+// A validated input graph in device memory (what lmgp_graph owns).
+struct InputGraph {
+  Pool* pool = nullptr;
+  std::shared_ptr<Pool> own_pool;
+  hipStream_t stream = nullptr;
+  uint64_t n = 0, nnz = 0;
+  int ew_kind = EW_UNIT;
+  int64_t cV = 0;
+  DBuf<uint64_t> xadj;
+  DBuf<uint32_t> adj;
+  DBuf<int32_t> ew32;
+  DBuf<int64_t> ew64;
+  DBuf<int64_t> nw;
+  DBuf<uint32_t> src;
+  const void* ew() const {
+    return ew_kind == EW_I32 ? (const void*)ew32.get()
+         : ew_kind == EW_I64 ? (const void*)ew64.get() : nullptr;
+  }
+};
+
+void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s);
+
+// One level of the union hierarchy.
+struct Level {
+  uint64_t n = 0, nnz = 0;
+  const uint64_t* xadj = nullptr;
+  const uint32_t* adj = nullptr;
+  const void* ew = nullptr;
+  int ew_kind = EW_UNIT;
+  const int64_t* nw = nullptr;
+  const uint32_t* src = nullptr;
+  const uint32_t* gid = nullptr;  // NULL when a single graph is present
+  // storage when owned
+  DBuf<uint64_t> o_xadj;
+  DBuf<uint32_t> o_adj;
+  DBuf<int64_t> o_ew;
+  DBuf<int64_t> o_nw;
+  DBuf<uint32_t> o_src;
+  DBuf<uint32_t> o_gid;
+  DBuf<uint32_t> map;              // node of the next level (EMPTY_KEY if the graph stops)
+  std::vector<uint32_t> graphs;    // batch indices of the graphs present, in union order
+  std::vector<uint64_t> nbase;     // node boundaries (graphs.size() + 1)
+  std::vector<uint64_t> ebase;     // entry boundaries (graphs.size() + 1)
+};
+
+// Per-graph state of a run.
+struct Job {
+  const InputGraph* g = nullptr;
+  uint32_t k = 1;
+  double eps = 0.03;
+  uint64_t seed = 0;
+  int64_t U = 1;
+  int64_t lmax = 0;
+  uint32_t nlevels = 1;  // levels of this graph's hierarchy
+  std::vector<lmgp_level_info> info;
+  std::vector<uint32_t> block;  // host copy of the final blocks (when requested)
+  lmgp_result res{};
+};
+
+class Engine {
+ public:
+  Engine(Pool& pool, hipStream_t s, const lmgp_params& p) : pool_(pool), s_(s), p_(p) {}
+  // Builds the hierarchy for all jobs (one union).
+  void coarsen(std::vector<Job>& jobs);
+  // Initial partitioning, refinement and evaluation; writes blocks.
+  void partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device);
+  std::vector<std::unique_ptr<Level>>& levels() { return levels_; }
+
+  int64_t t_coarsen_ns = 0, t_initial_ns = 0, t_refine_ns = 0;
+
+ private:
+  struct LpSpec {
+    bool refine;
+    uint32_t level;  // 1-based level index used in hashes
+    uint32_t rounds;
+  };
+  void cluster(Level& L, std::vector<Job>& jobs, std::vector<uint8_t>& active,
+               DBuf<uint32_t>& label, DBuf<int64_t>& W, DBuf<uint32_t>& csize,
+               std::vector<uint64_t>& ncl, std::vector<lmgp_level_info>& stats);
+  void run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec, std::vector<uint8_t>& active,
+              uint32_t* label, int64_t* W, size_t nlabels, uint32_t* csize,
+              const std::vector<uint64_t>& label_base, std::vector<uint64_t>* ncl,
+              std::vector<uint32_t>& rounds_run);
+  void two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t>& which,
+               uint32_t level, uint32_t* label, int64_t* W, uint32_t* csize,
+               std::vector<uint64_t>& ncl);
+  void build_union(std::vector<Job>& jobs);
+
+  Pool& pool_;
+  hipStream_t s_;
+  lmgp_params p_;
+  std::vector<std::unique_ptr<Level>> levels_;
+};
+
+// Recursive bipartitioning of a small host graph (coarsest level).
+void initial_partition_host(uint64_t n, const std::vector<uint64_t>& xadj,
+                            const std::vector<uint32_t>& adj, const std::vector<int64_t>& nw,
+                            uint32_t k, uint64_t seed, uint64_t level, std::vector<uint32_t>& block);
+
+lmgp_params default_params();
+void check_params(const lmgp_params& p);
+
+}  // namespace lmgp
+
+// The opaque graph handle of the C ABI.
+struct lmgp_graph {
+  lmgp::InputGraph g;
+};

@@ -1,0 +1,1018 @@
+// Host orchestration of the multilevel partitioner on one GPU.
+//
+// Algorithm 1 (coarsening with sparsification) runs over a union of graphs:
+// every kernel launch covers all graphs still coarsening, and each graph
+// keeps its own parameters (U, seed, budget, stop decisions).  A single
+// graph is the union of one.  Level decisions need a few scalars per level
+// on the host (cluster counts, coarse sizes, edge counts).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <initializer_list>
+
+#include "engine.h"
+
+namespace lmgp {
+
+typedef unsigned __int128 u128;
+
+namespace {
+
+uint64_t chain(uint64_t seed, uint64_t tag, std::initializer_list<uint64_t> xs) {
+  uint64_t s = hash_prefix(seed, tag);
+  for (uint64_t x : xs) s = hash_add(s, x);
+  return s;
+}
+
+template <class T>
+void h2d(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+void d2h(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+void sync(hipStream_t s) { HIP_CHECK(hipStreamSynchronize(s)); }
+
+// ------------------------------------------------------------ small kernels --
+__global__ void k_iota(uint32_t* a, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (uint32_t)i;
+}
+__global__ void k_copy_i64(int64_t* d, const int64_t* s, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+struct TableSize {
+  const uint64_t* xadj;
+  const uint32_t* list;
+  LMGP_D uint64_t operator()(uint64_t i) const {
+    const uint32_t u = list[i];
+    const uint64_t d = xadj[u + 1] - xadj[u];
+    uint64_t T = 1;
+    while (T < 2 * d) T <<= 1;
+    return T;
+  }
+};
+
+// 2-hop: light singletons (and their sort keys).
+struct SingletonFlag {
+  const uint32_t* label;
+  const uint32_t* csize;
+  const int64_t* nw;
+  const uint32_t* gid;
+  const GraphDesc* gd;
+  LMGP_D uint64_t operator()(uint64_t v) const {
+    const GraphDesc& d = gd[graph_of(gid, v)];
+    return d.active && csize[label[v]] == 1 && 2 * nw[v] <= d.cap;
+  }
+};
+
+__global__ void k_twohop_keys(SingletonFlag f, const uint64_t* xadj, const uint32_t* fav,
+                              const uint32_t* pos, uint64_t n, uint64_t* keys, uint32_t* vals) {
+  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || !f(v)) return;
+  const GraphDesc& d = f.gd[graph_of(f.gid, v)];
+  const uint64_t deg = xadj[v + 1] - xadj[v];
+  const uint32_t fv = deg ? fav[v] : EMPTY_KEY;
+  const uint64_t favkey = fv != EMPTY_KEY ? 2ull * fv : 2ull * (d.node_base + d.nodes - 1) + 1;
+  const uint64_t h = hash_add(d.pre_two, v - d.node_base) >> 32;
+  keys[pos[v]] = (favkey << 32) | h;
+  vals[pos[v]] = (uint32_t)v;
+}
+
+__global__ void k_seg_first(const uint64_t* keys, uint64_t ns, uint32_t* first) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const uint64_t fk = keys[p] >> 32;
+  if (p == 0 || (keys[p - 1] >> 32) != fk) first[fk] = (uint32_t)p;
+}
+
+__global__ void k_pair_flags(const uint64_t* keys, const uint32_t* vals, uint64_t ns,
+                             const uint32_t* first, const uint32_t* gid, uint32_t* flag,
+                             unsigned long long* pairs) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const uint64_t fk = keys[p] >> 32;
+  const uint64_t pos = p - first[fk];
+  const bool lead = (pos % 2 == 0) && p + 1 < ns && (keys[p + 1] >> 32) == fk;
+  flag[p] = lead;
+  if (lead) atomicAdd(&pairs[graph_of(gid, vals[p])], 1ull);
+}
+
+__global__ void k_pair_merge(const uint32_t* vals, const uint32_t* flag, const uint32_t* rank,
+                             uint64_t ns, const uint32_t* gid, const uint64_t* base,
+                             const uint64_t* cap, uint32_t* label, int64_t* W, const int64_t* nw,
+                             uint32_t* csize) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns || !flag[p]) return;
+  const uint32_t a = vals[p], b = vals[p + 1];
+  const uint32_t g = graph_of(gid, a);
+  if ((uint64_t)rank[p] - base[g] >= cap[g]) return;
+  const uint32_t la = label[a], lb = label[b];
+  label[b] = la;
+  W[la] += nw[b];
+  W[lb] -= nw[b];
+  csize[la] += 1;
+  csize[lb] -= 1;
+}
+
+// Union construction for batches: concatenate graphs with rebased ids.
+struct UnionPart {
+  const uint64_t* xadj;
+  const uint32_t* adj;
+  const void* ew;
+  int ew_kind;
+  const int64_t* nw;
+  uint64_t nbase, ebase, n, nnz;
+};
+
+__device__ uint32_t find_part(const uint64_t* bounds, uint32_t B, uint64_t i) {
+  uint32_t lo = 0, hi = B;  // bounds[lo] <= i < bounds[hi]
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (bounds[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_union_nodes(const UnionPart* parts, const uint64_t* nb, uint32_t B, uint64_t n,
+                              uint64_t* xadj, int64_t* nw, uint32_t* gid) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t g = find_part(nb, B, i);
+  const UnionPart pt = parts[g];
+  const uint64_t li = i - pt.nbase;
+  xadj[i] = pt.ebase + pt.xadj[li];
+  nw[i] = pt.nw[li];
+  gid[i] = g;
+  if (i == n - 1) xadj[n] = pt.ebase + pt.xadj[li + 1];
+}
+
+__global__ void k_union_entries(const UnionPart* parts, const uint64_t* eb, uint32_t B,
+                                uint64_t nnz, uint32_t* adj, int64_t* ew, uint32_t* src,
+                                const uint32_t* psrc_dummy) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t g = find_part(eb, B, e);
+  const UnionPart pt = parts[g];
+  const uint64_t le = e - pt.ebase;
+  adj[e] = (uint32_t)(pt.nbase + pt.adj[le]);
+  if (ew) {
+    int64_t w = 1;
+    if (pt.ew_kind == EW_I32) w = ((const int32_t*)pt.ew)[le];
+    else if (pt.ew_kind == EW_I64) w = ((const int64_t*)pt.ew)[le];
+    ew[e] = w;
+  }
+  (void)psrc_dummy;
+}
+
+__global__ void k_union_src(const UnionPart* parts, const uint32_t* const* srcs, const uint64_t* eb,
+                            uint32_t B, uint64_t nnz, uint32_t* src) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t g = find_part(eb, B, e);
+  src[e] = (uint32_t)(parts[g].nbase + srcs[g][e - parts[g].ebase]);
+}
+
+__global__ void k_to_local(const uint32_t* block, uint64_t n, uint32_t kbase, uint32_t* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = block[i] - kbase;
+}
+
+class Timer {
+ public:
+  explicit Timer(hipStream_t s) : s_(s) {
+    HIP_CHECK(hipEventCreate(&a_));
+    HIP_CHECK(hipEventCreate(&b_));
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a_);
+    (void)hipEventDestroy(b_);
+  }
+  void start() { HIP_CHECK(hipEventRecord(a_, s_)); }
+  int64_t stop_ns() {
+    HIP_CHECK(hipEventRecord(b_, s_));
+    HIP_CHECK(hipEventSynchronize(b_));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, a_, b_));
+    return (int64_t)((double)ms * 1e6);
+  }
+
+ private:
+  hipStream_t s_;
+  hipEvent_t a_, b_;
+};
+
+}  // namespace
+
+lmgp_params default_params() {
+  lmgp_params p;
+  p.tau_e_num = 1, p.tau_e_den = 2;
+  p.tau_d_num = 1, p.tau_d_den = 2;
+  p.rho_num = 4, p.rho_den = 1;
+  p.sampler = 0;
+  p.clim = 160;
+  p.shrink_num = 5, p.shrink_den = 2;
+  p.lp_rounds = 5, p.ref_rounds = 5, p.subrounds = 4;
+  p.max_levels = 64;
+  p.stop_num = 19, p.stop_den = 20;
+  return p;
+}
+
+void check_params(const lmgp_params& p) {
+  if (!p.tau_e_den || !p.tau_d_den || !p.rho_den) throw InvalidArg("zero denominator in params");
+  if (p.sampler != 0 && p.sampler != 2) throw InvalidArg("sampler must be 0 (threshold) or 2 (off)");
+  if (!p.clim) throw InvalidArg("clim must be positive");
+  if (!p.shrink_num) throw InvalidArg("shrink_num must be positive");
+  if (!p.subrounds || p.subrounds > 32) throw InvalidArg("subrounds must be in [1, 32]");
+  if (!p.max_levels) throw InvalidArg("max_levels must be positive");
+  if (!p.stop_den) throw InvalidArg("stop_den must be positive");
+}
+
+// ----------------------------------------------------------------- union --
+void Engine::build_union(std::vector<Job>& jobs) {
+  levels_.clear();
+  auto L = std::make_unique<Level>();
+  const uint32_t B = (uint32_t)jobs.size();
+  L->graphs.resize(B);
+  L->nbase.assign(B + 1, 0);
+  L->ebase.assign(B + 1, 0);
+  for (uint32_t b = 0; b < B; ++b) {
+    L->graphs[b] = b;
+    L->nbase[b + 1] = L->nbase[b] + jobs[b].g->n;
+    L->ebase[b + 1] = L->ebase[b] + jobs[b].g->nnz;
+  }
+  L->n = L->nbase[B];
+  L->nnz = L->ebase[B];
+  if (B == 1) {
+    const InputGraph& g = *jobs[0].g;
+    L->xadj = g.xadj.get();
+    L->adj = g.adj.get();
+    L->ew = g.ew();
+    L->ew_kind = g.ew_kind;
+    L->nw = g.nw.get();
+    L->src = g.src.get();
+    L->gid = nullptr;
+  } else {
+    bool all_unit = true, all_i32 = true;
+    for (auto& j : jobs) {
+      all_unit &= j.g->ew_kind == EW_UNIT;
+      all_i32 &= j.g->ew_kind == EW_I32;
+    }
+    std::vector<UnionPart> parts(B);
+    std::vector<const uint32_t*> srcs(B);
+    for (uint32_t b = 0; b < B; ++b) {
+      const InputGraph& g = *jobs[b].g;
+      parts[b] = UnionPart{g.xadj.get(), g.adj.get(), g.ew(), g.ew_kind, g.nw.get(),
+                           L->nbase[b], L->ebase[b], g.n, g.nnz};
+      srcs[b] = g.src.get();
+    }
+    DBuf<UnionPart> dparts(&pool_, s_, B);
+    DBuf<const uint32_t*> dsrcs(&pool_, s_, B);
+    DBuf<uint64_t> dnb(&pool_, s_, B + 1), deb(&pool_, s_, B + 1);
+    h2d(dparts.get(), parts.data(), B, s_);
+    h2d(dsrcs.get(), srcs.data(), B, s_);
+    h2d(dnb.get(), L->nbase.data(), B + 1, s_);
+    h2d(deb.get(), L->ebase.data(), B + 1, s_);
+    L->o_xadj.reset(&pool_, s_, L->n + 1);
+    L->o_nw.reset(&pool_, s_, L->n ? L->n : 1);
+    L->o_gid.reset(&pool_, s_, L->n ? L->n : 1);
+    L->o_adj.reset(&pool_, s_, L->nnz ? L->nnz : 1);
+    L->o_src.reset(&pool_, s_, L->nnz ? L->nnz : 1);
+    if (!all_unit) L->o_ew.reset(&pool_, s_, L->nnz ? L->nnz : 1);
+    if (L->n) {
+      k_union_nodes<<<grid_for(L->n, 256), 256, 0, s_>>>(dparts.get(), dnb.get(), B, L->n,
+                                                         L->o_xadj.get(), L->o_nw.get(),
+                                                         L->o_gid.get());
+      LAUNCH_CHECK();
+    } else {
+      device_zero(L->o_xadj.get(), sizeof(uint64_t), s_);
+    }
+    if (L->nnz) {
+      k_union_entries<<<grid_for(L->nnz, 256), 256, 0, s_>>>(
+          dparts.get(), deb.get(), B, L->nnz, L->o_adj.get(), all_unit ? nullptr : L->o_ew.get(),
+          L->o_src.get(), nullptr);
+      LAUNCH_CHECK();
+      k_union_src<<<grid_for(L->nnz, 256), 256, 0, s_>>>(dparts.get(), dsrcs.get(), deb.get(), B,
+                                                         L->nnz, L->o_src.get());
+      LAUNCH_CHECK();
+    }
+    (void)all_i32;
+    L->xadj = L->o_xadj.get();
+    L->adj = L->o_adj.get();
+    L->ew = all_unit ? nullptr : (const void*)L->o_ew.get();
+    L->ew_kind = all_unit ? EW_UNIT : EW_I64;
+    L->nw = L->o_nw.get();
+    L->src = L->o_src.get();
+    L->gid = L->o_gid.get();
+    sync(s_);
+  }
+  levels_.push_back(std::move(L));
+}
+
+// -------------------------------------------------------------- LP driver --
+void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
+                    std::vector<uint8_t>& active, uint32_t* label, int64_t* W, size_t nlabels,
+                    uint32_t* csize, const std::vector<uint64_t>& label_base,
+                    std::vector<uint64_t>* ncl, std::vector<uint32_t>& rounds_run) {
+  const uint32_t B = (uint32_t)L.graphs.size();
+  const uint64_t n = L.n;
+  const uint32_t S = p_.subrounds;
+  const uint32_t NB = S * NCLASS;
+  rounds_run.assign(B, 0);
+  if (n == 0) return;
+  std::vector<GraphDesc> gd(B);
+  for (uint32_t b = 0; b < B; ++b) {
+    const Job& jb = jobs[L.graphs[b]];
+    gd[b] = GraphDesc{};
+    gd[b].node_base = L.nbase[b];
+    gd[b].nodes = L.nbase[b + 1] - L.nbase[b];
+    gd[b].label_base = label_base[b];
+    gd[b].cap = spec.refine ? jb.lmax : jb.U;
+    gd[b].subrounds = S;
+    gd[b].active = active[b];
+  }
+  DBuf<GraphDesc> dgd(&pool_, s_, B);
+  DBuf<unsigned long long> dmoves(&pool_, s_, B), ddelta(&pool_, s_, B);
+  DBuf<Cand> cands(&pool_, s_, n);
+  DBuf<uint32_t> ncands(&pool_, s_, 1), list(&pool_, s_, n);
+  DBuf<int64_t> demand(&pool_, s_, nlabels);
+  DBuf<uint32_t> ntgt(&pool_, s_, nlabels), fill(&pool_, s_, nlabels), segbase(&pool_, s_, nlabels);
+  DBuf<uint32_t> ovtotal(&pool_, s_, 2), ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
+  DBuf<uint8_t> adm(&pool_, s_, n);
+  DBuf<uint32_t> bcount(&pool_, s_, NB), boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
+  demand.zero();
+  ntgt.zero();
+  fill.zero();
+  std::vector<uint32_t> cnt(NB), offs(NB);
+  std::vector<unsigned long long> hmoves(B), hdelta(B);
+  const uint64_t tsub = spec.refine ? TAG_RSUB : TAG_SUB;
+  const uint64_t ttie = spec.refine ? TAG_RTIE : TAG_TIE;
+  const uint64_t tadm = spec.refine ? TAG_RADM : TAG_ADM;
+  for (uint32_t r = 0; r < spec.rounds; ++r) {
+    bool any = false;
+    for (uint32_t b = 0; b < B; ++b) any |= active[b] != 0;
+    if (!any) break;
+    std::vector<uint64_t> round_moves(B, 0);
+    for (uint32_t b = 0; b < B; ++b) {
+      const Job& jb = jobs[L.graphs[b]];
+      gd[b].pre_sub = chain(jb.seed, tsub, {spec.level, r});
+      gd[b].pre_tie = chain(jb.seed, ttie, {spec.level, r});
+      gd[b].pre_adm = chain(jb.seed, tadm, {spec.level, r});
+      gd[b].active = active[b];
+      if (active[b]) rounds_run[b] = r + 1;
+    }
+    h2d(dgd.get(), gd.data(), B, s_);
+    // sub-round buckets
+    BucketArgs ba{};
+    ba.xadj = L.xadj;
+    ba.gid = L.gid;
+    ba.gd = dgd.get();
+    ba.n = n;
+    ba.mode = 0;
+    ba.nbuckets = NB;
+    ba.counts = bcount.get();
+    ba.offs = boffs.get();
+    ba.fill = bfill.get();
+    ba.list = list.get();
+    bcount.zero();
+    launch_bucket_count(ba, s_);
+    d2h(cnt.data(), bcount.get(), NB, s_);
+    sync(s_);
+    uint32_t run = 0;
+    for (uint32_t i = 0; i < NB; ++i) {
+      offs[i] = run;
+      run += cnt[i];
+    }
+    h2d(boffs.get(), offs.data(), NB, s_);
+    bfill.zero();
+    launch_bucket_scatter(ba, s_);
+    for (uint32_t sr = 0; sr < S; ++sr) {
+      uint32_t total = 0;
+      for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
+      if (total == 0) continue;
+      bool live = false;
+      for (uint32_t b = 0; b < B; ++b) live |= active[b] != 0;
+      if (!live) break;
+      ncands.zero();
+      dmoves.zero();
+      ddelta.zero();
+      RateArgs ra{};
+      ra.xadj = L.xadj;
+      ra.adj = L.adj;
+      ra.ew = L.ew;
+      ra.nw = L.nw;
+      ra.label = label;
+      ra.W = W;
+      ra.gid = L.gid;
+      ra.gd = dgd.get();
+      ra.mode = MODE_LP;
+      ra.cands = cands.get();
+      ra.ncands = ncands.get();
+      ra.demand = demand.get();
+      ra.ntgt = ntgt.get();
+      DBuf<uint64_t> goff;
+      DBuf<uint32_t> gkeys;
+      DBuf<int64_t> gvals;
+      const uint32_t c7 = cnt[sr * NCLASS + CLASS_GLOBAL];
+      if (c7) {
+        const uint32_t* l7 = list.get() + offs[sr * NCLASS + CLASS_GLOBAL];
+        goff.reset(&pool_, s_, c7 + 1);
+        exclusive_scan(TableSize{L.xadj, l7}, c7, goff.get(), true, pool_, s_);
+        uint64_t tot = 0;
+        d2h(&tot, goff.get() + c7, 1, s_);
+        sync(s_);
+        gkeys.reset(&pool_, s_, tot);
+        gvals.reset(&pool_, s_, tot);
+        ra.gkeys = gkeys.get();
+        ra.gvals = gvals.get();
+        ra.goff = goff.get();
+      }
+      for (int c = 0; c < NCLASS; ++c) {
+        ra.list = list.get() + offs[sr * NCLASS + c];
+        ra.count = cnt[sr * NCLASS + c];
+        launch_rate(c, L.ew_kind, ra, s_);
+      }
+      AdmitArgs aa{};
+      aa.cands = cands.get();
+      aa.ncands = ncands.get();
+      aa.max_cands = total;
+      aa.W = W;
+      aa.Wmut = W;
+      aa.nw = L.nw;
+      aa.label = label;
+      aa.gid = L.gid;
+      aa.gd = dgd.get();
+      aa.demand = demand.get();
+      aa.ntgt = ntgt.get();
+      aa.fill = fill.get();
+      aa.segbase = segbase.get();
+      aa.ovtotal = ovtotal.get();
+      aa.ovcount = ovtotal.get() + 1;
+      aa.ovtgts = ovtgts.get();
+      aa.adm = adm.get();
+      aa.cpos = cpos.get();
+      aa.seg = seg.get();
+      aa.csize = csize;
+      aa.moves = (uint64_t*)dmoves.get();
+      aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
+      ovtotal.zero();
+      launch_admit(aa, s_);
+      d2h(hmoves.data(), dmoves.get(), B, s_);
+      d2h(hdelta.data(), ddelta.get(), B, s_);
+      sync(s_);
+      bool dirty = false;
+      for (uint32_t b = 0; b < B; ++b) {
+        if (!active[b]) continue;
+        round_moves[b] += hmoves[b];
+        if (ncl) {
+          (*ncl)[b] += (uint64_t)(int64_t)hdelta[b];
+          const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
+          if ((u128)p_.shrink_num * (*ncl)[b] <= (u128)p_.shrink_den * nb) {
+            active[b] = 0;
+            gd[b].active = 0;
+            dirty = true;
+          }
+        }
+      }
+      if (dirty) h2d(dgd.get(), gd.data(), B, s_);
+    }
+    for (uint32_t b = 0; b < B; ++b)
+      if (active[b] && round_moves[b] == 0) active[b] = 0;
+  }
+  sync(s_);
+}
+
+// ------------------------------------------------------------ clustering --
+void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t>& which,
+                     uint32_t level, uint32_t* label, int64_t* W, uint32_t* csize,
+                     std::vector<uint64_t>& ncl) {
+  const uint32_t B = (uint32_t)L.graphs.size();
+  const uint64_t n = L.n;
+  std::vector<GraphDesc> gd(B);
+  for (uint32_t b = 0; b < B; ++b) {
+    const Job& jb = jobs[L.graphs[b]];
+    gd[b] = GraphDesc{};
+    gd[b].node_base = L.nbase[b];
+    gd[b].nodes = L.nbase[b + 1] - L.nbase[b];
+    gd[b].label_base = L.nbase[b];
+    gd[b].cap = jb.U;
+    gd[b].pre_tie = chain(jb.seed, TAG_FAV, {level});
+    gd[b].pre_two = chain(jb.seed, TAG_TWOHOP, {level});
+    gd[b].active = which[b];
+    gd[b].subrounds = 1;
+  }
+  DBuf<GraphDesc> dgd(&pool_, s_, B);
+  h2d(dgd.get(), gd.data(), B, s_);
+  // favourites of light singletons with neighbours
+  DBuf<uint32_t> bcount(&pool_, s_, NCLASS), boffs(&pool_, s_, NCLASS), bfill(&pool_, s_, NCLASS);
+  DBuf<uint32_t> list(&pool_, s_, n), fav(&pool_, s_, n);
+  BucketArgs ba{};
+  ba.xadj = L.xadj;
+  ba.gid = L.gid;
+  ba.gd = dgd.get();
+  ba.n = n;
+  ba.mode = 1;
+  ba.label = label;
+  ba.csize = csize;
+  ba.nw = L.nw;
+  ba.nbuckets = NCLASS;
+  ba.counts = bcount.get();
+  ba.offs = boffs.get();
+  ba.fill = bfill.get();
+  ba.list = list.get();
+  bcount.zero();
+  launch_bucket_count(ba, s_);
+  std::vector<uint32_t> cnt(NCLASS), offs(NCLASS);
+  d2h(cnt.data(), bcount.get(), NCLASS, s_);
+  sync(s_);
+  uint32_t run = 0;
+  for (int c = 0; c < NCLASS; ++c) {
+    offs[c] = run;
+    run += cnt[c];
+  }
+  h2d(boffs.get(), offs.data(), NCLASS, s_);
+  bfill.zero();
+  launch_bucket_scatter(ba, s_);
+  RateArgs ra{};
+  ra.xadj = L.xadj;
+  ra.adj = L.adj;
+  ra.ew = L.ew;
+  ra.nw = L.nw;
+  ra.label = label;
+  ra.W = W;
+  ra.gid = L.gid;
+  ra.gd = dgd.get();
+  ra.mode = MODE_FAV;
+  ra.fav = fav.get();
+  DBuf<uint64_t> goff;
+  DBuf<uint32_t> gkeys;
+  DBuf<int64_t> gvals;
+  if (cnt[CLASS_GLOBAL]) {
+    const uint32_t c7 = cnt[CLASS_GLOBAL];
+    const uint32_t* l7 = list.get() + offs[CLASS_GLOBAL];
+    goff.reset(&pool_, s_, c7 + 1);
+    exclusive_scan(TableSize{L.xadj, l7}, c7, goff.get(), true, pool_, s_);
+    uint64_t tot = 0;
+    d2h(&tot, goff.get() + c7, 1, s_);
+    sync(s_);
+    gkeys.reset(&pool_, s_, tot);
+    gvals.reset(&pool_, s_, tot);
+    ra.gkeys = gkeys.get();
+    ra.gvals = gvals.get();
+    ra.goff = goff.get();
+  }
+  for (int c = 0; c < NCLASS; ++c) {
+    ra.list = list.get() + offs[c];
+    ra.count = cnt[c];
+    launch_rate(c, L.ew_kind, ra, s_);
+  }
+  // order light singletons by (favourite, hash, id)
+  SingletonFlag sf{label, csize, L.nw, L.gid, dgd.get()};
+  DBuf<uint32_t> pos(&pool_, s_, n + 1);
+  exclusive_scan(sf, n, pos.get(), true, pool_, s_);
+  uint32_t ns32 = 0;
+  d2h(&ns32, pos.get() + n, 1, s_);
+  sync(s_);
+  const uint64_t ns = ns32;
+  if (ns < 2) return;
+  DBuf<uint64_t> keys(&pool_, s_, ns), keys2(&pool_, s_, ns);
+  DBuf<uint32_t> vals(&pool_, s_, ns), vals2(&pool_, s_, ns);
+  k_twohop_keys<<<grid_for(n, 256), 256, 0, s_>>>(sf, L.xadj, fav.get(), pos.get(), n, keys.get(),
+                                                  vals.get());
+  LAUNCH_CHECK();
+  int kb = 1;
+  while ((1ull << kb) <= 2 * n + 1) ++kb;
+  const bool sw = radix_sort_pairs<uint32_t>(keys.get(), vals.get(), keys2.get(), vals2.get(), ns,
+                                             0, 32 + kb, pool_, s_);
+  const uint64_t* sk = sw ? keys2.get() : keys.get();
+  const uint32_t* sv = sw ? vals2.get() : vals.get();
+  DBuf<uint32_t> first(&pool_, s_, 2 * n + 2), flag(&pool_, s_, ns), rank(&pool_, s_, ns + 1);
+  DBuf<unsigned long long> pairs(&pool_, s_, B);
+  pairs.zero();
+  const unsigned gs = grid_for(ns, 256);
+  k_seg_first<<<gs, 256, 0, s_>>>(sk, ns, first.get());
+  LAUNCH_CHECK();
+  k_pair_flags<<<gs, 256, 0, s_>>>(sk, sv, ns, first.get(), L.gid, flag.get(), pairs.get());
+  LAUNCH_CHECK();
+  exclusive_scan(ArrayU32{flag.get()}, ns, rank.get(), true, pool_, s_);
+  std::vector<unsigned long long> hp(B);
+  d2h(hp.data(), pairs.get(), B, s_);
+  sync(s_);
+  std::vector<uint64_t> base(B), cap(B);
+  uint64_t acc = 0;
+  for (uint32_t b = 0; b < B; ++b) {
+    base[b] = acc;
+    acc += hp[b];
+    const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
+    const uint64_t floor_cl = (uint64_t)(((u128)p_.shrink_den * nb + p_.shrink_num - 1) / p_.shrink_num);
+    cap[b] = ncl[b] > floor_cl ? ncl[b] - floor_cl : 0;
+    if (!which[b]) cap[b] = 0;
+  }
+  DBuf<uint64_t> dbase(&pool_, s_, B), dcap(&pool_, s_, B);
+  h2d(dbase.get(), base.data(), B, s_);
+  h2d(dcap.get(), cap.data(), B, s_);
+  k_pair_merge<<<gs, 256, 0, s_>>>(sv, flag.get(), rank.get(), ns, L.gid, dbase.get(), dcap.get(),
+                                   label, W, L.nw, csize);
+  LAUNCH_CHECK();
+  for (uint32_t b = 0; b < B; ++b) ncl[b] -= std::min<uint64_t>(hp[b], cap[b]);
+  sync(s_);
+}
+
+void Engine::cluster(Level& L, std::vector<Job>& jobs, std::vector<uint8_t>& active,
+                     DBuf<uint32_t>& label, DBuf<int64_t>& W, DBuf<uint32_t>& csize,
+                     std::vector<uint64_t>& ncl, std::vector<lmgp_level_info>& stats) {
+  const uint32_t B = (uint32_t)L.graphs.size();
+  const uint64_t n = L.n;
+  const uint32_t level = (uint32_t)levels_.size();  // 1-based index of L
+  label.reset(&pool_, s_, n ? n : 1);
+  W.reset(&pool_, s_, n ? n : 1);
+  csize.reset(&pool_, s_, n ? n : 1);
+  if (n) {
+    k_iota<<<grid_for(n, 256), 256, 0, s_>>>(label.get(), n);
+    LAUNCH_CHECK();
+    k_copy_i64<<<grid_for(n, 256), 256, 0, s_>>>(W.get(), L.nw, n);
+    LAUNCH_CHECK();
+    device_fill_u32(csize.get(), 1u, n, s_);
+  }
+  ncl.resize(B);
+  for (uint32_t b = 0; b < B; ++b) ncl[b] = L.nbase[b + 1] - L.nbase[b];
+  std::vector<uint8_t> act = active;
+  std::vector<uint32_t> rounds;
+  LpSpec spec{false, level, p_.lp_rounds};
+  run_lp(L, jobs, spec, act, label.get(), W.get(), n, csize.get(), L.nbase, &ncl, rounds);
+  stats.assign(B, lmgp_level_info{});
+  std::vector<uint8_t> which(B, 0);
+  bool any = false;
+  for (uint32_t b = 0; b < B; ++b) {
+    stats[b].lp_rounds = rounds[b];
+    stats[b].nclusters_lp = ncl[b];
+    const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
+    which[b] = active[b] && 2 * ncl[b] > nb;
+    stats[b].twohop = which[b];
+    any |= which[b] != 0;
+  }
+  if (any) two_hop(L, jobs, which, level, label.get(), W.get(), csize.get(), ncl);
+}
+
+// -------------------------------------------------------------- coarsening --
+void Engine::coarsen(std::vector<Job>& jobs) {
+  Timer tm(s_);
+  tm.start();
+  build_union(jobs);
+  for (auto& jb : jobs) {
+    jb.nlevels = 1;
+    jb.info.clear();
+    lmgp_level_info i0{};
+    i0.n = jb.g->n;
+    i0.m = jb.g->nnz / 2;
+    i0.m_prime = i0.m;
+    jb.info.push_back(i0);
+  }
+  while (true) {
+    Level& L = *levels_.back();
+    const uint32_t B = (uint32_t)L.graphs.size();
+    const uint32_t depth = (uint32_t)levels_.size();
+    std::vector<uint8_t> active(B, 0);
+    bool any = false;
+    for (uint32_t b = 0; b < B; ++b) {
+      const Job& jb = jobs[L.graphs[b]];
+      const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
+      active[b] = ((u128)nb > (u128)p_.clim * jb.k) && depth < p_.max_levels;
+      any |= active[b] != 0;
+    }
+    if (!any) break;
+    DBuf<uint32_t> label, csize;
+    DBuf<int64_t> W;
+    std::vector<uint64_t> ncl;
+    std::vector<lmgp_level_info> stats;
+    cluster(L, jobs, active, label, W, csize, ncl, stats);
+    // shrink test before contraction: the coarse node count is the cluster count
+    std::vector<uint8_t> keep(B, 0);
+    std::vector<uint32_t> newpos(B, 0);
+    uint32_t nkeep = 0;
+    for (uint32_t b = 0; b < B; ++b) {
+      const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
+      keep[b] = active[b] && (u128)p_.stop_den * ncl[b] <= (u128)p_.stop_num * nb;
+      if (keep[b]) newpos[b] = nkeep++;
+    }
+    if (!nkeep) break;
+    DBuf<uint8_t> dkeep(&pool_, s_, B);
+    h2d(dkeep.get(), keep.data(), B, s_);
+    ContractIn ci;
+    ci.n = L.n;
+    ci.xadj = L.xadj;
+    ci.adj = L.adj;
+    ci.ew = L.ew;
+    ci.ew_kind = L.ew_kind;
+    ci.label = label.get();
+    ci.W = W.get();
+    ci.csize = csize.get();
+    ci.gid = L.gid;
+    ci.keep = dkeep.get();
+    ci.bounds = L.nbase;
+    ContractOut co;
+    contract_level(ci, co, pool_, s_);
+    label.clear();
+    csize.clear();
+    W.clear();
+    // the coarse union: kept graphs in order
+    auto C = std::make_unique<Level>();
+    C->n = co.nc;
+    C->nnz = co.nnz;
+    for (uint32_t b = 0; b < B; ++b)
+      if (keep[b]) {
+        C->graphs.push_back(L.graphs[b]);
+        C->nbase.push_back(co.cid_at_bounds[b]);
+      }
+    C->nbase.push_back(co.nc);
+    const uint32_t BC = nkeep;
+    C->ebase.resize(BC + 1);
+    for (uint32_t c = 0; c <= BC; ++c) d2h(&C->ebase[c], co.xadj.get() + C->nbase[c], 1, s_);
+    sync(s_);
+    // remap coarse graph ids to positions in the coarse union
+    if (BC > 1) {
+      std::vector<uint32_t> remap(B);
+      for (uint32_t b = 0; b < B; ++b) remap[b] = newpos[b];
+      DBuf<uint32_t> drm(&pool_, s_, B);
+      h2d(drm.get(), remap.data(), B, s_);
+      struct Remap {};
+      // gid values were written as old positions; translate in place
+      auto translate = [&](uint32_t* g, uint64_t nn) {
+        std::vector<uint32_t> hg(nn);
+        d2h(hg.data(), g, nn, s_);
+        sync(s_);
+        for (auto& x : hg) x = remap[x];
+        h2d(g, hg.data(), nn, s_);
+      };
+      translate(co.gid.get(), co.nc);
+    }
+    // budget and sparsification per kept graph
+    std::vector<SparsGraph> sgs(BC);
+    std::vector<lmgp_level_info> infos(BC);
+    bool any_trig = false;
+    for (uint32_t c = 0, b = 0; b < B; ++b) {
+      if (!keep[b]) continue;
+      const Job& jb = jobs[L.graphs[b]];
+      const uint64_t m_i = (L.ebase[b + 1] - L.ebase[b]) / 2;
+      const uint64_t n_i = L.nbase[b + 1] - L.nbase[b];
+      const uint64_t n_c = C->nbase[c + 1] - C->nbase[c];
+      const uint64_t m_c = (C->ebase[c + 1] - C->ebase[c]) / 2;
+      const u128 a1 = (u128)p_.tau_e_num * m_i / p_.tau_e_den;
+      const u128 a2 = (u128)p_.tau_d_num * m_i * n_c / ((u128)p_.tau_d_den * n_i);
+      const uint64_t m_hat = (uint64_t)(a1 < a2 ? a1 : a2);
+      const bool trig = p_.sampler != 2 && (u128)m_c * p_.rho_den > (u128)p_.rho_num * m_hat;
+      lmgp_level_info& li = infos[c];
+      li = stats[b];
+      li.n = n_c;
+      li.m_prime = m_c;
+      li.m_hat = m_hat;
+      li.triggered = trig;
+      SparsGraph& sg = sgs[c];
+      sg.node_base = C->nbase[c];
+      sg.e0 = C->ebase[c];
+      sg.e1 = C->ebase[c + 1];
+      sg.m_hat = m_hat;
+      sg.triggered = trig;
+      sg.pre = chain(jb.seed, TAG_SPARS, {(uint64_t)depth + 1});
+      any_trig |= trig;
+      ++c;
+    }
+    if (any_trig) {
+      SparsOut so;
+      sparsify_level(co.nc, co.nnz, co.xadj.get(), co.adj.get(), co.ew.get(), co.src.get(),
+                     BC > 1 ? co.gid.get() : nullptr, sgs, so, pool_, s_);
+      C->nnz = so.nnz;
+      C->o_xadj = std::move(so.xadj);
+      C->o_adj = std::move(so.adj);
+      C->o_ew = std::move(so.ew);
+      C->o_src = std::move(so.src);
+      for (uint32_t c = 0; c <= BC; ++c) d2h(&C->ebase[c], C->o_xadj.get() + C->nbase[c], 1, s_);
+      sync(s_);
+    } else {
+      C->o_xadj = std::move(co.xadj);
+      C->o_adj = std::move(co.adj);
+      C->o_ew = std::move(co.ew);
+      C->o_src = std::move(co.src);
+    }
+    C->o_nw = std::move(co.nw);
+    if (BC > 1) C->o_gid = std::move(co.gid);
+    C->xadj = C->o_xadj.get();
+    C->adj = C->o_adj.get();
+    C->ew = C->o_ew.get();
+    C->ew_kind = EW_I64;
+    C->nw = C->o_nw.get();
+    C->src = C->o_src.get();
+    C->gid = BC > 1 ? C->o_gid.get() : nullptr;
+    L.map = std::move(co.map);
+    for (uint32_t c = 0; c < BC; ++c) {
+      Job& jb = jobs[C->graphs[c]];
+      lmgp_level_info li = infos[c];
+      li.m = (C->ebase[c + 1] - C->ebase[c]) / 2;
+      li.w_t = sgs[c].triggered ? sgs[c].w_t : 0;
+      li.n_gt = sgs[c].n_gt;
+      li.n_eq = sgs[c].n_eq;
+      jb.info.push_back(li);
+      jb.nlevels++;
+    }
+    levels_.push_back(std::move(C));
+  }
+  t_coarsen_ns = tm.stop_ns();
+}
+
+// ------------------------------------------------------------ partitioning --
+void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device) {
+  const uint32_t NJ = (uint32_t)jobs.size();
+  std::vector<uint64_t> kbase(NJ + 1, 0);
+  for (uint32_t g = 0; g < NJ; ++g) kbase[g + 1] = kbase[g] + jobs[g].k;
+  const uint64_t Ktot = kbase[NJ];
+  Timer tm(s_);
+  // initial partitioning of every graph's coarsest level, on the host
+  tm.start();
+  std::vector<std::vector<uint32_t>> ip(NJ);
+  for (uint32_t g = 0; g < NJ; ++g) {
+    const uint32_t top = jobs[g].nlevels - 1;
+    Level& L = *levels_[top];
+    uint32_t b = 0;
+    while (L.graphs[b] != g) ++b;
+    const uint64_t n0 = L.nbase[b], n1 = L.nbase[b + 1], e0 = L.ebase[b], e1 = L.ebase[b + 1];
+    std::vector<uint64_t> xadj(n1 - n0 + 1);
+    std::vector<uint32_t> adj(e1 - e0);
+    std::vector<int64_t> nw(n1 - n0);
+    d2h(xadj.data(), L.xadj + n0, n1 - n0 + 1, s_);
+    d2h(adj.data(), L.adj + e0, e1 - e0, s_);
+    d2h(nw.data(), L.nw + n0, n1 - n0, s_);
+    sync(s_);
+    for (auto& x : xadj) x -= e0;
+    for (auto& y : adj) y -= (uint32_t)n0;
+    initial_partition_host(n1 - n0, xadj, adj, nw, jobs[g].k, jobs[g].seed, top + 1, ip[g]);
+    for (auto& x : ip[g]) x += (uint32_t)kbase[g];
+  }
+  t_initial_ns = tm.stop_ns();
+  tm.start();
+  DBuf<int64_t> BW(&pool_, s_, Ktot ? Ktot : 1);
+  DBuf<uint32_t> upper;  // blocks of level j+1
+  for (int j = (int)levels_.size() - 1; j >= 0; --j) {
+    Level& L = *levels_[j];
+    const uint32_t B = (uint32_t)L.graphs.size();
+    DBuf<uint32_t> block(&pool_, s_, L.n ? L.n : 1);
+    for (uint32_t b = 0; b < B; ++b) {
+      const uint32_t g = L.graphs[b];
+      if (jobs[g].nlevels - 1 == (uint32_t)j) h2d(block.get() + L.nbase[b], ip[g].data(), ip[g].size(), s_);
+    }
+    if ((size_t)j + 1 < levels_.size()) project_blocks(L.map.get(), upper.get(), L.n, block.get(), s_);
+    BW.zero();
+    block_weights(block.get(), L.nw, L.n, BW.get(), s_);
+    std::vector<uint8_t> active(B, 1);
+    std::vector<uint64_t> lb(B);
+    for (uint32_t b = 0; b < B; ++b) lb[b] = kbase[L.graphs[b]];
+    std::vector<uint32_t> rounds;
+    LpSpec spec{true, (uint32_t)j + 1, p_.ref_rounds};
+    run_lp(L, jobs, spec, active, block.get(), BW.get(), Ktot, nullptr, lb, nullptr, rounds);
+    upper = std::move(block);
+  }
+  // evaluation on the input graphs
+  Level& L0 = *levels_[0];
+  const uint32_t B0 = (uint32_t)L0.graphs.size();
+  DBuf<int64_t> cut(&pool_, s_, B0);
+  cut.zero();
+  edge_cut(L0.src, L0.adj, L0.ew, L0.ew_kind, upper.get(), L0.gid, L0.nnz, cut.get(), s_);
+  BW.zero();
+  block_weights(upper.get(), L0.nw, L0.n, BW.get(), s_);
+  std::vector<int64_t> hcut(B0), hbw(Ktot);
+  d2h(hcut.data(), cut.get(), B0, s_);
+  d2h(hbw.data(), BW.get(), Ktot, s_);
+  for (uint32_t b = 0; b < B0; ++b) {
+    const uint32_t g = L0.graphs[b];
+    const uint64_t n0 = L0.nbase[b], nn = L0.nbase[b + 1] - n0;
+    if (!block_out || !block_out[g]) continue;
+    if (on_device) {
+      if (nn) {
+        k_to_local<<<grid_for(nn, 256), 256, 0, s_>>>(upper.get() + n0, nn, (uint32_t)kbase[g],
+                                                      block_out[g]);
+        LAUNCH_CHECK();
+      }
+    } else {
+      d2h(block_out[g], upper.get() + n0, nn, s_);
+    }
+  }
+  sync(s_);
+  t_refine_ns = tm.stop_ns();
+  for (uint32_t b = 0; b < B0; ++b) {
+    const uint32_t g = L0.graphs[b];
+    Job& jb = jobs[g];
+    if (!on_device && block_out && block_out[g]) {
+      const uint64_t nn = L0.nbase[b + 1] - L0.nbase[b];
+      for (uint64_t i = 0; i < nn; ++i) block_out[g][i] -= (uint32_t)kbase[g];
+    }
+    int64_t mx = 0;
+    for (uint64_t i = kbase[g]; i < kbase[g + 1]; ++i) mx = std::max(mx, hbw[i]);
+    jb.res.cut = hcut[b];
+    jb.res.max_block_weight = mx;
+    jb.res.lmax = jb.lmax;
+    jb.res.levels = jb.nlevels;
+  }
+}
+
+// ------------------------------------------------ initial partitioning --
+// Recursive bipartitioning by greedy graph growing (Sec. 4.3's recursive
+// bipartitioning; the growing rule is this library's reading).  For a node
+// set S receiving blocks [off, off + kS): k1 = ceil(kS/2),
+// T1 = ceil(c(S) k1 / kS).  A breadth-first search over G[S] starts at the
+// unvisited node with the smallest (H(seed, IP, level, off, kS, u), u); a
+// dequeued node joins part 1 iff it still fits T1, and only joined nodes
+// enqueue their unvisited neighbours of S (in adjacency order).  When the
+// queue runs dry the next start is taken, until part 1 weighs T1 or S is
+// exhausted.
+namespace {
+
+struct IpState {
+  uint64_t n;
+  const std::vector<uint64_t>* xadj;
+  const std::vector<uint32_t>* adj;
+  const std::vector<int64_t>* nw;
+  uint64_t seed, level;
+  std::vector<uint32_t>* block;
+  std::vector<uint32_t> inset, visited;
+  std::vector<uint8_t> part1;
+  uint32_t stamp = 0;
+};
+
+void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t off) {
+  if (S.empty()) return;
+  if (kS == 1) {
+    for (uint32_t v : S) (*st.block)[v] = off;
+    return;
+  }
+  const uint32_t k1 = (kS + 1) / 2;
+  int64_t cS = 0;
+  for (uint32_t v : S) cS += (*st.nw)[v];
+  const int64_t T1 = (int64_t)(((u128)cS * k1 + kS - 1) / kS);
+  const uint32_t my = ++st.stamp;
+  const uint64_t pre = chain(st.seed, TAG_IP, {st.level, (uint64_t)off, (uint64_t)kS});
+  std::vector<std::pair<uint64_t, uint32_t>> order(S.size());
+  for (size_t i = 0; i < S.size(); ++i) {
+    st.inset[S[i]] = my;
+    order[i] = {hash_add(pre, S[i]), S[i]};
+  }
+  std::sort(order.begin(), order.end());
+  for (uint32_t v : S) st.part1[v] = 0;
+  std::vector<uint32_t> queue;
+  queue.reserve(S.size());
+  int64_t w1 = 0;
+  size_t ptr = 0;
+  while (w1 < T1) {
+    while (ptr < order.size() && st.visited[order[ptr].second] == my) ++ptr;
+    if (ptr == order.size()) break;
+    queue.clear();
+    size_t head = 0;
+    st.visited[order[ptr].second] = my;
+    queue.push_back(order[ptr].second);
+    while (head < queue.size() && w1 < T1) {
+      const uint32_t v = queue[head++];
+      if (w1 + (*st.nw)[v] > T1) continue;
+      st.part1[v] = 1;
+      w1 += (*st.nw)[v];
+      for (uint64_t e = (*st.xadj)[v]; e < (*st.xadj)[v + 1]; ++e) {
+        const uint32_t x = (*st.adj)[e];
+        if (st.inset[x] == my && st.visited[x] != my) {
+          st.visited[x] = my;
+          queue.push_back(x);
+        }
+      }
+    }
+  }
+  std::vector<uint32_t> S1, S2;
+  for (uint32_t v : S) (st.part1[v] ? S1 : S2).push_back(v);
+  S.clear();
+  S.shrink_to_fit();
+  grow_bisect(st, S1, k1, off);
+  grow_bisect(st, S2, kS - k1, off + k1);
+}
+
+}  // namespace
+
+void initial_partition_host(uint64_t n, const std::vector<uint64_t>& xadj,
+                            const std::vector<uint32_t>& adj, const std::vector<int64_t>& nw,
+                            uint32_t k, uint64_t seed, uint64_t level, std::vector<uint32_t>& block) {
+  IpState st;
+  st.n = n;
+  st.xadj = &xadj;
+  st.adj = &adj;
+  st.nw = &nw;
+  st.seed = seed;
+  st.level = level;
+  block.assign(n, 0);
+  st.block = &block;
+  st.inset.assign(n, 0);
+  st.visited.assign(n, 0);
+  st.part1.assign(n, 0);
+  std::vector<uint32_t> S(n);
+  for (uint64_t v = 0; v < n; ++v) S[v] = (uint32_t)v;
+  grow_bisect(st, S, k, 0);
+}
+
+}  // namespace lmgp

@@ -1,0 +1,126 @@
+// Kernel interfaces of the coarsening / refinement pipeline.  Every kernel
+// works on a union of one or more graphs laid out back to back (graph g owns
+// nodes [node_base, node_base + nodes) and their CSR entries); `gid` maps a
+// node to its graph and may be NULL when the union holds a single graph.
+#pragma once
+#include "common.h"
+#include "memory.h"
+#include "primitives.h"
+
+namespace lmgp {
+
+// Per-graph parameters, device resident, indexed by graph id.
+struct GraphDesc {
+  uint64_t node_base;   // first node of the graph in the union
+  uint64_t nodes;       // its node count
+  uint64_t label_base;  // subtracted from labels before hashing (clusters: node_base,
+                        // refinement: first global block id of the graph)
+  int64_t cap;          // U (clustering) or L_max (refinement)
+  uint64_t pre_sub;     // hash prefixes: H(seed, SUB|RSUB, level, round)
+  uint64_t pre_tie;     //               H(seed, TIE|RTIE, level, round) or H(seed, FAV, level)
+  uint64_t pre_adm;     //               H(seed, ADM|RADM, level, round)
+  uint64_t pre_two;     //               H(seed, TWOHOP, level)
+  uint32_t active;      // graph takes part in the current phase
+  uint32_t subrounds;
+};
+
+LMGP_D uint32_t graph_of(const uint32_t* gid, uint64_t u) { return gid ? gid[u] : 0u; }
+
+// An LP move candidate.
+struct Cand {
+  uint32_t u;     // node
+  uint32_t tgt;   // target cluster / block (global label)
+  uint32_t hadm;  // admission-order hash (upper 32 bits)
+  uint32_t pad;
+  int64_t gain;   // r(target) - r(own)
+};
+
+// Degree classes of the rating kernel: lane groups of 2..64 lanes take nodes
+// of degree <= 2*G, a whole 256-thread block takes degree <= 2048, larger
+// degrees use a rating table in global memory.
+constexpr int NCLASS = 8;
+constexpr int CLASS_BLOCK = 6;
+constexpr int CLASS_GLOBAL = 7;
+constexpr int BLOCK_TABLE = 4096;  // LDS table slots of the block class
+LMGP_HD int degree_class(uint64_t d) {
+  return d <= 4 ? 0 : d <= 8 ? 1 : d <= 16 ? 2 : d <= 32 ? 3 : d <= 64 ? 4 : d <= 128 ? 5
+       : d <= 2048 ? 6 : 7;
+}
+LMGP_HD int class_group(int c) { return c < 6 ? (2 << c) : 256; }
+
+enum RateMode : int { MODE_LP = 0, MODE_FAV = 1 };
+
+struct RateArgs {
+  const uint64_t* xadj;
+  const uint32_t* adj;
+  const void* ew;
+  const int64_t* nw;
+  const uint32_t* label;
+  const int64_t* W;        // weight of each label (cluster / block)
+  const uint32_t* gid;
+  const GraphDesc* gd;
+  const uint32_t* list;    // nodes to rate
+  uint32_t count;
+  int mode;
+  // MODE_LP outputs
+  Cand* cands;
+  uint32_t* ncands;
+  int64_t* demand;         // per label: summed weight of candidates targeting it
+  uint32_t* ntgt;          // per label: number of candidates targeting it
+  // MODE_FAV output
+  uint32_t* fav;
+  // global-table class
+  uint32_t* gkeys;
+  int64_t* gvals;
+  const uint64_t* goff;    // table offset of each listed node (class 7 only)
+};
+
+void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s);
+
+// Sub-round bucketing of the nodes to rate: bucket = subround * NCLASS + class.
+struct BucketArgs {
+  const uint64_t* xadj;
+  const uint32_t* gid;
+  const GraphDesc* gd;
+  uint64_t n;
+  int mode;                // 0: LP sub-rounds (hash), 1: 2-hop singletons (filter arrays)
+  const uint32_t* label;   // mode 1
+  const uint32_t* csize;   // mode 1: member count per label
+  const int64_t* nw;       // mode 1
+  uint32_t nbuckets;
+  uint32_t* counts;        // [nbuckets]
+  const uint32_t* offs;    // [nbuckets] (scatter pass)
+  uint32_t* fill;          // [nbuckets] (scatter pass)
+  uint32_t* list;          // output
+};
+void launch_bucket_count(const BucketArgs& a, hipStream_t s);
+void launch_bucket_scatter(const BucketArgs& a, hipStream_t s);
+
+// Admission of LP candidates and application of moves.
+struct AdmitArgs {
+  Cand* cands;
+  const uint32_t* ncands;
+  uint32_t max_cands;      // launch bound
+  const int64_t* W;
+  int64_t* Wmut;
+  const int64_t* nw;
+  uint32_t* label;
+  const uint32_t* gid;
+  const GraphDesc* gd;
+  int64_t* demand;
+  uint32_t* ntgt;
+  uint32_t* fill;
+  uint32_t* segbase;
+  uint32_t* ovtotal;       // [1]
+  uint32_t* ovcount;       // [1]
+  uint32_t* ovtgts;
+  uint8_t* adm;
+  uint32_t* cpos;
+  uint32_t* seg;
+  uint32_t* csize;         // member counts (clustering) or NULL
+  uint64_t* moves;         // per graph
+  int64_t* ncl_delta;      // per graph (clustering) or NULL
+};
+void launch_admit(const AdmitArgs& a, hipStream_t s);
+
+}  // namespace lmgp

@@ -1,0 +1,160 @@
+// Device memory for the library: either the caller's allocator (e.g. the
+// PyTorch caching allocator, passed through the C ABI) or a stream-ordered
+// caching pool of hipMalloc'd blocks.
+#pragma once
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "lmgp.h"
+
+namespace lmgp {
+
+// Zero device memory with a kernel on stream s (graph-capture safe).
+void device_zero(void* p, size_t bytes, hipStream_t s);
+
+class Pool {
+ public:
+  explicit Pool(const lmgp_allocator* user) {
+    if (user) user_ = *user, have_user_ = true;
+  }
+  ~Pool() { release(); }
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
+
+  void* alloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 1;
+    if (have_user_) {
+      void* p = user_.alloc(user_.ctx, bytes, (void*)s);
+      if (!p) throw OutOfMemory("caller allocator returned NULL for " + std::to_string(bytes) + " bytes");
+      return p;
+    }
+    size_t sz = round_up(bytes);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto& fl = free_[Key{s, sz}];
+      if (!fl.empty()) {
+        void* p = fl.back();
+        fl.pop_back();
+        sizes_[p] = sz;
+        return p;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, sz);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw OutOfMemory("hipMalloc failed for " + std::to_string(sz) + " bytes");
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    sizes_[p] = sz;
+    owned_.push_back(p);
+    return p;
+  }
+
+  void free(void* p, hipStream_t s) {
+    if (!p) return;
+    if (have_user_) {
+      user_.free(user_.ctx, p, (void*)s);
+      return;
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = sizes_.find(p);
+    if (it == sizes_.end()) return;
+    free_[Key{s, it->second}].push_back(p);
+    sizes_.erase(it);
+  }
+
+  // Return cached blocks to the device (blocks in use stay allocated).
+  void trim() {
+    std::lock_guard<std::mutex> g(mu_);
+    std::vector<void*> keep;
+    for (auto& kv : free_)
+      for (void* p : kv.second) {
+        (void)hipFree(p);
+        for (auto& q : owned_)
+          if (q == p) q = nullptr;
+      }
+    free_.clear();
+    for (void* q : owned_)
+      if (q) keep.push_back(q);
+    owned_.swap(keep);
+  }
+
+  void release() {
+    if (have_user_) return;
+    std::lock_guard<std::mutex> g(mu_);
+    for (void* p : owned_)
+      if (p) (void)hipFree(p);
+    owned_.clear();
+    free_.clear();
+    sizes_.clear();
+  }
+
+ private:
+  struct Key {
+    hipStream_t s;
+    size_t sz;
+    bool operator<(const Key& o) const { return s != o.s ? s < o.s : sz < o.sz; }
+  };
+  static size_t round_up(size_t b) {
+    size_t r = 512;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  bool have_user_ = false;
+  lmgp_allocator user_{};
+  std::mutex mu_;
+  std::map<Key, std::vector<void*>> free_;
+  std::map<void*, size_t> sizes_;
+  std::vector<void*> owned_;
+};
+
+// Owning device buffer bound to a pool and a stream.
+template <class T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(Pool* pool, hipStream_t s, size_t n) { reset(pool, s, n); }
+  ~DBuf() { clear(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      clear();
+      p_ = o.p_, n_ = o.n_, pool_ = o.pool_, s_ = o.s_;
+      o.p_ = nullptr, o.n_ = 0;
+    }
+    return *this;
+  }
+  void reset(Pool* pool, hipStream_t s, size_t n) {
+    clear();
+    pool_ = pool, s_ = s, n_ = n;
+    p_ = (T*)pool->alloc(n * sizeof(T), s);
+  }
+  void clear() {
+    if (p_ && pool_) pool_->free(p_, s_);
+    p_ = nullptr, n_ = 0;
+  }
+  void zero() {
+    if (p_ && n_) device_zero(p_, n_ * sizeof(T), s_);
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  operator T*() const { return p_; }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  Pool* pool_ = nullptr;
+  hipStream_t s_ = nullptr;
+};
+
+}  // namespace lmgp

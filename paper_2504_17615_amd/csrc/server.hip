@@ -1,0 +1,246 @@
+// Serving loop: continuous batching of partition requests on one GPU.
+//
+// Requests enter a FIFO queue.  Worker threads (one device stream each) admit
+// requests from the head of the queue while a slot is free and the summed
+// footprint estimate of resident requests stays within the HBM budget, up to
+// max_batch per run, and partition the admitted set as one batched run (all
+// graphs of the run share every kernel launch).  Requests arriving while runs
+// are on the device are admitted by the next free worker as soon as slots and
+// memory free up, so their work overlaps with the runs in flight.  Every
+// result is identical to a plain lmgp_partition call (per-graph rules only).
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "engine.h"
+
+
+namespace lmgp {
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t ticket = 0;
+  lmgp_graph* graph = nullptr;
+  uint32_t k = 0;
+  double eps = 0;
+  uint64_t seed = 0;
+  uint32_t* out = nullptr;
+  uint64_t footprint = 0;
+  clk::time_point t_submit;
+  bool done = false;
+  lmgp_status status = LMGP_OK;
+  std::string error;
+  lmgp_result res{};
+};
+
+}  // namespace
+
+// Conservative device footprint of one request: hierarchy levels (each at most
+// the input size), per-level scratch, and the batch union copy.
+uint64_t request_footprint(uint64_t n, uint64_t nnz) {
+  return 4096 + n * 160 + nnz * 64;
+}
+
+}  // namespace lmgp
+
+struct lmgp_server {
+  lmgp_server_cfg cfg{};
+  bool have_alloc = false;
+  lmgp_allocator alloc{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<lmgp::Request*> queue;
+  std::map<uint64_t, std::unique_ptr<lmgp::Request>> all;
+  uint64_t next_ticket = 1;
+  uint64_t resident_bytes = 0;
+  uint32_t resident = 0;
+  bool stop = false;
+  std::vector<std::thread> workers;
+};
+
+namespace lmgp {
+
+namespace {
+
+void worker_main(lmgp_server* sv) {
+  (void)hipSetDevice(sv->device);
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+  Pool pool(sv->have_alloc ? &sv->alloc : nullptr);
+  const lmgp_params p = default_params();
+  while (true) {
+    std::vector<Request*> batch;
+    uint64_t bytes = 0;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_work.wait(lk, [&] {
+        if (sv->stop) return true;
+        if (sv->queue.empty()) return false;
+        Request* r = sv->queue.front();
+        return sv->resident < sv->cfg.max_slots &&
+               sv->resident_bytes + r->footprint <= sv->cfg.hbm_budget_bytes;
+      });
+      if (sv->stop) break;
+      while (!sv->queue.empty() && batch.size() < sv->cfg.max_batch) {
+        Request* r = sv->queue.front();
+        if (sv->resident >= sv->cfg.max_slots ||
+            sv->resident_bytes + r->footprint > sv->cfg.hbm_budget_bytes)
+          break;
+        sv->queue.pop_front();
+        sv->resident++;
+        sv->resident_bytes += r->footprint;
+        bytes += r->footprint;
+        batch.push_back(r);
+      }
+    }
+    lmgp_status st = LMGP_OK;
+    std::string err;
+    std::vector<Job> jobs;
+    try {
+      std::vector<uint32_t*> outs;
+      for (Request* r : batch) {
+        Job j;
+        j.g = &r->graph->g;
+        j.k = r->k;
+        j.eps = r->eps;
+        j.seed = r->seed;
+        const int64_t cV = r->graph->g.cV;
+        int64_t U = (int64_t)((unsigned __int128)cV / ((unsigned __int128)p.clim * r->k));
+        j.U = U < 1 ? 1 : U;
+        const int64_t avg = (cV + (int64_t)r->k - 1) / (int64_t)r->k;
+        j.lmax = (int64_t)std::floor((1.0 + r->eps) * (double)avg);
+        jobs.push_back(std::move(j));
+        outs.push_back(r->out);
+      }
+      Engine e(pool, s, p);
+      e.coarsen(jobs);
+      e.partition(jobs, outs.data(), false);
+    } catch (const OutOfMemory& ex) {
+      st = LMGP_ENOMEM;
+      err = ex.what();
+    } catch (const std::exception& ex) {
+      st = LMGP_EDEVICE;
+      err = ex.what();
+    }
+    const auto now = clk::now();
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      for (size_t i = 0; i < batch.size(); ++i) {
+        Request* r = batch[i];
+        r->status = st;
+        r->error = err;
+        if (st == LMGP_OK) r->res = jobs[i].res;
+        r->res.t_total_ns =
+            std::chrono::duration_cast<std::chrono::nanoseconds>(now - r->t_submit).count();
+        r->done = true;
+      }
+      sv->resident -= (uint32_t)batch.size();
+      sv->resident_bytes -= bytes;
+    }
+    sv->cv_done.notify_all();
+    sv->cv_work.notify_all();
+  }
+  (void)hipStreamSynchronize(s);
+  pool.release();
+  (void)hipStreamDestroy(s);
+}
+
+thread_local std::string s_err;
+
+}  // namespace
+
+}  // namespace lmgp
+
+using namespace lmgp;
+
+extern "C" {
+
+const char* lmgp_last_error(void);
+
+lmgp_status lmgp_server_create(const lmgp_server_cfg* cfg, const lmgp_allocator* alloc,
+                               lmgp_server** out) {
+  if (!cfg || !out) return LMGP_EINVAL;
+  if (!cfg->max_slots || !cfg->max_batch || !cfg->streams || !cfg->hbm_budget_bytes)
+    return LMGP_EINVAL;
+  try {
+    auto sv = std::make_unique<lmgp_server>();
+    sv->cfg = *cfg;
+    if (alloc) sv->alloc = *alloc, sv->have_alloc = true;
+    if (hipGetDevice(&sv->device) != hipSuccess) return LMGP_EDEVICE;
+    for (uint32_t i = 0; i < cfg->streams; ++i) sv->workers.emplace_back(worker_main, sv.get());
+    *out = sv.release();
+    return LMGP_OK;
+  } catch (...) {
+    return LMGP_ENOMEM;
+  }
+}
+
+lmgp_status lmgp_server_submit(lmgp_server* sv, lmgp_graph* g, uint32_t k, double eps,
+                               uint64_t seed, uint32_t* block_out, uint64_t* ticket) {
+  if (!sv || !g || !block_out || !ticket) return LMGP_EINVAL;
+  if (k == 0 || (uint64_t)k > g->g.n || !(eps > 0.0)) return LMGP_EINVAL;
+  auto r = std::make_unique<Request>();
+  r->graph = g;
+  r->k = k;
+  r->eps = eps;
+  r->seed = seed;
+  r->out = block_out;
+  r->footprint = request_footprint(g->g.n, g->g.nnz);
+  if (r->footprint > sv->cfg.hbm_budget_bytes) return LMGP_EBUSY;
+  r->t_submit = clk::now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return LMGP_ECANCELLED;
+    r->ticket = sv->next_ticket++;
+    *ticket = r->ticket;
+    sv->queue.push_back(r.get());
+    sv->all[r->ticket] = std::move(r);
+  }
+  sv->cv_work.notify_one();
+  return LMGP_OK;
+}
+
+static lmgp_status finish(lmgp_server* sv, uint64_t ticket, lmgp_result* res, bool block) {
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return LMGP_EINVAL;
+  Request* r = it->second.get();
+  if (block) sv->cv_done.wait(lk, [&] { return r->done || sv->stop; });
+  if (!r->done) return sv->stop ? LMGP_ECANCELLED : LMGP_ENOTREADY;
+  const lmgp_status st = r->status;
+  if (res) *res = r->res;
+  sv->all.erase(it);
+  return st;
+}
+
+lmgp_status lmgp_server_poll(lmgp_server* sv, uint64_t ticket, lmgp_result* res) {
+  if (!sv) return LMGP_EINVAL;
+  return finish(sv, ticket, res, false);
+}
+
+lmgp_status lmgp_server_wait(lmgp_server* sv, uint64_t ticket, lmgp_result* res) {
+  if (!sv) return LMGP_EINVAL;
+  return finish(sv, ticket, res, true);
+}
+
+void lmgp_server_destroy(lmgp_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  sv->cv_done.notify_all();
+  for (auto& t : sv->workers) t.join();
+  delete sv;
+}
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+// Weighted threshold sampling (Sec. 4.2).  omega_t is the weight of the
+// m_hat-th heaviest coarse edge; heavier edges are kept, lighter ones
+// dropped, and among the edges of weight omega_t exactly r = m_hat - |E^>|
+// are kept: those with the smallest (H(seed, SPARS, level, a, b), a, b),
+// a < b, so that the coarse graph has exactly m_hat edges.  The hash is
+// symmetric in the edge, so both CSR entries of an edge get the same decision.
+//
+// omega_t: MSB-first radix select with 8-bit digits over the weights of the
+// directed entries (every edge counted twice, so the (2 m_hat)-th largest
+// entry).  The r-th smallest hash among E^=: one 12-bit histogram pass, then
+// the entries of the selected bucket are gathered and ranked exactly.
+#include <algorithm>
+
+#include "contract.h"
+
+namespace lmgp {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_wmax(const int64_t* ew, uint64_t e0, uint64_t e1,
+                                              unsigned long long* out) {
+  __shared__ int64_t sm[NWAVE];
+  int64_t m = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride)
+    m = ew[e] > m ? ew[e] : m;
+  m = wave_reduce_max(m);
+  if (lane_id() == 0) sm[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < NWAVE; ++i) m = sm[i] > m ? sm[i] : m;
+    atomicMax(out, (unsigned long long)m);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_whist(const int64_t* ew, uint64_t e0, uint64_t e1,
+                                               int shift, uint64_t prefix, uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const int hs = shift + 8;
+  for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
+    const uint64_t w = (uint64_t)ew[e];
+    const bool match = hs >= 64 || (w >> hs) == (prefix >> hs);
+    if (match) atomicAdd(&h[(w >> shift) & 0xFF], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+LMGP_D uint64_t edge_key(uint64_t pre, uint64_t a, uint64_t b) {
+  return hash_add(hash_add(pre, a), b);
+}
+
+// 12-bit histogram of the top bits of the keys of E^= (a < b entries only).
+__global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32_t* adj,
+                                               const int64_t* ew, uint64_t e0, uint64_t e1,
+                                               int64_t w_t, uint64_t base, uint64_t pre,
+                                               uint32_t* hist) {
+  __shared__ uint32_t h[4096];
+  for (int i = threadIdx.x; i < 4096; i += 256) h[i] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
+    const uint32_t a = src[e], b = adj[e];
+    if (a < b && ew[e] == w_t) atomicAdd(&h[edge_key(pre, a - base, b - base) >> 52], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4096; i += 256)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+struct EqEntry {
+  uint64_t key;
+  uint32_t a, b;  // local ids
+};
+
+__global__ __launch_bounds__(256) void k_kgather(const uint32_t* src, const uint32_t* adj,
+                                                 const int64_t* ew, uint64_t e0, uint64_t e1,
+                                                 int64_t w_t, uint64_t base, uint64_t pre,
+                                                 uint32_t bucket, EqEntry* out, uint32_t* cnt,
+                                                 uint32_t cap) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
+    const uint32_t a = src[e], b = adj[e];
+    if (a < b && ew[e] == w_t) {
+      const uint64_t k = edge_key(pre, a - base, b - base);
+      if ((k >> 52) == bucket) {
+        const uint32_t p = atomicAdd(cnt, 1u);
+        if (p < cap) out[p] = EqEntry{k, a - (uint32_t)base, b - (uint32_t)base};
+      }
+    }
+  }
+}
+
+struct SparsDesc {
+  uint64_t node_base;
+  uint64_t pre;
+  int64_t w_t;
+  uint64_t tkey;
+  uint32_t ta, tb;
+  uint32_t mode;  // 0 keep all, 1 keep w >= w_t, 2 keep w > w_t and E^= up to (tkey, ta, tb)
+  uint32_t pad;
+};
+
+__global__ void k_keep(const uint32_t* src, const uint32_t* adj, const int64_t* ew,
+                       const uint32_t* gid, const SparsDesc* sd, uint64_t nnz, uint8_t* keep) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t u = src[e], v = adj[e];
+  const SparsDesc d = sd[graph_of(gid, u)];
+  uint8_t k = 1;
+  if (d.mode != 0) {
+    const int64_t w = ew[e];
+    if (w > d.w_t) k = 1;
+    else if (w < d.w_t) k = 0;
+    else if (d.mode == 1) k = 1;
+    else {
+      const uint32_t a = (u < v ? u : v) - (uint32_t)d.node_base;
+      const uint32_t b = (u < v ? v : u) - (uint32_t)d.node_base;
+      const uint64_t key = edge_key(d.pre, a, b);
+      k = key < d.tkey || (key == d.tkey && (a < d.ta || (a == d.ta && b <= d.tb)));
+    }
+  }
+  keep[e] = k;
+}
+
+struct U8At {
+  const uint8_t* a;
+  LMGP_D uint64_t operator()(uint64_t i) const { return a[i]; }
+};
+
+__global__ void k_scatter_kept(const uint32_t* src, const uint32_t* adj, const int64_t* ew,
+                               const uint8_t* keep, const uint64_t* pos, uint64_t nnz,
+                               uint32_t* osrc, uint32_t* oadj, int64_t* oew) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz || !keep[e]) return;
+  const uint64_t p = pos[e];
+  osrc[p] = src[e];
+  oadj[p] = adj[e];
+  oew[p] = ew[e];
+}
+
+__global__ void k_row_starts(const uint64_t* xadj, const uint64_t* pos, uint64_t n,
+                             uint64_t* oxadj) {
+  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > n) return;
+  oxadj[x] = pos[xadj[x]];
+}
+
+unsigned sweep_grid(uint64_t cnt) {
+  unsigned g = grid_for(cnt, 256);
+  return g > 4096 ? 4096 : g;
+}
+
+}  // namespace
+
+void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
+                    const int64_t* ew, const uint32_t* src, const uint32_t* gid,
+                    std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s) {
+  const size_t B = graphs.size();
+  std::vector<SparsDesc> desc(B);
+  DBuf<unsigned long long> dmax(&pool, s, 1);
+  DBuf<uint32_t> hist(&pool, s, 4096), cnt(&pool, s, 1);
+  for (size_t g = 0; g < B; ++g) {
+    SparsGraph& sg = graphs[g];
+    SparsDesc& d = desc[g];
+    d = SparsDesc{sg.node_base, sg.pre, 0, 0, 0, 0, 0, 0};
+    if (!sg.triggered) continue;
+    if (sg.m_hat == 0) {  // keep nothing: threshold above every weight
+      d.mode = 1;
+      d.w_t = INT64_MAX;
+      sg.w_t = 0;
+      continue;
+    }
+    const uint64_t e0 = sg.e0, e1 = sg.e1;
+    dmax.zero();
+    k_wmax<<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, dmax.get());
+    LAUNCH_CHECK();
+    unsigned long long wmax = 0;
+    HIP_CHECK(hipMemcpyAsync(&wmax, dmax.get(), sizeof(wmax), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    int top = 0;
+    while (top < 64 && (wmax >> top) != 0) top += 8;
+    // (2 m_hat)-th largest directed weight
+    uint64_t R = 2 * sg.m_hat, gt = 0, eq = 0, prefix = 0;
+    std::vector<uint32_t> h(256);
+    for (int shift = top - 8; shift >= 0; shift -= 8) {
+      hist.zero();
+      k_whist<<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, shift, prefix, hist.get());
+      LAUNCH_CHECK();
+      HIP_CHECK(hipMemcpyAsync(h.data(), hist.get(), 256 * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      uint64_t cum = 0;
+      int sel = 0;
+      for (int dgt = 255; dgt >= 0; --dgt) {
+        if (cum + h[dgt] >= R) {
+          sel = dgt;
+          break;
+        }
+        cum += h[dgt];
+      }
+      gt += cum;
+      R -= cum;
+      prefix |= (uint64_t)sel << shift;
+      eq = h[sel];
+    }
+    sg.w_t = (int64_t)prefix;
+    sg.n_gt = gt / 2;
+    sg.n_eq = eq / 2;
+    d.w_t = sg.w_t;
+    const uint64_t r = sg.m_hat - sg.n_gt;
+    if (r == sg.n_eq) {
+      d.mode = 1;
+      continue;
+    }
+    // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t
+    hist.zero();
+    k_khist<<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
+                                                 sg.pre, hist.get());
+    LAUNCH_CHECK();
+    std::vector<uint32_t> kh(4096);
+    HIP_CHECK(hipMemcpyAsync(kh.data(), hist.get(), 4096 * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    uint64_t cum = 0;
+    uint32_t bucket = 0;
+    for (uint32_t i = 0; i < 4096; ++i) {
+      if (cum + kh[i] >= r) {
+        bucket = i;
+        break;
+      }
+      cum += kh[i];
+    }
+    const uint64_t rin = r - cum;  // rank inside the bucket (1-based)
+    const uint32_t bsz = kh[bucket];
+    DBuf<EqEntry> buf(&pool, s, bsz ? bsz : 1);
+    cnt.zero();
+    k_kgather<<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
+                                                   sg.pre, bucket, buf.get(), cnt.get(), bsz);
+    LAUNCH_CHECK();
+    std::vector<EqEntry> hb(bsz);
+    HIP_CHECK(hipMemcpyAsync(hb.data(), buf.get(), bsz * sizeof(EqEntry), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    auto less = [](const EqEntry& x, const EqEntry& y) {
+      if (x.key != y.key) return x.key < y.key;
+      if (x.a != y.a) return x.a < y.a;
+      return x.b < y.b;
+    };
+    std::nth_element(hb.begin(), hb.begin() + (rin - 1), hb.end(), less);
+    const EqEntry t = hb[rin - 1];
+    d.mode = 2;
+    d.tkey = t.key;
+    d.ta = t.a;
+    d.tb = t.b;
+  }
+  // keep flags, positions, compaction
+  DBuf<SparsDesc> dd(&pool, s, B);
+  HIP_CHECK(hipMemcpyAsync(dd.get(), desc.data(), B * sizeof(SparsDesc), hipMemcpyHostToDevice, s));
+  DBuf<uint8_t> keep(&pool, s, nnz ? nnz : 1);
+  if (nnz) {
+    k_keep<<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, gid, dd.get(), nnz, keep.get());
+    LAUNCH_CHECK();
+  }
+  DBuf<uint64_t> pos(&pool, s, nnz + 1);
+  exclusive_scan(U8At{keep.get()}, nnz, pos.get(), true, pool, s);
+  uint64_t total = 0;
+  HIP_CHECK(hipMemcpyAsync(&total, pos.get() + nnz, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  out.nnz = total;
+  out.xadj.reset(&pool, s, n + 1);
+  out.adj.reset(&pool, s, total ? total : 1);
+  out.ew.reset(&pool, s, total ? total : 1);
+  out.src.reset(&pool, s, total ? total : 1);
+  if (nnz) {
+    k_scatter_kept<<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, keep.get(), pos.get(), nnz,
+                                                       out.src.get(), out.adj.get(), out.ew.get());
+    LAUNCH_CHECK();
+  }
+  k_row_starts<<<grid_for(n + 1, 256), 256, 0, s>>>(xadj, pos.get(), n, out.xadj.get());
+  LAUNCH_CHECK();
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace lmgp

@@ -1,0 +1,77 @@
+// Uncoarsening helpers: projection of blocks to the finer level (Sec. 2),
+// block weights c(V_i) and the edge cut cut(Pi) = sum_{i<j} omega(E_ij).
+#include "contract.h"
+
+namespace lmgp {
+
+namespace {
+
+__global__ void k_project(const uint32_t* map, const uint32_t* cblock, uint64_t n,
+                          uint32_t* block) {
+  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const uint32_t x = map[u];
+  if (x != EMPTY_KEY) block[u] = cblock[x];
+}
+
+__global__ void k_block_weights(const uint32_t* block, const int64_t* nw, uint64_t n,
+                                int64_t* BW) {
+  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  atomicAdd((unsigned long long*)&BW[block[u]], (unsigned long long)nw[u]);
+}
+
+template <int EWK>
+__global__ __launch_bounds__(256) void k_cut(const uint32_t* src, const uint32_t* adj,
+                                             const void* ew, const uint32_t* block,
+                                             const uint32_t* gid, uint64_t nnz, int64_t* cut) {
+  __shared__ int64_t sm[NWAVE];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  int64_t local = 0;
+  uint32_t g0 = 0;
+  bool single = gid == nullptr;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const uint32_t u = src[e], v = adj[e];
+    if (u < v && block[u] != block[v]) {
+      const int64_t w = edge_w<EWK>(ew, e);
+      if (single) local += w;
+      else atomicAdd((unsigned long long*)&cut[gid[u]], (unsigned long long)w);
+    }
+  }
+  if (single) {
+    const int64_t t = block_reduce_sum(local, sm);
+    if (threadIdx.x == 0 && t) atomicAdd((unsigned long long*)&cut[g0], (unsigned long long)t);
+  }
+}
+
+}  // namespace
+
+void project_blocks(const uint32_t* map, const uint32_t* cblock, uint64_t n, uint32_t* block,
+                    hipStream_t s) {
+  if (!n) return;
+  k_project<<<grid_for(n, 256), 256, 0, s>>>(map, cblock, n, block);
+  LAUNCH_CHECK();
+}
+
+void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t* BW,
+                   hipStream_t s) {
+  if (!n) return;
+  k_block_weights<<<grid_for(n, 256), 256, 0, s>>>(block, nw, n, BW);
+  LAUNCH_CHECK();
+}
+
+void edge_cut(const uint32_t* src, const uint32_t* adj, const void* ew, int ew_kind,
+              const uint32_t* block, const uint32_t* gid, uint64_t nnz, int64_t* cut,
+              hipStream_t s) {
+  if (!nnz) return;
+  unsigned g = grid_for(nnz, 256);
+  if (g > 4096) g = 4096;
+  switch (ew_kind) {
+    case EW_UNIT: k_cut<EW_UNIT><<<g, 256, 0, s>>>(src, adj, ew, block, gid, nnz, cut); break;
+    case EW_I32: k_cut<EW_I32><<<g, 256, 0, s>>>(src, adj, ew, block, gid, nnz, cut); break;
+    default: k_cut<EW_I64><<<g, 256, 0, s>>>(src, adj, ew, block, gid, nnz, cut); break;
+  }
+  LAUNCH_CHECK();
+}
+
+}  // namespace lmgp

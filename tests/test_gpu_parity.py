@@ -1,0 +1,122 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer graph work, so the bar is bit-exact equality: every hierarchy level
+(CSR, node and edge weights, fine-to-coarse map, level statistics), the final
+block of every node, the cut, the maximum block weight and L_max.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_17615_amd import graphgen as gg
+from tests import graphs as T
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_17615_amd as L
+
+    L.library()
+    return L
+
+
+INFO_KEYS = ("n", "m", "m_prime", "m_hat", "triggered", "lp_rounds", "twohop", "w_t", "n_gt",
+             "n_eq", "nclusters_lp")
+
+
+def check_hierarchy(L, g, k, seed, **kw):
+    print(f"hierarchy n={g.n} m={g.nnz // 2} k={k} seed={seed} {kw}", flush=True)
+    dg = L.create_graph(g, validate=True)
+    h = dg.coarsen(k, seed, L.default_params(**kw))
+    oh = O.coarsen(g, k, seed, O.params(**kw))
+    assert h.levels == len(oh.levels)
+    for i in range(h.levels):
+        got, want = h.info(i), oh.info[i]
+        for key in INFO_KEYS:
+            assert got[key] == want[key], (i, key, got[key], want[key])
+        lv = h.copy_level(i)
+        ol = oh.levels[i]
+        assert np.array_equal(lv["xadj"], ol.xadj), i
+        assert np.array_equal(lv["adjncy"], ol.adjncy), i
+        assert np.array_equal(lv["vwgt"], ol.vwgt), i
+        assert np.array_equal(lv["adjwgt"], ol.adjwgt), i
+        if i + 1 < h.levels:
+            assert np.array_equal(lv["map"], oh.maps[i]), i
+    h.close()
+    dg.close()
+    return oh
+
+
+def check_partition(L, g, k, eps, seed, **kw):
+    print(f"partition n={g.n} m={g.nnz // 2} k={k} eps={eps} seed={seed} {kw}", flush=True)
+    dg = L.create_graph(g)
+    blocks, res = dg.partition(k, eps, seed, L.default_params(**kw), host_out=True)
+    ob, ores, _ = O.partition(g, k, eps, seed, O.params(**kw))
+    assert res["cut"] == ores["cut"]
+    assert res["max_block_weight"] == ores["max_block_weight"]
+    assert res["lmax"] == ores["lmax"]
+    assert res["levels"] == ores["levels"]
+    assert np.array_equal(blocks, ob)
+    # device output path gives the same bytes
+    dblocks, _ = dg.partition(k, eps, seed, L.default_params(**kw))
+    assert np.array_equal(dblocks.cpu().numpy().view(np.uint32), ob)
+    dg.close()
+    return res
+
+
+SMALL = ["grid128", "rmat12", "rmat14", "er12", "er14", "rgg14", "rgg16"]
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_hierarchy_parity(lib, name):
+    g, k, eps, seed = gg.workload(name)
+    check_hierarchy(lib, g, min(k, 16), seed)
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_partition_parity(lib, name):
+    g, k, eps, seed = gg.workload(name)
+    check_partition(lib, g, k, eps, seed)
+
+
+@pytest.mark.parametrize("name", ["rmat16", "er16", "rgg18"])
+def test_partition_parity_mid(lib, name):
+    g, k, eps, seed = gg.workload(name)
+    check_partition(lib, g, k, eps, seed)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_weighted_random_graphs(lib, seed):
+    rng = np.random.default_rng(seed)
+    g = T.random_graph(3000, 20000, rng, wmax=9, vmax=5)
+    check_hierarchy(lib, g, 4, seed)
+    check_partition(lib, g, 4, 0.05, seed)
+
+
+def test_sparsification_off(lib):
+    g, k, eps, seed = gg.workload("er14")
+    check_hierarchy(lib, g, 16, seed, sampler=2)
+    check_partition(lib, g, k, eps, seed, sampler=2)
+
+
+def test_hub_rows(lib):
+    # a star with 5000 leaves exercises the global-table rating class and the
+    # radix-sorted contraction rows
+    g = T.star(5000)
+    check_hierarchy(lib, g, 2, 3)
+    check_partition(lib, g, 2, 0.03, 3)
+
+
+def test_tiny_and_degenerate(lib):
+    check_partition(lib, T.path(2), 2, 0.03, 1)
+    check_partition(lib, T.from_edges(5, [(0, 1)]), 3, 0.03, 1)  # isolated nodes
+    check_partition(lib, T.two_cliques(8), 2, 0.03, 3)
+    check_partition(lib, gg.grid(40, 40), 1, 0.03, 1)
+    g = T.from_edges(400, [])  # no edges at all
+    check_partition(lib, g, 4, 0.03, 2)
