@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the multilevel partitioner on one MI355X.
+
+One step = one full pass of the hot path over the resident input graph:
+coarsening with sparsification (LP clustering, 2-hop, contraction, threshold
+sampling), recursive bipartitioning of the coarsest graph, LP refinement on
+every level and the cut/balance evaluation (one lmgp_partition call).
+
+metric: input edges/s through coarsen+refine = m / (T_coarsen + T_refine),
+with T measured by events on the library's stream (the initial bipartitioning
+and the whole-call wall time are reported beside it).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+WORKLOADS = {
+    # name: (description, generator recipe)
+    "rmat22": "R-MAT scale 22 (n=4,194,304), edge factor 16, a=0.57 b=0.19 c=0.19 d=0.05, "
+              "self-loops/duplicates removed, symmetrised, unit weights, k=64, eps=0.03, seed=1",
+    "er22": "Erdos-Renyi G(n=2^22, m=2^26), unit weights, k=128, eps=0.03, seed=1",
+    "rgg24": "random geometric graph n=2^24, avg degree 12, w=1+floor(8(1-d/r)), k=256, "
+             "eps=0.03, seed=1",
+    "grid128": "2D grid 128x128, unit weights, k=4, eps=0.03, seed=1",
+}
+
+
+def cpu_baseline(sample: str):
+    """The CPU oracle (single-threaded) on a bounded sample of the workload."""
+    import oracle as O
+    from paper_2504_17615_amd import graphgen as gg
+
+    g, k, eps, seed = gg.workload(sample)
+    t0 = time.perf_counter()
+    _, res, times = O.partition(g, k, eps, seed)
+    wall = time.perf_counter() - t0
+    cr = times["coarsen"] + times["refine"]
+    return {"value": g.m / cr, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}: same generator recipe at smaller scale (n={g.n}, m={g.m}), "
+                      f"full partition k={k}; coarsen+refine {cr:.2f}s of {wall:.2f}s wall",
+            "cut": res["cut"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", default="rmat18")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2504_17615_amd as L
+    from paper_2504_17615_amd import graphgen as gg
+
+    L.library()
+    t_gen = time.perf_counter()
+    g, k, eps, seed = gg.workload(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    m = g.m
+    dev = L.create_graph(g)
+    del g
+    out = torch.empty(dev.n, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        dev.partition(k, eps, seed, out=out)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        L.profile_read(reset=True)
+        L.profile_enable(True)
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, res = dev.partition(k, eps, seed, out=out)
+        results.append(res)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {}
+    if not args.no_profile:
+        L.profile_enable(False)
+        stats = L.profile_read(reset=True)
+    K = args.steps
+    wall = (t1 - t0) / K
+    cr = sum(r["t_coarsen_ns"] + r["t_refine_ns"] for r in results) / K * 1e-9
+    ph = {p: sum(r[f"t_{p}_ns"] for r in results) / K * 1e-6 for p in ("coarsen", "initial",
+                                                                       "refine")}
+    roof = None
+    if stats:
+        name, st = max(stats.items(), key=lambda kv: kv[1]["total_ns"])
+        per_launch_bytes = st["bytes"] / st["launches"]
+        per_launch_ns = st["total_ns"] / st["launches"]
+        achieved = per_launch_bytes / per_launch_ns  # bytes/ns == GB/s
+        roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "launches": st["launches"],
+                "avg_launch_us": round(per_launch_ns / 1e3, 2),
+                "bytes_per_launch": int(per_launch_bytes)}
+        tot = sum(s["total_ns"] for s in stats.values())
+        tb = sum(s["bytes"] for s in stats.values())
+        roof["lp_rate_all"] = {"achieved": round(tb / tot, 1), "frac": round(tb / tot / HBM_PEAK_GBS, 4),
+                               "share_of_step": round(tot / K / 1e9 / wall, 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_sample)
+    line = {
+        "metric": "input edges/s through coarsen+refine",
+        "value": m / cr,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "n": dev.n, "m": m, "k": k, "eps": eps, "seed": seed,
+                   "parallelism": "single GPU"},
+        "phases_ms": {p: round(v, 3) for p, v in ph.items()},
+        "wall_edges_per_s": m / wall,
+        "cut": results[-1]["cut"],
+        "max_block_weight": results[-1]["max_block_weight"],
+        "lmax": results[-1]["lmax"],
+        "levels": results[-1]["levels"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "gen_s": round(t_gen, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,6 +198,24 @@ lmgp_status lmgp_server_poll(lmgp_server *s, uint64_t ticket, lmgp_result *res);
 lmgp_status lmgp_server_wait(lmgp_server *s, uint64_t ticket, lmgp_result *res);
 void lmgp_server_destroy(lmgp_server *s);
 
+/* Measurement support.  When enabled (process-wide), launches of the main
+ * kernels are bracketed by events on their stream; each kernel family
+ * accumulates its launch count, summed event time and the algorithmic bytes
+ * the launches must move (input reads and output writes counted once).
+ * Enabling adds two event records per launch. */
+typedef struct {
+  char name[48];
+  uint64_t launches;
+  uint64_t total_ns;
+  uint64_t bytes;
+} lmgp_kernel_stat;
+
+lmgp_status lmgp_profile_enable(uint32_t on);
+/* Writes up to `max` entries to `out` (may be NULL), the number of families
+ * to *count; reset = 1 clears the accumulated statistics afterwards. */
+lmgp_status lmgp_profile_read(lmgp_kernel_stat *out, uint32_t max, uint32_t *count,
+                              uint32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,4 +19,6 @@ from ._binding import (  # noqa: F401
     default_params,
     library,
     partition_batch,
+    profile_enable,
+    profile_read,
 )

@@ -96,7 +96,30 @@ _SIGS = {
     "lmgp_server_poll": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "lmgp_server_wait": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "lmgp_server_destroy": ([ctypes.c_void_p], None),
+    "lmgp_profile_enable": ([ctypes.c_uint32], ctypes.c_int),
+    "lmgp_profile_read": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32],
+                          ctypes.c_int),
 }
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64),
+                ("total_ns", ctypes.c_uint64), ("bytes", ctypes.c_uint64)]
+
+
+def profile_enable(on: bool = True):
+    _check(library().lmgp_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """Per kernel family: launches, summed event time (ns), algorithmic bytes."""
+    cnt = ctypes.c_uint32()
+    _check(library().lmgp_profile_read(None, 0, ctypes.byref(cnt), 0))
+    arr = (KernelStat * max(1, cnt.value))()
+    _check(library().lmgp_profile_read(arr, cnt.value, ctypes.byref(cnt), 1 if reset else 0))
+    return {arr[i].name.decode(): dict(launches=int(arr[i].launches),
+                                       total_ns=int(arr[i].total_ns), bytes=int(arr[i].bytes))
+            for i in range(cnt.value)}
 
 EXPORTED = tuple(_SIGS)
 

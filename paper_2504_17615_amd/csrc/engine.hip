@@ -344,6 +344,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<uint32_t> ovtotal(&pool_, s_, 2), ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
   DBuf<uint8_t> adm(&pool_, s_, n);
   DBuf<uint32_t> bcount(&pool_, s_, NB), boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
+  DBuf<unsigned long long> bdeg(&pool_, s_, NB);
+  std::vector<unsigned long long> degs(NB);
   demand.zero();
   ntgt.zero();
   fill.zero();
@@ -375,12 +377,15 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     ba.mode = 0;
     ba.nbuckets = NB;
     ba.counts = bcount.get();
+    ba.degs = bdeg.get();
     ba.offs = boffs.get();
     ba.fill = bfill.get();
     ba.list = list.get();
     bcount.zero();
+    bdeg.zero();
     launch_bucket_count(ba, s_);
     d2h(cnt.data(), bcount.get(), NB, s_);
+    d2h(degs.data(), bdeg.get(), NB, s_);
     sync(s_);
     uint32_t run = 0;
     for (uint32_t i = 0; i < NB; ++i) {
@@ -434,6 +439,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       for (int c = 0; c < NCLASS; ++c) {
         ra.list = list.get() + offs[sr * NCLASS + c];
         ra.count = cnt[sr * NCLASS + c];
+        ra.degsum = degs[sr * NCLASS + c];
         launch_rate(c, L.ew_kind, ra, s_);
       }
       AdmitArgs aa{};

@@ -61,6 +61,7 @@ struct RateArgs {
   const GraphDesc* gd;
   const uint32_t* list;    // nodes to rate
   uint32_t count;
+  uint64_t degsum;         // summed degree of the listed nodes (for measurement)
   int mode;
   // MODE_LP outputs
   Cand* cands;
@@ -89,6 +90,7 @@ struct BucketArgs {
   const int64_t* nw;       // mode 1
   uint32_t nbuckets;
   uint32_t* counts;        // [nbuckets]
+  unsigned long long* degs;  // [nbuckets] summed degrees (count pass)
   const uint32_t* offs;    // [nbuckets] (scatter pass)
   uint32_t* fill;          // [nbuckets] (scatter pass)
   uint32_t* list;          // output

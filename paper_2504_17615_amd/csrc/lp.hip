@@ -12,6 +12,7 @@
 // round, u) asc, u asc) and the longest prefix that fits cap - W_start(K) is
 // admitted; all admitted moves are applied together.
 #include "kernels.h"
+#include "profiler.h"
 
 namespace lmgp {
 
@@ -101,8 +102,10 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
   uint32_t* key = skey + grp * T;
   unsigned long long* val = sval + grp * T;
   const uint64_t idx = (uint64_t)blockIdx.x * GPB + grp;
-  const bool valid = idx < a.count;
+  bool valid = idx < a.count;
   const uint32_t u = valid ? a.list[idx] : 0u;
+  // graphs of a batch may stop in the middle of a round
+  if (valid && a.gid && !a.gd[a.gid[u]].active) valid = false;
 #pragma unroll
   for (int s = gl; s < T; s += G) {
     key[s] = EMPTY_KEY;
@@ -151,6 +154,7 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
+  if (a.gid && !a.gd[a.gid[u]].active) return;
   for (int s = threadIdx.x; s < T; s += 256) {
     key[s] = EMPTY_KEY;
     val[s] = 0;
@@ -195,6 +199,7 @@ __global__ __launch_bounds__(256) void k_rate_global(RateArgs a) {
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
+  if (a.gid && !a.gd[a.gid[u]].active) return;
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   uint64_t T = 1;
   while (T < 2 * (end - beg)) T <<= 1;
@@ -247,9 +252,29 @@ __global__ __launch_bounds__(256) void k_rate_global(RateArgs a) {
   }
 }
 
+const char* rate_name(int cls, int ewk) {
+  static const char* names[3][NCLASS] = {
+      {"lp_rate_g2_unit", "lp_rate_g4_unit", "lp_rate_g8_unit", "lp_rate_g16_unit",
+       "lp_rate_g32_unit", "lp_rate_g64_unit", "lp_rate_block_unit", "lp_rate_global_unit"},
+      {"lp_rate_g2_i32", "lp_rate_g4_i32", "lp_rate_g8_i32", "lp_rate_g16_i32",
+       "lp_rate_g32_i32", "lp_rate_g64_i32", "lp_rate_block_i32", "lp_rate_global_i32"},
+      {"lp_rate_g2_i64", "lp_rate_g4_i64", "lp_rate_g8_i64", "lp_rate_g16_i64",
+       "lp_rate_g32_i64", "lp_rate_g64_i64", "lp_rate_block_i64", "lp_rate_global_i64"}};
+  return names[ewk][cls];
+}
+
+// Algorithmic bytes of rating `count` nodes with `degsum` entries: per node the
+// two offsets, its list slot, label and weight (32 B); per entry the neighbour
+// id, its label and the edge weight (if stored).
+uint64_t rate_bytes(int ewk, uint64_t count, uint64_t degsum) {
+  const uint64_t bw = ewk == EW_UNIT ? 0 : ewk == EW_I32 ? 4 : 8;
+  return 32 * count + (8 + bw) * degsum;
+}
+
 template <int EWK>
 void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (a.count == 0) return;
+  ProfScope prof(rate_name(cls, EWK), rate_bytes(EWK, a.count, a.degsum), s);
   if (cls < CLASS_BLOCK) {
     const int G = class_group(cls);
     const unsigned grid = grid_for(a.count, 256 / G);
@@ -288,16 +313,24 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
 
 __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
   __shared__ uint32_t h[256];
-  for (int i = threadIdx.x; i < 256; i += 256) h[i] = 0;
+  __shared__ unsigned long long hd[256];
+  h[threadIdx.x] = 0;
+  hd[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < a.n; u += stride) {
     int b = bucket_of(a, u);
-    if (b >= 0) atomicAdd(&h[b], 1u);
+    if (b >= 0) {
+      atomicAdd(&h[b], 1u);
+      atomicAdd(&hd[b], (unsigned long long)(a.xadj[u + 1] - a.xadj[u]));
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256)
-    if (h[i]) atomicAdd(&a.counts[i], h[i]);
+    if (h[i]) {
+      atomicAdd(&a.counts[i], h[i]);
+      if (a.degs) atomicAdd(&a.degs[i], hd[i]);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {

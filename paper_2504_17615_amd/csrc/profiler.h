@@ -1,0 +1,63 @@
+// Optional per-kernel timing: launches of the main kernels are bracketed with
+// events on their stream and charged the algorithmic bytes they must move.
+#pragma once
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace lmgp {
+
+struct KernelStat {
+  uint64_t launches = 0;
+  uint64_t total_ns = 0;
+  uint64_t bytes = 0;
+};
+
+class Profiler {
+ public:
+  static Profiler& get();
+  bool on() const { return on_.load(std::memory_order_relaxed); }
+  void enable(bool v) { on_.store(v); }
+  // Record the start of a launch; returns a slot id (or -1 when disabled).
+  int begin(const char* name, uint64_t bytes, hipStream_t s);
+  void end(int slot, hipStream_t s);
+  // Resolve recorded events (synchronises them) and accumulate.
+  void collect();
+  std::map<std::string, KernelStat> read(bool reset);
+  void reset();
+
+ private:
+  struct Rec {
+    std::string name;
+    uint64_t bytes;
+    hipEvent_t a, b;
+  };
+  hipEvent_t take_event();
+  std::atomic<bool> on_{false};
+  std::mutex mu_;
+  std::vector<Rec> pending_;
+  std::vector<hipEvent_t> free_;
+  std::map<std::string, KernelStat> stats_;
+};
+
+// RAII bracket of one launch.
+class ProfScope {
+ public:
+  ProfScope(const char* name, uint64_t bytes, hipStream_t s) : s_(s) {
+    Profiler& p = Profiler::get();
+    slot_ = p.on() ? p.begin(name, bytes, s) : -1;
+  }
+  ~ProfScope() {
+    if (slot_ >= 0) Profiler::get().end(slot_, s_);
+  }
+
+ private:
+  hipStream_t s_;
+  int slot_;
+};
+
+}  // namespace lmgp

@@ -1,0 +1,100 @@
+#include <cstring>
+
+#include "profiler.h"
+#include "lmgp.h"
+
+namespace lmgp {
+
+Profiler& Profiler::get() {
+  static Profiler p;
+  return p;
+}
+
+hipEvent_t Profiler::take_event() {
+  if (!free_.empty()) {
+    hipEvent_t e = free_.back();
+    free_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+
+int Profiler::begin(const char* name, uint64_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> g(mu_);
+  Rec r{name, bytes, take_event(), take_event()};
+  HIP_CHECK(hipEventRecord(r.a, s));
+  pending_.push_back(r);
+  return (int)pending_.size() - 1;
+}
+
+void Profiler::end(int slot, hipStream_t s) {
+  std::lock_guard<std::mutex> g(mu_);
+  if (slot < 0 || (size_t)slot >= pending_.size()) return;
+  HIP_CHECK(hipEventRecord(pending_[slot].b, s));
+}
+
+void Profiler::collect() {
+  std::lock_guard<std::mutex> g(mu_);
+  for (Rec& r : pending_) {
+    HIP_CHECK(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+    KernelStat& st = stats_[r.name];
+    st.launches++;
+    st.total_ns += (uint64_t)((double)ms * 1e6);
+    st.bytes += r.bytes;
+    free_.push_back(r.a);
+    free_.push_back(r.b);
+  }
+  pending_.clear();
+}
+
+std::map<std::string, KernelStat> Profiler::read(bool reset) {
+  collect();
+  std::lock_guard<std::mutex> g(mu_);
+  auto out = stats_;
+  if (reset) stats_.clear();
+  return out;
+}
+
+void Profiler::reset() {
+  collect();
+  std::lock_guard<std::mutex> g(mu_);
+  stats_.clear();
+}
+
+}  // namespace lmgp
+
+extern "C" {
+
+lmgp_status lmgp_profile_enable(uint32_t on) {
+  lmgp::Profiler::get().enable(on != 0);
+  return LMGP_OK;
+}
+
+lmgp_status lmgp_profile_read(lmgp_kernel_stat* out, uint32_t max, uint32_t* count,
+                              uint32_t reset) {
+  if (!count) return LMGP_EINVAL;
+  try {
+    auto st = lmgp::Profiler::get().read(reset != 0);
+    uint32_t i = 0;
+    for (auto& kv : st) {
+      if (out && i < max) {
+        std::memset(out[i].name, 0, sizeof(out[i].name));
+        std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+        out[i].launches = kv.second.launches;
+        out[i].total_ns = kv.second.total_ns;
+        out[i].bytes = kv.second.bytes;
+      }
+      ++i;
+    }
+    *count = i;
+    return LMGP_OK;
+  } catch (...) {
+    return LMGP_EDEVICE;
+  }
+}
+
+}  // extern "C"
