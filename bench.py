@@ -116,6 +116,11 @@ def main():
         tb = sum(s["bytes"] for s in stats.values())
         roof["lp_rate_all"] = {"achieved": round(tb / tot, 1), "frac": round(tb / tot / HBM_PEAK_GBS, 4),
                                "share_of_step": round(tot / K / 1e9 / wall, 3)}
+        roof["families"] = {nm: {"launches": s["launches"],
+                                 "avg_us": round(s["total_ns"] / s["launches"] / 1e3, 1),
+                                 "GBps": round(s["bytes"] / max(1, s["total_ns"]), 1),
+                                 "ms_per_step": round(s["total_ns"] / K / 1e6, 2)}
+                            for nm, s in sorted(stats.items(), key=lambda kv: -kv[1]["total_ns"])}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_sample)

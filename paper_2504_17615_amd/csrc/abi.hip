@@ -120,6 +120,21 @@ __global__ __launch_bounds__(256) void k_sum_i64(const int64_t* a, uint64_t n, i
   if (threadIdx.x == 0) atomicAdd((unsigned long long*)out, (unsigned long long)t);
 }
 
+// Sum of the weights of all entries (weights are validated positive).
+template <int EWK>
+__global__ __launch_bounds__(256) void k_sum_w(const void* ew, uint64_t nnz, int64_t* out) {
+  __shared__ int64_t sm[NWAVE];
+  int64_t s = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+    const int64_t w = edge_w<EWK>(ew, e);
+    s += w > 0 ? w : 0;
+    if (s > (1ll << 40)) s = 1ll << 40;  // saturate: only "below 2^32" matters
+  }
+  const int64_t t = block_reduce_sum(s, sm);
+  if (threadIdx.x == 0) atomicAdd((unsigned long long*)out, (unsigned long long)t);
+}
+
 std::string describe(uint32_t bad) {
   std::string m = "invalid graph:";
   if (bad & BAD_XADJ) m += " xadj not monotone from 0 to nnz;";
@@ -235,15 +250,26 @@ void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
     }
     LAUNCH_CHECK();
   }
-  DBuf<int64_t> tot(&pool, s, 1);
+  DBuf<int64_t> tot(&pool, s, 2);
   tot.zero();
   unsigned gs = grid_for(v.n, 256);
   k_sum_i64<<<gs > 1024 ? 1024 : gs, 256, 0, s>>>(g.nw.get(), v.n, tot.get());
   LAUNCH_CHECK();
+  if (v.nnz && g.ew_kind != EW_UNIT) {
+    unsigned ge = grid_for(v.nnz, 256);
+    if (g.ew_kind == EW_I32)
+      k_sum_w<EW_I32><<<ge > 1024 ? 1024 : ge, 256, 0, s>>>(g.ew32.get(), v.nnz, tot.get() + 1);
+    else
+      k_sum_w<EW_I64><<<ge > 1024 ? 1024 : ge, 256, 0, s>>>(g.ew64.get(), v.nnz, tot.get() + 1);
+    LAUNCH_CHECK();
+  }
+  int64_t hw = 0;
   HIP_CHECK(hipMemcpyAsync(&bad, err.get(), 4, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(&g.cV, tot.get(), 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&hw, tot.get() + 1, 8, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   if (bad) throw InvalidArg(describe(bad));
+  g.wtot = g.ew_kind == EW_UNIT ? v.nnz : (uint64_t)hw;
 }
 
 }  // namespace lmgp

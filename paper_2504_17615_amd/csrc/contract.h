@@ -77,7 +77,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
 // --------------------------------------------------------------- refinement --
 void project_blocks(const uint32_t* map, const uint32_t* cblock, uint64_t n, uint32_t* block,
                     hipStream_t s);
-void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t* BW,
+void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t* BW, uint64_t K,
                    hipStream_t s);
 // cut per graph over entries with src < adj (int64 atomics into cut[g])
 void edge_cut(const uint32_t* src, const uint32_t* adj, const void* ew, int ew_kind,

@@ -60,14 +60,24 @@ __global__ void k_members(const uint64_t* xadj, const uint32_t* map, uint64_t n,
 }
 
 // Row size classes: 0 = wave, 1 = block, 2 = radix sort.
-__global__ void k_row_classes(const unsigned long long* degsum, uint64_t nc, uint32_t* counts,
-                              uint32_t* lists, uint64_t cap) {
-  uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nc) return;
-  const uint64_t d = degsum[x];
-  const int c = d <= ROW_A ? 0 : d <= ROW_B ? 1 : 2;
-  const uint32_t p = atomicAdd(&counts[c], 1u);
-  lists[(uint64_t)c * cap + p] = (uint32_t)x;
+__global__ __launch_bounds__(256) void k_row_classes(const unsigned long long* degsum, uint64_t nc,
+                                                     uint32_t* counts, uint32_t* lists,
+                                                     uint64_t cap) {
+  __shared__ uint32_t lc[3], base[3];
+  if (threadIdx.x < 3) lc[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = -1;
+  uint32_t lp = 0;
+  if (x < nc) {
+    const uint64_t d = degsum[x];
+    c = d <= ROW_A ? 0 : d <= ROW_B ? 1 : 2;
+    lp = atomicAdd(&lc[c], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 && lc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], lc[threadIdx.x]);
+  __syncthreads();
+  if (c >= 0) lists[(uint64_t)c * cap + base[c] + lp] = (uint32_t)x;
 }
 
 template <int EWK>

@@ -16,6 +16,7 @@ struct InputGraph {
   uint64_t n = 0, nnz = 0;
   int ew_kind = EW_UNIT;
   int64_t cV = 0;
+  uint64_t wtot = 0;  // sum of the weights of all entries (bounds every rating)
   DBuf<uint64_t> xadj;
   DBuf<uint32_t> adj;
   DBuf<int32_t> ew32;
@@ -99,6 +100,7 @@ class Engine {
   Pool& pool_;
   hipStream_t s_;
   lmgp_params p_;
+  bool packed_ = false;  // all ratings < 2^32: packed hub tables
   std::vector<std::unique_ptr<Level>> levels_;
 };
 

@@ -93,12 +93,18 @@ __global__ void k_pair_flags(const uint64_t* keys, const uint32_t* vals, uint64_
                              const uint32_t* first, const uint32_t* gid, uint32_t* flag,
                              unsigned long long* pairs) {
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ns) return;
-  const uint64_t fk = keys[p] >> 32;
-  const uint64_t pos = p - first[fk];
-  const bool lead = (pos % 2 == 0) && p + 1 < ns && (keys[p + 1] >> 32) == fk;
-  flag[p] = lead;
-  if (lead) atomicAdd(&pairs[graph_of(gid, vals[p])], 1ull);
+  bool lead = false;
+  if (p < ns) {
+    const uint64_t fk = keys[p] >> 32;
+    const uint64_t pos = p - first[fk];
+    lead = (pos % 2 == 0) && p + 1 < ns && (keys[p + 1] >> 32) == fk;
+    flag[p] = lead;
+    if (lead && gid) atomicAdd(&pairs[gid[vals[p]]], 1ull);
+  }
+  if (!gid) {  // one graph: one atomic per wave
+    const uint64_t c = __popcll(__ballot(lead));
+    if (lane_id() == 0 && c) atomicAdd(&pairs[0], (unsigned long long)c);
+  }
 }
 
 __global__ void k_pair_merge(const uint32_t* vals, const uint32_t* flag, const uint32_t* rank,
@@ -415,32 +421,19 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       ra.gid = L.gid;
       ra.gd = dgd.get();
       ra.mode = MODE_LP;
+      ra.packed = packed_ ? 1 : 0;
       ra.cands = cands.get();
       ra.ncands = ncands.get();
       ra.demand = demand.get();
       ra.ntgt = ntgt.get();
-      DBuf<uint64_t> goff;
-      DBuf<uint32_t> gkeys;
-      DBuf<int64_t> gvals;
-      const uint32_t c7 = cnt[sr * NCLASS + CLASS_GLOBAL];
-      if (c7) {
-        const uint32_t* l7 = list.get() + offs[sr * NCLASS + CLASS_GLOBAL];
-        goff.reset(&pool_, s_, c7 + 1);
-        exclusive_scan(TableSize{L.xadj, l7}, c7, goff.get(), true, pool_, s_);
-        uint64_t tot = 0;
-        d2h(&tot, goff.get() + c7, 1, s_);
-        sync(s_);
-        gkeys.reset(&pool_, s_, tot);
-        gvals.reset(&pool_, s_, tot);
-        ra.gkeys = gkeys.get();
-        ra.gvals = gvals.get();
-        ra.goff = goff.get();
-      }
       for (int c = 0; c < NCLASS; ++c) {
         ra.list = list.get() + offs[sr * NCLASS + c];
         ra.count = cnt[sr * NCLASS + c];
         ra.degsum = degs[sr * NCLASS + c];
-        launch_rate(c, L.ew_kind, ra, s_);
+        if (c == CLASS_GLOBAL || (c == CLASS_BIG && !packed_))
+          launch_rate_hubs(L.ew_kind, ra, pool_, s_);
+        else
+          launch_rate(c, L.ew_kind, ra, s_);
       }
       AdmitArgs aa{};
       aa.cands = cands.get();
@@ -553,28 +546,15 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ra.gid = L.gid;
   ra.gd = dgd.get();
   ra.mode = MODE_FAV;
+  ra.packed = packed_ ? 1 : 0;
   ra.fav = fav.get();
-  DBuf<uint64_t> goff;
-  DBuf<uint32_t> gkeys;
-  DBuf<int64_t> gvals;
-  if (cnt[CLASS_GLOBAL]) {
-    const uint32_t c7 = cnt[CLASS_GLOBAL];
-    const uint32_t* l7 = list.get() + offs[CLASS_GLOBAL];
-    goff.reset(&pool_, s_, c7 + 1);
-    exclusive_scan(TableSize{L.xadj, l7}, c7, goff.get(), true, pool_, s_);
-    uint64_t tot = 0;
-    d2h(&tot, goff.get() + c7, 1, s_);
-    sync(s_);
-    gkeys.reset(&pool_, s_, tot);
-    gvals.reset(&pool_, s_, tot);
-    ra.gkeys = gkeys.get();
-    ra.gvals = gvals.get();
-    ra.goff = goff.get();
-  }
   for (int c = 0; c < NCLASS; ++c) {
     ra.list = list.get() + offs[c];
     ra.count = cnt[c];
-    launch_rate(c, L.ew_kind, ra, s_);
+    if (c == CLASS_GLOBAL || (c == CLASS_BIG && !packed_))
+      launch_rate_hubs(L.ew_kind, ra, pool_, s_);
+    else
+      launch_rate(c, L.ew_kind, ra, s_);
   }
   // order light singletons by (favourite, hash, id)
   SingletonFlag sf{label, csize, L.nw, L.gid, dgd.get()};
@@ -669,6 +649,10 @@ void Engine::coarsen(std::vector<Job>& jobs) {
   Timer tm(s_);
   tm.start();
   build_union(jobs);
+  // a rating never exceeds the total entry weight of its graph (contraction
+  // only merges weight, sparsification only drops it)
+  packed_ = true;
+  for (auto& jb : jobs) packed_ &= jb.g->wtot < (1ull << 32) && jb.g->nnz < (1ull << 32);
   for (auto& jb : jobs) {
     jb.nlevels = 1;
     jb.info.clear();
@@ -871,7 +855,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     }
     if ((size_t)j + 1 < levels_.size()) project_blocks(L.map.get(), upper.get(), L.n, block.get(), s_);
     BW.zero();
-    block_weights(block.get(), L.nw, L.n, BW.get(), s_);
+    block_weights(block.get(), L.nw, L.n, BW.get(), Ktot, s_);
     std::vector<uint8_t> active(B, 1);
     std::vector<uint64_t> lb(B);
     for (uint32_t b = 0; b < B; ++b) lb[b] = kbase[L.graphs[b]];
@@ -887,7 +871,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
   cut.zero();
   edge_cut(L0.src, L0.adj, L0.ew, L0.ew_kind, upper.get(), L0.gid, L0.nnz, cut.get(), s_);
   BW.zero();
-  block_weights(upper.get(), L0.nw, L0.n, BW.get(), s_);
+  block_weights(upper.get(), L0.nw, L0.n, BW.get(), Ktot, s_);
   std::vector<int64_t> hcut(B0), hbw(Ktot);
   d2h(hcut.data(), cut.get(), B0, s_);
   d2h(hbw.data(), BW.get(), Ktot, s_);

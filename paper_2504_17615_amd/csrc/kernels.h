@@ -36,15 +36,18 @@ struct Cand {
 };
 
 // Degree classes of the rating kernel: lane groups of 2..64 lanes take nodes
-// of degree <= 2*G, a whole 256-thread block takes degree <= 2048, larger
-// degrees use a rating table in global memory.
-constexpr int NCLASS = 8;
+// of degree <= 2*G, a whole 256-thread block takes degree <= 2048, a
+// 1024-thread block with a 16384-slot packed LDS table (128 KiB of the 160 KiB
+// LDS) takes degree <= 8192, larger degrees use tables in global memory.
+constexpr int NCLASS = 9;
 constexpr int CLASS_BLOCK = 6;
-constexpr int CLASS_GLOBAL = 7;
+constexpr int CLASS_BIG = 7;
+constexpr int CLASS_GLOBAL = 8;
 constexpr int BLOCK_TABLE = 4096;  // LDS table slots of the block class
+constexpr int BIG_TABLE = 16384;   // packed LDS slots of the big-block class
 LMGP_HD int degree_class(uint64_t d) {
   return d <= 4 ? 0 : d <= 8 ? 1 : d <= 16 ? 2 : d <= 32 ? 3 : d <= 64 ? 4 : d <= 128 ? 5
-       : d <= 2048 ? 6 : 7;
+       : d <= 2048 ? 6 : d <= 8192 ? 7 : 8;
 }
 LMGP_HD int class_group(int c) { return c < 6 ? (2 << c) : 256; }
 
@@ -74,9 +77,13 @@ struct RateArgs {
   uint32_t* gkeys;
   int64_t* gvals;
   const uint64_t* goff;    // table offset of each listed node (class 7 only)
+  unsigned long long* gtab;  // packed (label << 32 | rating) slots
+  int packed;              // every rating fits in 32 bits: use gtab
 };
 
 void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s);
+// Degree class CLASS_GLOBAL: tables in global memory, split over many blocks.
+void launch_rate_hubs(int ew_kind, const RateArgs& a, Pool& pool, hipStream_t s);
 
 // Sub-round bucketing of the nodes to rate: bucket = subround * NCLASS + class.
 struct BucketArgs {

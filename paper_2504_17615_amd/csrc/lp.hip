@@ -191,38 +191,46 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
   }
 }
 
-// One block per node with a rating table in global memory (degree > 2048).
+constexpr unsigned long long EMPTY_SLOT = ~0ull;  // packed slot: label EMPTY_KEY
+
+// Packed LDS table: label in the high half of a slot, rating in the low half
+// (valid when every rating fits in 32 bits).
+template <int T>
+LMGP_D void lds_add_packed(unsigned long long* tab, uint32_t K, unsigned long long w) {
+  constexpr int LOGT = __builtin_ctz(T);
+  uint32_t s = (K * 0x9E3779B1u) >> (32 - LOGT);
+  while (true) {
+    unsigned long long cur = tab[s];
+    if (cur == EMPTY_SLOT) {
+      cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
+      if (cur == EMPTY_SLOT) return;
+    }
+    if ((uint32_t)(cur >> 32) == K) {
+      atomicAdd(&tab[s], w);
+      return;
+    }
+    s = (s + 1) & (T - 1);
+  }
+}
+
+// One 1024-thread block per node of degree in (2048, 8192], packed table of
+// 16384 slots in LDS (load <= 1/2).
 template <int EWK>
-__global__ __launch_bounds__(256) void k_rate_global(RateArgs a) {
-  __shared__ Best sb[NWAVE];
-  __shared__ int64_t so[NWAVE];
+__global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
+  constexpr int T = BIG_TABLE;
+  constexpr int NW = 1024 / WAVE;
+  __shared__ unsigned long long tab[T];
+  __shared__ Best sb[NW];
+  __shared__ int64_t so[NW];
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
   if (a.gid && !a.gd[a.gid[u]].active) return;
-  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
-  uint64_t T = 1;
-  while (T < 2 * (end - beg)) T <<= 1;
-  uint32_t* key = a.gkeys + a.goff[idx];
-  unsigned long long* val = (unsigned long long*)(a.gvals + a.goff[idx]);
-  for (uint64_t s = threadIdx.x; s < T; s += 256) {
-    key[s] = EMPTY_KEY;
-    val[s] = 0;
-  }
+  for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
   __syncthreads();
-  for (uint64_t e = beg + threadIdx.x; e < end; e += 256) {
-    uint32_t K = a.label[a.adj[e]];
-    uint64_t w = (uint64_t)edge_w<EWK>(a.ew, e);
-    uint64_t s = ((uint64_t)K * 0x9E3779B97F4A7C15ull) & (T - 1);
-    while (true) {
-      uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
-      if (prev == EMPTY_KEY || prev == K) {
-        atomicAdd(&val[s], (unsigned long long)w);
-        break;
-      }
-      s = (s + 1) & (T - 1);
-    }
-  }
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  for (uint64_t e = beg + threadIdx.x; e < end; e += 1024)
+    lds_add_packed<T>(tab, a.label[a.adj[e]], (unsigned long long)edge_w<EWK>(a.ew, e));
   __syncthreads();
   const GraphDesc gd = a.gd[graph_of(a.gid, u)];
   const uint32_t own = a.label[u];
@@ -230,11 +238,11 @@ __global__ __launch_bounds__(256) void k_rate_global(RateArgs a) {
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
   int64_t r_own = 0;
-  for (uint64_t s = threadIdx.x; s < T; s += 256) {
-    uint32_t K = __hip_atomic_load(&key[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (K == EMPTY_KEY) continue;
-    int64_t r = (int64_t)__hip_atomic_load(&val[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    consider(a, K, r, own, cu, gd.cap, pre_u, gd.label_base, best, r_own);
+  for (int s = threadIdx.x; s < T; s += 1024) {
+    const unsigned long long v = tab[s];
+    if (v != EMPTY_SLOT)
+      consider(a, (uint32_t)(v >> 32), (int64_t)(v & 0xFFFFFFFFull), own, cu, gd.cap, pre_u,
+               gd.label_base, best, r_own);
   }
   reduce_best<WAVE>(best, r_own);
   const int w = threadIdx.x / WAVE;
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(256) void k_rate_global(RateArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < NWAVE; ++i) {
+    for (int i = 1; i < NW; ++i) {
       if (better(sb[i].r, sb[i].h, sb[i].K, best)) best = sb[i];
       r_own = so[i] > r_own ? so[i] : r_own;
     }
@@ -252,14 +260,226 @@ __global__ __launch_bounds__(256) void k_rate_global(RateArgs a) {
   }
 }
 
+// ------------------------------------------------- hub nodes (degree > 2048) --
+// A hub's rating table lives in global memory; its adjacency is split into
+// chunks of HUB_CHUNK entries rated by separate blocks, and its table into
+// chunks of HUB_SLOTS slots evaluated by separate blocks, so that a few hubs
+// still spread over the whole GPU.
+constexpr int HUB_CHUNK = 2048;
+constexpr int HUB_SLOTS = 4096;
+
+struct HubArgs {
+  RateArgs a;
+  const uint64_t* toff;  // table offset of hub i (c + 1 entries)
+  const uint64_t* coff;  // first insert chunk of hub i
+  const uint64_t* soff;  // first slot chunk of hub i
+  uint64_t slots;        // total table slots
+  struct Partial* part;  // one per slot chunk
+};
+
+struct Partial {
+  int64_t r;
+  uint64_t h;
+  uint32_t K;
+  uint32_t pad;
+  int64_t r_own;
+};
+
+LMGP_D uint32_t find_hub(const uint64_t* off, uint32_t c, uint64_t b) {
+  uint32_t lo = 0, hi = c;  // off[lo] <= b < off[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+LMGP_D bool hub_active(const RateArgs& a, uint32_t u) {
+  return !a.gid || a.gd[a.gid[u]].active;
+}
+
+__global__ void k_hub_clear(HubArgs h) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < h.slots; i += stride) {
+    if (h.a.packed) {
+      h.a.gtab[i] = EMPTY_SLOT;
+    } else {
+      h.a.gkeys[i] = EMPTY_KEY;
+      h.a.gvals[i] = 0;
+    }
+  }
+}
+
+// Add w to label K of a global table of T slots (T a power of two).
+LMGP_D void hub_add(const RateArgs& a, uint64_t base, uint64_t T, uint32_t K,
+                    unsigned long long w) {
+  uint64_t s = ((uint64_t)K * 0x9E3779B97F4A7C15ull) & (T - 1);
+  if (a.packed) {
+    // one 64-bit word per slot: label in the high half, rating in the low half
+    unsigned long long* tab = a.gtab + base;
+    while (true) {
+      unsigned long long cur = tab[s];
+      if (cur == EMPTY_SLOT) {
+        cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
+        if (cur == EMPTY_SLOT) return;
+      }
+      if ((uint32_t)(cur >> 32) == K) {
+        atomicAdd(&tab[s], w);
+        return;
+      }
+      s = (s + 1) & (T - 1);
+    }
+  }
+  uint32_t* key = a.gkeys + base;
+  unsigned long long* val = (unsigned long long*)(a.gvals + base);
+  while (true) {
+    const uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
+    if (prev == EMPTY_KEY || prev == K) {
+      atomicAdd(&val[s], w);
+      return;
+    }
+    s = (s + 1) & (T - 1);
+  }
+}
+
+// Each block sums its chunk per label in LDS first, then adds the distinct
+// labels to the hub's global table (neighbours of a coarse hub share few
+// labels, so this removes most same-address global atomics).
+template <int EWK>
+__global__ __launch_bounds__(256) void k_hub_insert(HubArgs h) {
+  constexpr int LT = 2 * HUB_CHUNK;
+  __shared__ uint32_t lk[LT];
+  __shared__ unsigned long long lv[LT];
+  const RateArgs& a = h.a;
+  const uint32_t i = find_hub(h.coff, a.count, blockIdx.x);
+  const uint32_t u = a.list[i];
+  if (!hub_active(a, u)) return;
+  for (int s = threadIdx.x; s < LT; s += 256) {
+    lk[s] = EMPTY_KEY;
+    lv[s] = 0;
+  }
+  __syncthreads();
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  const uint64_t c0 = beg + (uint64_t)(blockIdx.x - h.coff[i]) * HUB_CHUNK;
+  const uint64_t c1 = c0 + HUB_CHUNK < end ? c0 + HUB_CHUNK : end;
+  for (uint64_t e = c0 + threadIdx.x; e < c1; e += 256)
+    lds_insert<LT>(lk, lv, a.label[a.adj[e]], (uint64_t)edge_w<EWK>(a.ew, e));
+  __syncthreads();
+  const uint64_t T = h.toff[i + 1] - h.toff[i];
+  for (int ls = threadIdx.x; ls < LT; ls += 256) {
+    const uint32_t K = lk[ls];
+    if (K != EMPTY_KEY) hub_add(a, h.toff[i], T, K, lv[ls]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hub_eval(HubArgs h) {
+  __shared__ Best sb[NWAVE];
+  __shared__ int64_t so[NWAVE];
+  const RateArgs& a = h.a;
+  const uint32_t i = find_hub(h.soff, a.count, blockIdx.x);
+  const uint32_t u = a.list[i];
+  if (!hub_active(a, u)) return;
+  const uint64_t T = h.toff[i + 1] - h.toff[i];
+  const uint32_t* key = a.gkeys + h.toff[i];
+  const unsigned long long* val = (const unsigned long long*)(a.gvals + h.toff[i]);
+  const unsigned long long* tab = a.gtab + h.toff[i];
+  const uint64_t s0 = (uint64_t)(blockIdx.x - h.soff[i]) * HUB_SLOTS;
+  const uint64_t s1 = s0 + HUB_SLOTS < T ? s0 + HUB_SLOTS : T;
+  const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+  const uint32_t own = a.label[u];
+  const int64_t cu = a.nw[u];
+  const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+  Best best{0, 0, 0};
+  int64_t r_own = 0;
+  for (uint64_t s = s0 + threadIdx.x; s < s1; s += 256) {
+    uint32_t K;
+    int64_t r;
+    if (a.packed) {
+      const unsigned long long v = tab[s];
+      K = (uint32_t)(v >> 32);
+      r = (int64_t)(v & 0xFFFFFFFFull);
+    } else {
+      K = key[s];
+      r = (int64_t)val[s];
+    }
+    if (K != EMPTY_KEY) consider(a, K, r, own, cu, gd.cap, pre_u, gd.label_base, best, r_own);
+  }
+  reduce_best<WAVE>(best, r_own);
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    sb[w] = best;
+    so[w] = r_own;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NWAVE; ++q) {
+      if (better(sb[q].r, sb[q].h, sb[q].K, best)) best = sb[q];
+      r_own = so[q] > r_own ? so[q] : r_own;
+    }
+    h.part[blockIdx.x] = Partial{best.r, best.h, best.K, 0, r_own};
+  }
+}
+
+__global__ void k_hub_final(HubArgs h) {
+  const RateArgs& a = h.a;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.count) return;
+  const uint32_t u = a.list[i];
+  if (!hub_active(a, u)) return;
+  Best best{0, 0, 0};
+  int64_t r_own = 0;
+  for (uint64_t p = h.soff[i]; p < h.soff[i + 1]; ++p) {
+    const Partial q = h.part[p];
+    if (better(q.r, q.h, q.K, best)) best = Best{q.r, q.h, q.K};
+    r_own = q.r_own > r_own ? q.r_own : r_own;
+  }
+  const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+  emit(a, u, gd, best, r_own, a.nw[u]);
+}
+
+struct HubTable {
+  const uint64_t* xadj;
+  const uint32_t* list;
+  LMGP_D uint64_t operator()(uint64_t i) const {
+    const uint32_t u = list[i];
+    const uint64_t d = xadj[u + 1] - xadj[u];
+    uint64_t T = 1;
+    while (T < 2 * d) T <<= 1;
+    return T;
+  }
+};
+struct HubChunks {
+  const uint64_t* xadj;
+  const uint32_t* list;
+  LMGP_D uint64_t operator()(uint64_t i) const {
+    const uint32_t u = list[i];
+    return ceil_div(xadj[u + 1] - xadj[u], HUB_CHUNK);
+  }
+};
+struct HubSlotChunks {
+  const uint64_t* xadj;
+  const uint32_t* list;
+  LMGP_D uint64_t operator()(uint64_t i) const {
+    const uint32_t u = list[i];
+    const uint64_t d = xadj[u + 1] - xadj[u];
+    uint64_t T = 1;
+    while (T < 2 * d) T <<= 1;
+    return ceil_div(T, HUB_SLOTS);
+  }
+};
+
 const char* rate_name(int cls, int ewk) {
   static const char* names[3][NCLASS] = {
       {"lp_rate_g2_unit", "lp_rate_g4_unit", "lp_rate_g8_unit", "lp_rate_g16_unit",
-       "lp_rate_g32_unit", "lp_rate_g64_unit", "lp_rate_block_unit", "lp_rate_global_unit"},
+       "lp_rate_g32_unit", "lp_rate_g64_unit", "lp_rate_block_unit", "lp_rate_big_unit",
+       "lp_rate_global_unit"},
       {"lp_rate_g2_i32", "lp_rate_g4_i32", "lp_rate_g8_i32", "lp_rate_g16_i32",
-       "lp_rate_g32_i32", "lp_rate_g64_i32", "lp_rate_block_i32", "lp_rate_global_i32"},
+       "lp_rate_g32_i32", "lp_rate_g64_i32", "lp_rate_block_i32", "lp_rate_big_i32",
+       "lp_rate_global_i32"},
       {"lp_rate_g2_i64", "lp_rate_g4_i64", "lp_rate_g8_i64", "lp_rate_g16_i64",
-       "lp_rate_g32_i64", "lp_rate_g64_i64", "lp_rate_block_i64", "lp_rate_global_i64"}};
+       "lp_rate_g32_i64", "lp_rate_g64_i64", "lp_rate_block_i64", "lp_rate_big_i64",
+       "lp_rate_global_i64"}};
   return names[ewk][cls];
 }
 
@@ -288,9 +508,56 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
     }
   } else if (cls == CLASS_BLOCK) {
     k_rate_block<EWK><<<a.count, 256, 0, s>>>(a);
+  } else if (cls == CLASS_BIG) {
+    if (!a.packed) throw InvalidArg("big-block class needs packed ratings");
+    k_rate_big<EWK><<<a.count, 1024, 0, s>>>(a);
   } else {
-    k_rate_global<EWK><<<a.count, 256, 0, s>>>(a);
+    throw InvalidArg("hub class needs launch_rate_hubs");
   }
+  LAUNCH_CHECK();
+}
+
+template <int EWK>
+void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
+  const uint32_t c = ra.count;
+  DBuf<uint64_t> toff(&pool, s, c + 1), coff(&pool, s, c + 1), soff(&pool, s, c + 1);
+  exclusive_scan(HubTable{ra.xadj, ra.list}, c, toff.get(), true, pool, s);
+  exclusive_scan(HubChunks{ra.xadj, ra.list}, c, coff.get(), true, pool, s);
+  exclusive_scan(HubSlotChunks{ra.xadj, ra.list}, c, soff.get(), true, pool, s);
+  uint64_t tot[3] = {0, 0, 0};
+  HIP_CHECK(hipMemcpyAsync(&tot[0], toff.get() + c, 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&tot[1], coff.get() + c, 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&tot[2], soff.get() + c, 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  DBuf<uint32_t> keys;
+  DBuf<int64_t> vals;
+  DBuf<unsigned long long> tab;
+  if (ra.packed) {
+    tab.reset(&pool, s, tot[0]);
+  } else {
+    keys.reset(&pool, s, tot[0]);
+    vals.reset(&pool, s, tot[0]);
+  }
+  DBuf<Partial> part(&pool, s, tot[2]);
+  HubArgs h;
+  h.a = ra;
+  h.a.gkeys = keys.get();
+  h.a.gvals = vals.get();
+  h.a.gtab = tab.get();
+  h.toff = toff.get();
+  h.coff = coff.get();
+  h.soff = soff.get();
+  h.slots = tot[0];
+  h.part = part.get();
+  ProfScope prof(rate_name(CLASS_GLOBAL, EWK), rate_bytes(EWK, ra.count, ra.degsum), s);
+  unsigned gc = grid_for(tot[0], 256);
+  k_hub_clear<<<gc > 4096 ? 4096 : gc, 256, 0, s>>>(h);
+  LAUNCH_CHECK();
+  k_hub_insert<EWK><<<(unsigned)tot[1], 256, 0, s>>>(h);
+  LAUNCH_CHECK();
+  k_hub_eval<<<(unsigned)tot[2], 256, 0, s>>>(h);
+  LAUNCH_CHECK();
+  k_hub_final<<<grid_for(c, 64), 64, 0, s>>>(h);
   LAUNCH_CHECK();
 }
 
@@ -333,26 +600,32 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
     }
 }
 
+// Each block takes 2048 consecutive nodes, counts them per bucket in LDS and
+// reserves its range of every bucket with one atomic (order inside a bucket
+// does not affect any result).
+constexpr int BK_ITEMS = 8;
+
 __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t lt = lanemask_lt();
-  // iterate whole waves so that the ballots below are convergent
-  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < a.n; base += stride) {
-    const uint64_t u = base + threadIdx.x;
-    int b = u < a.n ? bucket_of(a, u) : -1;
-    uint64_t pending = __ballot(b >= 0);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const int lb = __shfl(b, leader);
-      const uint64_t peers = __ballot(b == lb) & pending;
-      uint32_t basepos = 0;
-      if (lane_id() == leader) basepos = atomicAdd(&a.fill[lb], (uint32_t)__popcll(peers));
-      basepos = __shfl(basepos, leader);
-      if ((peers >> lane_id()) & 1ull) {
-        a.list[a.offs[lb] + basepos + (uint32_t)__popcll(peers & lt)] = (uint32_t)u;
-      }
-      pending &= ~peers;
-    }
+  __shared__ uint32_t cnt[256], base[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t b0 = (uint64_t)blockIdx.x * 256 * BK_ITEMS;
+  int bk[BK_ITEMS];
+  uint32_t lp[BK_ITEMS];
+#pragma unroll
+  for (int j = 0; j < BK_ITEMS; ++j) {
+    const uint64_t u = b0 + (uint64_t)j * 256 + threadIdx.x;
+    bk[j] = u < a.n ? bucket_of(a, u) : -1;
+    lp[j] = bk[j] >= 0 ? atomicAdd(&cnt[bk[j]], 1u) : 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x < a.nbuckets && cnt[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&a.fill[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < BK_ITEMS; ++j) {
+    const uint64_t u = b0 + (uint64_t)j * 256 + threadIdx.x;
+    if (bk[j] >= 0) a.list[a.offs[bk[j]] + base[bk[j]] + lp[j]] = (uint32_t)u;
   }
 }
 
@@ -435,121 +708,163 @@ __global__ __launch_bounds__(256) void k_adm_seg_wave(AdmitArgs a) {
   }
 }
 
-// Larger segments: one block each; LDS bitonic sort up to 1024 entries,
-// in-place bitonic sort over global memory beyond that.
-constexpr int SEG_LDS = 1024;
+LMGP_D uint64_t block_min(uint64_t v, uint64_t* sred) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, WAVE);
+    v = o < v ? o : v;
+  }
+  if (lane_id() == 0) sred[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  uint64_t r = sred[0];
+  for (int i = 1; i < NWAVE; ++i) r = sred[i] < r ? sred[i] : r;
+  __syncthreads();
+  return r;
+}
 
+LMGP_D uint64_t block_max(uint64_t v, uint64_t* sred) {
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, WAVE);
+    v = o > v ? o : v;
+  }
+  if (lane_id() == 0) sred[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  uint64_t r = sred[0];
+  for (int i = 1; i < NWAVE; ++i) r = sred[i] > r ? sred[i] : r;
+  __syncthreads();
+  return r;
+}
+
+// Segments of more than 64 candidates: one block each.  Instead of sorting,
+// a weighted MSB-first radix select finds the first key (in admission order)
+// at which the summed node weight exceeds the room; every smaller key is
+// admitted, which is exactly the longest fitting prefix (keys are unique).
 __global__ __launch_bounds__(256) void k_adm_seg_block(AdmitArgs a) {
-  __shared__ uint64_t shi[SEG_LDS], slo[SEG_LDS];
-  __shared__ uint32_t sci[SEG_LDS];
-  __shared__ int64_t sm[NWAVE];
-  __shared__ int64_t carry;
+  __shared__ unsigned long long whist[256];
+  __shared__ uint64_t sred[NWAVE];
+  __shared__ int s_digit;
+  __shared__ int64_t s_rem;
   const uint32_t nt = *a.ovcount;
   for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
     const uint32_t t = a.ovtgts[j];
     const uint32_t size = a.ntgt[t];
     if (size <= WAVE) continue;
     const uint32_t base = a.segbase[t];
-    uint32_t N = 1;
-    while (N < size) N <<= 1;
-    const bool in_lds = size <= SEG_LDS;
-    if (in_lds) {
-      for (uint32_t i = threadIdx.x; i < N; i += 256) {
-        if (i < size) {
-          uint32_t ci = a.seg[base + i];
-          cand_key(a.cands[ci], shi[i], slo[i]);
-          sci[i] = ci;
-        } else {
-          shi[i] = ~0ull;
-          slo[i] = ~0ull;
-          sci[i] = 0;
-        }
-      }
-      __syncthreads();
-      for (uint32_t k = 2; k <= N; k <<= 1) {
-        for (uint32_t j2 = k >> 1; j2 > 0; j2 >>= 1) {
-          for (uint32_t i = threadIdx.x; i < N; i += 256) {
-            const uint32_t p = (j2 == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j2);
-            if (p > i && key_less(shi[p], slo[p], shi[i], slo[i])) {
-              uint64_t th = shi[i], tl = slo[i];
-              uint32_t tc = sci[i];
-              shi[i] = shi[p], slo[i] = slo[p], sci[i] = sci[p];
-              shi[p] = th, slo[p] = tl, sci[p] = tc;
-            }
-          }
-          __syncthreads();
-        }
-      }
-    } else {
-      uint32_t* sg = a.seg + base;
-      for (uint32_t k = 2; k <= N; k <<= 1) {
-        for (uint32_t j2 = k >> 1; j2 > 0; j2 >>= 1) {
-          for (uint32_t i = threadIdx.x; i < N; i += 256) {
-            const uint32_t p = (j2 == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j2);
-            if (p > i && p < size) {
-              uint64_t ih, il, ph, pl;
-              cand_key(a.cands[sg[i]], ih, il);
-              cand_key(a.cands[sg[p]], ph, pl);
-              if (key_less(ph, pl, ih, il)) {
-                uint32_t tc = sg[i];
-                sg[i] = sg[p];
-                sg[p] = tc;
-              }
-            }
-          }
-          __threadfence_block();
-          __syncthreads();
-        }
-      }
-    }
-    // prefix sums of node weights in sorted order, admit while within room
-    const uint32_t u0 = a.cands[a.seg[base]].u;
+    const uint32_t* sg = a.seg + base;
+    const uint32_t u0 = a.cands[sg[0]].u;
     const int64_t room = a.gd[cand_graph(a, u0)].cap - a.W[t];
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (uint32_t off = 0; off < size; off += 256) {
-      const uint32_t i = off + threadIdx.x;
-      uint32_t ci = 0;
-      int64_t w = 0;
-      if (i < size) {
-        ci = in_lds ? sci[i] : a.seg[base + i];
-        w = a.nw[a.cands[ci].u];
-      }
-      int64_t tot;
-      int64_t ex = block_exclusive_scan(w, sm, tot);
-      const int64_t incl = carry + ex + w;
-      if (i < size && incl <= room) a.adm[ci] = 1;
+    // range of the keys: digits above the highest differing bit are shared
+    uint64_t mnh = ~0ull, mxh = 0, mnl = ~0ull, mxl = 0;
+    for (uint32_t i = threadIdx.x; i < size; i += 256) {
+      uint64_t h, l;
+      cand_key(a.cands[sg[i]], h, l);
+      mnh = h < mnh ? h : mnh;
+      mxh = h > mxh ? h : mxh;
+      mnl = l < mnl ? l : mnl;
+      mxl = l > mxl ? l : mxl;
+    }
+    mnh = block_min(mnh, sred);
+    mxh = block_max(mxh, sred);
+    mnl = block_min(mnl, sred);
+    mxl = block_max(mxl, sred);
+    // digit positions 15..0: 15..8 are the bytes of hi, 7..0 those of lo
+    int top;
+    if (mnh != mxh) top = 8 + (63 - __clzll(mnh ^ mxh)) / 8;
+    else top = mnl != mxl ? (63 - __clzll(mnl ^ mxl)) / 8 : -1;
+    // threshold prefix: digits above `top` are shared by every key; each pass
+    // below fixes one more digit and compares only the digits above it
+    uint64_t ph = mnh, pl = mnl;
+    int64_t rem = room;  // weight still admissible below the threshold
+    for (int pos = top; pos >= 0; --pos) {
+      for (int i = threadIdx.x; i < 256; i += 256) whist[i] = 0;
       __syncthreads();
-      if (threadIdx.x == 0) carry += tot;
+      const int sh = 8 * (pos & 7);
+      for (uint32_t i = threadIdx.x; i < size; i += 256) {
+        const Cand c = a.cands[sg[i]];
+        uint64_t h, l;
+        cand_key(c, h, l);
+        // same digits above pos as the threshold prefix
+        bool match;
+        if (pos >= 8) {
+          const int hs = sh + 8;
+          match = hs >= 64 || (h >> hs) == (ph >> hs);
+        } else {
+          const int hs = sh + 8;
+          match = h == ph && (hs >= 64 || (l >> hs) == (pl >> hs));
+        }
+        if (match) {
+          const uint32_t d = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
+          atomicAdd(&whist[d], (unsigned long long)a.nw[c.u]);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int64_t cum = 0;
+        int dsel = 255;
+        for (int d = 0; d < 256; ++d) {
+          const int64_t w = (int64_t)whist[d];
+          if (cum + w > rem) {
+            dsel = d;
+            break;
+          }
+          cum += w;
+        }
+        s_digit = dsel;
+        s_rem = rem - cum;
+      }
+      __syncthreads();
+      const uint64_t dd = (uint64_t)s_digit;
+      rem = s_rem;
+      if (pos >= 8) ph = (ph & ~(0xFFull << sh)) | (dd << sh);
+      else pl = (pl & ~(0xFFull << sh)) | (dd << sh);
       __syncthreads();
     }
+    // the threshold key (ph, pl) is the first key that no longer fits
+    for (uint32_t i = threadIdx.x; i < size; i += 256) {
+      const uint32_t ci = sg[i];
+      uint64_t h, l;
+      cand_key(a.cands[ci], h, l);
+      if (key_less(h, l, ph, pl)) a.adm[ci] = 1;
+    }
+    __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
   const uint32_t nc = *a.ncands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  const Cand c = a.cands[i];
-  const uint32_t t = c.tgt;
-  if (a.adm[i]) {
-    const uint32_t g = cand_graph(a, c.u);
+  uint64_t mv = 0;
+  int64_t dl = 0;
+  if (i < nc && a.adm[i]) {
+    const Cand c = a.cands[i];
+    const uint32_t t = c.tgt;
     const uint32_t own = a.label[c.u];
     const int64_t cu = a.nw[c.u];
     a.label[c.u] = t;
     const int64_t old_t = (int64_t)atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
     const int64_t old_o =
         (int64_t)atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
-    atomicAdd((unsigned long long*)&a.moves[g], 1ull);
-    if (a.ncl_delta) {
-      // clusters that become empty / non-empty; the sum over all moves is
-      // order independent because W never goes negative
-      int64_t d = (old_t == 0 ? 1 : 0) - (old_o == cu ? 1 : 0);
-      if (d) atomicAdd((unsigned long long*)&a.ncl_delta[g], (unsigned long long)d);
-    }
+    // clusters that become non-empty / empty; the sum over all moves is order
+    // independent because W never goes negative
+    mv = 1;
+    dl = (old_t == 0 ? 1 : 0) - (old_o == cu ? 1 : 0);
     if (a.csize) {
       atomicAdd(&a.csize[t], 1u);
       atomicSub(&a.csize[own], 1u);
+    }
+    if (a.gid) {
+      const uint32_t g = a.gid[c.u];
+      atomicAdd((unsigned long long*)&a.moves[g], 1ull);
+      if (a.ncl_delta && dl) atomicAdd((unsigned long long*)&a.ncl_delta[g], (unsigned long long)dl);
+    }
+  }
+  if (!a.gid) {  // one graph: one atomic per wave
+    mv = wave_reduce_sum(mv);
+    dl = wave_reduce_sum(dl);
+    if (lane_id() == 0) {
+      if (mv) atomicAdd((unsigned long long*)&a.moves[0], (unsigned long long)mv);
+      if (a.ncl_delta && dl) atomicAdd((unsigned long long*)&a.ncl_delta[0], (unsigned long long)dl);
     }
   }
 }
@@ -567,6 +882,15 @@ __global__ __launch_bounds__(256) void k_adm_reset(AdmitArgs a) {
 
 }  // namespace
 
+void launch_rate_hubs(int ew_kind, const RateArgs& a, Pool& pool, hipStream_t s) {
+  if (a.count == 0) return;
+  switch (ew_kind) {
+    case EW_UNIT: launch_hubs_t<EW_UNIT>(a, pool, s); break;
+    case EW_I32: launch_hubs_t<EW_I32>(a, pool, s); break;
+    default: launch_hubs_t<EW_I64>(a, pool, s); break;
+  }
+}
+
 void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s) {
   switch (ew_kind) {
     case EW_UNIT: launch_rate_t<EW_UNIT>(cls, a, s); break;
@@ -583,9 +907,7 @@ void launch_bucket_count(const BucketArgs& a, hipStream_t s) {
 }
 
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s) {
-  unsigned g = grid_for(a.n, 256);
-  if (g > 2048) g = 2048;
-  k_bucket_scatter<<<g, 256, 0, s>>>(a);
+  k_bucket_scatter<<<grid_for(a.n, 256 * BK_ITEMS), 256, 0, s>>>(a);
   LAUNCH_CHECK();
 }
 

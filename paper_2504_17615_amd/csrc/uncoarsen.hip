@@ -14,11 +14,25 @@ __global__ void k_project(const uint32_t* map, const uint32_t* cblock, uint64_t 
   if (x != EMPTY_KEY) block[u] = cblock[x];
 }
 
-__global__ void k_block_weights(const uint32_t* block, const int64_t* nw, uint64_t n,
-                                int64_t* BW) {
-  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  atomicAdd((unsigned long long*)&BW[block[u]], (unsigned long long)nw[u]);
+// Block weights; with at most 4096 blocks the sums are privatised in LDS.
+constexpr uint64_t BW_LDS = 4096;
+
+__global__ __launch_bounds__(256) void k_block_weights(const uint32_t* block, const int64_t* nw,
+                                                       uint64_t n, int64_t* BW, uint64_t K) {
+  __shared__ unsigned long long h[BW_LDS];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if (K <= BW_LDS) {
+    for (uint64_t i = threadIdx.x; i < K; i += 256) h[i] = 0;
+    __syncthreads();
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+      atomicAdd(&h[block[u]], (unsigned long long)nw[u]);
+    __syncthreads();
+    for (uint64_t i = threadIdx.x; i < K; i += 256)
+      if (h[i]) atomicAdd((unsigned long long*)&BW[i], h[i]);
+  } else {
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+      atomicAdd((unsigned long long*)&BW[block[u]], (unsigned long long)nw[u]);
+  }
 }
 
 template <int EWK>
@@ -53,10 +67,12 @@ void project_blocks(const uint32_t* map, const uint32_t* cblock, uint64_t n, uin
   LAUNCH_CHECK();
 }
 
-void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t* BW,
+void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t* BW, uint64_t K,
                    hipStream_t s) {
   if (!n) return;
-  k_block_weights<<<grid_for(n, 256), 256, 0, s>>>(block, nw, n, BW);
+  unsigned g = grid_for(n, 256);
+  if (g > 1024) g = 1024;
+  k_block_weights<<<g, 256, 0, s>>>(block, nw, n, BW, K);
   LAUNCH_CHECK();
 }
 

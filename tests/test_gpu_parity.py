@@ -113,6 +113,19 @@ def test_hub_rows(lib):
     check_partition(lib, g, 2, 0.03, 3)
 
 
+def test_hub_rows_heavy_weights(lib):
+    # total edge weight >= 2^32 switches the hub and big-node rating tables
+    # from packed 64-bit slots to separate key / 64-bit value arrays
+    s = T.star(12000)
+    rng = np.random.default_rng(5)
+    a, b, _ = T.edges_of(s)
+    w = rng.integers(1 << 19, 1 << 20, size=len(a))
+    g = T.from_edges(s.n, np.stack([a, b], 1), w)
+    assert int(g.adjwgt.sum()) >= 1 << 32
+    check_hierarchy(lib, g, 2, 3)
+    check_partition(lib, g, 2, 0.03, 3)
+
+
 def test_tiny_and_degenerate(lib):
     check_partition(lib, T.path(2), 2, 0.03, 1)
     check_partition(lib, T.from_edges(5, [(0, 1)]), 3, 0.03, 1)  # isolated nodes
