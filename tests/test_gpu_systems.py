@@ -1,0 +1,130 @@
+"""GPU: batched runs and the serving loop give exactly the plain results.
+
+Tolerance 0: every graph's blocks, cut, maximum block weight and L_max must be
+identical alone (lmgp_partition), inside batches of different compositions
+(lmgp_partition_batch) and inside the serving mix (lmgp_server_*), and equal
+to the CPU oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_17615_amd import graphgen as gg
+from tests import graphs as T
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_17615_amd as L
+
+    L.library()
+    return L
+
+
+def _mix():
+    rng = np.random.default_rng(42)
+    return [
+        (gg.grid(40, 40), 4, 0.03, 1),
+        (gg.rmat(12), 16, 0.03, 2),
+        (gg.er(1 << 12, 1 << 15, seed=9), 8, 0.05, 3),
+        (gg.rgg(1 << 14), 32, 0.03, 4),
+        (T.random_graph(3000, 20000, rng, wmax=9, vmax=5), 4, 0.03, 5),
+        (T.star(3000), 2, 0.03, 6),
+        (T.path(300), 3, 0.1, 7),
+        (gg.rmat(14), 64, 0.03, 8),
+    ]
+
+
+@pytest.fixture(scope="module")
+def solo(lib):
+    out = []
+    for g, k, eps, seed in _mix():
+        dg = lib.create_graph(g)
+        b, r = dg.partition(k, eps, seed, host_out=True)
+        ob, ores, _ = O.partition(g, k, eps, seed)
+        assert np.array_equal(b, ob) and r["cut"] == ores["cut"]
+        out.append((dg, k, eps, seed, b, r))
+    return out
+
+
+def _same(r1, r2):
+    return all(r1[f] == r2[f] for f in ("cut", "max_block_weight", "lmax", "levels"))
+
+
+@pytest.mark.parametrize("order", ["all", "reversed", "subset", "pairs"])
+def test_batch_equals_solo(lib, solo, order):
+    idx = list(range(len(solo)))
+    groups = {"all": [idx], "reversed": [idx[::-1]], "subset": [[1, 3, 5, 7], [0, 2, 4, 6]],
+              "pairs": [[i, (i + 3) % len(idx)] for i in range(0, len(idx), 2)]}[order]
+    for grp in groups:
+        print("batch", grp, flush=True)
+        dgs = [solo[i][0] for i in grp]
+        outs, res = lib.partition_batch(dgs, [solo[i][1] for i in grp], [solo[i][2] for i in grp],
+                                        [solo[i][3] for i in grp])
+        for j, i in enumerate(grp):
+            got = outs[j].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, solo[i][4]), (order, i)
+            assert _same(res[j], solo[i][5]), (order, i, res[j], solo[i][5])
+
+
+def test_batch_of_one_equals_plain(lib, solo):
+    dg, k, eps, seed, b, r = solo[1]
+    outs, res = lib.partition_batch([dg], [k], [eps], [seed])
+    assert np.array_equal(outs[0].cpu().numpy().view(np.uint32), b)
+
+
+@pytest.mark.parametrize("budget_mib,slots,batch,streams", [(4096, 16, 8, 2), (64, 8, 4, 2),
+                                                            (4096, 4, 1, 1)])
+def test_server_results_equal_solo(lib, solo, budget_mib, slots, batch, streams):
+    srv = lib.Server(hbm_budget_bytes=budget_mib << 20, max_slots=slots, max_batch=batch,
+                     streams=streams)
+    tickets = []
+    for rep in range(2):
+        for i, (dg, k, eps, seed, b, r) in enumerate(solo):
+            tickets.append((i, srv.submit(dg, k, eps, seed)))
+    for i, t in tickets:
+        out, res = srv.wait(t)
+        assert np.array_equal(out, solo[i][4]), i
+        assert _same(res, solo[i][5]), (i, res, solo[i][5])
+        assert res["t_total_ns"] > 0
+    srv.close()
+
+
+def test_server_rejects_request_beyond_budget(lib, solo):
+    srv = lib.Server(hbm_budget_bytes=1 << 20, max_slots=2, max_batch=2, streams=1)
+    dg = solo[7][0]  # rmat14: footprint estimate well above 1 MiB
+    with pytest.raises(lib.LmgpError) as e:
+        srv.submit(dg, 64, 0.03, 1)
+    assert e.value.status == 5  # LMGP_EBUSY
+    srv.close()
+
+
+def test_invalid_graphs_rejected_on_device(lib):
+    bad = [
+        T.G(3, np.array([0, 1, 2, 2], np.uint64), np.array([1, 5], np.uint32)),  # id >= n
+        T.G(3, np.array([0, 1, 2, 2], np.uint64), np.array([0, 0], np.uint32)),  # self loop
+        T.G(3, np.array([0, 2, 1, 2], np.uint64), np.array([1, 0], np.uint32)),  # xadj dips
+    ]
+    for g in bad:
+        with pytest.raises(lib.LmgpError) as e:
+            lib.create_graph(g)
+        assert e.value.status == 1
+    asym = T.G(3, np.array([0, 1, 1, 1], np.uint64), np.array([1], np.uint32))
+    with pytest.raises(lib.LmgpError):
+        lib.create_graph(T.G(3, np.array([0, 1, 1, 2], np.uint64), np.array([1, 1], np.uint32)),
+                         validate=True)
+    del asym
+    w = T.from_edges(4, [(0, 1), (1, 2)], weights=[3, 0])  # zero weight
+    with pytest.raises(lib.LmgpError):
+        lib.create_graph(w)
+    g = gg.grid(8, 8)
+    dg = lib.create_graph(g)
+    for k, eps in ((0, 0.03), (65, 0.03), (4, 0.0), (4, -1.0)):
+        with pytest.raises(lib.LmgpError) as e:
+            dg.partition(k, eps, 1, host_out=True)
+        assert e.value.status == 1
