@@ -17,6 +17,7 @@ struct ContractIn {
   const uint32_t* csize = nullptr;  // cluster member counts indexed by label
   const uint32_t* gid = nullptr;
   const uint8_t* keep = nullptr;    // device, per graph: contract this graph
+  int packed = 0;                   // every edge weight and row sum is below 2^32
   std::vector<uint64_t> bounds;     // node boundaries of the graphs (B + 1 values)
 };
 

@@ -7,7 +7,9 @@
 // each coarse row gathers the mapped neighbours of its members, sorts them by
 // neighbour id and sums runs of equal ids.  Rows of <= 64 fine entries are
 // sorted in registers by one wavefront, rows of <= 2048 in LDS by one block,
-// larger rows by the device-wide radix sort.  Rows are first written to a
+// rows of <= 16384 (when every edge weight fits in 32 bits) as packed
+// (neighbour << 32 | weight) words in LDS by one 1024-thread block, larger
+// rows by the device-wide radix sort.  Rows are first written to a
 // scratch area at offset prefix(sum of member degrees), then compacted.
 #include "contract.h"
 
@@ -17,6 +19,9 @@ namespace {
 
 constexpr int ROW_A = WAVE;   // <= 64 entries: wave
 constexpr int ROW_B = 2048;   // <= 2048 entries: block, LDS
+constexpr int ROW_C = 8192;   // <= 8192 entries: 1024-thread block, packed LDS words
+constexpr int ROW_D = 16384;  // <= 16384 entries: the same with a 128 KiB LDS array
+constexpr int NROWCLS = 5;
 
 __global__ void k_map(const uint32_t* label, const uint32_t* cid, const uint32_t* gid,
                       const uint8_t* keep, uint64_t n, uint32_t* map) {
@@ -59,23 +64,25 @@ __global__ void k_members(const uint64_t* xadj, const uint32_t* map, uint64_t n,
   if (d) atomicAdd(&degsum[x], (unsigned long long)d);
 }
 
-// Row size classes: 0 = wave, 1 = block, 2 = radix sort.
+// Row size classes: 0 = wave, 1 = block, 2 = radix sort, 3 and 4 = big block
+// with 8192 / 16384 LDS words (only when `packed`).
 __global__ __launch_bounds__(256) void k_row_classes(const unsigned long long* degsum, uint64_t nc,
-                                                     uint32_t* counts, uint32_t* lists,
+                                                     int packed, uint32_t* counts, uint32_t* lists,
                                                      uint64_t cap) {
-  __shared__ uint32_t lc[3], base[3];
-  if (threadIdx.x < 3) lc[threadIdx.x] = 0;
+  __shared__ uint32_t lc[NROWCLS], base[NROWCLS];
+  if (threadIdx.x < NROWCLS) lc[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1;
   uint32_t lp = 0;
   if (x < nc) {
     const uint64_t d = degsum[x];
-    c = d <= ROW_A ? 0 : d <= ROW_B ? 1 : 2;
+    c = d <= ROW_A ? 0 : d <= ROW_B ? 1 : (packed && d <= ROW_C) ? 3 : (packed && d <= ROW_D) ? 4 : 2;
     lp = atomicAdd(&lc[c], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 3 && lc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], lc[threadIdx.x]);
+  if (threadIdx.x < NROWCLS && lc[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], lc[threadIdx.x]);
   __syncthreads();
   if (c >= 0) lists[(uint64_t)c * cap + base[c] + lp] = (uint32_t)x;
 }
@@ -257,6 +264,93 @@ __global__ __launch_bounds__(256) void k_rows_block(ContractArgs a, const uint32
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)carry;
 }
 
+// Rows with 2049..CAP fine entries, every weight below 2^32: one 1024-thread
+// block per row; entries are packed as (neighbour << 32 | weight), so one
+// 64-bit LDS word moves per compare-exchange of the bitonic sort.  Self
+// entries pack as (EMPTY_KEY << 32) and padding as all ones: both sort last.
+template <int EWK, int CAP>
+__global__ __launch_bounds__(1024) void k_rows_big(ContractArgs a, const uint32_t* rows,
+                                                   uint32_t nrows) {
+  constexpr int NT = 1024, NW = NT / WAVE;
+  __shared__ unsigned long long sv[CAP];
+  __shared__ uint64_t mex[NT], mbeg[NT];
+  __shared__ uint64_t sm[NW];
+  __shared__ uint64_t s_pos;
+  const uint32_t r = blockIdx.x;
+  if (r >= nrows) return;
+  const uint32_t x = rows[r];
+  const uint64_t m0 = a.mstart[x], m1 = a.mstart[x + 1];
+  const uint64_t deg = a.degsum[x];
+  uint32_t N = 1;
+  while (N < deg) N <<= 1;
+  if (threadIdx.x == 0) s_pos = 0;
+  __syncthreads();
+  for (uint64_t mb = m0; mb < m1; mb += NT) {
+    const uint64_t mi = mb + threadIdx.x;
+    uint64_t beg = 0, d = 0;
+    if (mi < m1) {
+      const uint32_t u = a.members[mi];
+      beg = a.xadj[u];
+      d = a.xadj[u + 1] - beg;
+    }
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t, NW>(d, sm, tot);
+    mex[threadIdx.x] = (mi < m1) ? ex : ~0ull;
+    mbeg[threadIdx.x] = beg;
+    __syncthreads();
+    const uint64_t pos = s_pos;
+    for (uint64_t t = threadIdx.x; t < tot; t += NT) {
+      int lo = 0;
+      for (int step = NT / 2; step > 0; step >>= 1)
+        if (mex[lo + step] <= t) lo += step;
+      uint32_t k;
+      int64_t w;
+      load_entry<EWK>(a, mbeg[lo] + (t - mex[lo]), x, k, w);
+      sv[pos + t] = ((unsigned long long)k << 32) | (uint32_t)w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_pos = pos + tot;
+    __syncthreads();
+  }
+  for (uint32_t i = (uint32_t)deg + threadIdx.x; i < N; i += NT) sv[i] = ~0ull;
+  __syncthreads();
+  // bitonic sort, ascending: each thread owns compare-exchange pairs
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t q = threadIdx.x; q < N / 2; q += NT) {
+        const uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+        const uint32_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i | j);
+        const unsigned long long vi = sv[i], vp = sv[p];
+        if (vp < vi) {
+          sv[i] = vp;
+          sv[p] = vi;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint64_t base = a.tmpoff[x];
+  uint64_t carry = 0;
+  for (uint32_t off = 0; off < N; off += NT) {
+    const uint32_t i = off + threadIdx.x;
+    const uint32_t key = i < N ? (uint32_t)(sv[i] >> 32) : EMPTY_KEY;
+    const bool head = key != EMPTY_KEY && (i == 0 || (uint32_t)(sv[i - 1] >> 32) != key);
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t, NW>((uint64_t)head, sm, tot);
+    if (head) {
+      int64_t sum = 0;
+      for (uint32_t j = i; j < N && (uint32_t)(sv[j] >> 32) == key; ++j) sum += (uint32_t)sv[j];
+      const uint64_t o = base + carry + ex;
+      a.tkey[o] = key;
+      a.tw[o] = sum;
+      a.tsrc[o] = x;
+    }
+    carry += tot;
+  }
+  for (uint64_t i = carry + threadIdx.x; i < deg; i += NT) a.tkey[base + i] = EMPTY_KEY;
+  if (threadIdx.x == 0) a.ndist[x] = (uint32_t)carry;
+}
+
 // Rows with > 2048 entries: gather (rank << 32 | neighbour) keys for the
 // radix sort; self entries get neighbour EMPTY_KEY and are dropped later.
 template <int EWK>
@@ -419,13 +513,14 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   uint64_t mt = 0;
   HIP_CHECK(hipMemcpyAsync(&mt, tmpoff.get() + nc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   // row classes
-  DBuf<uint32_t> rcount(&pool, s, 3), rlists(&pool, s, 3 * (nc ? nc : 1));
+  DBuf<uint32_t> rcount(&pool, s, NROWCLS), rlists(&pool, s, NROWCLS * (nc ? nc : 1));
   rcount.zero();
   if (nc) {
-    k_row_classes<<<grid_for(nc, 256), 256, 0, s>>>(degsum.get(), nc, rcount.get(), rlists.get(), nc);
+    k_row_classes<<<grid_for(nc, 256), 256, 0, s>>>(degsum.get(), nc, in.packed, rcount.get(),
+                                                    rlists.get(), nc);
     LAUNCH_CHECK();
   }
-  uint32_t rc[3] = {0, 0, 0};
+  uint32_t rc[NROWCLS] = {0, 0, 0, 0, 0};
   HIP_CHECK(hipMemcpyAsync(rc, rcount.get(), sizeof(rc), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   DBuf<uint32_t> tkey(&pool, s, mt ? mt : 1), tsrc(&pool, s, mt ? mt : 1), ndist(&pool, s, nc + 1);
@@ -446,6 +541,8 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   const uint32_t* listA = rlists.get();
   const uint32_t* listB = rlists.get() + nc;
   const uint32_t* listC = rlists.get() + 2 * nc;
+  const uint32_t* listD = rlists.get() + 3 * nc;
+  const uint32_t* listE = rlists.get() + 4 * nc;
   auto launch_rows = [&](auto ewk) {
     constexpr int EWK = decltype(ewk)::value;
     if (rc[0]) {
@@ -454,6 +551,14 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
     }
     if (rc[1]) {
       k_rows_block<EWK><<<rc[1], 256, 0, s>>>(a, listB, rc[1]);
+      LAUNCH_CHECK();
+    }
+    if (rc[3]) {
+      k_rows_big<EWK, ROW_C><<<rc[3], 1024, 0, s>>>(a, listD, rc[3]);
+      LAUNCH_CHECK();
+    }
+    if (rc[4]) {
+      k_rows_big<EWK, ROW_D><<<rc[4], 1024, 0, s>>>(a, listE, rc[4]);
       LAUNCH_CHECK();
     }
     if (rc[2]) {

@@ -6,7 +6,9 @@
 // graph is the union of one.  Level decisions need a few scalars per level
 // on the host (cluster counts, coarse sizes, edge counts).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <cstring>
 #include <initializer_list>
 
@@ -421,6 +423,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       ra.gid = L.gid;
       ra.gd = dgd.get();
       ra.mode = MODE_LP;
+      ra.phase = spec.refine ? 1 : 0;
       ra.packed = packed_ ? 1 : 0;
       ra.cands = cands.get();
       ra.ncands = ncands.get();
@@ -546,6 +549,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ra.gid = L.gid;
   ra.gd = dgd.get();
   ra.mode = MODE_FAV;
+  ra.phase = 2;
   ra.packed = packed_ ? 1 : 0;
   ra.fav = fav.get();
   for (int c = 0; c < NCLASS; ++c) {
@@ -704,6 +708,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     ci.gid = L.gid;
     ci.keep = dkeep.get();
     ci.bounds = L.nbase;
+    ci.packed = packed_;
     ContractOut co;
     contract_level(ci, co, pool_, s_);
     label.clear();
@@ -926,26 +931,32 @@ struct IpState {
   const std::vector<int64_t>* nw;
   uint64_t seed, level;
   std::vector<uint32_t>* block;
-  std::vector<uint32_t> inset, visited;
+  // stamps: sibling subproblems own disjoint node sets, so they may run on
+  // different threads; a stamp read for a node of another set only tells
+  // "not mine"
+  std::unique_ptr<std::atomic<uint32_t>[]> inset, visited;
   std::vector<uint8_t> part1;
-  uint32_t stamp = 0;
+  std::atomic<uint32_t> stamp{0};
 };
 
-void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t off) {
+constexpr int IP_PAR_DEPTH = 4;  // up to 16 concurrent subproblems
+
+void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t off, int depth) {
   if (S.empty()) return;
   if (kS == 1) {
     for (uint32_t v : S) (*st.block)[v] = off;
     return;
   }
+  const auto rl = std::memory_order_relaxed;
   const uint32_t k1 = (kS + 1) / 2;
   int64_t cS = 0;
   for (uint32_t v : S) cS += (*st.nw)[v];
   const int64_t T1 = (int64_t)(((u128)cS * k1 + kS - 1) / kS);
-  const uint32_t my = ++st.stamp;
+  const uint32_t my = st.stamp.fetch_add(1) + 1;
   const uint64_t pre = chain(st.seed, TAG_IP, {st.level, (uint64_t)off, (uint64_t)kS});
   std::vector<std::pair<uint64_t, uint32_t>> order(S.size());
   for (size_t i = 0; i < S.size(); ++i) {
-    st.inset[S[i]] = my;
+    st.inset[S[i]].store(my, rl);
     order[i] = {hash_add(pre, S[i]), S[i]};
   }
   std::sort(order.begin(), order.end());
@@ -955,11 +966,11 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   int64_t w1 = 0;
   size_t ptr = 0;
   while (w1 < T1) {
-    while (ptr < order.size() && st.visited[order[ptr].second] == my) ++ptr;
+    while (ptr < order.size() && st.visited[order[ptr].second].load(rl) == my) ++ptr;
     if (ptr == order.size()) break;
     queue.clear();
     size_t head = 0;
-    st.visited[order[ptr].second] = my;
+    st.visited[order[ptr].second].store(my, rl);
     queue.push_back(order[ptr].second);
     while (head < queue.size() && w1 < T1) {
       const uint32_t v = queue[head++];
@@ -968,8 +979,8 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
       w1 += (*st.nw)[v];
       for (uint64_t e = (*st.xadj)[v]; e < (*st.xadj)[v + 1]; ++e) {
         const uint32_t x = (*st.adj)[e];
-        if (st.inset[x] == my && st.visited[x] != my) {
-          st.visited[x] = my;
+        if (st.inset[x].load(rl) == my && st.visited[x].load(rl) != my) {
+          st.visited[x].store(my, rl);
           queue.push_back(x);
         }
       }
@@ -979,8 +990,14 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   for (uint32_t v : S) (st.part1[v] ? S1 : S2).push_back(v);
   S.clear();
   S.shrink_to_fit();
-  grow_bisect(st, S1, k1, off);
-  grow_bisect(st, S2, kS - k1, off + k1);
+  if (depth < IP_PAR_DEPTH && !S1.empty() && !S2.empty()) {
+    std::thread t([&] { grow_bisect(st, S1, k1, off, depth + 1); });
+    grow_bisect(st, S2, kS - k1, off + k1, depth + 1);
+    t.join();
+  } else {
+    grow_bisect(st, S1, k1, off, depth + 1);
+    grow_bisect(st, S2, kS - k1, off + k1, depth + 1);
+  }
 }
 
 }  // namespace
@@ -997,12 +1014,16 @@ void initial_partition_host(uint64_t n, const std::vector<uint64_t>& xadj,
   st.level = level;
   block.assign(n, 0);
   st.block = &block;
-  st.inset.assign(n, 0);
-  st.visited.assign(n, 0);
+  st.inset.reset(new std::atomic<uint32_t>[n]);
+  st.visited.reset(new std::atomic<uint32_t>[n]);
+  for (uint64_t v = 0; v < n; ++v) {
+    st.inset[v].store(0, std::memory_order_relaxed);
+    st.visited[v].store(0, std::memory_order_relaxed);
+  }
   st.part1.assign(n, 0);
   std::vector<uint32_t> S(n);
   for (uint64_t v = 0; v < n; ++v) S[v] = (uint32_t)v;
-  grow_bisect(st, S, k, 0);
+  grow_bisect(st, S, k, 0, 0);
 }
 
 }  // namespace lmgp

@@ -65,6 +65,7 @@ struct RateArgs {
   const uint32_t* list;    // nodes to rate
   uint32_t count;
   uint64_t degsum;         // summed degree of the listed nodes (for measurement)
+  int phase;               // 0 clustering, 1 refinement, 2 favourites (for measurement)
   int mode;
   // MODE_LP outputs
   Cand* cands;

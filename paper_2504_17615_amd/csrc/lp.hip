@@ -11,6 +11,10 @@
 // Per target the proposals are ordered by (gain desc, hi32 H(ADM, level,
 // round, u) asc, u asc) and the longest prefix that fits cap - W_start(K) is
 // admitted; all admitted moves are applied together.
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
 #include "kernels.h"
 #include "profiler.h"
 
@@ -91,7 +95,40 @@ LMGP_D void lds_insert(uint32_t* key, unsigned long long* val, uint32_t K, uint6
   }
 }
 
+// Table of 2^logt slots (logt >= 1): runtime-sized variant.
+LMGP_D void lds_insert_n(uint32_t* key, unsigned long long* val, uint32_t K, uint64_t w,
+                         int logt) {
+  const uint32_t mask = (1u << logt) - 1;
+  uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
+  while (true) {
+    uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
+    if (prev == EMPTY_KEY || prev == K) {
+      atomicAdd(&val[s], (unsigned long long)w);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+// log2 of the table size of a node of degree d: at least twice the degree
+// (load <= 1/2), at least 2^lo slots, at most 2^hi.
+LMGP_D int table_log(uint64_t d, int lo, int hi) {
+  int l = lo;
+  while (l < hi && (1ull << l) < 2 * d) ++l;
+  return l;
+}
+
+template <int G>
+LMGP_D int64_t group_sum(int64_t v) {
+#pragma unroll
+  for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
+  return v;
+}
+
 // Lane groups of G lanes (G <= 64) rate one node each; degree <= 2G, table 4G.
+// Entries whose label is the node's own label are summed in registers and
+// inserted once per group: in refinement and in settled clusters most
+// neighbours share that label, and their LDS atomics would all hit one slot.
 template <int G, int EWK>
 __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
   constexpr int T = 4 * G;
@@ -113,23 +150,28 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
   }
   wave_sync();
   uint64_t beg = 0, end = 0;
+  uint32_t own = EMPTY_KEY;
   if (valid) {
     beg = a.xadj[u];
     end = a.xadj[u + 1];
+    own = a.label[u];
   }
+  int64_t acc = 0;
   for (uint64_t e = beg + gl; e < end; e += G) {
-    uint32_t K = a.label[a.adj[e]];
-    lds_insert<T>(key, val, K, (uint64_t)edge_w<EWK>(a.ew, e));
+    const uint32_t K = a.label[a.adj[e]];
+    const int64_t w = edge_w<EWK>(a.ew, e);
+    if (K == own) acc += w;
+    else lds_insert<T>(key, val, K, (uint64_t)w);
   }
+  acc = group_sum<G>(acc);
+  if (gl == 0 && acc > 0) lds_insert<T>(key, val, own, (uint64_t)acc);
   wave_sync();
   Best best{0, 0, 0};
   int64_t r_own = 0;
   GraphDesc gd{};
-  uint32_t own = 0;
   int64_t cu = 0;
   if (valid) {
     gd = a.gd[graph_of(a.gid, u)];
-    own = a.label[u];
     cu = a.nw[u];
     const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
 #pragma unroll
@@ -140,32 +182,65 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
     }
   }
   reduce_best<G>(best, r_own);
-  if (valid && gl == 0) emit(a, u, gd, best, r_own, cu);
+  if (a.mode == MODE_FAV) {
+    if (valid && gl == 0) emit(a, u, gd, best, r_own, cu);
+    return;
+  }
+  // candidates of the whole wave take consecutive slots (one atomic per wave)
+  const bool cand = valid && gl == 0 && best.r > r_own;
+  const uint64_t mask = __ballot(cand);
+  if (!mask) return;
+  const int leader = __ffsll((long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(a.ncands, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (cand) {
+    Cand c;
+    c.u = u;
+    c.tgt = best.K;
+    c.hadm = (uint32_t)(hash_add(gd.pre_adm, (uint64_t)u - gd.node_base) >> 32);
+    c.pad = 0;
+    c.gain = best.r - r_own;
+    a.cands[base + (uint32_t)__popcll(mask & lanemask_lt())] = c;
+    atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
+    atomicAdd(&a.ntgt[best.K], 1u);
+  }
 }
 
-// One 256-thread block per node; degree <= 2048, LDS table of 4096 slots.
+// One 256-thread block per node; degree <= 2048, LDS table of up to 4096
+// slots, sized to twice the degree.  Own-label entries are summed in registers.
 template <int EWK>
 __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
-  constexpr int T = BLOCK_TABLE;
-  __shared__ uint32_t key[T];
-  __shared__ unsigned long long val[T];
+  __shared__ uint32_t key[BLOCK_TABLE];
+  __shared__ unsigned long long val[BLOCK_TABLE];
   __shared__ Best sb[NWAVE];
   __shared__ int64_t so[NWAVE];
+  __shared__ int64_t sm[NWAVE];
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
   if (a.gid && !a.gd[a.gid[u]].active) return;
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  const int logt = table_log(end - beg, 8, __builtin_ctz(BLOCK_TABLE));
+  const int T = 1 << logt;
   for (int s = threadIdx.x; s < T; s += 256) {
     key[s] = EMPTY_KEY;
     val[s] = 0;
   }
   __syncthreads();
-  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
-  for (uint64_t e = beg + threadIdx.x; e < end; e += 256)
-    lds_insert<T>(key, val, a.label[a.adj[e]], (uint64_t)edge_w<EWK>(a.ew, e));
+  const uint32_t own = a.label[u];
+  int64_t acc = 0;
+  for (uint64_t e = beg + threadIdx.x; e < end; e += 256) {
+    const uint32_t K = a.label[a.adj[e]];
+    const int64_t w = edge_w<EWK>(a.ew, e);
+    if (K == own) acc += w;
+    else lds_insert_n(key, val, K, (uint64_t)w, logt);
+  }
+  int64_t acc_tot;
+  (void)block_exclusive_scan(acc, sm, acc_tot);
+  if (threadIdx.x == 0 && acc_tot > 0) lds_insert_n(key, val, own, (uint64_t)acc_tot, logt);
   __syncthreads();
   const GraphDesc gd = a.gd[graph_of(a.gid, u)];
-  const uint32_t own = a.label[u];
   const int64_t cu = a.nw[u];
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
@@ -213,27 +288,56 @@ LMGP_D void lds_add_packed(unsigned long long* tab, uint32_t K, unsigned long lo
   }
 }
 
+// Runtime-sized variant of lds_add_packed: 2^logt slots.
+LMGP_D void lds_add_packed_n(unsigned long long* tab, uint32_t K, unsigned long long w, int logt) {
+  const uint32_t mask = (1u << logt) - 1;
+  uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
+  while (true) {
+    unsigned long long cur = tab[s];
+    if (cur == EMPTY_SLOT) {
+      cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
+      if (cur == EMPTY_SLOT) return;
+    }
+    if ((uint32_t)(cur >> 32) == K) {
+      atomicAdd(&tab[s], w);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
 // One 1024-thread block per node of degree in (2048, 8192], packed table of
-// 16384 slots in LDS (load <= 1/2).
+// up to 16384 slots in LDS sized to twice the degree (load <= 1/2).
+// Own-label entries are summed in registers.
 template <int EWK>
 __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
-  constexpr int T = BIG_TABLE;
   constexpr int NW = 1024 / WAVE;
-  __shared__ unsigned long long tab[T];
+  __shared__ unsigned long long tab[BIG_TABLE];
   __shared__ Best sb[NW];
   __shared__ int64_t so[NW];
+  __shared__ int64_t sm[NW];
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
   if (a.gid && !a.gd[a.gid[u]].active) return;
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  const int logt = table_log(end - beg, 10, __builtin_ctz(BIG_TABLE));
+  const int T = 1 << logt;
   for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
   __syncthreads();
-  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
-  for (uint64_t e = beg + threadIdx.x; e < end; e += 1024)
-    lds_add_packed<T>(tab, a.label[a.adj[e]], (unsigned long long)edge_w<EWK>(a.ew, e));
+  const uint32_t own = a.label[u];
+  int64_t acc = 0;
+  for (uint64_t e = beg + threadIdx.x; e < end; e += 1024) {
+    const uint32_t K = a.label[a.adj[e]];
+    const int64_t w = edge_w<EWK>(a.ew, e);
+    if (K == own) acc += w;
+    else lds_add_packed_n(tab, K, (unsigned long long)w, logt);
+  }
+  int64_t acc_tot;
+  (void)block_exclusive_scan<int64_t, NW>(acc, sm, acc_tot);
+  if (threadIdx.x == 0 && acc_tot > 0) lds_add_packed_n(tab, own, (unsigned long long)acc_tot, logt);
   __syncthreads();
   const GraphDesc gd = a.gd[graph_of(a.gid, u)];
-  const uint32_t own = a.label[u];
   const int64_t cu = a.nw[u];
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
@@ -438,6 +542,108 @@ __global__ void k_hub_final(HubArgs h) {
   emit(a, u, gd, best, r_own, a.nw[u]);
 }
 
+// Label-range partitioned hub rating (packed ratings only): the labels of hub
+// i are split into P_i hash ranges of about HUB_RANGE entries; block j of hub i
+// scans the whole adjacency and aggregates only labels of range j in a packed
+// LDS table, so no global atomics are needed.  Probing is bounded: a range
+// that does not fit raises `overflow` and the caller recomputes the hubs with
+// the global tables (same ratings, same result).
+constexpr int HUB_RANGE = 6144;
+
+LMGP_D uint32_t label_range(uint32_t K, uint32_t P) {
+  uint32_t h = K * 0x9E3779B1u;
+  h ^= h >> 15;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  return (uint32_t)(((uint64_t)h * P) >> 32);
+}
+
+template <int T>
+LMGP_D bool lds_add_bounded(unsigned long long* tab, uint32_t K, unsigned long long w) {
+  constexpr int LOGT = __builtin_ctz(T);
+  uint32_t s = (K * 0x9E3779B1u) >> (32 - LOGT);
+  for (int probe = 0; probe < T; ++probe) {
+    unsigned long long cur = tab[s];
+    if (cur == EMPTY_SLOT) {
+      cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
+      if (cur == EMPTY_SLOT) return true;
+    }
+    if ((uint32_t)(cur >> 32) == K) {
+      atomicAdd(&tab[s], w);
+      return true;
+    }
+    s = (s + 1) & (T - 1);
+  }
+  return false;
+}
+
+template <int EWK>
+__global__ __launch_bounds__(1024) void k_hub_range(HubArgs h, uint32_t* overflow) {
+  constexpr int T = BIG_TABLE;
+  constexpr int NW = 1024 / WAVE;
+  __shared__ unsigned long long tab[T];
+  __shared__ Best sb[NW];
+  __shared__ int64_t so[NW];
+  __shared__ int sfull;
+  const RateArgs& a = h.a;
+  const uint32_t i = find_hub(h.soff, a.count, blockIdx.x);
+  const uint32_t u = a.list[i];
+  if (!hub_active(a, u)) return;
+  const uint32_t P = (uint32_t)(h.soff[i + 1] - h.soff[i]);
+  const uint32_t j = (uint32_t)(blockIdx.x - h.soff[i]);
+  for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
+  if (threadIdx.x == 0) sfull = 0;
+  __syncthreads();
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  bool ok = true;
+  for (uint64_t e = beg + threadIdx.x; e < end && ok; e += 1024) {
+    const uint32_t K = a.label[a.adj[e]];
+    if (label_range(K, P) != j) continue;
+    ok = lds_add_bounded<T>(tab, K, (unsigned long long)edge_w<EWK>(a.ew, e));
+  }
+  if (!ok) sfull = 1;
+  __syncthreads();
+  if (sfull) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;
+  }
+  const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+  const uint32_t own = a.label[u];
+  const int64_t cu = a.nw[u];
+  const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+  Best best{0, 0, 0};
+  int64_t r_own = 0;
+  for (int s = threadIdx.x; s < T; s += 1024) {
+    const unsigned long long v = tab[s];
+    if (v != EMPTY_SLOT)
+      consider(a, (uint32_t)(v >> 32), (int64_t)(v & 0xFFFFFFFFull), own, cu, gd.cap, pre_u,
+               gd.label_base, best, r_own);
+  }
+  reduce_best<WAVE>(best, r_own);
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    sb[w] = best;
+    so[w] = r_own;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NW; ++q) {
+      if (better(sb[q].r, sb[q].h, sb[q].K, best)) best = sb[q];
+      r_own = so[q] > r_own ? so[q] : r_own;
+    }
+    h.part[blockIdx.x] = Partial{best.r, best.h, best.K, 0, r_own};
+  }
+}
+
+struct HubRanges {
+  const uint64_t* xadj;
+  const uint32_t* list;
+  LMGP_D uint64_t operator()(uint64_t i) const {
+    const uint32_t u = list[i];
+    return ceil_div(xadj[u + 1] - xadj[u], HUB_RANGE);
+  }
+};
+
 struct HubTable {
   const uint64_t* xadj;
   const uint32_t* list;
@@ -469,18 +675,14 @@ struct HubSlotChunks {
   }
 };
 
-const char* rate_name(int cls, int ewk) {
-  static const char* names[3][NCLASS] = {
-      {"lp_rate_g2_unit", "lp_rate_g4_unit", "lp_rate_g8_unit", "lp_rate_g16_unit",
-       "lp_rate_g32_unit", "lp_rate_g64_unit", "lp_rate_block_unit", "lp_rate_big_unit",
-       "lp_rate_global_unit"},
-      {"lp_rate_g2_i32", "lp_rate_g4_i32", "lp_rate_g8_i32", "lp_rate_g16_i32",
-       "lp_rate_g32_i32", "lp_rate_g64_i32", "lp_rate_block_i32", "lp_rate_big_i32",
-       "lp_rate_global_i32"},
-      {"lp_rate_g2_i64", "lp_rate_g4_i64", "lp_rate_g8_i64", "lp_rate_g16_i64",
-       "lp_rate_g32_i64", "lp_rate_g64_i64", "lp_rate_block_i64", "lp_rate_big_i64",
-       "lp_rate_global_i64"}};
-  return names[ewk][cls];
+// Profiler family of a rating launch: phase, degree class, edge-weight type
+// (e.g. "cl_rate_block_i64" for clustering, "rf_" refinement, "fv_" 2-hop
+// favourites).
+std::string rate_name(int phase, int cls, int ewk) {
+  static const char* ph[3] = {"cl_rate_", "rf_rate_", "fv_rate_"};
+  static const char* cn[NCLASS] = {"g2", "g4", "g8", "g16", "g32", "g64", "block", "big", "global"};
+  static const char* wn[3] = {"_unit", "_i32", "_i64"};
+  return std::string(ph[phase]) + cn[cls] + wn[ewk];
 }
 
 // Algorithmic bytes of rating `count` nodes with `degsum` entries: per node the
@@ -494,7 +696,7 @@ uint64_t rate_bytes(int ewk, uint64_t count, uint64_t degsum) {
 template <int EWK>
 void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (a.count == 0) return;
-  ProfScope prof(rate_name(cls, EWK), rate_bytes(EWK, a.count, a.degsum), s);
+  ProfScope prof(rate_name(a.phase, cls, EWK).c_str(), rate_bytes(EWK, a.count, a.degsum), s);
   if (cls < CLASS_BLOCK) {
     const int G = class_group(cls);
     const unsigned grid = grid_for(a.count, 256 / G);
@@ -520,6 +722,41 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
 template <int EWK>
 void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   const uint32_t c = ra.count;
+  ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK).c_str(),
+                 rate_bytes(EWK, ra.count, ra.degsum), s);
+  // LMGP_HUB_TABLES=global forces the global-table path (used by the tests to
+  // cover the fallback taken when a label range overflows its LDS table)
+  const char* force = std::getenv("LMGP_HUB_TABLES");
+  // refinement labels are blocks: few distinct labels per hub, so the chunked
+  // global tables see few atomics and re-reading the adjacency per range would
+  // cost more
+  const bool ranges =
+      ra.packed && ra.phase != 1 && !(force && std::strcmp(force, "global") == 0);
+  if (ranges) {
+    // label-range partitioning in LDS; global tables only if a range overflows
+    DBuf<uint64_t> roff(&pool, s, c + 1);
+    exclusive_scan(HubRanges{ra.xadj, ra.list}, c, roff.get(), true, pool, s);
+    uint64_t nr = 0;
+    HIP_CHECK(hipMemcpyAsync(&nr, roff.get() + c, 8, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    DBuf<Partial> part(&pool, s, nr);
+    DBuf<uint32_t> ovf(&pool, s, 1);
+    ovf.zero();
+    HubArgs h{};
+    h.a = ra;
+    h.soff = roff.get();
+    h.part = part.get();
+    k_hub_range<EWK><<<(unsigned)nr, 1024, 0, s>>>(h, ovf.get());
+    LAUNCH_CHECK();
+    uint32_t overflow = 0;
+    HIP_CHECK(hipMemcpyAsync(&overflow, ovf.get(), 4, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (!overflow) {
+      k_hub_final<<<grid_for(c, 64), 64, 0, s>>>(h);
+      LAUNCH_CHECK();
+      return;
+    }
+  }
   DBuf<uint64_t> toff(&pool, s, c + 1), coff(&pool, s, c + 1), soff(&pool, s, c + 1);
   exclusive_scan(HubTable{ra.xadj, ra.list}, c, toff.get(), true, pool, s);
   exclusive_scan(HubChunks{ra.xadj, ra.list}, c, coff.get(), true, pool, s);
@@ -549,7 +786,6 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   h.soff = soff.get();
   h.slots = tot[0];
   h.part = part.get();
-  ProfScope prof(rate_name(CLASS_GLOBAL, EWK), rate_bytes(EWK, ra.count, ra.degsum), s);
   unsigned gc = grid_for(tot[0], 256);
   k_hub_clear<<<gc > 4096 ? 4096 : gc, 256, 0, s>>>(h);
   LAUNCH_CHECK();

@@ -43,9 +43,10 @@ LMGP_D T wave_reduce_max(T v) {
   return v;
 }
 
-// Exclusive scan across a 256-thread block; `total` receives the block sum.
-// smem must hold NWAVE elements.  Contains __syncthreads.
-template <class T>
+// Exclusive scan across a block of NW waves (default: a 256-thread block);
+// `total` receives the block sum.  smem must hold NW elements.  Contains
+// __syncthreads.
+template <class T, int NW = NWAVE>
 LMGP_D T block_exclusive_scan(T v, T* smem, T& total) {
   const int w = threadIdx.x / WAVE, l = lane_id();
   T inc = wave_inclusive_scan(v);
@@ -53,7 +54,7 @@ LMGP_D T block_exclusive_scan(T v, T* smem, T& total) {
   __syncthreads();
   T before = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < NWAVE; ++i) {
+  for (int i = 0; i < NW; ++i) {
     T s = smem[i];
     if (i < w) before += s;
     tot += s;

@@ -105,12 +105,32 @@ def test_sparsification_off(lib):
     check_partition(lib, g, k, eps, seed, sampler=2)
 
 
-def test_hub_rows(lib):
-    # a star with 5000 leaves exercises the global-table rating class and the
-    # radix-sorted contraction rows
-    g = T.star(5000)
+@pytest.mark.parametrize("leaves", [5000, 12000])
+def test_hub_rows(lib, leaves):
+    # stars exercise the big-node rating classes and the 1024-thread LDS
+    # contraction rows (8192- and 16384-word classes)
+    g = T.star(leaves)
     check_hierarchy(lib, g, 2, 3)
     check_partition(lib, g, 2, 0.03, 3)
+
+
+@pytest.mark.parametrize("tables", ["ranges", "global"])
+def test_hub_rating_paths(lib, tables, monkeypatch):
+    # degree 20000 > 8192: label-range LDS rating, or forced global tables
+    if tables == "global":
+        monkeypatch.setenv("LMGP_HUB_TABLES", "global")
+    rng = np.random.default_rng(9)
+    s = T.star(20000)
+    a, b, _ = T.edges_of(s)
+    extra = set()
+    while len(extra) < 30000:  # leaves also linked among themselves
+        x, y = rng.integers(1, s.n, size=2)
+        if x != y:
+            extra.add((min(x, y), max(x, y)))
+    e = np.concatenate([np.stack([a, b], 1), np.array(sorted(extra))])
+    g = T.from_edges(s.n, e)
+    check_hierarchy(lib, g, 4, 3)
+    check_partition(lib, g, 4, 0.03, 3)
 
 
 def test_hub_rows_heavy_weights(lib):
