@@ -15,6 +15,8 @@
 #include <cstring>
 #include <string>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 #include "profiler.h"
 
@@ -56,6 +58,21 @@ LMGP_D void consider(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, int
     return;
   }
   if (a.mode == MODE_LP && a.W[K] + cu > cap) return;
+  if (r < best.r) return;
+  uint64_t h = hash_add(pre_u, (uint64_t)K - label_base);
+  if (better(r, h, K, best)) best = Best{r, h, K};
+}
+
+// As consider, with W[K] already loaded by the caller (wk; unused for the own
+// label and in MODE_FAV), so that a thread can issue its W gathers together.
+LMGP_D void consider_w(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, int64_t cu,
+                       int64_t cap, int64_t wk, uint64_t pre_u, uint64_t label_base, Best& best,
+                       int64_t& r_own) {
+  if (K == own) {
+    r_own = r;
+    return;
+  }
+  if (a.mode == MODE_LP && wk + cu > cap) return;
   if (r < best.r) return;
   uint64_t h = hash_add(pre_u, (uint64_t)K - label_base);
   if (better(r, h, K, best)) best = Best{r, h, K};
@@ -157,11 +174,22 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
     own = a.label[u];
   }
   int64_t acc = 0;
-  for (uint64_t e = beg + gl; e < end; e += G) {
-    const uint32_t K = a.label[a.adj[e]];
-    const int64_t w = edge_w<EWK>(a.ew, e);
-    if (K == own) acc += w;
-    else lds_insert<T>(key, val, K, (uint64_t)w);
+  {
+    // degree <= 2G: at most two entries per lane, loads issued together
+    const uint64_t e0 = beg + gl, e1 = e0 + G;
+    const uint32_t v0 = e0 < end ? a.adj[e0] : 0u, v1 = e1 < end ? a.adj[e1] : 0u;
+    const int64_t w0 = e0 < end ? edge_w<EWK>(a.ew, e0) : 0;
+    const int64_t w1 = e1 < end ? edge_w<EWK>(a.ew, e1) : 0;
+    const uint32_t K0 = e0 < end ? a.label[v0] : EMPTY_KEY;
+    const uint32_t K1 = e1 < end ? a.label[v1] : EMPTY_KEY;
+    if (K0 != EMPTY_KEY) {
+      if (K0 == own) acc += w0;
+      else lds_insert<T>(key, val, K0, (uint64_t)w0);
+    }
+    if (K1 != EMPTY_KEY) {
+      if (K1 == own) acc += w1;
+      else lds_insert<T>(key, val, K1, (uint64_t)w1);
+    }
   }
   acc = group_sum<G>(acc);
   if (gl == 0 && acc > 0) lds_insert<T>(key, val, own, (uint64_t)acc);
@@ -174,12 +202,19 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
     gd = a.gd[graph_of(a.gid, u)];
     cu = a.nw[u];
     const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+    constexpr int SPL = T / G;  // slots per lane
+    uint32_t Ks[SPL];
+    int64_t wk[SPL];
 #pragma unroll
-    for (int s = gl; s < T; s += G) {
-      uint32_t K = key[s];
-      if (K != EMPTY_KEY)
-        consider(a, K, (int64_t)val[s], own, cu, gd.cap, pre_u, gd.label_base, best, r_own);
-    }
+    for (int j = 0; j < SPL; ++j) Ks[j] = key[gl + j * G];
+#pragma unroll
+    for (int j = 0; j < SPL; ++j)
+      wk[j] = (Ks[j] != EMPTY_KEY && Ks[j] != own && a.mode == MODE_LP) ? a.W[Ks[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < SPL; ++j)
+      if (Ks[j] != EMPTY_KEY)
+        consider_w(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, wk[j], pre_u,
+                   gd.label_base, best, r_own);
   }
   reduce_best<G>(best, r_own);
   if (a.mode == MODE_FAV) {
@@ -230,11 +265,24 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
   __syncthreads();
   const uint32_t own = a.label[u];
   int64_t acc = 0;
-  for (uint64_t e = beg + threadIdx.x; e < end; e += 256) {
-    const uint32_t K = a.label[a.adj[e]];
-    const int64_t w = edge_w<EWK>(a.ew, e);
-    if (K == own) acc += w;
-    else lds_insert_n(key, val, K, (uint64_t)w, logt);
+  constexpr int U = 4;  // entries per thread whose loads are issued together
+  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * 256) {
+    uint32_t v[U], K[U];
+    int64_t w[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint64_t e = e0 + (uint64_t)j * 256;
+      v[j] = e < end ? a.adj[e] : 0u;
+      w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * 256 < end ? a.label[v[j]] : EMPTY_KEY;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (K[j] == EMPTY_KEY) continue;
+      if (K[j] == own) acc += w[j];
+      else lds_insert_n(key, val, K[j], (uint64_t)w[j], logt);
+    }
   }
   int64_t acc_tot;
   (void)block_exclusive_scan(acc, sm, acc_tot);
@@ -245,10 +293,20 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
   int64_t r_own = 0;
-  for (int s = threadIdx.x; s < T; s += 256) {
-    uint32_t K = key[s];
-    if (K != EMPTY_KEY)
-      consider(a, K, (int64_t)val[s], own, cu, gd.cap, pre_u, gd.label_base, best, r_own);
+  constexpr int SB = 4;  // slots per thread whose W gathers are issued together
+  for (int s0 = threadIdx.x; s0 < T; s0 += SB * 256) {
+    uint32_t Ks[SB];
+    int64_t wk[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) Ks[j] = s0 + j * 256 < T ? key[s0 + j * 256] : EMPTY_KEY;
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+      wk[j] = (Ks[j] != EMPTY_KEY && Ks[j] != own && a.mode == MODE_LP) ? a.W[Ks[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+      if (Ks[j] != EMPTY_KEY)
+        consider_w(a, Ks[j], (int64_t)val[s0 + j * 256], own, cu, gd.cap, wk[j], pre_u,
+                   gd.label_base, best, r_own);
   }
   reduce_best<WAVE>(best, r_own);
   const int w = threadIdx.x / WAVE;
@@ -327,11 +385,24 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   __syncthreads();
   const uint32_t own = a.label[u];
   int64_t acc = 0;
-  for (uint64_t e = beg + threadIdx.x; e < end; e += 1024) {
-    const uint32_t K = a.label[a.adj[e]];
-    const int64_t w = edge_w<EWK>(a.ew, e);
-    if (K == own) acc += w;
-    else lds_add_packed_n(tab, K, (unsigned long long)w, logt);
+  constexpr int U = 4;  // entries per thread whose loads are issued together
+  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * 1024) {
+    uint32_t v[U], K[U];
+    int64_t w[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint64_t e = e0 + (uint64_t)j * 1024;
+      v[j] = e < end ? a.adj[e] : 0u;
+      w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * 1024 < end ? a.label[v[j]] : EMPTY_KEY;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (K[j] == EMPTY_KEY) continue;
+      if (K[j] == own) acc += w[j];
+      else lds_add_packed_n(tab, K[j], (unsigned long long)w[j], logt);
+    }
   }
   int64_t acc_tot;
   (void)block_exclusive_scan<int64_t, NW>(acc, sm, acc_tot);
@@ -342,11 +413,22 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
   int64_t r_own = 0;
-  for (int s = threadIdx.x; s < T; s += 1024) {
-    const unsigned long long v = tab[s];
-    if (v != EMPTY_SLOT)
-      consider(a, (uint32_t)(v >> 32), (int64_t)(v & 0xFFFFFFFFull), own, cu, gd.cap, pre_u,
-               gd.label_base, best, r_own);
+  constexpr int SB = 4;  // slots per thread whose W gathers are issued together
+  for (int s0 = threadIdx.x; s0 < T; s0 += SB * 1024) {
+    unsigned long long v[SB];
+    int64_t wk[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) v[j] = s0 + j * 1024 < T ? tab[s0 + j * 1024] : EMPTY_SLOT;
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      const uint32_t K = (uint32_t)(v[j] >> 32);
+      wk[j] = (v[j] != EMPTY_SLOT && K != own && a.mode == MODE_LP) ? a.W[K] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+      if (v[j] != EMPTY_SLOT)
+        consider_w(a, (uint32_t)(v[j] >> 32), (int64_t)(v[j] & 0xFFFFFFFFull), own, cu, gd.cap,
+                   wk[j], pre_u, gd.label_base, best, r_own);
   }
   reduce_best<WAVE>(best, r_own);
   const int w = threadIdx.x / WAVE;
@@ -679,10 +761,17 @@ struct HubSlotChunks {
 // (e.g. "cl_rate_block_i64" for clustering, "rf_" refinement, "fv_" 2-hop
 // favourites).
 std::string rate_name(int phase, int cls, int ewk) {
-  static const char* ph[3] = {"cl_rate_", "rf_rate_", "fv_rate_"};
-  static const char* cn[NCLASS] = {"g2", "g4", "g8", "g16", "g32", "g64", "block", "big", "global"};
-  static const char* wn[3] = {"_unit", "_i32", "_i64"};
-  return std::string(ph[phase]) + cn[cls] + wn[ewk];
+  // "<phase>:<kernel>": the kernel part is the HIP kernel's template name, so
+  // that event timings line up with a kernel trace; the hub class brackets
+  // several kernels and is named rate_hubs
+  static const char* ph[3] = {"cl:", "rf:", "fv:"};
+  const int w = ewk;
+  std::string k;
+  if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
+  else if (cls == CLASS_BLOCK) k = "k_rate_block<" + std::to_string(w) + ">";
+  else if (cls == CLASS_BIG) k = "k_rate_big<" + std::to_string(w) + ">";
+  else k = "rate_hubs<" + std::to_string(w) + ">";
+  return std::string(ph[phase]) + k;
 }
 
 // Algorithmic bytes of rating `count` nodes with `degsum` entries: per node the
@@ -696,23 +785,25 @@ uint64_t rate_bytes(int ewk, uint64_t count, uint64_t degsum) {
 template <int EWK>
 void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (a.count == 0) return;
-  ProfScope prof(rate_name(a.phase, cls, EWK).c_str(), rate_bytes(EWK, a.count, a.degsum), s);
+  // single-kernel classes: the launch timestamps its own start and end
+  ProfLaunch prof(rate_name(a.phase, cls, EWK).c_str(), rate_bytes(EWK, a.count, a.degsum));
+  const hipEvent_t e0 = prof.start(), e1 = prof.stop();
   if (cls < CLASS_BLOCK) {
     const int G = class_group(cls);
-    const unsigned grid = grid_for(a.count, 256 / G);
+    const dim3 grid(grid_for(a.count, 256 / G)), blk(256);
     switch (G) {
-      case 2: k_rate_group<2, EWK><<<grid, 256, 0, s>>>(a); break;
-      case 4: k_rate_group<4, EWK><<<grid, 256, 0, s>>>(a); break;
-      case 8: k_rate_group<8, EWK><<<grid, 256, 0, s>>>(a); break;
-      case 16: k_rate_group<16, EWK><<<grid, 256, 0, s>>>(a); break;
-      case 32: k_rate_group<32, EWK><<<grid, 256, 0, s>>>(a); break;
-      default: k_rate_group<64, EWK><<<grid, 256, 0, s>>>(a); break;
+      case 2: hipExtLaunchKernelGGL(k_rate_group<2, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 4: hipExtLaunchKernelGGL(k_rate_group<4, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 8: hipExtLaunchKernelGGL(k_rate_group<8, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 16: hipExtLaunchKernelGGL(k_rate_group<16, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 32: hipExtLaunchKernelGGL(k_rate_group<32, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
+      default: hipExtLaunchKernelGGL(k_rate_group<64, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
     }
   } else if (cls == CLASS_BLOCK) {
-    k_rate_block<EWK><<<a.count, 256, 0, s>>>(a);
+    hipExtLaunchKernelGGL(k_rate_block<EWK>, dim3(a.count), dim3(256), 0, s, e0, e1, 0, a);
   } else if (cls == CLASS_BIG) {
     if (!a.packed) throw InvalidArg("big-block class needs packed ratings");
-    k_rate_big<EWK><<<a.count, 1024, 0, s>>>(a);
+    hipExtLaunchKernelGGL(k_rate_big<EWK>, dim3(a.count), dim3(1024), 0, s, e0, e1, 0, a);
   } else {
     throw InvalidArg("hub class needs launch_rate_hubs");
   }

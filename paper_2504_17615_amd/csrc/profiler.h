@@ -1,5 +1,7 @@
-// Optional per-kernel timing: launches of the main kernels are bracketed with
-// events on their stream and charged the algorithmic bytes they must move.
+// Optional per-kernel timing: launches of the main kernels are timed with
+// events (recorded by the launch itself where the launch is a single kernel,
+// else bracketing the launches on their stream) and charged the algorithmic
+// bytes they must move.
 #pragma once
 #include <atomic>
 #include <map>
@@ -24,6 +26,9 @@ class Profiler {
   void enable(bool v) { on_.store(v); }
   // Record the start of a launch; returns a slot id (or -1 when disabled).
   int begin(const char* name, uint64_t bytes, hipStream_t s);
+  // For a launch that records its own start and end (hipExtLaunchKernelGGL):
+  // hands out the two events to pass to it.
+  void begin_ext(const char* name, uint64_t bytes, hipEvent_t* a, hipEvent_t* b);
   void end(int slot, hipStream_t s);
   // Resolve recorded events (synchronises them) and accumulate.
   void collect();
@@ -58,6 +63,21 @@ class ProfScope {
  private:
   hipStream_t s_;
   int slot_;
+};
+
+// Events for one hipExtLaunchKernelGGL launch, which timestamps the kernel's
+// own start and end (null when profiling is off: a plain launch).
+class ProfLaunch {
+ public:
+  ProfLaunch(const char* name, uint64_t bytes) {
+    Profiler& p = Profiler::get();
+    if (p.on()) p.begin_ext(name, bytes, &a_, &b_);
+  }
+  hipEvent_t start() const { return a_; }
+  hipEvent_t stop() const { return b_; }
+
+ private:
+  hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
 }  // namespace lmgp

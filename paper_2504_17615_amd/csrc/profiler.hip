@@ -29,6 +29,14 @@ int Profiler::begin(const char* name, uint64_t bytes, hipStream_t s) {
   return (int)pending_.size() - 1;
 }
 
+void Profiler::begin_ext(const char* name, uint64_t bytes, hipEvent_t* a, hipEvent_t* b) {
+  std::lock_guard<std::mutex> g(mu_);
+  Rec r{name, bytes, take_event(), take_event()};
+  pending_.push_back(r);
+  *a = r.a;
+  *b = r.b;
+}
+
 void Profiler::end(int slot, hipStream_t s) {
   std::lock_guard<std::mutex> g(mu_);
   if (slot < 0 || (size_t)slot >= pending_.size()) return;
@@ -40,11 +48,15 @@ void Profiler::collect() {
   for (Rec& r : pending_) {
     HIP_CHECK(hipEventSynchronize(r.b));
     float ms = 0;
-    HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
-    KernelStat& st = stats_[r.name];
-    st.launches++;
-    st.total_ns += (uint64_t)((double)ms * 1e6);
-    st.bytes += r.bytes;
+    // a launch that failed before it ran left its events unrecorded: skip it
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      KernelStat& st = stats_[r.name];
+      st.launches++;
+      st.total_ns += (uint64_t)((double)ms * 1e6);
+      st.bytes += r.bytes;
+    } else {
+      (void)hipGetLastError();
+    }
     free_.push_back(r.a);
     free_.push_back(r.b);
   }
