@@ -46,6 +46,56 @@ __global__ void k_copy_i64(int64_t* d, const int64_t* s, uint64_t n) {
   if (i < n) d[i] = s[i];
 }
 
+// LP control on the device, one thread per graph.  The stop decisions of a
+// sub-round are taken where the counts are, so that the host reads them once
+// per round (with the next round's bucket counts) instead of after every
+// sub-round.
+struct LpCtl {
+  GraphDesc* gd;
+  uint32_t B;
+  unsigned long long* moves;        // moves of the current sub-round (admission output)
+  unsigned long long* delta;        // cluster-count change of the sub-round (two's complement)
+  unsigned long long* round_moves;  // moves of the current round
+  unsigned long long* ncl;          // cluster count (clustering) or NULL
+  uint32_t* rounds_run;             // rounds in which the graph was active
+  uint32_t* flags;                  // active flag at the start of the current round
+  const uint64_t* pre;              // [round][graph][3]: SUB, TIE, ADM hash prefixes
+  uint32_t shrink_num, shrink_den;
+};
+
+// After a sub-round: count its moves; in clustering apply the cluster-count
+// change and stop a graph once shrink_num * |C| <= shrink_den * n.
+__global__ void k_lp_after_sub(LpCtl c) {
+  for (uint32_t b = threadIdx.x; b < c.B; b += blockDim.x) {
+    GraphDesc& g = c.gd[b];
+    if (g.active) {
+      c.round_moves[b] += c.moves[b];
+      if (c.ncl) {
+        c.ncl[b] += c.delta[b];
+        if ((u128)c.shrink_num * c.ncl[b] <= (u128)c.shrink_den * g.nodes) g.active = 0;
+      }
+    }
+    c.moves[b] = 0;
+    c.delta[b] = 0;
+  }
+}
+
+// Start of round r: a graph that made no move in round r - 1 stops; the
+// others take round r's hash prefixes.
+__global__ void k_lp_round(LpCtl c, uint32_t r) {
+  for (uint32_t b = threadIdx.x; b < c.B; b += blockDim.x) {
+    GraphDesc& g = c.gd[b];
+    if (r > 0 && g.active && c.round_moves[b] == 0) g.active = 0;
+    c.round_moves[b] = 0;
+    const uint64_t* p = c.pre + ((uint64_t)r * c.B + b) * 3;
+    g.pre_sub = p[0];
+    g.pre_tie = p[1];
+    g.pre_adm = p[2];
+    if (g.active) c.rounds_run[b] = r + 1;
+    c.flags[b] = g.active;
+  }
+}
+
 struct TableSize {
   const uint64_t* xadj;
   const uint32_t* list;
@@ -358,43 +408,64 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ntgt.zero();
   fill.zero();
   std::vector<uint32_t> cnt(NB), offs(NB);
-  std::vector<unsigned long long> hmoves(B), hdelta(B);
   const uint64_t tsub = spec.refine ? TAG_RSUB : TAG_SUB;
   const uint64_t ttie = spec.refine ? TAG_RTIE : TAG_TIE;
   const uint64_t tadm = spec.refine ? TAG_RADM : TAG_ADM;
-  for (uint32_t r = 0; r < spec.rounds; ++r) {
-    bool any = false;
-    for (uint32_t b = 0; b < B; ++b) any |= active[b] != 0;
-    if (!any) break;
-    std::vector<uint64_t> round_moves(B, 0);
+  // hash prefixes of every round, uploaded once
+  const uint32_t R = spec.rounds;
+  std::vector<uint64_t> pre((size_t)R * B * 3);
+  for (uint32_t r = 0; r < R; ++r)
     for (uint32_t b = 0; b < B; ++b) {
       const Job& jb = jobs[L.graphs[b]];
-      gd[b].pre_sub = chain(jb.seed, tsub, {spec.level, r});
-      gd[b].pre_tie = chain(jb.seed, ttie, {spec.level, r});
-      gd[b].pre_adm = chain(jb.seed, tadm, {spec.level, r});
-      gd[b].active = active[b];
-      if (active[b]) rounds_run[b] = r + 1;
+      uint64_t* q = &pre[((size_t)r * B + b) * 3];
+      q[0] = chain(jb.seed, tsub, {spec.level, r});
+      q[1] = chain(jb.seed, ttie, {spec.level, r});
+      q[2] = chain(jb.seed, tadm, {spec.level, r});
     }
-    h2d(dgd.get(), gd.data(), B, s_);
-    // sub-round buckets
-    BucketArgs ba{};
-    ba.xadj = L.xadj;
-    ba.gid = L.gid;
-    ba.gd = dgd.get();
-    ba.n = n;
-    ba.mode = 0;
-    ba.nbuckets = NB;
-    ba.counts = bcount.get();
-    ba.degs = bdeg.get();
-    ba.offs = boffs.get();
-    ba.fill = bfill.get();
-    ba.list = list.get();
+  DBuf<uint64_t> dpre(&pool_, s_, pre.size() ? pre.size() : 1);
+  DBuf<unsigned long long> dround(&pool_, s_, B), dncl(&pool_, s_, B);
+  DBuf<uint32_t> drounds(&pool_, s_, B), dflags(&pool_, s_, B);
+  h2d(dpre.get(), pre.data(), pre.size(), s_);
+  h2d(dgd.get(), gd.data(), B, s_);
+  if (ncl) h2d(dncl.get(), (const unsigned long long*)ncl->data(), B, s_);
+  dmoves.zero();
+  ddelta.zero();
+  dround.zero();
+  drounds.zero();
+  LpCtl ctl{dgd.get(), B, dmoves.get(), ddelta.get(), dround.get(), ncl ? dncl.get() : nullptr,
+            drounds.get(), dflags.get(), dpre.get(), p_.shrink_num, p_.shrink_den};
+  BucketArgs ba{};
+  ba.xadj = L.xadj;
+  ba.gid = L.gid;
+  ba.gd = dgd.get();
+  ba.n = n;
+  ba.mode = 0;
+  ba.nbuckets = NB;
+  ba.counts = bcount.get();
+  ba.degs = bdeg.get();
+  ba.offs = boffs.get();
+  ba.fill = bfill.get();
+  ba.list = list.get();
+  std::vector<uint32_t> flags(B);
+  // Stop decisions (node-reduction cap after a sub-round, no moves in a
+  // round) are taken on the device; the host reads the active flags together
+  // with the next round's bucket counts, once per round.
+  auto begin_round = [&](uint32_t r) {
+    k_lp_round<<<1, 256, 0, s_>>>(ctl, r);
+    LAUNCH_CHECK();
     bcount.zero();
     bdeg.zero();
     launch_bucket_count(ba, s_);
     d2h(cnt.data(), bcount.get(), NB, s_);
     d2h(degs.data(), bdeg.get(), NB, s_);
+    d2h(flags.data(), dflags.get(), B, s_);
     sync(s_);
+  };
+  for (uint32_t r = 0; r < R; ++r) {
+    begin_round(r);
+    bool any = false;
+    for (uint32_t b = 0; b < B; ++b) any |= flags[b] != 0;
+    if (!any) break;
     uint32_t run = 0;
     for (uint32_t i = 0; i < NB; ++i) {
       offs[i] = run;
@@ -407,12 +478,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       uint32_t total = 0;
       for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
       if (total == 0) continue;
-      bool live = false;
-      for (uint32_t b = 0; b < B; ++b) live |= active[b] != 0;
-      if (!live) break;
       ncands.zero();
-      dmoves.zero();
-      ddelta.zero();
       RateArgs ra{};
       ra.xadj = L.xadj;
       ra.adj = L.adj;
@@ -463,29 +529,17 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
       ovtotal.zero();
       launch_admit(aa, s_);
-      d2h(hmoves.data(), dmoves.get(), B, s_);
-      d2h(hdelta.data(), ddelta.get(), B, s_);
-      sync(s_);
-      bool dirty = false;
-      for (uint32_t b = 0; b < B; ++b) {
-        if (!active[b]) continue;
-        round_moves[b] += hmoves[b];
-        if (ncl) {
-          (*ncl)[b] += (uint64_t)(int64_t)hdelta[b];
-          const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
-          if ((u128)p_.shrink_num * (*ncl)[b] <= (u128)p_.shrink_den * nb) {
-            active[b] = 0;
-            gd[b].active = 0;
-            dirty = true;
-          }
-        }
-      }
-      if (dirty) h2d(dgd.get(), gd.data(), B, s_);
+      k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+      LAUNCH_CHECK();
     }
-    for (uint32_t b = 0; b < B; ++b)
-      if (active[b] && round_moves[b] == 0) active[b] = 0;
   }
+  std::vector<unsigned long long> hncl(B);
+  d2h(rounds_run.data(), drounds.get(), B, s_);
+  if (ncl) d2h(hncl.data(), dncl.get(), B, s_);
   sync(s_);
+  if (ncl)
+    for (uint32_t b = 0; b < B; ++b) (*ncl)[b] = hncl[b];
+  for (uint32_t b = 0; b < B; ++b) active[b] = flags[b] != 0;
 }
 
 // ------------------------------------------------------------ clustering --

@@ -158,8 +158,8 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
   const uint64_t idx = (uint64_t)blockIdx.x * GPB + grp;
   bool valid = idx < a.count;
   const uint32_t u = valid ? a.list[idx] : 0u;
-  // graphs of a batch may stop in the middle of a round
-  if (valid && a.gid && !a.gd[a.gid[u]].active) valid = false;
+  // a graph may stop in the middle of a round (its flag is cleared on the device)
+  if (valid && !a.gd[graph_of(a.gid, u)].active) valid = false;
 #pragma unroll
   for (int s = gl; s < T; s += G) {
     key[s] = EMPTY_KEY;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
-  if (a.gid && !a.gd[a.gid[u]].active) return;
+  if (!a.gd[graph_of(a.gid, u)].active) return;
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   const int logt = table_log(end - beg, 8, __builtin_ctz(BLOCK_TABLE));
   const int T = 1 << logt;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
-  if (a.gid && !a.gd[a.gid[u]].active) return;
+  if (!a.gd[graph_of(a.gid, u)].active) return;
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   const int logt = table_log(end - beg, 10, __builtin_ctz(BIG_TABLE));
   const int T = 1 << logt;
@@ -482,7 +482,7 @@ LMGP_D uint32_t find_hub(const uint64_t* off, uint32_t c, uint64_t b) {
 }
 
 LMGP_D bool hub_active(const RateArgs& a, uint32_t u) {
-  return !a.gid || a.gd[a.gid[u]].active;
+  return a.gd[graph_of(a.gid, u)].active;
 }
 
 __global__ void k_hub_clear(HubArgs h) {
