@@ -408,6 +408,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ntgt.zero();
   fill.zero();
   std::vector<uint32_t> cnt(NB), offs(NB);
+  // refinement with few labels: demand and segment slots from block-privatised
+  // histograms in the admission instead of contended atomics
+  const uint32_t few = spec.refine && nlabels <= FEW_LABELS ? (uint32_t)nlabels : 0u;
   const uint64_t tsub = spec.refine ? TAG_RSUB : TAG_SUB;
   const uint64_t ttie = spec.refine ? TAG_RTIE : TAG_TIE;
   const uint64_t tadm = spec.refine ? TAG_RADM : TAG_ADM;
@@ -491,6 +494,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       ra.mode = MODE_LP;
       ra.phase = spec.refine ? 1 : 0;
       ra.packed = packed_ ? 1 : 0;
+      ra.few = few;
       ra.cands = cands.get();
       ra.ncands = ncands.get();
       ra.demand = demand.get();
@@ -527,6 +531,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       aa.csize = csize;
       aa.moves = (uint64_t*)dmoves.get();
       aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
+      aa.few = few;
       ovtotal.zero();
       launch_admit(aa, s_);
       k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);

@@ -80,7 +80,13 @@ struct RateArgs {
   const uint64_t* goff;    // table offset of each listed node (class 7 only)
   unsigned long long* gtab;  // packed (label << 32 | rating) slots
   int packed;              // every rating fits in 32 bits: use gtab
+  uint32_t few;            // labels < few <= FEW_LABELS: demand and ntgt are counted
+                           // by the admission (block-privatised), not here
 };
+
+// Label counts up to this use block-privatised LDS histograms in admission
+// (refinement: labels are the k blocks of each graph).
+constexpr uint32_t FEW_LABELS = 1024;
 
 void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s);
 // Degree class CLASS_GLOBAL: tables in global memory, split over many blocks.
@@ -130,6 +136,7 @@ struct AdmitArgs {
   uint32_t* csize;         // member counts (clustering) or NULL
   uint64_t* moves;         // per graph
   int64_t* ncl_delta;      // per graph (clustering) or NULL
+  uint32_t few;            // labels < few <= FEW_LABELS (see RateArgs), else 0
 };
 void launch_admit(const AdmitArgs& a, hipStream_t s);
 

@@ -93,8 +93,10 @@ LMGP_D void emit(const RateArgs& a, uint32_t u, const GraphDesc& gd, const Best&
     c.pad = 0;
     c.gain = best.r - r_own;
     a.cands[i] = c;
-    atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
-    atomicAdd(&a.ntgt[best.K], 1u);
+    if (!a.few) {
+      atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
+      atomicAdd(&a.ntgt[best.K], 1u);
+    }
   }
 }
 
@@ -237,8 +239,10 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
     c.pad = 0;
     c.gain = best.r - r_own;
     a.cands[base + (uint32_t)__popcll(mask & lanemask_lt())] = c;
-    atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
-    atomicAdd(&a.ntgt[best.K], 1u);
+    if (!a.few) {
+      atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
+      atomicAdd(&a.ntgt[best.K], 1u);
+    }
   }
 }
 
@@ -959,6 +963,120 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
 // ------------------------------------------------------------- admission --
 LMGP_D uint32_t cand_graph(const AdmitArgs& a, uint32_t u) { return graph_of(a.gid, u); }
 
+// Few labels (refinement): per-target demand and candidate count from
+// block-privatised LDS histograms, one global atomic per block and target.
+constexpr int ADM_ITEMS = 8;
+
+__global__ __launch_bounds__(256) void k_adm_count_few(AdmitArgs a) {
+  __shared__ unsigned long long sd[FEW_LABELS];
+  __shared__ uint32_t sn[FEW_LABELS];
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256) {
+    sd[t] = 0;
+    sn[t] = 0;
+  }
+  __syncthreads();
+  const uint32_t nc = *a.ncands;
+  const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
+#pragma unroll
+  for (int j = 0; j < ADM_ITEMS; ++j) {
+    const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
+    if (i < nc) {
+      const Cand c = a.cands[i];
+      atomicAdd(&sd[c.tgt], (unsigned long long)a.nw[c.u]);
+      atomicAdd(&sn[c.tgt], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256)
+    if (sn[t]) {
+      atomicAdd((unsigned long long*)&a.demand[t], sd[t]);
+      atomicAdd(&a.ntgt[t], sn[t]);
+    }
+}
+
+// Few labels: as k_adm_classify, with the segment slots of a block's
+// overflowing candidates reserved by one atomic per block and target.
+__global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
+  __shared__ uint32_t cnt[FEW_LABELS], base[FEW_LABELS];
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256) cnt[t] = 0;
+  __syncthreads();
+  const uint32_t nc = *a.ncands;
+  const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
+  uint32_t tg[ADM_ITEMS], lp[ADM_ITEMS];
+#pragma unroll
+  for (int j = 0; j < ADM_ITEMS; ++j) {
+    const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
+    tg[j] = EMPTY_KEY;
+    if (i < nc) {
+      const Cand c = a.cands[i];
+      const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
+      if (a.W[c.tgt] + a.demand[c.tgt] <= cap) {
+        a.adm[i] = 1;
+      } else {
+        a.adm[i] = 0;
+        tg[j] = c.tgt;
+        lp[j] = atomicAdd(&cnt[c.tgt], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256)
+    if (cnt[t]) {
+      const uint32_t p = atomicAdd(&a.fill[t], cnt[t]);
+      base[t] = p;
+      if (p == 0) {
+        a.segbase[t] = atomicAdd(a.ovtotal, a.ntgt[t]);
+        a.ovtgts[atomicAdd(a.ovcount, 1u)] = t;
+      }
+    }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ADM_ITEMS; ++j)
+    if (tg[j] != EMPTY_KEY) a.cpos[b0 + (uint64_t)j * 256 + threadIdx.x] = base[tg[j]] + lp[j];
+}
+
+// Few labels without cluster bookkeeping (refinement): apply the admitted
+// moves; label weight changes are summed per block in LDS.
+__global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
+  __shared__ long long dw[FEW_LABELS];
+  __shared__ uint64_t smv[NWAVE];
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256) dw[t] = 0;
+  __syncthreads();
+  const uint32_t nc = *a.ncands;
+  const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
+  uint64_t mv = 0;
+#pragma unroll
+  for (int j = 0; j < ADM_ITEMS; ++j) {
+    const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
+    if (i < nc && a.adm[i]) {
+      const Cand c = a.cands[i];
+      const uint32_t own = a.label[c.u];
+      const long long cu = a.nw[c.u];
+      a.label[c.u] = c.tgt;
+      atomicAdd((unsigned long long*)&dw[c.tgt], (unsigned long long)cu);
+      atomicAdd((unsigned long long*)&dw[own], (unsigned long long)(-cu));
+      if (a.gid) atomicAdd((unsigned long long*)&a.moves[a.gid[c.u]], 1ull);
+      else ++mv;
+    }
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256)
+    if (dw[t]) atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)dw[t]);
+  if (!a.gid) {
+    uint64_t tot;
+    (void)block_exclusive_scan(mv, smv, tot);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&a.moves[0], (unsigned long long)tot);
+  }
+}
+
+__global__ void k_adm_reset_few(AdmitArgs a) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < a.few; t += gridDim.x * blockDim.x) {
+    a.demand[t] = 0;
+    a.ntgt[t] = 0;
+    a.fill[t] = 0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
   const uint32_t nc = *a.ncands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1241,7 +1359,17 @@ void launch_bucket_scatter(const BucketArgs& a, hipStream_t s) {
 void launch_admit(const AdmitArgs& a, hipStream_t s) {
   if (a.max_cands == 0) return;
   const unsigned g = grid_for(a.max_cands, 256);
-  k_adm_classify<<<g, 256, 0, s>>>(a);
+  const bool few = a.few > 0 && a.few <= FEW_LABELS;
+  const bool few_apply = few && !a.csize && !a.ncl_delta;
+  if (a.few > FEW_LABELS) throw InvalidArg("too many labels for the few-label admission");
+  if (few) {
+    const unsigned gi = grid_for(a.max_cands, 256 * ADM_ITEMS);
+    k_adm_count_few<<<gi, 256, 0, s>>>(a);
+    LAUNCH_CHECK();
+    k_adm_classify_few<<<gi, 256, 0, s>>>(a);
+  } else {
+    k_adm_classify<<<g, 256, 0, s>>>(a);
+  }
   LAUNCH_CHECK();
   k_adm_scatter<<<g, 256, 0, s>>>(a);
   LAUNCH_CHECK();
@@ -1252,9 +1380,11 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
   unsigned gb = a.max_cands < 1024 ? a.max_cands : 1024;
   k_adm_seg_block<<<gb, 256, 0, s>>>(a);
   LAUNCH_CHECK();
-  k_adm_apply<<<g, 256, 0, s>>>(a);
+  if (few_apply) k_adm_apply_few<<<grid_for(a.max_cands, 256 * ADM_ITEMS), 256, 0, s>>>(a);
+  else k_adm_apply<<<g, 256, 0, s>>>(a);
   LAUNCH_CHECK();
-  k_adm_reset<<<g, 256, 0, s>>>(a);
+  if (few) k_adm_reset_few<<<grid_for(a.few, 256), 256, 0, s>>>(a);
+  else k_adm_reset<<<g, 256, 0, s>>>(a);
   LAUNCH_CHECK();
 }
 

@@ -128,3 +128,18 @@ def test_invalid_graphs_rejected_on_device(lib):
         with pytest.raises(lib.LmgpError) as e:
             dg.partition(k, eps, 1, host_out=True)
         assert e.value.status == 1
+
+
+def test_batch_with_many_labels_equals_solo(lib):
+    # 20 graphs with k = 64: the union has 1280 blocks, more than the
+    # few-label admission takes, so the batch refines through the global
+    # atomic path while every solo run uses the block-privatised one
+    graphs = [gg.rmat(12, seed=s) for s in range(20)]
+    dgs = [lib.create_graph(g) for g in graphs]
+    outs, res = lib.partition_batch(dgs, [64] * 20, [0.03] * 20, list(range(20)))
+    for i, dg in enumerate(dgs):
+        b, r = dg.partition(64, 0.03, i, host_out=True)
+        assert np.array_equal(outs[i].cpu().numpy().view(np.uint32), b), i
+        assert _same(res[i], r), (i, res[i], r)
+    ob, ores, _ = O.partition(graphs[3], 64, 0.03, 3)
+    assert np.array_equal(outs[3].cpu().numpy().view(np.uint32), ob)
