@@ -396,7 +396,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<GraphDesc> dgd(&pool_, s_, B);
   DBuf<unsigned long long> dmoves(&pool_, s_, B), ddelta(&pool_, s_, B);
   DBuf<Cand> cands(&pool_, s_, n);
-  DBuf<uint32_t> ncands(&pool_, s_, 1), list(&pool_, s_, n);
+  DBuf<uint32_t> list(&pool_, s_, n);
   DBuf<int64_t> demand(&pool_, s_, nlabels);
   DBuf<uint32_t> ntgt(&pool_, s_, nlabels), fill(&pool_, s_, nlabels), segbase(&pool_, s_, nlabels);
   DBuf<uint32_t> ovtotal(&pool_, s_, 2), ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
@@ -481,7 +481,6 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       uint32_t total = 0;
       for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
       if (total == 0) continue;
-      ncands.zero();
       RateArgs ra{};
       ra.xadj = L.xadj;
       ra.adj = L.adj;
@@ -495,12 +494,11 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       ra.phase = spec.refine ? 1 : 0;
       ra.packed = packed_ ? 1 : 0;
       ra.few = few;
-      ra.cands = cands.get();
-      ra.ncands = ncands.get();
       ra.demand = demand.get();
       ra.ntgt = ntgt.get();
       for (int c = 0; c < NCLASS; ++c) {
         ra.list = list.get() + offs[sr * NCLASS + c];
+        ra.cands = cands.get() + (offs[sr * NCLASS + c] - offs[sr * NCLASS]);
         ra.count = cnt[sr * NCLASS + c];
         ra.degsum = degs[sr * NCLASS + c];
         if (c == CLASS_GLOBAL || (c == CLASS_BIG && !packed_))
@@ -510,7 +508,6 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       }
       AdmitArgs aa{};
       aa.cands = cands.get();
-      aa.ncands = ncands.get();
       aa.max_cands = total;
       aa.W = W;
       aa.Wmut = W;

@@ -68,8 +68,7 @@ struct RateArgs {
   int phase;               // 0 clustering, 1 refinement, 2 favourites (for measurement)
   int mode;
   // MODE_LP outputs
-  Cand* cands;
-  uint32_t* ncands;
+  Cand* cands;             // slot i belongs to list[i]; tgt = EMPTY_KEY: no move
   int64_t* demand;         // per label: summed weight of candidates targeting it
   uint32_t* ntgt;          // per label: number of candidates targeting it
   // MODE_FAV output
@@ -114,9 +113,8 @@ void launch_bucket_scatter(const BucketArgs& a, hipStream_t s);
 
 // Admission of LP candidates and application of moves.
 struct AdmitArgs {
-  Cand* cands;
-  const uint32_t* ncands;
-  uint32_t max_cands;      // launch bound
+  Cand* cands;             // dense slots, tgt = EMPTY_KEY for no candidate
+  uint32_t max_cands;      // number of slots
   const int64_t* W;
   int64_t* Wmut;
   const int64_t* nw;

@@ -78,14 +78,23 @@ LMGP_D void consider_w(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, i
   if (better(r, h, K, best)) best = Best{r, h, K};
 }
 
-LMGP_D void emit(const RateArgs& a, uint32_t u, const GraphDesc& gd, const Best& best,
-                 int64_t r_own, int64_t cu) {
+// Candidate slots are dense: the node at position idx of the rated list owns
+// slot idx and marks it empty (tgt = EMPTY_KEY) when it proposes no move, so
+// that no global counter is needed.
+LMGP_D void no_cand(const RateArgs& a, uint32_t idx) {
+  if (a.mode == MODE_LP) a.cands[idx].tgt = EMPTY_KEY;
+}
+
+LMGP_D void emit(const RateArgs& a, uint32_t idx, uint32_t u, const GraphDesc& gd,
+                 const Best& best, int64_t r_own, int64_t cu) {
   if (a.mode == MODE_FAV) {
     a.fav[u] = best.r > 0 ? best.K : EMPTY_KEY;
     return;
   }
-  if (best.r > r_own) {
-    uint32_t i = atomicAdd(a.ncands, 1u);
+  if (!(best.r > r_own)) {
+    a.cands[idx].tgt = EMPTY_KEY;
+  } else {
+    const uint32_t i = idx;
     Cand c;
     c.u = u;
     c.tgt = best.K;
@@ -219,30 +228,9 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
                    gd.label_base, best, r_own);
   }
   reduce_best<G>(best, r_own);
-  if (a.mode == MODE_FAV) {
-    if (valid && gl == 0) emit(a, u, gd, best, r_own, cu);
-    return;
-  }
-  // candidates of the whole wave take consecutive slots (one atomic per wave)
-  const bool cand = valid && gl == 0 && best.r > r_own;
-  const uint64_t mask = __ballot(cand);
-  if (!mask) return;
-  const int leader = __ffsll((long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(a.ncands, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  if (cand) {
-    Cand c;
-    c.u = u;
-    c.tgt = best.K;
-    c.hadm = (uint32_t)(hash_add(gd.pre_adm, (uint64_t)u - gd.node_base) >> 32);
-    c.pad = 0;
-    c.gain = best.r - r_own;
-    a.cands[base + (uint32_t)__popcll(mask & lanemask_lt())] = c;
-    if (!a.few) {
-      atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
-      atomicAdd(&a.ntgt[best.K], 1u);
-    }
+  if (gl == 0 && idx < a.count) {
+    if (valid) emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
+    else no_cand(a, (uint32_t)idx);  // graph stopped
   }
 }
 
@@ -258,7 +246,10 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
-  if (!a.gd[graph_of(a.gid, u)].active) return;
+  if (!a.gd[graph_of(a.gid, u)].active) {
+    if (threadIdx.x == 0) no_cand(a, (uint32_t)idx);
+    return;
+  }
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   const int logt = table_log(end - beg, 8, __builtin_ctz(BLOCK_TABLE));
   const int T = 1 << logt;
@@ -324,7 +315,7 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
       if (better(sb[i].r, sb[i].h, sb[i].K, best)) best = sb[i];
       r_own = so[i] > r_own ? so[i] : r_own;
     }
-    emit(a, u, gd, best, r_own, cu);
+    emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
   }
 }
 
@@ -381,7 +372,10 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
-  if (!a.gd[graph_of(a.gid, u)].active) return;
+  if (!a.gd[graph_of(a.gid, u)].active) {
+    if (threadIdx.x == 0) no_cand(a, (uint32_t)idx);
+    return;
+  }
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   const int logt = table_log(end - beg, 10, __builtin_ctz(BIG_TABLE));
   const int T = 1 << logt;
@@ -446,7 +440,7 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
       if (better(sb[i].r, sb[i].h, sb[i].K, best)) best = sb[i];
       r_own = so[i] > r_own ? so[i] : r_own;
     }
-    emit(a, u, gd, best, r_own, cu);
+    emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
   }
 }
 
@@ -616,7 +610,10 @@ __global__ void k_hub_final(HubArgs h) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.count) return;
   const uint32_t u = a.list[i];
-  if (!hub_active(a, u)) return;
+  if (!hub_active(a, u)) {
+    no_cand(a, i);
+    return;
+  }
   Best best{0, 0, 0};
   int64_t r_own = 0;
   for (uint64_t p = h.soff[i]; p < h.soff[i + 1]; ++p) {
@@ -625,7 +622,7 @@ __global__ void k_hub_final(HubArgs h) {
     r_own = q.r_own > r_own ? q.r_own : r_own;
   }
   const GraphDesc gd = a.gd[graph_of(a.gid, u)];
-  emit(a, u, gd, best, r_own, a.nw[u]);
+  emit(a, i, u, gd, best, r_own, a.nw[u]);
 }
 
 // Label-range partitioned hub rating (packed ratings only): the labels of hub
@@ -975,12 +972,12 @@ __global__ __launch_bounds__(256) void k_adm_count_few(AdmitArgs a) {
     sn[t] = 0;
   }
   __syncthreads();
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
 #pragma unroll
   for (int j = 0; j < ADM_ITEMS; ++j) {
     const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
-    if (i < nc) {
+    if (i < nc && a.cands[i].tgt != EMPTY_KEY) {
       const Cand c = a.cands[i];
       atomicAdd(&sd[c.tgt], (unsigned long long)a.nw[c.u]);
       atomicAdd(&sn[c.tgt], 1u);
@@ -1000,14 +997,16 @@ __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
   __shared__ uint32_t cnt[FEW_LABELS], base[FEW_LABELS];
   for (uint32_t t = threadIdx.x; t < a.few; t += 256) cnt[t] = 0;
   __syncthreads();
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
   uint32_t tg[ADM_ITEMS], lp[ADM_ITEMS];
 #pragma unroll
   for (int j = 0; j < ADM_ITEMS; ++j) {
     const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
     tg[j] = EMPTY_KEY;
-    if (i < nc) {
+    if (i < nc && a.cands[i].tgt == EMPTY_KEY) {
+      a.adm[i] = 0;
+    } else if (i < nc) {
       const Cand c = a.cands[i];
       const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
       if (a.W[c.tgt] + a.demand[c.tgt] <= cap) {
@@ -1042,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
   __shared__ uint64_t smv[NWAVE];
   for (uint32_t t = threadIdx.x; t < a.few; t += 256) dw[t] = 0;
   __syncthreads();
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
   uint64_t mv = 0;
 #pragma unroll
@@ -1078,10 +1077,14 @@ __global__ void k_adm_reset_few(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc) return;
   const Cand c = a.cands[i];
+  if (c.tgt == EMPTY_KEY) {
+    a.adm[i] = 0;
+    return;
+  }
   const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
   const uint32_t t = c.tgt;
   if (a.W[t] + a.demand[t] <= cap) {
@@ -1098,10 +1101,11 @@ __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_scatter(AdmitArgs a) {
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc || a.adm[i]) return;
-  a.seg[a.segbase[a.cands[i].tgt] + a.cpos[i]] = i;
+  const uint32_t t = a.cands[i].tgt;
+  if (t != EMPTY_KEY) a.seg[a.segbase[t] + a.cpos[i]] = i;
 }
 
 // Admission order key: (gain desc, hadm asc, u asc) as two uint64 words.
@@ -1277,7 +1281,7 @@ __global__ __launch_bounds__(256) void k_adm_seg_block(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t mv = 0;
   int64_t dl = 0;
@@ -1316,10 +1320,11 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
 
 // Reset the per-target scratch for the next sub-round (after every reader).
 __global__ __launch_bounds__(256) void k_adm_reset(AdmitArgs a) {
-  const uint32_t nc = *a.ncands;
+  const uint32_t nc = a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc) return;
   const uint32_t t = a.cands[i].tgt;
+  if (t == EMPTY_KEY) return;
   a.demand[t] = 0;
   a.ntgt[t] = 0;
   a.fill[t] = 0;
