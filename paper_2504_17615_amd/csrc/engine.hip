@@ -96,17 +96,6 @@ __global__ void k_lp_round(LpCtl c, uint32_t r) {
   }
 }
 
-struct TableSize {
-  const uint64_t* xadj;
-  const uint32_t* list;
-  LMGP_D uint64_t operator()(uint64_t i) const {
-    const uint32_t u = list[i];
-    const uint64_t d = xadj[u + 1] - xadj[u];
-    uint64_t T = 1;
-    while (T < 2 * d) T <<= 1;
-    return T;
-  }
-};
 
 // 2-hop: light singletons (and their sort keys).
 struct SingletonFlag {
@@ -501,7 +490,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
         ra.cands = cands.get() + (offs[sr * NCLASS + c] - offs[sr * NCLASS]);
         ra.count = cnt[sr * NCLASS + c];
         ra.degsum = degs[sr * NCLASS + c];
-        if (c == CLASS_GLOBAL || (c == CLASS_BIG && !packed_))
+        if (c == CLASS_GLOBAL || (is_big_class(c) && !packed_))
           launch_rate_hubs(L.ew_kind, ra, pool_, s_);
         else
           launch_rate(c, L.ew_kind, ra, s_);
@@ -611,7 +600,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   for (int c = 0; c < NCLASS; ++c) {
     ra.list = list.get() + offs[c];
     ra.count = cnt[c];
-    if (c == CLASS_GLOBAL || (c == CLASS_BIG && !packed_))
+    if (c == CLASS_GLOBAL || (is_big_class(c) && !packed_))
       launch_rate_hubs(L.ew_kind, ra, pool_, s_);
     else
       launch_rate(c, L.ew_kind, ra, s_);

@@ -36,20 +36,29 @@ struct Cand {
 };
 
 // Degree classes of the rating kernel: lane groups of 2..64 lanes take nodes
-// of degree <= 2*G, a whole 256-thread block takes degree <= 2048, a
-// 1024-thread block with a 16384-slot packed LDS table (128 KiB of the 160 KiB
-// LDS) takes degree <= 8192, larger degrees use tables in global memory.
-constexpr int NCLASS = 9;
-constexpr int CLASS_BLOCK = 6;
-constexpr int CLASS_BIG = 7;
-constexpr int CLASS_GLOBAL = 8;
-constexpr int BLOCK_TABLE = 4096;  // LDS table slots of the block class
-constexpr int BIG_TABLE = 16384;   // packed LDS slots of the big-block class
+// of degree <= 2*G (classes 0..5); a 256-thread block takes degree <= 256,
+// 512, 1024 or 2048 with an LDS table of twice that many slots (classes
+// 6..9, so that small tables keep occupancy high); a 1024-thread block with a
+// packed LDS table of 8192 slots (load <= 3/4) takes degree <= 6144 and one
+// of 16384 slots (128 KiB of the 160 KiB LDS) degree <= 8192 (classes 10,
+// 11); larger degrees use tables in global memory (class 12).
+constexpr int NCLASS = 13;
+constexpr int CLASS_BLOCK = 6;   // first block class
+constexpr int CLASS_BIG = 10;    // first big-block class
+constexpr int CLASS_GLOBAL = 12;
+constexpr int BLOCK_TABLE = 4096;  // largest LDS table of the block classes
+constexpr int BIG_TABLE = 16384;   // largest packed LDS table of the big-block classes
 LMGP_HD int degree_class(uint64_t d) {
   return d <= 4 ? 0 : d <= 8 ? 1 : d <= 16 ? 2 : d <= 32 ? 3 : d <= 64 ? 4 : d <= 128 ? 5
-       : d <= 2048 ? 6 : d <= 8192 ? 7 : 8;
+       : d <= 256 ? 6 : d <= 512 ? 7 : d <= 1024 ? 8 : d <= 2048 ? 9
+       : d <= 6144 ? 10 : d <= 8192 ? 11 : 12;
 }
 LMGP_HD int class_group(int c) { return c < 6 ? (2 << c) : 256; }
+// log2 of the LDS table of a block / big-block class
+LMGP_HD int class_table_log(int c) { return c < CLASS_BIG ? c + 3 : c == CLASS_BIG ? 13 : 14; }
+LMGP_HD bool is_big_class(int c) { return c == CLASS_BIG || c == CLASS_BIG + 1; }
+// Sub-round bucket histograms hold at most this many (sub-round, class) pairs.
+constexpr uint32_t MAX_BUCKETS = 512;
 
 enum RateMode : int { MODE_LP = 0, MODE_FAV = 1 };
 

@@ -138,14 +138,6 @@ LMGP_D void lds_insert_n(uint32_t* key, unsigned long long* val, uint32_t K, uin
   }
 }
 
-// log2 of the table size of a node of degree d: at least twice the degree
-// (load <= 1/2), at least 2^lo slots, at most 2^hi.
-LMGP_D int table_log(uint64_t d, int lo, int hi) {
-  int l = lo;
-  while (l < hi && (1ull << l) < 2 * d) ++l;
-  return l;
-}
-
 template <int G>
 LMGP_D int64_t group_sum(int64_t v) {
 #pragma unroll
@@ -234,12 +226,14 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
   }
 }
 
-// One 256-thread block per node; degree <= 2048, LDS table of up to 4096
-// slots, sized to twice the degree.  Own-label entries are summed in registers.
-template <int EWK>
+// One 256-thread block per node of degree <= 2^(LOGT-1), LDS table of 2^LOGT
+// slots (load <= 1/2).  Own-label entries are summed in registers.
+template <int EWK, int LOGT>
 __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
-  __shared__ uint32_t key[BLOCK_TABLE];
-  __shared__ unsigned long long val[BLOCK_TABLE];
+  constexpr int T = 1 << LOGT;
+  constexpr int logt = LOGT;
+  __shared__ uint32_t key[T];
+  __shared__ unsigned long long val[T];
   __shared__ Best sb[NWAVE];
   __shared__ int64_t so[NWAVE];
   __shared__ int64_t sm[NWAVE];
@@ -251,8 +245,6 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
     return;
   }
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
-  const int logt = table_log(end - beg, 8, __builtin_ctz(BLOCK_TABLE));
-  const int T = 1 << logt;
   for (int s = threadIdx.x; s < T; s += 256) {
     key[s] = EMPTY_KEY;
     val[s] = 0;
@@ -359,13 +351,16 @@ LMGP_D void lds_add_packed_n(unsigned long long* tab, uint32_t K, unsigned long 
   }
 }
 
-// One 1024-thread block per node of degree in (2048, 8192], packed table of
-// up to 16384 slots in LDS sized to twice the degree (load <= 1/2).
-// Own-label entries are summed in registers.
-template <int EWK>
+// One 1024-thread block per node of degree in (2048, 8192], packed LDS table
+// of 2^LOGT slots: 8192 slots for degree <= 6144 (load <= 3/4, two blocks
+// fit a CU), 16384 for degree <= 8192.  Own-label entries are summed in
+// registers.
+template <int EWK, int LOGT>
 __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   constexpr int NW = 1024 / WAVE;
-  __shared__ unsigned long long tab[BIG_TABLE];
+  constexpr int T = 1 << LOGT;
+  constexpr int logt = LOGT;
+  __shared__ unsigned long long tab[T];
   __shared__ Best sb[NW];
   __shared__ int64_t so[NW];
   __shared__ int64_t sm[NW];
@@ -377,8 +372,6 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
     return;
   }
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
-  const int logt = table_log(end - beg, 10, __builtin_ctz(BIG_TABLE));
-  const int T = 1 << logt;
   for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
   __syncthreads();
   const uint32_t own = a.label[u];
@@ -769,8 +762,10 @@ std::string rate_name(int phase, int cls, int ewk) {
   const int w = ewk;
   std::string k;
   if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
-  else if (cls == CLASS_BLOCK) k = "k_rate_block<" + std::to_string(w) + ">";
-  else if (cls == CLASS_BIG) k = "k_rate_big<" + std::to_string(w) + ">";
+  else if (cls < CLASS_BIG)
+    k = "k_rate_block<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ">";
+  else if (is_big_class(cls))
+    k = "k_rate_big<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ">";
   else k = "rate_hubs<" + std::to_string(w) + ">";
   return std::string(ph[phase]) + k;
 }
@@ -800,15 +795,106 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
       case 32: hipExtLaunchKernelGGL(k_rate_group<32, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
       default: hipExtLaunchKernelGGL(k_rate_group<64, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
     }
-  } else if (cls == CLASS_BLOCK) {
-    hipExtLaunchKernelGGL(k_rate_block<EWK>, dim3(a.count), dim3(256), 0, s, e0, e1, 0, a);
-  } else if (cls == CLASS_BIG) {
+  } else if (cls < CLASS_BIG) {
+    const dim3 grid(a.count), blk(256);
+    switch (cls - CLASS_BLOCK) {
+      case 0: hipExtLaunchKernelGGL(k_rate_block<EWK, 9>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 1: hipExtLaunchKernelGGL(k_rate_block<EWK, 10>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 2: hipExtLaunchKernelGGL(k_rate_block<EWK, 11>, grid, blk, 0, s, e0, e1, 0, a); break;
+      default: hipExtLaunchKernelGGL(k_rate_block<EWK, 12>, grid, blk, 0, s, e0, e1, 0, a); break;
+    }
+  } else if (is_big_class(cls)) {
     if (!a.packed) throw InvalidArg("big-block class needs packed ratings");
-    hipExtLaunchKernelGGL(k_rate_big<EWK>, dim3(a.count), dim3(1024), 0, s, e0, e1, 0, a);
+    const dim3 grid(a.count), blk(1024);
+    if (cls == CLASS_BIG) hipExtLaunchKernelGGL(k_rate_big<EWK, 13>, grid, blk, 0, s, e0, e1, 0, a);
+    else hipExtLaunchKernelGGL(k_rate_big<EWK, 14>, grid, blk, 0, s, e0, e1, 0, a);
   } else {
     throw InvalidArg("hub class needs launch_rate_hubs");
   }
   LAUNCH_CHECK();
+}
+
+// Few labels (refinement with at most FEW_LABELS blocks): a hub's ratings
+// are a dense row of `few` entries in global memory.  Each block rates a chunk
+// of HUB_CHUNK entries into per-wave dense LDS rows (a chunk's labels fall on
+// few addresses, so each wave keeps its own copy), merges the copies and adds
+// its non-zero ratings to the hub's row.
+template <int EWK>
+__global__ __launch_bounds__(256) void k_hub_few_insert(HubArgs h, unsigned long long* rows) {
+  __shared__ unsigned long long tab[NWAVE * FEW_LABELS];
+  const RateArgs& a = h.a;
+  const uint32_t few = a.few;
+  const uint64_t b = blockIdx.x;
+  if (b >= h.coff[a.count]) return;  // the grid is an upper bound
+  for (uint32_t t = threadIdx.x; t < NWAVE * few; t += 256) tab[t] = 0;
+  __syncthreads();
+  const uint32_t i = find_hub(h.coff, a.count, b);
+  const uint32_t u = a.list[i];
+  if (!hub_active(a, u)) return;  // uniform over the block
+  const uint64_t beg = a.xadj[u] + (b - h.coff[i]) * HUB_CHUNK;
+  const uint64_t lim = a.xadj[u + 1];
+  const uint64_t end = beg + HUB_CHUNK < lim ? beg + HUB_CHUNK : lim;
+  unsigned long long* mt = tab + (threadIdx.x / WAVE) * few;
+  constexpr int U = HUB_CHUNK / 256;
+  uint32_t v[U];
+  int64_t w[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    const uint64_t e = beg + (uint64_t)j * 256 + threadIdx.x;
+    v[j] = e < end ? a.adj[e] : 0u;
+    w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    const uint64_t e = beg + (uint64_t)j * 256 + threadIdx.x;
+    if (e < end) atomicAdd(&mt[a.label[v[j]]], (unsigned long long)w[j]);
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < few; t += 256) {
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) sum += tab[q * few + t];
+    if (sum) atomicAdd(&rows[(uint64_t)i * few + t], sum);
+  }
+}
+
+// One block per hub: the best label of its dense row.
+__global__ __launch_bounds__(256) void k_hub_few_final(HubArgs h, const unsigned long long* rows) {
+  __shared__ Best sb[NWAVE];
+  __shared__ int64_t so[NWAVE];
+  const RateArgs& a = h.a;
+  const uint32_t i = blockIdx.x;
+  const uint32_t u = a.list[i];
+  if (!hub_active(a, u)) {
+    if (threadIdx.x == 0) no_cand(a, i);
+    return;
+  }
+  const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+  const uint32_t own = a.label[u];
+  const int64_t cu = a.nw[u];
+  const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+  Best best{0, 0, 0};
+  int64_t r_own = 0;
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256) {
+    const int64_t r = (int64_t)rows[(uint64_t)i * a.few + t];
+    if (r == 0) continue;  // not adjacent (edge weights are positive)
+    const int64_t wk = (t != own && a.mode == MODE_LP) ? a.W[t] : 0;
+    consider_w(a, t, r, own, cu, gd.cap, wk, pre_u, gd.label_base, best, r_own);
+  }
+  reduce_best<WAVE>(best, r_own);
+  const int wv = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    sb[wv] = best;
+    so[wv] = r_own;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NWAVE; ++q) {
+      if (better(sb[q].r, sb[q].h, sb[q].K, best)) best = sb[q];
+      r_own = so[q] > r_own ? so[q] : r_own;
+    }
+    emit(a, i, u, gd, best, r_own, cu);
+  }
 }
 
 template <int EWK>
@@ -819,6 +905,24 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   // LMGP_HUB_TABLES=global forces the global-table path (used by the tests to
   // cover the fallback taken when a label range overflows its LDS table)
   const char* force = std::getenv("LMGP_HUB_TABLES");
+  if (ra.few && ra.few <= FEW_LABELS && ra.mode == MODE_LP &&
+      !(force && std::strcmp(force, "global") == 0)) {
+    // dense rows of `few` ratings; the chunk grid is an upper bound (blocks
+    // past the last chunk exit), so no host round trip is needed
+    DBuf<uint64_t> coff(&pool, s, c + 1);
+    exclusive_scan(HubChunks{ra.xadj, ra.list}, c, coff.get(), true, pool, s);
+    DBuf<unsigned long long> rows(&pool, s, (uint64_t)c * ra.few);
+    rows.zero();
+    HubArgs h{};
+    h.a = ra;
+    h.coff = coff.get();
+    const uint64_t nchunks = ra.degsum / HUB_CHUNK + c;
+    k_hub_few_insert<EWK><<<(unsigned)nchunks, 256, 0, s>>>(h, rows.get());
+    LAUNCH_CHECK();
+    k_hub_few_final<<<c, 256, 0, s>>>(h, rows.get());
+    LAUNCH_CHECK();
+    return;
+  }
   // refinement labels are blocks: few distinct labels per hub, so the chunked
   // global tables see few atomics and re-reading the adjacency per range would
   // cost more
@@ -907,10 +1011,12 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
-  __shared__ uint32_t h[256];
-  __shared__ unsigned long long hd[256];
-  h[threadIdx.x] = 0;
-  hd[threadIdx.x] = 0;
+  __shared__ uint32_t h[MAX_BUCKETS];
+  __shared__ unsigned long long hd[MAX_BUCKETS];
+  for (uint32_t i = threadIdx.x; i < MAX_BUCKETS; i += 256) {
+    h[i] = 0;
+    hd[i] = 0;
+  }
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < a.n; u += stride) {
@@ -934,8 +1040,8 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
 constexpr int BK_ITEMS = 8;
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
-  __shared__ uint32_t cnt[256], base[256];
-  cnt[threadIdx.x] = 0;
+  __shared__ uint32_t cnt[MAX_BUCKETS], base[MAX_BUCKETS];
+  for (uint32_t i = threadIdx.x; i < MAX_BUCKETS; i += 256) cnt[i] = 0;
   __syncthreads();
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * BK_ITEMS;
   int bk[BK_ITEMS];
@@ -947,8 +1053,8 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
     lp[j] = bk[j] >= 0 ? atomicAdd(&cnt[bk[j]], 1u) : 0u;
   }
   __syncthreads();
-  if (threadIdx.x < a.nbuckets && cnt[threadIdx.x])
-    base[threadIdx.x] = atomicAdd(&a.fill[threadIdx.x], cnt[threadIdx.x]);
+  for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256)
+    if (cnt[i]) base[i] = atomicAdd(&a.fill[i], cnt[i]);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < BK_ITEMS; ++j) {
@@ -1350,6 +1456,7 @@ void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s) {
 }
 
 void launch_bucket_count(const BucketArgs& a, hipStream_t s) {
+  if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
   unsigned g = grid_for(a.n, 256);
   if (g > 2048) g = 2048;
   k_bucket_count<<<g, 256, 0, s>>>(a);
@@ -1357,6 +1464,7 @@ void launch_bucket_count(const BucketArgs& a, hipStream_t s) {
 }
 
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s) {
+  if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
   k_bucket_scatter<<<grid_for(a.n, 256 * BK_ITEMS), 256, 0, s>>>(a);
   LAUNCH_CHECK();
 }

@@ -99,16 +99,25 @@ def test_weighted_random_graphs(lib, seed):
     check_partition(lib, g, 4, 0.05, seed)
 
 
+@pytest.mark.parametrize("subrounds", [1, 32])
+def test_subround_counts(lib, subrounds):
+    # 32 sub-rounds x 13 degree classes: the largest bucket histogram
+    g, k, eps, seed = gg.workload("rmat14")
+    check_hierarchy(lib, g, 16, seed, subrounds=subrounds)
+    check_partition(lib, g, k, eps, seed, subrounds=subrounds)
+
+
 def test_sparsification_off(lib):
     g, k, eps, seed = gg.workload("er14")
     check_hierarchy(lib, g, 16, seed, sampler=2)
     check_partition(lib, g, k, eps, seed, sampler=2)
 
 
-@pytest.mark.parametrize("leaves", [5000, 12000])
+@pytest.mark.parametrize("leaves", [5000, 7000, 12000])
 def test_hub_rows(lib, leaves):
-    # stars exercise the big-node rating classes and the 1024-thread LDS
-    # contraction rows (8192- and 16384-word classes)
+    # stars exercise the big-node rating classes (8192- and 16384-slot tables,
+    # global tables) and the 1024-thread LDS contraction rows (8192- and
+    # 16384-word classes)
     g = T.star(leaves)
     check_hierarchy(lib, g, 2, 3)
     check_partition(lib, g, 2, 0.03, 3)
