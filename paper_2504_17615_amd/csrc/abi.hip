@@ -352,6 +352,7 @@ lmgp_status lmgp_hierarchy_copy_level(const lmgp_hierarchy* h, uint32_t level, u
   return guard([&] {
     if (!h) throw InvalidArg("NULL hierarchy");
     if (level >= h->jobs[0].nlevels) throw InvalidArg("level out of range");
+    h->engine->ensure_sorted(level);  // exported rows are sorted by neighbour id
     auto& levels = h->engine->levels();
     const Level& L = *levels[level];
     hipStream_t s = h->stream;

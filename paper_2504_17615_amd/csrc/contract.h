@@ -18,6 +18,10 @@ struct ContractIn {
   const uint32_t* gid = nullptr;
   const uint8_t* keep = nullptr;    // device, per graph: contract this graph
   int packed = 0;                   // every edge weight and row sum is below 2^32
+  // false: coarse rows are aggregated in LDS hash tables and left in table
+  // order (every consumer on the device is order independent); true: rows
+  // sorted by neighbour id
+  bool sorted = true;
   std::vector<uint64_t> bounds;     // node boundaries of the graphs (B + 1 values)
 };
 
@@ -49,6 +53,12 @@ struct ContractArgs {
 };
 
 void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStream_t s);
+
+// Sorts every row of a duplicate-free CSR by neighbour id (the row lengths do
+// not change, so xadj stays valid); the weights come out as int64.
+void sort_rows(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
+               const void* ew, int ew_kind, int packed, DBuf<uint32_t>& out_adj,
+               DBuf<int64_t>& out_ew, DBuf<uint32_t>& out_src, Pool& pool, hipStream_t s);
 
 // ---------------------------------------------------------- sparsification --
 struct SparsGraph {

@@ -4,13 +4,20 @@
 // labels in ascending label order; coarse rows are sorted and duplicate-free.
 //
 // Layout: the members of every coarse node are bucketed (counting sort);
-// each coarse row gathers the mapped neighbours of its members, sorts them by
-// neighbour id and sums runs of equal ids.  Rows of <= 64 fine entries are
+// each coarse row gathers the mapped neighbours of its members and sums the
+// weights of equal neighbour ids.  On the coarsening path the sums are formed
+// in an LDS hash table and written in table order (no consumer depends on the
+// order of a row); where order matters (the coarsest level handed to the
+// initial partitioning, exported levels) rows are sorted: by neighbour id,
+// then equal ids summed.  Rows of <= 64 fine entries are
 // sorted in registers by one wavefront, rows of <= 2048 in LDS by one block,
 // rows of <= 16384 (when every edge weight fits in 32 bits) as packed
 // (neighbour << 32 | weight) words in LDS by one 1024-thread block, larger
 // rows by the device-wide radix sort.  Rows are first written to a
 // scratch area at offset prefix(sum of member degrees), then compacted.
+#include <cstdlib>
+#include <cstring>
+
 #include "contract.h"
 
 namespace lmgp {
@@ -21,7 +28,24 @@ constexpr int ROW_A = WAVE;   // <= 64 entries: wave
 constexpr int ROW_B = 2048;   // <= 2048 entries: block, LDS
 constexpr int ROW_C = 8192;   // <= 8192 entries: 1024-thread block, packed LDS words
 constexpr int ROW_D = 16384;  // <= 16384 entries: the same with a 128 KiB LDS array
-constexpr int NROWCLS = 5;
+constexpr int NROWCLS = 9;
+// Row classes.  Sorted: 0 wave, 1 block bitonic, 3/4 big bitonic (packed),
+// 2 radix.  Hash aggregation: 0 wave (sorted anyway), 5 block <= 512 entries,
+// 6 block <= 2048, 7 big <= 6144 and 8 big <= 12288 (packed), 2 radix.
+LMGP_D int row_class(uint64_t d, int packed, int sorted) {
+  if (d <= ROW_A) return 0;
+  if (sorted) {
+    if (d <= ROW_B) return 1;
+    if (packed && d <= ROW_C) return 3;
+    if (packed && d <= ROW_D) return 4;
+    return 2;
+  }
+  if (d <= 512) return 5;
+  if (d <= ROW_B) return 6;
+  if (packed && d <= 6144) return 7;
+  if (packed && d <= 12288) return 8;
+  return 2;
+}
 
 __global__ void k_map(const uint32_t* label, const uint32_t* cid, const uint32_t* gid,
                       const uint8_t* keep, uint64_t n, uint32_t* map) {
@@ -64,11 +88,10 @@ __global__ void k_members(const uint64_t* xadj, const uint32_t* map, uint64_t n,
   if (d) atomicAdd(&degsum[x], (unsigned long long)d);
 }
 
-// Row size classes: 0 = wave, 1 = block, 2 = radix sort, 3 and 4 = big block
-// with 8192 / 16384 LDS words (only when `packed`).
+// Row size classes (see row_class), counted per block and listed.
 __global__ __launch_bounds__(256) void k_row_classes(const unsigned long long* degsum, uint64_t nc,
-                                                     int packed, uint32_t* counts, uint32_t* lists,
-                                                     uint64_t cap) {
+                                                     int packed, int sorted, uint32_t* counts,
+                                                     uint32_t* lists, uint64_t cap) {
   __shared__ uint32_t lc[NROWCLS], base[NROWCLS];
   if (threadIdx.x < NROWCLS) lc[threadIdx.x] = 0;
   __syncthreads();
@@ -77,7 +100,7 @@ __global__ __launch_bounds__(256) void k_row_classes(const unsigned long long* d
   uint32_t lp = 0;
   if (x < nc) {
     const uint64_t d = degsum[x];
-    c = d <= ROW_A ? 0 : d <= ROW_B ? 1 : (packed && d <= ROW_C) ? 3 : (packed && d <= ROW_D) ? 4 : 2;
+    c = row_class(d, packed, sorted);
     lp = atomicAdd(&lc[c], 1u);
   }
   __syncthreads();
@@ -351,6 +374,137 @@ __global__ __launch_bounds__(1024) void k_rows_big(ContractArgs a, const uint32_
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)carry;
 }
 
+LMGP_D void row_insert(uint32_t* key, unsigned long long* val, uint32_t K, uint64_t w, int logt) {
+  const uint32_t mask = (1u << logt) - 1;
+  uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
+  while (true) {
+    const uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
+    if (prev == EMPTY_KEY || prev == K) {
+      atomicAdd(&val[s], (unsigned long long)w);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+LMGP_D void row_insert_packed(unsigned long long* tab, uint32_t K, unsigned long long w, int logt) {
+  const uint32_t mask = (1u << logt) - 1;
+  uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
+  while (true) {
+    unsigned long long cur = tab[s];
+    if (cur == ~0ull) {
+      cur = atomicCAS(&tab[s], ~0ull, ((unsigned long long)K << 32) | w);
+      if (cur == ~0ull) return;
+    }
+    if ((uint32_t)(cur >> 32) == K) {
+      atomicAdd(&tab[s], w);
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+// Hash-aggregated rows: one block of NT threads per coarse row, LDS table of
+// 2^LOGT slots (load <= 1/2, 3/4 for the packed 1024-thread classes); packed
+// slots hold (neighbour << 32 | summed weight).  The distinct neighbours are
+// written in slot order.
+template <int EWK, int NT, int LOGT, bool PACK>
+__global__ __launch_bounds__(NT) void k_rows_hash(ContractArgs a, const uint32_t* rows,
+                                                  uint32_t nrows) {
+  constexpr int T = 1 << LOGT, NW = NT / WAVE;
+  __shared__ unsigned long long tab[PACK ? T : 1];
+  __shared__ uint32_t skey[PACK ? 1 : T];
+  __shared__ unsigned long long sval[PACK ? 1 : T];
+  __shared__ uint64_t mex[NT], mbeg[NT];
+  __shared__ uint64_t sm[NW];
+  __shared__ uint64_t s_pos;
+  const uint32_t r = blockIdx.x;
+  if (r >= nrows) return;
+  const uint32_t x = rows[r];
+  const uint64_t m0 = a.mstart[x], m1 = a.mstart[x + 1];
+  const uint64_t deg = a.degsum[x];
+  for (int i = threadIdx.x; i < T; i += NT) {
+    if (PACK) {
+      tab[i] = ~0ull;
+    } else {
+      skey[i] = EMPTY_KEY;
+      sval[i] = 0;
+    }
+  }
+  if (threadIdx.x == 0) s_pos = 0;
+  __syncthreads();
+  for (uint64_t mb = m0; mb < m1; mb += NT) {
+    const uint64_t mi = mb + threadIdx.x;
+    uint64_t beg = 0, d = 0;
+    if (mi < m1) {
+      const uint32_t u = a.members[mi];
+      beg = a.xadj[u];
+      d = a.xadj[u + 1] - beg;
+    }
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t, NW>(d, sm, tot);
+    mex[threadIdx.x] = (mi < m1) ? ex : ~0ull;
+    mbeg[threadIdx.x] = beg;
+    __syncthreads();
+    constexpr int U = 4;
+    for (uint64_t t0 = threadIdx.x; t0 < tot; t0 += (uint64_t)U * NT) {
+      uint32_t k[U];
+      int64_t w[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const uint64_t t = t0 + (uint64_t)j * NT;
+        k[j] = EMPTY_KEY;
+        w[j] = 0;
+        if (t < tot) {
+          int lo = 0;
+          for (int step = NT / 2; step > 0; step >>= 1)
+            if (mex[lo + step] <= t) lo += step;
+          load_entry<EWK>(a, mbeg[lo] + (t - mex[lo]), x, k[j], w[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        if (k[j] == EMPTY_KEY) continue;  // self entry or past the chunk
+        if (PACK) row_insert_packed(tab, k[j], (unsigned long long)w[j], LOGT);
+        else row_insert(skey, sval, k[j], (uint64_t)w[j], LOGT);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_pos += tot;
+    __syncthreads();
+  }
+  // occupied slots -> consecutive outputs; each thread owns T / NT slots
+  constexpr int SPT = T / NT;
+  const int s0 = threadIdx.x * SPT;
+  uint64_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < SPT; ++j)
+    mine += PACK ? (tab[s0 + j] != ~0ull) : (skey[s0 + j] != EMPTY_KEY);
+  uint64_t tot;
+  uint64_t o = a.tmpoff[x] + block_exclusive_scan<uint64_t, NW>(mine, sm, tot);
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    uint32_t k;
+    int64_t w;
+    if (PACK) {
+      const unsigned long long v = tab[s0 + j];
+      k = (uint32_t)(v >> 32);
+      w = (int64_t)(v & 0xFFFFFFFFull);
+      if (v == ~0ull) continue;
+    } else {
+      k = skey[s0 + j];
+      w = (int64_t)sval[s0 + j];
+      if (k == EMPTY_KEY) continue;
+    }
+    a.tkey[o] = k;
+    a.tw[o] = w;
+    a.tsrc[o] = x;
+    ++o;
+  }
+  for (uint64_t i = tot + threadIdx.x; i < deg; i += NT) a.tkey[a.tmpoff[x] + i] = EMPTY_KEY;
+  if (threadIdx.x == 0) a.ndist[x] = (uint32_t)tot;
+}
+
 // Rows with > 2048 entries: gather (rank << 32 | neighbour) keys for the
 // radix sort; self entries get neighbour EMPTY_KEY and are dropped later.
 template <int EWK>
@@ -395,6 +549,108 @@ __global__ __launch_bounds__(256) void k_rows_gather(ContractArgs a, const uint3
     if (threadIdx.x == 0) s_pos = pos + tot;
     __syncthreads();
   }
+}
+
+// Rows of more than 12288 entries on the hash path (packed weights): the
+// row's gathered entries are split into R = ceil(deg / 6144) hash ranges of
+// their neighbour ids; block j of the row aggregates range j in a packed LDS
+// table of 16384 slots (expected load < 3/8) and appends its distinct
+// entries to the row.  Probing is bounded: a range that does not fit sets
+// `overflow` and the caller rebuilds these rows with the radix sort.
+constexpr int RANGE_ENTRIES = 6144;
+constexpr int RANGE_LOGT = 14;
+
+LMGP_D uint32_t key_range(uint32_t k, uint32_t R) {
+  uint32_t h = k * 0x9E3779B1u;
+  h ^= h >> 15;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  return (uint32_t)(((uint64_t)h * R) >> 32);
+}
+
+struct RangeCount {
+  const unsigned long long* degsum;
+  const uint32_t* rows;
+  LMGP_D uint64_t operator()(uint64_t i) const { return ceil_div(degsum[rows[i]], RANGE_ENTRIES); }
+};
+
+__global__ __launch_bounds__(1024) void k_rows_range(ContractArgs a, const uint32_t* rows,
+                                                     uint32_t nrows, const uint64_t* goff,
+                                                     const uint64_t* gkey, const int64_t* gw,
+                                                     const uint64_t* roff, uint32_t* rowfill,
+                                                     uint32_t* overflow) {
+  constexpr int T = 1 << RANGE_LOGT, NT = 1024, NW = NT / WAVE;
+  __shared__ unsigned long long tab[T];
+  __shared__ uint64_t sm[NW];
+  __shared__ int s_full;
+  __shared__ uint32_t s_base;
+  const uint64_t b = blockIdx.x;
+  uint32_t lo = 0, hi = nrows;  // roff[lo] <= b < roff[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (roff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t r = lo;
+  const uint32_t x = rows[r];
+  const uint32_t R = (uint32_t)(roff[r + 1] - roff[r]);
+  const uint32_t j = (uint32_t)(b - roff[r]);
+  for (int i = threadIdx.x; i < T; i += NT) tab[i] = ~0ull;
+  if (threadIdx.x == 0) s_full = 0;
+  __syncthreads();
+  for (uint64_t e = goff[r] + threadIdx.x; e < goff[r + 1]; e += NT) {
+    const uint32_t k = (uint32_t)gkey[e];
+    if (k == EMPTY_KEY || key_range(k, R) != j) continue;
+    const unsigned long long w = (unsigned long long)gw[e];
+    uint32_t sl = (k * 0x9E3779B1u) >> (32 - RANGE_LOGT);
+    int probe = 0;
+    for (; probe < T; ++probe) {
+      unsigned long long cur = tab[sl];
+      if (cur == ~0ull) {
+        cur = atomicCAS(&tab[sl], ~0ull, ((unsigned long long)k << 32) | w);
+        if (cur == ~0ull) break;
+      }
+      if ((uint32_t)(cur >> 32) == k) {
+        atomicAdd(&tab[sl], w);
+        break;
+      }
+      sl = (sl + 1) & (T - 1);
+    }
+    if (probe == T) s_full = 1;
+  }
+  __syncthreads();
+  if (s_full) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+    return;  // uniform: s_full is read after the barrier
+  }
+  constexpr int SPT = T / NT;
+  const int s0 = threadIdx.x * SPT;
+  uint64_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) mine += tab[s0 + q] != ~0ull;
+  uint64_t tot;
+  const uint64_t ex = block_exclusive_scan<uint64_t, NW>(mine, sm, tot);
+  if (threadIdx.x == 0) s_base = atomicAdd(&rowfill[r], (uint32_t)tot);
+  __syncthreads();
+  uint64_t o = a.tmpoff[x] + s_base + ex;
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const unsigned long long v = tab[s0 + q];
+    if (v == ~0ull) continue;
+    a.tkey[o] = (uint32_t)(v >> 32);
+    a.tw[o] = (int64_t)(v & 0xFFFFFFFFull);
+    a.tsrc[o] = x;
+    ++o;
+  }
+}
+
+__global__ void k_rows_range_finish(ContractArgs a, const uint32_t* rows, const uint32_t* rowfill) {
+  const uint32_t r = blockIdx.x;
+  const uint32_t x = rows[r];
+  const uint64_t nd = rowfill[r];
+  const uint64_t deg = a.degsum[x];
+  for (uint64_t i = nd + threadIdx.x; i < deg; i += blockDim.x) a.tkey[a.tmpoff[x] + i] = EMPTY_KEY;
+  if (threadIdx.x == 0) a.ndist[x] = (uint32_t)nd;
 }
 
 struct HeadFlag {
@@ -463,6 +719,122 @@ struct U64AtList {
   LMGP_D uint64_t operator()(uint64_t i) const { return a[list[i]]; }
 };
 
+// Rows of the coarse nodes 0..nc-1 described by a (members, degree sums,
+// scratch offsets): one launch per row class.
+void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int ew_kind,
+                Pool& pool, hipStream_t s) {
+  DBuf<uint32_t> rcount(&pool, s, NROWCLS), rlists(&pool, s, NROWCLS * (nc ? nc : 1));
+  rcount.zero();
+  if (nc) {
+    k_row_classes<<<grid_for(nc, 256), 256, 0, s>>>(a.degsum, nc, packed, sorted ? 1 : 0,
+                                                    rcount.get(), rlists.get(), nc);
+    LAUNCH_CHECK();
+  }
+  uint32_t rc[NROWCLS] = {};
+  HIP_CHECK(hipMemcpyAsync(rc, rcount.get(), sizeof(rc), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  const uint32_t* listA = rlists.get();
+  const uint32_t* listB = rlists.get() + nc;
+  const uint32_t* listC = rlists.get() + 2 * nc;
+  const uint32_t* listD = rlists.get() + 3 * nc;
+  const uint32_t* listE = rlists.get() + 4 * nc;
+  auto list_of = [&](int c) { return (const uint32_t*)rlists.get() + (uint64_t)c * nc; };
+  auto launch_rows = [&](auto ewk) {
+    constexpr int EWK = decltype(ewk)::value;
+    if (rc[0]) {
+      k_rows_wave<EWK><<<grid_for(rc[0], 4), 256, 0, s>>>(a, listA, rc[0]);
+      LAUNCH_CHECK();
+    }
+    if (rc[1]) {
+      k_rows_block<EWK><<<rc[1], 256, 0, s>>>(a, listB, rc[1]);
+      LAUNCH_CHECK();
+    }
+    if (rc[3]) {
+      k_rows_big<EWK, ROW_C><<<rc[3], 1024, 0, s>>>(a, listD, rc[3]);
+      LAUNCH_CHECK();
+    }
+    if (rc[4]) {
+      k_rows_big<EWK, ROW_D><<<rc[4], 1024, 0, s>>>(a, listE, rc[4]);
+      LAUNCH_CHECK();
+    }
+    if (rc[5]) {
+      if (packed) k_rows_hash<EWK, 256, 10, true><<<rc[5], 256, 0, s>>>(a, list_of(5), rc[5]);
+      else k_rows_hash<EWK, 256, 10, false><<<rc[5], 256, 0, s>>>(a, list_of(5), rc[5]);
+      LAUNCH_CHECK();
+    }
+    if (rc[6]) {
+      if (packed) k_rows_hash<EWK, 256, 12, true><<<rc[6], 256, 0, s>>>(a, list_of(6), rc[6]);
+      else k_rows_hash<EWK, 256, 12, false><<<rc[6], 256, 0, s>>>(a, list_of(6), rc[6]);
+      LAUNCH_CHECK();
+    }
+    if (rc[7]) {
+      k_rows_hash<EWK, 1024, 13, true><<<rc[7], 1024, 0, s>>>(a, list_of(7), rc[7]);
+      LAUNCH_CHECK();
+    }
+    if (rc[8]) {
+      k_rows_hash<EWK, 1024, 14, true><<<rc[8], 1024, 0, s>>>(a, list_of(8), rc[8]);
+      LAUNCH_CHECK();
+    }
+    if (rc[2]) {
+      DBuf<uint64_t> goff(&pool, s, rc[2] + 1);
+      exclusive_scan(U64AtList{a.degsum, listC}, rc[2], goff.get(), true, pool, s);
+      uint64_t gt = 0;
+      HIP_CHECK(hipMemcpyAsync(&gt, goff.get() + rc[2], sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      DBuf<uint64_t> gk(&pool, s, gt), gk2(&pool, s, gt);
+      DBuf<int64_t> gwv(&pool, s, gt), gw2(&pool, s, gt);
+      k_rows_gather<EWK><<<rc[2], 256, 0, s>>>(a, listC, rc[2], goff.get(), gk.get(), gwv.get());
+      LAUNCH_CHECK();
+      if (!sorted && packed) {
+        DBuf<uint64_t> roff(&pool, s, rc[2] + 1);
+        exclusive_scan(RangeCount{a.degsum, listC}, rc[2], roff.get(), true, pool, s);
+        uint64_t nr = 0;
+        HIP_CHECK(hipMemcpyAsync(&nr, roff.get() + rc[2], 8, hipMemcpyDeviceToHost, s));
+        DBuf<uint32_t> rowfill(&pool, s, rc[2]), ovf(&pool, s, 1);
+        rowfill.zero();
+        ovf.zero();
+        HIP_CHECK(hipStreamSynchronize(s));
+        k_rows_range<<<(unsigned)nr, 1024, 0, s>>>(a, listC, rc[2], goff.get(), gk.get(), gwv.get(),
+                                                   roff.get(), rowfill.get(), ovf.get());
+        LAUNCH_CHECK();
+        uint32_t overflow = 0;
+        HIP_CHECK(hipMemcpyAsync(&overflow, ovf.get(), 4, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        // LMGP_ROW_RANGES=overflow takes the fallback as if a range had not fit
+        // (used by the tests: the radix rows must overwrite the range output)
+        const char* force = std::getenv("LMGP_ROW_RANGES");
+        if (force && std::strcmp(force, "overflow") == 0) overflow = 1;
+        if (!overflow) {
+          k_rows_range_finish<<<rc[2], 256, 0, s>>>(a, listC, rowfill.get());
+          LAUNCH_CHECK();
+          HIP_CHECK(hipStreamSynchronize(s));  // keep scratch alive until done
+          return;
+        }
+        // a range did not fit: sort these rows instead (overwrites them)
+      }
+      int rbits = 1;
+      while ((1ull << rbits) < rc[2]) ++rbits;
+      bool swapped = radix_sort_pairs<int64_t>(gk.get(), gwv.get(), gk2.get(), gw2.get(), gt, 0,
+                                                32 + rbits, pool, s);
+      const uint64_t* sk = swapped ? gk2.get() : gk.get();
+      const int64_t* sw = swapped ? gw2.get() : gwv.get();
+      DBuf<uint32_t> hpos(&pool, s, gt + 1);
+      exclusive_scan(HeadFlag{sk}, gt, hpos.get(), true, pool, s);
+      k_rows_reduce<<<grid_for(gt, 256), 256, 0, s>>>(a, listC, rc[2], goff.get(), sk, sw,
+                                                      hpos.get(), gt);
+      LAUNCH_CHECK();
+      k_rows_finish<<<rc[2], 256, 0, s>>>(a, listC, rc[2], goff.get(), hpos.get());
+      LAUNCH_CHECK();
+      HIP_CHECK(hipStreamSynchronize(s));  // keep scratch alive until done
+    }
+  };
+  switch (ew_kind) {
+    case EW_UNIT: launch_rows(std::integral_constant<int, EW_UNIT>()); break;
+    case EW_I32: launch_rows(std::integral_constant<int, EW_I32>()); break;
+    default: launch_rows(std::integral_constant<int, EW_I64>()); break;
+  }
+}
+
 }  // namespace
 
 void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStream_t s) {
@@ -512,17 +884,6 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   exclusive_scan(ArrayU64{(const uint64_t*)degsum.get()}, nc, tmpoff.get(), true, pool, s);
   uint64_t mt = 0;
   HIP_CHECK(hipMemcpyAsync(&mt, tmpoff.get() + nc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  // row classes
-  DBuf<uint32_t> rcount(&pool, s, NROWCLS), rlists(&pool, s, NROWCLS * (nc ? nc : 1));
-  rcount.zero();
-  if (nc) {
-    k_row_classes<<<grid_for(nc, 256), 256, 0, s>>>(degsum.get(), nc, in.packed, rcount.get(),
-                                                    rlists.get(), nc);
-    LAUNCH_CHECK();
-  }
-  uint32_t rc[NROWCLS] = {0, 0, 0, 0, 0};
-  HIP_CHECK(hipMemcpyAsync(rc, rcount.get(), sizeof(rc), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
   DBuf<uint32_t> tkey(&pool, s, mt ? mt : 1), tsrc(&pool, s, mt ? mt : 1), ndist(&pool, s, nc + 1);
   DBuf<int64_t> tw(&pool, s, mt ? mt : 1);
   ContractArgs a{};
@@ -538,60 +899,7 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   a.tw = tw.get();
   a.tsrc = tsrc.get();
   a.ndist = ndist.get();
-  const uint32_t* listA = rlists.get();
-  const uint32_t* listB = rlists.get() + nc;
-  const uint32_t* listC = rlists.get() + 2 * nc;
-  const uint32_t* listD = rlists.get() + 3 * nc;
-  const uint32_t* listE = rlists.get() + 4 * nc;
-  auto launch_rows = [&](auto ewk) {
-    constexpr int EWK = decltype(ewk)::value;
-    if (rc[0]) {
-      k_rows_wave<EWK><<<grid_for(rc[0], 4), 256, 0, s>>>(a, listA, rc[0]);
-      LAUNCH_CHECK();
-    }
-    if (rc[1]) {
-      k_rows_block<EWK><<<rc[1], 256, 0, s>>>(a, listB, rc[1]);
-      LAUNCH_CHECK();
-    }
-    if (rc[3]) {
-      k_rows_big<EWK, ROW_C><<<rc[3], 1024, 0, s>>>(a, listD, rc[3]);
-      LAUNCH_CHECK();
-    }
-    if (rc[4]) {
-      k_rows_big<EWK, ROW_D><<<rc[4], 1024, 0, s>>>(a, listE, rc[4]);
-      LAUNCH_CHECK();
-    }
-    if (rc[2]) {
-      DBuf<uint64_t> goff(&pool, s, rc[2] + 1);
-      exclusive_scan(U64AtList{degsum.get(), listC}, rc[2], goff.get(), true, pool, s);
-      uint64_t gt = 0;
-      HIP_CHECK(hipMemcpyAsync(&gt, goff.get() + rc[2], sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
-      DBuf<uint64_t> gk(&pool, s, gt), gk2(&pool, s, gt);
-      DBuf<int64_t> gwv(&pool, s, gt), gw2(&pool, s, gt);
-      k_rows_gather<EWK><<<rc[2], 256, 0, s>>>(a, listC, rc[2], goff.get(), gk.get(), gwv.get());
-      LAUNCH_CHECK();
-      int rbits = 1;
-      while ((1ull << rbits) < rc[2]) ++rbits;
-      bool swapped = radix_sort_pairs<int64_t>(gk.get(), gwv.get(), gk2.get(), gw2.get(), gt, 0,
-                                                32 + rbits, pool, s);
-      const uint64_t* sk = swapped ? gk2.get() : gk.get();
-      const int64_t* sw = swapped ? gw2.get() : gwv.get();
-      DBuf<uint32_t> hpos(&pool, s, gt + 1);
-      exclusive_scan(HeadFlag{sk}, gt, hpos.get(), true, pool, s);
-      k_rows_reduce<<<grid_for(gt, 256), 256, 0, s>>>(a, listC, rc[2], goff.get(), sk, sw,
-                                                      hpos.get(), gt);
-      LAUNCH_CHECK();
-      k_rows_finish<<<rc[2], 256, 0, s>>>(a, listC, rc[2], goff.get(), hpos.get());
-      LAUNCH_CHECK();
-      HIP_CHECK(hipStreamSynchronize(s));  // keep scratch alive until done
-    }
-  };
-  switch (in.ew_kind) {
-    case EW_UNIT: launch_rows(std::integral_constant<int, EW_UNIT>()); break;
-    case EW_I32: launch_rows(std::integral_constant<int, EW_I32>()); break;
-    default: launch_rows(std::integral_constant<int, EW_I64>()); break;
-  }
+  build_rows(a, nc, in.packed, in.sorted, in.ew_kind, pool, s);
   // coarse CSR
   out.xadj.reset(&pool, s, nc + 1);
   exclusive_scan(U32At{ndist.get()}, nc, out.xadj.get(), true, pool, s);
@@ -607,6 +915,51 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
                                                    out.src.get(), out.xadj.get());
     LAUNCH_CHECK();
   }
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+namespace {
+__global__ void k_identity_rows(const uint64_t* xadj, uint64_t n, uint32_t* id, uint64_t* mstart,
+                                unsigned long long* deg) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  mstart[i] = i;
+  if (i < n) {
+    id[i] = (uint32_t)i;
+    deg[i] = xadj[i + 1] - xadj[i];
+  }
+}
+}  // namespace
+
+// Row sorting as a contraction with the identity map: every node is its own
+// single member, no entry is a self entry and no two entries merge, so every
+// row keeps its length and lands at its own offset.
+void sort_rows(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
+               const void* ew, int ew_kind, int packed, DBuf<uint32_t>& out_adj,
+               DBuf<int64_t>& out_ew, DBuf<uint32_t>& out_src, Pool& pool, hipStream_t s) {
+  out_adj.reset(&pool, s, nnz ? nnz : 1);
+  out_ew.reset(&pool, s, nnz ? nnz : 1);
+  out_src.reset(&pool, s, nnz ? nnz : 1);
+  if (n == 0) return;
+  DBuf<uint32_t> id(&pool, s, n), ndist(&pool, s, n);
+  DBuf<uint64_t> mstart(&pool, s, n + 1);
+  DBuf<unsigned long long> deg(&pool, s, n);
+  k_identity_rows<<<grid_for(n + 1, 256), 256, 0, s>>>(xadj, n, id.get(), mstart.get(), deg.get());
+  LAUNCH_CHECK();
+  ContractArgs a{};
+  a.xadj = xadj;
+  a.adj = adj;
+  a.ew = ew;
+  a.map = id.get();
+  a.mstart = mstart.get();
+  a.members = id.get();
+  a.degsum = deg.get();
+  a.tmpoff = xadj;
+  a.tkey = out_adj.get();
+  a.tw = out_ew.get();
+  a.tsrc = out_src.get();
+  a.ndist = ndist.get();
+  build_rows(a, n, packed, true, ew_kind, pool, s);
   HIP_CHECK(hipStreamSynchronize(s));
 }
 

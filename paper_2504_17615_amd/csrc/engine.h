@@ -49,6 +49,7 @@ struct Level {
   DBuf<uint32_t> o_src;
   DBuf<uint32_t> o_gid;
   DBuf<uint32_t> map;              // node of the next level (EMPTY_KEY if the graph stops)
+  bool sorted = true;              // rows sorted by neighbour id (else in hash-table order)
   std::vector<uint32_t> graphs;    // batch indices of the graphs present, in union order
   std::vector<uint64_t> nbase;     // node boundaries (graphs.size() + 1)
   std::vector<uint64_t> ebase;     // entry boundaries (graphs.size() + 1)
@@ -76,6 +77,8 @@ class Engine {
   // Initial partitioning, refinement and evaluation; writes blocks.
   void partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device);
   std::vector<std::unique_ptr<Level>>& levels() { return levels_; }
+  // Sorts the rows of level i in place if they are not sorted yet.
+  void ensure_sorted(size_t i);
 
   int64_t t_coarsen_ns = 0, t_initial_ns = 0, t_refine_ns = 0;
 

@@ -693,6 +693,22 @@ void Engine::cluster(Level& L, std::vector<Job>& jobs, std::vector<uint8_t>& act
   if (any) two_hop(L, jobs, which, level, label.get(), W.get(), csize.get(), ncl);
 }
 
+void Engine::ensure_sorted(size_t i) {
+  Level& L = *levels_.at(i);
+  if (L.sorted) return;
+  DBuf<uint32_t> adj, src;
+  DBuf<int64_t> ew;
+  sort_rows(L.n, L.nnz, L.xadj, L.adj, L.ew, L.ew_kind, packed_ ? 1 : 0, adj, ew, src, pool_, s_);
+  L.o_adj = std::move(adj);
+  L.o_ew = std::move(ew);
+  L.o_src = std::move(src);
+  L.adj = L.o_adj.get();
+  L.ew = L.o_ew.get();
+  L.ew_kind = EW_I64;
+  L.src = L.o_src.get();
+  L.sorted = true;
+}
+
 // -------------------------------------------------------------- coarsening --
 void Engine::coarsen(std::vector<Job>& jobs) {
   Timer tm(s_);
@@ -754,6 +770,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     ci.keep = dkeep.get();
     ci.bounds = L.nbase;
     ci.packed = packed_;
+    ci.sorted = false;
     ContractOut co;
     contract_level(ci, co, pool_, s_);
     label.clear();
@@ -840,6 +857,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     }
     C->o_nw = std::move(co.nw);
     if (BC > 1) C->o_gid = std::move(co.gid);
+    C->sorted = false;
     C->xadj = C->o_xadj.get();
     C->adj = C->o_adj.get();
     C->ew = C->o_ew.get();
@@ -860,6 +878,9 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     }
     levels_.push_back(std::move(C));
   }
+  // the initial partitioning visits neighbours in ascending order: sort the
+  // coarsest level of every graph (coarse rows are built in hash order)
+  for (auto& jb : jobs) ensure_sorted(jb.nlevels - 1);
   t_coarsen_ns = tm.stop_ns();
 }
 

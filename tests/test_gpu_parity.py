@@ -142,6 +142,25 @@ def test_hub_rating_paths(lib, tables, monkeypatch):
     check_partition(lib, g, 4, 0.03, 3)
 
 
+@pytest.mark.parametrize("mode", ["ranges", "overflow"])
+def test_large_contraction_rows(lib, mode, monkeypatch):
+    # coarse rows of more than 12288 entries: hash ranges in LDS, or the
+    # radix-sorted rows that replace them when a range does not fit
+    if mode == "overflow":
+        monkeypatch.setenv("LMGP_ROW_RANGES", "overflow")
+    rng = np.random.default_rng(4)
+    s = T.star(30000)
+    a, b, _ = T.edges_of(s)
+    extra = set()
+    while len(extra) < 60000:
+        x, y = rng.integers(1, s.n, size=2)
+        if x != y:
+            extra.add((min(x, y), max(x, y)))
+    g = T.from_edges(s.n, np.concatenate([np.stack([a, b], 1), np.array(sorted(extra))]))
+    check_hierarchy(lib, g, 4, 5)
+    check_partition(lib, g, 4, 0.03, 5)
+
+
 def test_hub_rows_heavy_weights(lib):
     # total edge weight >= 2^32 switches the hub and big-node rating tables
     # from packed 64-bit slots to separate key / 64-bit value arrays
