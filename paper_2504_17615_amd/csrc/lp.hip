@@ -1263,6 +1263,7 @@ __global__ __launch_bounds__(256) void k_adm_seg_wave(AdmitArgs a) {
   }
 }
 
+template <int NW = NWAVE>
 LMGP_D uint64_t block_min(uint64_t v, uint64_t* sred) {
 #pragma unroll
   for (int d = WAVE / 2; d > 0; d >>= 1) {
@@ -1272,11 +1273,12 @@ LMGP_D uint64_t block_min(uint64_t v, uint64_t* sred) {
   if (lane_id() == 0) sred[threadIdx.x / WAVE] = v;
   __syncthreads();
   uint64_t r = sred[0];
-  for (int i = 1; i < NWAVE; ++i) r = sred[i] < r ? sred[i] : r;
+  for (int i = 1; i < NW; ++i) r = sred[i] < r ? sred[i] : r;
   __syncthreads();
   return r;
 }
 
+template <int NW = NWAVE>
 LMGP_D uint64_t block_max(uint64_t v, uint64_t* sred) {
 #pragma unroll
   for (int d = WAVE / 2; d > 0; d >>= 1) {
@@ -1286,7 +1288,7 @@ LMGP_D uint64_t block_max(uint64_t v, uint64_t* sred) {
   if (lane_id() == 0) sred[threadIdx.x / WAVE] = v;
   __syncthreads();
   uint64_t r = sred[0];
-  for (int i = 1; i < NWAVE; ++i) r = sred[i] > r ? sred[i] : r;
+  for (int i = 1; i < NW; ++i) r = sred[i] > r ? sred[i] : r;
   __syncthreads();
   return r;
 }
@@ -1295,63 +1297,60 @@ LMGP_D uint64_t block_max(uint64_t v, uint64_t* sred) {
 // a weighted MSB-first radix select finds the first key (in admission order)
 // at which the summed node weight exceeds the room; every smaller key is
 // admitted, which is exactly the longest fitting prefix (keys are unique).
-__global__ __launch_bounds__(256) void k_adm_seg_block(AdmitArgs a) {
+// Each digit pass admits the candidates whose digit is below the threshold's,
+// drops those above and carries only the ones that share it to the next pass
+// (compacted into the segment's scratch, ping-pong with cpos), so the passes
+// after the first touch few candidates.
+constexpr int SEG_NT = 512;
+
+__global__ __launch_bounds__(SEG_NT) void k_adm_seg_block(AdmitArgs a) {
+  constexpr int NW = SEG_NT / WAVE;
   __shared__ unsigned long long whist[256];
-  __shared__ uint64_t sred[NWAVE];
+  __shared__ uint64_t sred[NW];
   __shared__ int s_digit;
   __shared__ int64_t s_rem;
+  __shared__ uint32_t s_cnt;
   const uint32_t nt = *a.ovcount;
   for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
     const uint32_t t = a.ovtgts[j];
     const uint32_t size = a.ntgt[t];
     if (size <= WAVE) continue;
     const uint32_t base = a.segbase[t];
-    const uint32_t* sg = a.seg + base;
-    const uint32_t u0 = a.cands[sg[0]].u;
+    uint32_t* in = a.seg + base;
+    uint32_t* out = a.cpos + base;  // cpos is free once the segments are scattered
+    const uint32_t u0 = a.cands[in[0]].u;
     const int64_t room = a.gd[cand_graph(a, u0)].cap - a.W[t];
     // range of the keys: digits above the highest differing bit are shared
     uint64_t mnh = ~0ull, mxh = 0, mnl = ~0ull, mxl = 0;
-    for (uint32_t i = threadIdx.x; i < size; i += 256) {
+    for (uint32_t i = threadIdx.x; i < size; i += SEG_NT) {
       uint64_t h, l;
-      cand_key(a.cands[sg[i]], h, l);
+      cand_key(a.cands[in[i]], h, l);
       mnh = h < mnh ? h : mnh;
       mxh = h > mxh ? h : mxh;
       mnl = l < mnl ? l : mnl;
       mxl = l > mxl ? l : mxl;
     }
-    mnh = block_min(mnh, sred);
-    mxh = block_max(mxh, sred);
-    mnl = block_min(mnl, sred);
-    mxl = block_max(mxl, sred);
+    mnh = block_min<NW>(mnh, sred);
+    mxh = block_max<NW>(mxh, sred);
+    mnl = block_min<NW>(mnl, sred);
+    mxl = block_max<NW>(mxl, sred);
     // digit positions 15..0: 15..8 are the bytes of hi, 7..0 those of lo
     int top;
     if (mnh != mxh) top = 8 + (63 - __clzll(mnh ^ mxh)) / 8;
     else top = mnl != mxl ? (63 - __clzll(mnl ^ mxl)) / 8 : -1;
-    // threshold prefix: digits above `top` are shared by every key; each pass
-    // below fixes one more digit and compares only the digits above it
-    uint64_t ph = mnh, pl = mnl;
     int64_t rem = room;  // weight still admissible below the threshold
-    for (int pos = top; pos >= 0; --pos) {
-      for (int i = threadIdx.x; i < 256; i += 256) whist[i] = 0;
+    uint32_t cur = size;  // candidates sharing the threshold's digits so far
+    for (int pos = top; pos >= 0 && cur > 0; --pos) {
+      for (int i = threadIdx.x; i < 256; i += SEG_NT) whist[i] = 0;
+      if (threadIdx.x == 0) s_cnt = 0;
       __syncthreads();
       const int sh = 8 * (pos & 7);
-      for (uint32_t i = threadIdx.x; i < size; i += 256) {
-        const Cand c = a.cands[sg[i]];
+      for (uint32_t i = threadIdx.x; i < cur; i += SEG_NT) {
+        const Cand c = a.cands[in[i]];
         uint64_t h, l;
         cand_key(c, h, l);
-        // same digits above pos as the threshold prefix
-        bool match;
-        if (pos >= 8) {
-          const int hs = sh + 8;
-          match = hs >= 64 || (h >> hs) == (ph >> hs);
-        } else {
-          const int hs = sh + 8;
-          match = h == ph && (hs >= 64 || (l >> hs) == (pl >> hs));
-        }
-        if (match) {
-          const uint32_t d = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
-          atomicAdd(&whist[d], (unsigned long long)a.nw[c.u]);
-        }
+        const uint32_t d = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
+        atomicAdd(&whist[d], (unsigned long long)a.nw[c.u]);
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -1369,20 +1368,24 @@ __global__ __launch_bounds__(256) void k_adm_seg_block(AdmitArgs a) {
         s_rem = rem - cum;
       }
       __syncthreads();
-      const uint64_t dd = (uint64_t)s_digit;
+      const uint32_t dsel = (uint32_t)s_digit;
+      for (uint32_t i = threadIdx.x; i < cur; i += SEG_NT) {
+        const uint32_t ci = in[i];
+        uint64_t h, l;
+        cand_key(a.cands[ci], h, l);
+        const uint32_t d = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
+        if (d < dsel) a.adm[ci] = 1;
+        else if (d == dsel) out[atomicAdd(&s_cnt, 1u)] = ci;
+      }
+      __syncthreads();
       rem = s_rem;
-      if (pos >= 8) ph = (ph & ~(0xFFull << sh)) | (dd << sh);
-      else pl = (pl & ~(0xFFull << sh)) | (dd << sh);
+      cur = s_cnt;
+      uint32_t* tmp = in;
+      in = out;
+      out = tmp;
       __syncthreads();
     }
-    // the threshold key (ph, pl) is the first key that no longer fits
-    for (uint32_t i = threadIdx.x; i < size; i += 256) {
-      const uint32_t ci = sg[i];
-      uint64_t h, l;
-      cand_key(a.cands[ci], h, l);
-      if (key_less(h, l, ph, pl)) a.adm[ci] = 1;
-    }
-    __syncthreads();
+    // what is left (one key: keys are unique) is the threshold: not admitted
   }
 }
 
@@ -1490,8 +1493,10 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
   if (gs > 1024) gs = 1024;
   k_adm_seg_wave<<<gs, 256, 0, s>>>(a);
   LAUNCH_CHECK();
-  unsigned gb = a.max_cands < 1024 ? a.max_cands : 1024;
-  k_adm_seg_block<<<gb, 256, 0, s>>>(a);
+  // at most max_cands / 65 segments exceed a wave
+  unsigned gb = a.max_cands / (WAVE + 1) + 1;
+  if (gb > 1024) gb = 1024;
+  k_adm_seg_block<<<gb, SEG_NT, 0, s>>>(a);
   LAUNCH_CHECK();
   if (few_apply) k_adm_apply_few<<<grid_for(a.max_cands, 256 * ADM_ITEMS), 256, 0, s>>>(a);
   else k_adm_apply<<<g, 256, 0, s>>>(a);
