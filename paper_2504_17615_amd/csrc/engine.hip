@@ -431,6 +431,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.gid = L.gid;
   ba.gd = dgd.get();
   ba.n = n;
+  ba.nw = L.nw;
   ba.mode = 0;
   ba.nbuckets = NB;
   ba.counts = bcount.get();

@@ -109,7 +109,7 @@ struct BucketArgs {
   int mode;                // 0: LP sub-rounds (hash), 1: 2-hop singletons (filter arrays)
   const uint32_t* label;   // mode 1
   const uint32_t* csize;   // mode 1: member count per label
-  const int64_t* nw;       // mode 1
+  const int64_t* nw;       // node weights
   uint32_t nbuckets;
   uint32_t* counts;        // [nbuckets]
   unsigned long long* degs;  // [nbuckets] summed degrees (count pass)

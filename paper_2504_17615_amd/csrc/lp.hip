@@ -437,6 +437,79 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   }
 }
 
+// Refinement with few labels (blocks, at most FEW_LABELS): nodes of the block
+// and big-block classes rate into a dense LDS row indexed by the label, with
+// no hashing and no probing; NT threads per node.
+template <int EWK, int NT>
+__global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a) {
+  constexpr int NW = NT / WAVE;
+  __shared__ unsigned long long tab[FEW_LABELS];
+  __shared__ Best sb[NW];
+  __shared__ int64_t so[NW];
+  __shared__ int64_t sm[NW];
+  const uint64_t idx = blockIdx.x;
+  if (idx >= a.count) return;
+  const uint32_t u = a.list[idx];
+  if (!a.gd[graph_of(a.gid, u)].active) {
+    if (threadIdx.x == 0) no_cand(a, (uint32_t)idx);
+    return;
+  }
+  const uint32_t few = a.few;
+  for (uint32_t t = threadIdx.x; t < few; t += NT) tab[t] = 0;
+  __syncthreads();
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  const uint32_t own = a.label[u];
+  int64_t acc = 0;
+  constexpr int U = 4;
+  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * NT) {
+    uint32_t v[U], K[U];
+    int64_t w[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint64_t e = e0 + (uint64_t)j * NT;
+      v[j] = e < end ? a.adj[e] : 0u;
+      w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * NT < end ? a.label[v[j]] : EMPTY_KEY;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (K[j] == EMPTY_KEY) continue;
+      if (K[j] == own) acc += w[j];
+      else atomicAdd(&tab[K[j]], (unsigned long long)w[j]);
+    }
+  }
+  int64_t acc_tot;
+  (void)block_exclusive_scan<int64_t, NW>(acc, sm, acc_tot);
+  if (threadIdx.x == 0) tab[own] += (unsigned long long)acc_tot;
+  __syncthreads();
+  const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+  const int64_t cu = a.nw[u];
+  const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+  Best best{0, 0, 0};
+  int64_t r_own = 0;
+  for (uint32_t t = threadIdx.x; t < few; t += NT) {
+    const int64_t r = (int64_t)tab[t];
+    if (r == 0) continue;  // not adjacent (edge weights are positive)
+    const int64_t wk = t != own ? a.W[t] : 0;
+    consider_w(a, t, r, own, cu, gd.cap, wk, pre_u, gd.label_base, best, r_own);
+  }
+  reduce_best<WAVE>(best, r_own);
+  const int wv = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    sb[wv] = best;
+    so[wv] = r_own;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NW; ++q) {
+      if (better(sb[q].r, sb[q].h, sb[q].K, best)) best = sb[q];
+      r_own = so[q] > r_own ? so[q] : r_own;
+    }
+    emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
+  }
+}
+
 // ------------------------------------------------- hub nodes (degree > 2048) --
 // A hub's rating table lives in global memory; its adjacency is split into
 // chunks of HUB_CHUNK entries rated by separate blocks, and its table into
@@ -624,7 +697,7 @@ __global__ void k_hub_final(HubArgs h) {
 // LDS table, so no global atomics are needed.  Probing is bounded: a range
 // that does not fit raises `overflow` and the caller recomputes the hubs with
 // the global tables (same ratings, same result).
-constexpr int HUB_RANGE = 6144;
+constexpr int HUB_RANGE = 12288;
 
 LMGP_D uint32_t label_range(uint32_t K, uint32_t P) {
   uint32_t h = K * 0x9E3779B1u;
@@ -754,14 +827,16 @@ struct HubSlotChunks {
 // Profiler family of a rating launch: phase, degree class, edge-weight type
 // (e.g. "cl_rate_block_i64" for clustering, "rf_" refinement, "fv_" 2-hop
 // favourites).
-std::string rate_name(int phase, int cls, int ewk) {
+std::string rate_name(int phase, int cls, int ewk, bool few) {
   // "<phase>:<kernel>": the kernel part is the HIP kernel's template name, so
   // that event timings line up with a kernel trace; the hub class brackets
   // several kernels and is named rate_hubs
   static const char* ph[3] = {"cl:", "rf:", "fv:"};
   const int w = ewk;
   std::string k;
-  if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
+  if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_GLOBAL)
+    k = "k_rate_dense<" + std::to_string(w) + ", " + (cls < CLASS_BIG ? "256>" : "1024>");
+  else if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
   else if (cls < CLASS_BIG)
     k = "k_rate_block<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ">";
   else if (is_big_class(cls))
@@ -782,7 +857,8 @@ template <int EWK>
 void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (a.count == 0) return;
   // single-kernel classes: the launch timestamps its own start and end
-  ProfLaunch prof(rate_name(a.phase, cls, EWK).c_str(), rate_bytes(EWK, a.count, a.degsum));
+  const bool few = a.few && a.few <= FEW_LABELS && a.mode == MODE_LP;
+  ProfLaunch prof(rate_name(a.phase, cls, EWK, few).c_str(), rate_bytes(EWK, a.count, a.degsum));
   const hipEvent_t e0 = prof.start(), e1 = prof.stop();
   if (cls < CLASS_BLOCK) {
     const int G = class_group(cls);
@@ -795,6 +871,11 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
       case 32: hipExtLaunchKernelGGL(k_rate_group<32, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
       default: hipExtLaunchKernelGGL(k_rate_group<64, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
     }
+  } else if (a.few && a.few <= FEW_LABELS && a.mode == MODE_LP && cls < CLASS_GLOBAL) {
+    if (cls < CLASS_BIG)
+      hipExtLaunchKernelGGL(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), 0, s, e0, e1, 0, a);
+    else
+      hipExtLaunchKernelGGL(k_rate_dense<EWK, 1024>, dim3(a.count), dim3(1024), 0, s, e0, e1, 0, a);
   } else if (cls < CLASS_BIG) {
     const dim3 grid(a.count), blk(256);
     switch (cls - CLASS_BLOCK) {
@@ -900,7 +981,7 @@ __global__ __launch_bounds__(256) void k_hub_few_final(HubArgs h, const unsigned
 template <int EWK>
 void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   const uint32_t c = ra.count;
-  ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK).c_str(),
+  ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK, false).c_str(),
                  rate_bytes(EWK, ra.count, ra.degsum), s);
   // LMGP_HUB_TABLES=global forces the global-table path (used by the tests to
   // cover the fallback taken when a label range overflows its LDS table)
@@ -1001,6 +1082,9 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
   const uint64_t d = a.xadj[u + 1] - a.xadj[u];
   if (d == 0) return -1;
   if (a.mode == 0) {
+    // a node at least as heavy as the capacity can join no label (every
+    // adjacent label weighs at least one), so rating it cannot produce a move
+    if (a.nw[u] >= gd.cap) return -1;
     uint32_t sr = subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds);
     return (int)(sr * NCLASS + degree_class(d));
   }
