@@ -58,7 +58,9 @@ struct LpCtl {
   unsigned long long* round_moves;  // moves of the current round
   unsigned long long* ncl;          // cluster count (clustering) or NULL
   uint32_t* rounds_run;             // rounds in which the graph was active
-  uint32_t* flags;                  // active flag at the start of the current round
+  unsigned long long* rstate;       // [2 nb] bucket counters, then [B] active flags
+  uint32_t nb;                      // buckets (sub-rounds x degree classes)
+  uint32_t* ovtotal;                // admission overflow counters [2], cleared here
   const uint64_t* pre;              // [round][graph][3]: SUB, TIE, ADM hash prefixes
   uint32_t shrink_num, shrink_den;
 };
@@ -78,6 +80,7 @@ __global__ void k_lp_after_sub(LpCtl c) {
     c.moves[b] = 0;
     c.delta[b] = 0;
   }
+  if (threadIdx.x < 2) c.ovtotal[threadIdx.x] = 0;
 }
 
 // Start of round r: a graph that made no move in round r - 1 stops; the
@@ -92,8 +95,9 @@ __global__ void k_lp_round(LpCtl c, uint32_t r) {
     g.pre_tie = p[1];
     g.pre_adm = p[2];
     if (g.active) c.rounds_run[b] = r + 1;
-    c.flags[b] = g.active;
+    c.rstate[2 * c.nb + b] = g.active;
   }
+  for (uint32_t i = threadIdx.x; i < 2 * c.nb; i += blockDim.x) c.rstate[i] = 0;
 }
 
 
@@ -390,13 +394,16 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<uint32_t> ntgt(&pool_, s_, nlabels), fill(&pool_, s_, nlabels), segbase(&pool_, s_, nlabels);
   DBuf<uint32_t> ovtotal(&pool_, s_, 2), ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
   DBuf<uint8_t> adm(&pool_, s_, n);
-  DBuf<uint32_t> bcount(&pool_, s_, NB), boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
-  DBuf<unsigned long long> bdeg(&pool_, s_, NB);
-  std::vector<unsigned long long> degs(NB);
+  DBuf<uint32_t> boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
+  // per-round state read by the host in one copy: bucket counts, bucket
+  // degree sums, active flags
+  DBuf<unsigned long long> rstate(&pool_, s_, 2 * NB + B);
+  std::vector<unsigned long long> hstate(2 * NB + B);
   demand.zero();
   ntgt.zero();
   fill.zero();
   std::vector<uint32_t> cnt(NB), offs(NB);
+  std::vector<unsigned long long> degs(NB);
   // refinement with few labels: demand and segment slots from block-privatised
   // histograms in the admission instead of contended atomics
   const uint32_t few = spec.refine && nlabels <= FEW_LABELS ? (uint32_t)nlabels : 0u;
@@ -416,7 +423,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     }
   DBuf<uint64_t> dpre(&pool_, s_, pre.size() ? pre.size() : 1);
   DBuf<unsigned long long> dround(&pool_, s_, B), dncl(&pool_, s_, B);
-  DBuf<uint32_t> drounds(&pool_, s_, B), dflags(&pool_, s_, B);
+  DBuf<uint32_t> drounds(&pool_, s_, B);
   h2d(dpre.get(), pre.data(), pre.size(), s_);
   h2d(dgd.get(), gd.data(), B, s_);
   if (ncl) h2d(dncl.get(), (const unsigned long long*)ncl->data(), B, s_);
@@ -424,8 +431,10 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ddelta.zero();
   dround.zero();
   drounds.zero();
+  ovtotal.zero();
   LpCtl ctl{dgd.get(), B, dmoves.get(), ddelta.get(), dround.get(), ncl ? dncl.get() : nullptr,
-            drounds.get(), dflags.get(), dpre.get(), p_.shrink_num, p_.shrink_den};
+            drounds.get(), rstate.get(), NB, ovtotal.get(), dpre.get(), p_.shrink_num,
+            p_.shrink_den};
   BucketArgs ba{};
   ba.xadj = L.xadj;
   ba.gid = L.gid;
@@ -434,38 +443,36 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.nw = L.nw;
   ba.mode = 0;
   ba.nbuckets = NB;
-  ba.counts = bcount.get();
-  ba.degs = bdeg.get();
+  ba.counts = rstate.get();
+  ba.degs = rstate.get() + NB;
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();
-  std::vector<uint32_t> flags(B);
   // Stop decisions (node-reduction cap after a sub-round, no moves in a
   // round) are taken on the device; the host reads the active flags together
-  // with the next round's bucket counts, once per round.
+  // with the next round's bucket counts, in one copy per round.
   auto begin_round = [&](uint32_t r) {
-    k_lp_round<<<1, 256, 0, s_>>>(ctl, r);
+    k_lp_round<<<1, 256, 0, s_>>>(ctl, r);  // also clears the bucket counters
     LAUNCH_CHECK();
-    bcount.zero();
-    bdeg.zero();
     launch_bucket_count(ba, s_);
-    d2h(cnt.data(), bcount.get(), NB, s_);
-    d2h(degs.data(), bdeg.get(), NB, s_);
-    d2h(flags.data(), dflags.get(), B, s_);
+    launch_bucket_offsets(ba, s_);
+    d2h(hstate.data(), rstate.get(), hstate.size(), s_);
     sync(s_);
+    for (uint32_t i = 0; i < NB; ++i) {
+      cnt[i] = (uint32_t)hstate[i];
+      degs[i] = hstate[NB + i];
+    }
   };
   for (uint32_t r = 0; r < R; ++r) {
     begin_round(r);
     bool any = false;
-    for (uint32_t b = 0; b < B; ++b) any |= flags[b] != 0;
+    for (uint32_t b = 0; b < B; ++b) any |= hstate[2 * NB + b] != 0;
     if (!any) break;
     uint32_t run = 0;
     for (uint32_t i = 0; i < NB; ++i) {
-      offs[i] = run;
+      offs[i] = run;  // the same prefix the device computed into boffs
       run += cnt[i];
     }
-    h2d(boffs.get(), offs.data(), NB, s_);
-    bfill.zero();
     launch_bucket_scatter(ba, s_);
     for (uint32_t sr = 0; sr < S; ++sr) {
       uint32_t total = 0;
@@ -519,8 +526,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       aa.moves = (uint64_t*)dmoves.get();
       aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
       aa.few = few;
-      ovtotal.zero();
-      launch_admit(aa, s_);
+      launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
       k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
       LAUNCH_CHECK();
     }
@@ -531,7 +537,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   sync(s_);
   if (ncl)
     for (uint32_t b = 0; b < B; ++b) (*ncl)[b] = hncl[b];
-  for (uint32_t b = 0; b < B; ++b) active[b] = flags[b] != 0;
+  for (uint32_t b = 0; b < B; ++b) active[b] = hstate[2 * NB + b] != 0;
 }
 
 // ------------------------------------------------------------ clustering --
@@ -556,7 +562,8 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   DBuf<GraphDesc> dgd(&pool_, s_, B);
   h2d(dgd.get(), gd.data(), B, s_);
   // favourites of light singletons with neighbours
-  DBuf<uint32_t> bcount(&pool_, s_, NCLASS), boffs(&pool_, s_, NCLASS), bfill(&pool_, s_, NCLASS);
+  DBuf<unsigned long long> bcount(&pool_, s_, NCLASS);
+  DBuf<uint32_t> boffs(&pool_, s_, NCLASS), bfill(&pool_, s_, NCLASS);
   DBuf<uint32_t> list(&pool_, s_, n), fav(&pool_, s_, n);
   BucketArgs ba{};
   ba.xadj = L.xadj;
@@ -574,16 +581,17 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ba.list = list.get();
   bcount.zero();
   launch_bucket_count(ba, s_);
+  launch_bucket_offsets(ba, s_);
+  std::vector<unsigned long long> hcnt(NCLASS);
   std::vector<uint32_t> cnt(NCLASS), offs(NCLASS);
-  d2h(cnt.data(), bcount.get(), NCLASS, s_);
+  d2h(hcnt.data(), bcount.get(), NCLASS, s_);
   sync(s_);
   uint32_t run = 0;
   for (int c = 0; c < NCLASS; ++c) {
+    cnt[c] = (uint32_t)hcnt[c];
     offs[c] = run;
     run += cnt[c];
   }
-  h2d(boffs.get(), offs.data(), NCLASS, s_);
-  bfill.zero();
   launch_bucket_scatter(ba, s_);
   RateArgs ra{};
   ra.xadj = L.xadj;

@@ -111,13 +111,15 @@ struct BucketArgs {
   const uint32_t* csize;   // mode 1: member count per label
   const int64_t* nw;       // node weights
   uint32_t nbuckets;
-  uint32_t* counts;        // [nbuckets]
+  unsigned long long* counts;  // [nbuckets]
   unsigned long long* degs;  // [nbuckets] summed degrees (count pass)
-  const uint32_t* offs;    // [nbuckets] (scatter pass)
+  uint32_t* offs;          // [nbuckets] (offsets pass writes, scatter pass reads)
   uint32_t* fill;          // [nbuckets] (scatter pass)
   uint32_t* list;          // output
 };
 void launch_bucket_count(const BucketArgs& a, hipStream_t s);
+// offs = exclusive prefix of counts, fill = 0 (one small block on the device).
+void launch_bucket_offsets(const BucketArgs& a, hipStream_t s);
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s);
 
 // Admission of LP candidates and application of moves.

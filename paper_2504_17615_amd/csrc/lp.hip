@@ -1113,9 +1113,24 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256)
     if (h[i]) {
-      atomicAdd(&a.counts[i], h[i]);
+      atomicAdd(&a.counts[i], (unsigned long long)h[i]);
       if (a.degs) atomicAdd(&a.degs[i], hd[i]);
     }
+}
+
+__global__ void k_bucket_offsets(BucketArgs a) {
+  // nbuckets <= MAX_BUCKETS: one wave scans them in chunks of 64
+  uint32_t run = 0;
+  for (uint32_t i0 = 0; i0 < a.nbuckets; i0 += WAVE) {
+    const uint32_t i = i0 + lane_id();
+    const uint32_t c = i < a.nbuckets ? (uint32_t)a.counts[i] : 0u;
+    const uint32_t inc = wave_inclusive_scan(c);
+    if (i < a.nbuckets) {
+      a.offs[i] = run + inc - c;
+      a.fill[i] = 0;
+    }
+    run += __shfl(inc, WAVE - 1);
+  }
 }
 
 // Each block takes 2048 consecutive nodes, counts them per bucket in LDS and
@@ -1229,7 +1244,14 @@ __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
 __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
   __shared__ long long dw[FEW_LABELS];
   __shared__ uint64_t smv[NWAVE];
-  for (uint32_t t = threadIdx.x; t < a.few; t += 256) dw[t] = 0;
+  for (uint32_t t = threadIdx.x; t < a.few; t += 256) {
+    dw[t] = 0;
+    if (blockIdx.x == 0) {  // per-target scratch for the next sub-round
+      a.demand[t] = 0;
+      a.ntgt[t] = 0;
+      a.fill[t] = 0;
+    }
+  }
   __syncthreads();
   const uint32_t nc = a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
@@ -1308,11 +1330,10 @@ LMGP_D bool key_less(uint64_t ahi, uint64_t alo, uint64_t bhi, uint64_t blo) {
 }
 
 // Segments of at most 64 candidates: one wave, bitonic sort in registers.
-__global__ __launch_bounds__(256) void k_adm_seg_wave(AdmitArgs a) {
+LMGP_D void seg_waves(const AdmitArgs& a, uint32_t wid, uint32_t waves) {
   const uint32_t nt = *a.ovcount;
-  const uint32_t waves = gridDim.x * (blockDim.x / WAVE);
   const int l = lane_id();
-  for (uint32_t j = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; j < nt; j += waves) {
+  for (uint32_t j = wid; j < nt; j += waves) {
     const uint32_t t = a.ovtgts[j];
     const uint32_t size = a.ntgt[t];
     if (size > WAVE) continue;
@@ -1387,13 +1408,16 @@ LMGP_D uint64_t block_max(uint64_t v, uint64_t* sred) {
 // after the first touch few candidates.
 constexpr int SEG_NT = 512;
 
-__global__ __launch_bounds__(SEG_NT) void k_adm_seg_block(AdmitArgs a) {
+__global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
   constexpr int NW = SEG_NT / WAVE;
   __shared__ unsigned long long whist[256];
   __shared__ uint64_t sred[NW];
   __shared__ int s_digit;
   __shared__ int64_t s_rem;
   __shared__ uint32_t s_cnt;
+  // segments of at most 64 candidates: one wave each
+  seg_waves(a, blockIdx.x * NW + threadIdx.x / WAVE, gridDim.x * NW);
+  // larger segments: one block each
   const uint32_t nt = *a.ovcount;
   for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
     const uint32_t t = a.ovtgts[j];
@@ -1501,6 +1525,16 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
       if (a.ncl_delta && dl) atomicAdd((unsigned long long*)&a.ncl_delta[g], (unsigned long long)dl);
     }
   }
+  // clear the per-target scratch for the next sub-round (no kernel of this
+  // admission reads it any more)
+  if (i < nc && !a.few) {
+    const uint32_t t = a.cands[i].tgt;
+    if (t != EMPTY_KEY) {
+      a.demand[t] = 0;
+      a.ntgt[t] = 0;
+      a.fill[t] = 0;
+    }
+  }
   if (!a.gid) {  // one graph: one atomic per wave
     mv = wave_reduce_sum(mv);
     dl = wave_reduce_sum(dl);
@@ -1511,17 +1545,6 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
   }
 }
 
-// Reset the per-target scratch for the next sub-round (after every reader).
-__global__ __launch_bounds__(256) void k_adm_reset(AdmitArgs a) {
-  const uint32_t nc = a.max_cands;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  const uint32_t t = a.cands[i].tgt;
-  if (t == EMPTY_KEY) return;
-  a.demand[t] = 0;
-  a.ntgt[t] = 0;
-  a.fill[t] = 0;
-}
 
 }  // namespace
 
@@ -1550,6 +1573,12 @@ void launch_bucket_count(const BucketArgs& a, hipStream_t s) {
   LAUNCH_CHECK();
 }
 
+void launch_bucket_offsets(const BucketArgs& a, hipStream_t s) {
+  if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
+  k_bucket_offsets<<<1, 64, 0, s>>>(a);
+  LAUNCH_CHECK();
+}
+
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s) {
   if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
   k_bucket_scatter<<<grid_for(a.n, 256 * BK_ITEMS), 256, 0, s>>>(a);
@@ -1573,20 +1602,21 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
   LAUNCH_CHECK();
   k_adm_scatter<<<g, 256, 0, s>>>(a);
   LAUNCH_CHECK();
-  unsigned gs = grid_for(a.max_cands, 4);
+  // one wave per small segment, one block per segment above 64 candidates
+  unsigned gs = grid_for(a.max_cands, SEG_NT / WAVE);
   if (gs > 1024) gs = 1024;
-  k_adm_seg_wave<<<gs, 256, 0, s>>>(a);
+  k_adm_seg<<<gs, SEG_NT, 0, s>>>(a);
   LAUNCH_CHECK();
-  // at most max_cands / 65 segments exceed a wave
-  unsigned gb = a.max_cands / (WAVE + 1) + 1;
-  if (gb > 1024) gb = 1024;
-  k_adm_seg_block<<<gb, SEG_NT, 0, s>>>(a);
-  LAUNCH_CHECK();
-  if (few_apply) k_adm_apply_few<<<grid_for(a.max_cands, 256 * ADM_ITEMS), 256, 0, s>>>(a);
-  else k_adm_apply<<<g, 256, 0, s>>>(a);
-  LAUNCH_CHECK();
-  if (few) k_adm_reset_few<<<grid_for(a.few, 256), 256, 0, s>>>(a);
-  else k_adm_reset<<<g, 256, 0, s>>>(a);
+  // apply (clearing the per-target scratch as it goes)
+  if (few_apply) {
+    k_adm_apply_few<<<grid_for(a.max_cands, 256 * ADM_ITEMS), 256, 0, s>>>(a);
+  } else {
+    k_adm_apply<<<g, 256, 0, s>>>(a);
+    if (few) {
+      LAUNCH_CHECK();
+      k_adm_reset_few<<<grid_for(a.few, 256), 256, 0, s>>>(a);
+    }
+  }
   LAUNCH_CHECK();
 }
 
