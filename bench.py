@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -125,6 +127,167 @@ def copy_calibration(mib: int):
     del src, dst
 
 
+def _hash64(x: int) -> int:
+    """SplitMix64 finaliser, for the seeded request mix of the serving bench."""
+    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return x ^ (x >> 31)
+
+
+def bench_batch(args) -> dict:
+    """Batched path: B 128x128 grids (the small configuration's shape) with
+    seeds 1..B, k=4, partitioned by one lmgp_partition_batch call per step;
+    beside it the same graphs one plain call at a time (on a prefix)."""
+    import torch
+
+    import paper_2504_17615_amd as L
+    from paper_2504_17615_amd import graphgen as gg
+
+    L.library()
+    B = args.batch_graphs
+    g = gg.grid(128, 128)
+    dgs = [L.create_graph(g) for _ in range(B)]
+    ks, eps, seeds = [4] * B, [0.03] * B, list(range(1, B + 1))
+    outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(B)]
+    for _ in range(args.warmup):
+        L.partition_batch(dgs, ks, eps, seeds, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(args.steps):
+        _, r = L.partition_batch(dgs, ks, eps, seeds, outs=outs)
+        res.append(r[0])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    cr = sum(r["t_coarsen_ns"] + r["t_refine_ns"] for r in res) / len(res) * 1e-9
+    m_tot = g.m * B
+    # plain calls, one graph at a time, on a prefix of the same requests
+    P = min(B, args.plain_prefix)
+    for i in range(min(P, 8)):
+        dgs[i].partition(4, 0.03, seeds[i], out=outs[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pcr = 0.0
+    for i in range(P):
+        _, r = dgs[i].partition(4, 0.03, seeds[i], out=outs[i])
+        pcr += (r["t_coarsen_ns"] + r["t_refine_ns"]) * 1e-9
+    torch.cuda.synchronize()
+    pwall = (time.perf_counter() - t0) / P
+    return {
+        "metric": "input edges/s through coarsen+refine", "value": m_tot / cr, "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"grid128 x {B}", "description": f"{B} 128x128 grids, seeds 1..{B}, "
+                   "k=4, eps=0.03, one batched call per step", "graphs": B, "m_total": m_tot},
+        "graphs_per_s": B / wall, "wall_edges_per_s": m_tot / wall,
+        "plain": {"graphs": P, "edges_per_s": g.m / (pcr / P), "graphs_per_s": 1.0 / pwall,
+                  "ms_per_graph": pwall * 1e3},
+        "batch_vs_plain_graphs_per_s": (B / wall) / (1.0 / pwall),
+    }
+
+
+def _request_mix(n_req: int, lo_exp: float, hi_exp: float):
+    """Seeded request mix: n = floor(10^(lo + (hi-lo) u)) nodes, a third each
+    grid / R-MAT (edge factor 16, scale round(log2 n)) / Erdos-Renyi G(n, 16n),
+    k = 2 (1 + H mod 128), eps 0.03, seed = request index."""
+    from paper_2504_17615_amd import graphgen as gg
+
+    reqs = []
+    for i in range(n_req):
+        u = (_hash64(3 * i) >> 11) / float(1 << 53)
+        n = int(10 ** (lo_exp + (hi_exp - lo_exp) * u))
+        kind = _hash64(3 * i + 1) % 3
+        k = 2 * (1 + _hash64(3 * i + 2) % 128)
+        if kind == 0:
+            rows = max(2, int(n ** 0.5))
+            g = gg.grid(rows, -(-n // rows))
+        elif kind == 1:
+            g = gg.rmat(max(4, round(np.log2(n))), seed=i + 1)
+        else:
+            g = gg.er(n, 16 * n, seed=i + 1)
+        reqs.append((g, min(k, g.n), 0.03, i + 1))
+    return reqs
+
+
+def bench_serve(args) -> dict:
+    """Serving loop: requests arrive as a Poisson process at `load` x the plain
+    path's measured capacity; latency = completion - arrival.  The plain path
+    is the same request sequence served one call at a time, FIFO, with the
+    service times measured here."""
+    import threading
+
+    import torch
+
+    import paper_2504_17615_amd as L
+
+    L.library()
+    t_gen = time.perf_counter()
+    reqs = _request_mix(args.requests, 3.0, args.max_exp)
+    t_gen = time.perf_counter() - t_gen
+    dgs = [L.create_graph(g) for g, _, _, _ in reqs]
+    m_tot = sum(g.m for g, _, _, _ in reqs)
+    for i in range(min(8, len(reqs))):
+        dgs[i].partition(reqs[i][1], reqs[i][2], reqs[i][3], host_out=True)
+    torch.cuda.synchronize()
+    # plain capacity: per-request service times on one stream
+    svc = []
+    for dg, (g, k, eps, seed) in zip(dgs, reqs):
+        t0 = time.perf_counter()
+        dg.partition(k, eps, seed, host_out=True)
+        svc.append(time.perf_counter() - t0)
+    mu = len(reqs) / sum(svc)
+    lam = args.load * mu
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+    # plain FIFO under the same arrivals
+    fin, plain_lat = 0.0, []
+    for a, s in zip(arrivals, svc):
+        fin = max(fin, a) + s
+        plain_lat.append(fin - a)
+    srv = L.Server(hbm_budget_bytes=args.hbm_budget_gib << 30, max_slots=args.slots,
+                   max_batch=args.max_batch, streams=args.streams)
+    tickets = [None] * len(reqs)
+    done = [0.0] * len(reqs)
+    start = time.perf_counter() + 0.05
+
+    def submitter():
+        for i, (dg, (g, k, eps, seed)) in enumerate(zip(dgs, reqs)):
+            dt = start + arrivals[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(dg, k, eps, seed)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    for i in range(len(reqs)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        srv.wait(tickets[i])
+        done[i] = time.perf_counter() - start
+    th.join()
+    srv.close()
+    lat = np.array(done) - arrivals
+    makespan = done[-1] - arrivals[0]
+    return {
+        "metric": "serving latency and throughput", "value": float(np.percentile(lat, 99) * 1e3),
+        "unit": "ms p99", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": f"request mix x {len(reqs)}",
+                   "description": _request_mix.__doc__.split("\n")[0] + " ...",
+                   "n_range": [1000, int(10 ** args.max_exp)], "load": args.load,
+                   "requests": len(reqs), "m_total": m_tot, "slots": args.slots,
+                   "max_batch": args.max_batch, "streams": args.streams},
+        "server": {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                   "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                   "graphs_per_s": len(reqs) / makespan},
+        "plain_fifo": {"p50_ms": float(np.percentile(plain_lat, 50) * 1e3),
+                       "p99_ms": float(np.percentile(plain_lat, 99) * 1e3),
+                       "capacity_graphs_per_s": mu},
+        "arrival_rate_per_s": lam, "gen_s": round(t_gen, 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,11 +299,28 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="launch one plain copy of this size first (counter calibration)")
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+                    help="single: the headline workload; batch: many small graphs in one "
+                         "batched call; serve: Poisson request stream through the server")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--plain-prefix", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--max-exp", type=float, default=5.0, help="request sizes up to 10^max_exp")
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--hbm-budget-gib", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode != "single":
+        line = bench_batch(args) if args.mode == "batch" else bench_serve(args)
+        print(json.dumps(line), flush=True)
+        return
 
     import torch
 
