@@ -99,6 +99,8 @@ class Engine {
                uint32_t level, uint32_t* label, int64_t* W, uint32_t* csize,
                std::vector<uint64_t>& ncl);
   void build_union(std::vector<Job>& jobs);
+  void rate_classes(RateArgs ra, const uint32_t* cnt, const uint32_t* offs,
+                    const unsigned long long* degs, int ew_kind);
 
   Pool& pool_;
   hipStream_t s_;

@@ -365,6 +365,46 @@ void Engine::build_union(std::vector<Job>& jobs) {
 }
 
 // -------------------------------------------------------------- LP driver --
+// Rates the nodes of one sub-round: ra.list (and ra.cands) point at the
+// first degree class; cnt/offs/degs per class, offs absolute in the list.
+void Engine::rate_classes(RateArgs ra, const uint32_t* cnt, const uint32_t* offs,
+                          const unsigned long long* degs, int ew_kind) {
+  const uint32_t* list0 = ra.list;
+  Cand* cands0 = ra.cands;
+  auto span = [&](int c0, int c1) {
+    RateArgs r = ra;
+    r.list = list0 + (offs[c0] - offs[0]);
+    if (cands0) r.cands = cands0 + (offs[c0] - offs[0]);
+    r.count = 0;
+    r.degsum = 0;
+    for (int c = c0; c <= c1; ++c) {
+      r.count += cnt[c];
+      r.degsum += degs ? degs[c] : 0;
+    }
+    return r;
+  };
+  uint32_t gcnt[6], goff[6];
+  uint64_t gdeg = 0;
+  for (int c = 0; c < CLASS_BLOCK; ++c) {
+    gcnt[c] = cnt[c];
+    goff[c] = offs[c] - offs[0];
+    gdeg += degs ? degs[c] : 0;
+  }
+  launch_rate_groups(ew_kind, ra, gcnt, goff, gdeg, s_);
+  const bool dense = ra.few && ra.few <= FEW_LABELS && ra.mode == MODE_LP;
+  if (dense) {  // refinement, few blocks: dense LDS rows, one launch per block size
+    launch_rate(CLASS_BLOCK, ew_kind, span(CLASS_BLOCK, CLASS_BIG - 1), s_);
+    launch_rate(CLASS_BIG, ew_kind, span(CLASS_BIG, CLASS_GLOBAL - 1), s_);
+  } else {
+    for (int c = CLASS_BLOCK; c < CLASS_BIG; ++c) launch_rate(c, ew_kind, span(c, c), s_);
+    for (int c = CLASS_BIG; c < CLASS_GLOBAL; ++c) {
+      if (packed_) launch_rate(c, ew_kind, span(c, c), s_);
+      else launch_rate_hubs(ew_kind, span(c, c), pool_, s_);
+    }
+  }
+  launch_rate_hubs(ew_kind, span(CLASS_GLOBAL, CLASS_GLOBAL), pool_, s_);
+}
+
 void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
                     std::vector<uint8_t>& active, uint32_t* label, int64_t* W, size_t nlabels,
                     uint32_t* csize, const std::vector<uint64_t>& label_base,
@@ -493,16 +533,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       ra.few = few;
       ra.demand = demand.get();
       ra.ntgt = ntgt.get();
-      for (int c = 0; c < NCLASS; ++c) {
-        ra.list = list.get() + offs[sr * NCLASS + c];
-        ra.cands = cands.get() + (offs[sr * NCLASS + c] - offs[sr * NCLASS]);
-        ra.count = cnt[sr * NCLASS + c];
-        ra.degsum = degs[sr * NCLASS + c];
-        if (c == CLASS_GLOBAL || (is_big_class(c) && !packed_))
-          launch_rate_hubs(L.ew_kind, ra, pool_, s_);
-        else
-          launch_rate(c, L.ew_kind, ra, s_);
-      }
+      ra.list = list.get() + offs[sr * NCLASS];
+      ra.cands = cands.get();
+      rate_classes(ra, &cnt[sr * NCLASS], &offs[sr * NCLASS], &degs[sr * NCLASS], L.ew_kind);
       AdmitArgs aa{};
       aa.cands = cands.get();
       aa.max_cands = total;
@@ -606,14 +639,8 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ra.phase = 2;
   ra.packed = packed_ ? 1 : 0;
   ra.fav = fav.get();
-  for (int c = 0; c < NCLASS; ++c) {
-    ra.list = list.get() + offs[c];
-    ra.count = cnt[c];
-    if (c == CLASS_GLOBAL || (is_big_class(c) && !packed_))
-      launch_rate_hubs(L.ew_kind, ra, pool_, s_);
-    else
-      launch_rate(c, L.ew_kind, ra, s_);
-  }
+  ra.list = list.get();
+  rate_classes(ra, cnt.data(), offs.data(), nullptr, L.ew_kind);
   // order light singletons by (favourite, hash, id)
   SingletonFlag sf{label, csize, L.nw, L.gid, dgd.get()};
   DBuf<uint32_t> pos(&pool_, s_, n + 1);

@@ -149,16 +149,20 @@ LMGP_D int64_t group_sum(int64_t v) {
 // Entries whose label is the node's own label are summed in registers and
 // inserted once per group: in refinement and in settled clusters most
 // neighbours share that label, and their LDS atomics would all hit one slot.
+// Every lane-group class uses 1024 LDS slots per 256-thread block (256 / G
+// groups of 4G slots), so all six share one launch (k_rate_groups).
+constexpr int GROUP_SLOTS = 1024;
+
 template <int G, int EWK>
-__global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
+LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sval,
+                       uint64_t blk) {
   constexpr int T = 4 * G;
   constexpr int GPB = 256 / G;
-  __shared__ uint32_t skey[GPB * T];
-  __shared__ unsigned long long sval[GPB * T];
+  static_assert(GPB * T == GROUP_SLOTS, "group tables fill the block's slots");
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   uint32_t* key = skey + grp * T;
   unsigned long long* val = sval + grp * T;
-  const uint64_t idx = (uint64_t)blockIdx.x * GPB + grp;
+  const uint64_t idx = blk * GPB + grp;
   bool valid = idx < a.count;
   const uint32_t u = valid ? a.list[idx] : 0u;
   // a graph may stop in the middle of a round (its flag is cleared on the device)
@@ -223,6 +227,33 @@ __global__ __launch_bounds__(256) void k_rate_group(RateArgs a) {
   if (gl == 0 && idx < a.count) {
     if (valid) emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
     else no_cand(a, (uint32_t)idx);  // graph stopped
+  }
+}
+
+// The six lane-group classes in one launch: block b belongs to the class c
+// with split.bstart[c] <= b < split.bstart[c + 1]; each class has its own
+// list range (and candidate slots) at split.off[c].
+template <int EWK>
+__global__ __launch_bounds__(256) void k_rate_groups(RateArgs a, GroupSplit split) {
+  __shared__ uint32_t skey[GROUP_SLOTS];
+  __shared__ unsigned long long sval[GROUP_SLOTS];
+  const uint32_t b = blockIdx.x;
+  int c = 0;
+#pragma unroll
+  for (int q = 1; q < 6; ++q)
+    if (b >= split.bstart[q]) c = q;
+  RateArgs r = a;
+  r.list = a.list + split.off[c];
+  if (a.mode == MODE_LP) r.cands = a.cands + split.off[c];
+  r.count = split.count[c];
+  const uint64_t blk = b - split.bstart[c];
+  switch (c) {
+    case 0: rate_group<2, EWK>(r, skey, sval, blk); break;
+    case 1: rate_group<4, EWK>(r, skey, sval, blk); break;
+    case 2: rate_group<8, EWK>(r, skey, sval, blk); break;
+    case 3: rate_group<16, EWK>(r, skey, sval, blk); break;
+    case 4: rate_group<32, EWK>(r, skey, sval, blk); break;
+    default: rate_group<64, EWK>(r, skey, sval, blk); break;
   }
 }
 
@@ -854,6 +885,28 @@ uint64_t rate_bytes(int ewk, uint64_t count, uint64_t degsum) {
 }
 
 template <int EWK>
+void launch_groups_t(const RateArgs& a, const uint32_t* count, const uint32_t* off,
+                     uint64_t degsum, hipStream_t s) {
+  GroupSplit split{};
+  uint32_t blocks = 0, total = 0;
+  for (int c = 0; c < 6; ++c) {
+    split.bstart[c] = blocks;
+    split.off[c] = off[c];
+    split.count[c] = count[c];
+    blocks += grid_for(count[c], 256 / class_group(c));
+    total += count[c];
+  }
+  split.bstart[6] = blocks;
+  if (!blocks) return;
+  const char* ph[3] = {"cl:", "rf:", "fv:"};
+  ProfLaunch prof((std::string(ph[a.phase]) + "k_rate_groups<" + std::to_string(EWK) + ">").c_str(),
+                  rate_bytes(EWK, total, degsum));
+  hipExtLaunchKernelGGL(k_rate_groups<EWK>, dim3(blocks), dim3(256), 0, s, prof.start(),
+                        prof.stop(), 0, a, split);
+  LAUNCH_CHECK();
+}
+
+template <int EWK>
 void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (a.count == 0) return;
   // single-kernel classes: the launch timestamps its own start and end
@@ -861,16 +914,7 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   ProfLaunch prof(rate_name(a.phase, cls, EWK, few).c_str(), rate_bytes(EWK, a.count, a.degsum));
   const hipEvent_t e0 = prof.start(), e1 = prof.stop();
   if (cls < CLASS_BLOCK) {
-    const int G = class_group(cls);
-    const dim3 grid(grid_for(a.count, 256 / G)), blk(256);
-    switch (G) {
-      case 2: hipExtLaunchKernelGGL(k_rate_group<2, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
-      case 4: hipExtLaunchKernelGGL(k_rate_group<4, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
-      case 8: hipExtLaunchKernelGGL(k_rate_group<8, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
-      case 16: hipExtLaunchKernelGGL(k_rate_group<16, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
-      case 32: hipExtLaunchKernelGGL(k_rate_group<32, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
-      default: hipExtLaunchKernelGGL(k_rate_group<64, EWK>, grid, blk, 0, s, e0, e1, 0, a); break;
-    }
+    throw InvalidArg("lane-group classes are launched by launch_rate_groups");
   } else if (a.few && a.few <= FEW_LABELS && a.mode == MODE_LP && cls < CLASS_GLOBAL) {
     if (cls < CLASS_BIG)
       hipExtLaunchKernelGGL(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), 0, s, e0, e1, 0, a);
@@ -1554,6 +1598,15 @@ void launch_rate_hubs(int ew_kind, const RateArgs& a, Pool& pool, hipStream_t s)
     case EW_UNIT: launch_hubs_t<EW_UNIT>(a, pool, s); break;
     case EW_I32: launch_hubs_t<EW_I32>(a, pool, s); break;
     default: launch_hubs_t<EW_I64>(a, pool, s); break;
+  }
+}
+
+void launch_rate_groups(int ew_kind, const RateArgs& a, const uint32_t* count,
+                        const uint32_t* off, uint64_t degsum, hipStream_t s) {
+  switch (ew_kind) {
+    case EW_UNIT: launch_groups_t<EW_UNIT>(a, count, off, degsum, s); break;
+    case EW_I32: launch_groups_t<EW_I32>(a, count, off, degsum, s); break;
+    default: launch_groups_t<EW_I64>(a, count, off, degsum, s); break;
   }
 }
 
