@@ -383,20 +383,23 @@ void Engine::rate_classes(RateArgs ra, const uint32_t* cnt, const uint32_t* offs
     }
     return r;
   };
-  uint32_t gcnt[6], goff[6];
+  const bool dense = ra.few && ra.few <= FEW_LABELS && ra.mode == MODE_LP;
+  // dense refinement rates every block class with one launch: only the lane
+  // groups go through the merged small-class launch then
+  const int nsmall = dense ? CLASS_BLOCK : GROUP_CLASSES;
+  uint32_t gcnt[GROUP_CLASSES] = {}, goff[GROUP_CLASSES] = {};
   uint64_t gdeg = 0;
-  for (int c = 0; c < CLASS_BLOCK; ++c) {
+  for (int c = 0; c < nsmall; ++c) {
     gcnt[c] = cnt[c];
     goff[c] = offs[c] - offs[0];
     gdeg += degs ? degs[c] : 0;
   }
   launch_rate_groups(ew_kind, ra, gcnt, goff, gdeg, s_);
-  const bool dense = ra.few && ra.few <= FEW_LABELS && ra.mode == MODE_LP;
   if (dense) {  // refinement, few blocks: dense LDS rows, one launch per block size
     launch_rate(CLASS_BLOCK, ew_kind, span(CLASS_BLOCK, CLASS_BIG - 1), s_);
     launch_rate(CLASS_BIG, ew_kind, span(CLASS_BIG, CLASS_GLOBAL - 1), s_);
   } else {
-    for (int c = CLASS_BLOCK; c < CLASS_BIG; ++c) launch_rate(c, ew_kind, span(c, c), s_);
+    for (int c = GROUP_CLASSES; c < CLASS_BIG; ++c) launch_rate(c, ew_kind, span(c, c), s_);
     for (int c = CLASS_BIG; c < CLASS_GLOBAL; ++c) {
       if (packed_) launch_rate(c, ew_kind, span(c, c), s_);
       else launch_rate_hubs(ew_kind, span(c, c), pool_, s_);
@@ -595,7 +598,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   DBuf<GraphDesc> dgd(&pool_, s_, B);
   h2d(dgd.get(), gd.data(), B, s_);
   // favourites of light singletons with neighbours
-  DBuf<unsigned long long> bcount(&pool_, s_, NCLASS);
+  DBuf<unsigned long long> bcount(&pool_, s_, 2 * NCLASS);  // counts, then degree sums
   DBuf<uint32_t> boffs(&pool_, s_, NCLASS), bfill(&pool_, s_, NCLASS);
   DBuf<uint32_t> list(&pool_, s_, n), fav(&pool_, s_, n);
   BucketArgs ba{};
@@ -609,15 +612,16 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ba.nw = L.nw;
   ba.nbuckets = NCLASS;
   ba.counts = bcount.get();
+  ba.degs = bcount.get() + NCLASS;
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();
   bcount.zero();
   launch_bucket_count(ba, s_);
   launch_bucket_offsets(ba, s_);
-  std::vector<unsigned long long> hcnt(NCLASS);
+  std::vector<unsigned long long> hcnt(2 * NCLASS);
   std::vector<uint32_t> cnt(NCLASS), offs(NCLASS);
-  d2h(hcnt.data(), bcount.get(), NCLASS, s_);
+  d2h(hcnt.data(), bcount.get(), 2 * NCLASS, s_);
   sync(s_);
   uint32_t run = 0;
   for (int c = 0; c < NCLASS; ++c) {
@@ -640,7 +644,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ra.packed = packed_ ? 1 : 0;
   ra.fav = fav.get();
   ra.list = list.get();
-  rate_classes(ra, cnt.data(), offs.data(), nullptr, L.ew_kind);
+  rate_classes(ra, cnt.data(), offs.data(), hcnt.data() + NCLASS, L.ew_kind);
   // order light singletons by (favourite, hash, id)
   SingletonFlag sf{label, csize, L.nw, L.gid, dgd.get()};
   DBuf<uint32_t> pos(&pool_, s_, n + 1);

@@ -96,17 +96,19 @@ struct RateArgs {
 // (refinement: labels are the k blocks of each graph).
 constexpr uint32_t FEW_LABELS = 1024;
 
-// Lane-group split of one launch over the classes 0..5.
+// Split of one launch over the classes 0..GROUP_CLASSES-1 (lane groups and
+// the two smallest block classes).
+constexpr int GROUP_CLASSES = 8;
 struct GroupSplit {
-  uint32_t bstart[7];  // first block of each class (and the total)
-  uint32_t off[6];     // list (and candidate slot) offset of each class
-  uint32_t count[6];   // nodes of each class
+  uint32_t bstart[GROUP_CLASSES + 1];  // first block of each class (and the total)
+  uint32_t off[GROUP_CLASSES];         // list (and candidate slot) offset of each class
+  uint32_t count[GROUP_CLASSES];       // nodes of each class
 };
 
 // One rating launch for a degree class >= CLASS_BLOCK (a.count nodes of a.list).
 void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s);
-// The lane-group classes 0..5 in one launch; count/off per class, off relative
-// to a.list (and a.cands).
+// The classes 0..GROUP_CLASSES-1 in one launch; count/off per class, off
+// relative to a.list (and a.cands).
 void launch_rate_groups(int ew_kind, const RateArgs& a, const uint32_t* count,
                         const uint32_t* off, uint64_t degsum, hipStream_t s);
 // Degree class CLASS_GLOBAL: tables in global memory, split over many blocks.

@@ -150,7 +150,8 @@ LMGP_D int64_t group_sum(int64_t v) {
 // inserted once per group: in refinement and in settled clusters most
 // neighbours share that label, and their LDS atomics would all hit one slot.
 // Every lane-group class uses 1024 LDS slots per 256-thread block (256 / G
-// groups of 4G slots), so all six share one launch (k_rate_groups).
+// groups of 4G slots), and so do the two smallest block classes (one node
+// per block, 512 or 1024 slots): all eight share one launch (k_rate_groups).
 constexpr int GROUP_SLOTS = 1024;
 
 template <int G, int EWK>
@@ -230,45 +231,23 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   }
 }
 
-// The six lane-group classes in one launch: block b belongs to the class c
-// with split.bstart[c] <= b < split.bstart[c + 1]; each class has its own
-// list range (and candidate slots) at split.off[c].
-template <int EWK>
-__global__ __launch_bounds__(256) void k_rate_groups(RateArgs a, GroupSplit split) {
-  __shared__ uint32_t skey[GROUP_SLOTS];
-  __shared__ unsigned long long sval[GROUP_SLOTS];
-  const uint32_t b = blockIdx.x;
-  int c = 0;
-#pragma unroll
-  for (int q = 1; q < 6; ++q)
-    if (b >= split.bstart[q]) c = q;
-  RateArgs r = a;
-  r.list = a.list + split.off[c];
-  if (a.mode == MODE_LP) r.cands = a.cands + split.off[c];
-  r.count = split.count[c];
-  const uint64_t blk = b - split.bstart[c];
-  switch (c) {
-    case 0: rate_group<2, EWK>(r, skey, sval, blk); break;
-    case 1: rate_group<4, EWK>(r, skey, sval, blk); break;
-    case 2: rate_group<8, EWK>(r, skey, sval, blk); break;
-    case 3: rate_group<16, EWK>(r, skey, sval, blk); break;
-    case 4: rate_group<32, EWK>(r, skey, sval, blk); break;
-    default: rate_group<64, EWK>(r, skey, sval, blk); break;
-  }
-}
 
 // One 256-thread block per node of degree <= 2^(LOGT-1), LDS table of 2^LOGT
 // slots (load <= 1/2).  Own-label entries are summed in registers.
+struct BlockScratch {
+  Best sb[NWAVE];
+  int64_t so[NWAVE];
+  int64_t sm[NWAVE];
+};
+
 template <int EWK, int LOGT>
-__global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
+LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val,
+                       BlockScratch& bs, uint64_t idx) {
   constexpr int T = 1 << LOGT;
   constexpr int logt = LOGT;
-  __shared__ uint32_t key[T];
-  __shared__ unsigned long long val[T];
-  __shared__ Best sb[NWAVE];
-  __shared__ int64_t so[NWAVE];
-  __shared__ int64_t sm[NWAVE];
-  const uint64_t idx = blockIdx.x;
+  Best* sb = bs.sb;
+  int64_t* so = bs.so;
+  int64_t* sm = bs.sm;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
   if (!a.gd[graph_of(a.gid, u)].active) {
@@ -339,6 +318,44 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
       r_own = so[i] > r_own ? so[i] : r_own;
     }
     emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
+  }
+}
+
+template <int EWK, int LOGT>
+__global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
+  __shared__ uint32_t key[1 << LOGT];
+  __shared__ unsigned long long val[1 << LOGT];
+  __shared__ BlockScratch bs;
+  rate_block<EWK, LOGT>(a, key, val, bs, blockIdx.x);
+}
+
+// The classes 0..7 in one launch: block b belongs to the class c
+// with split.bstart[c] <= b < split.bstart[c + 1]; each class has its own
+// list range (and candidate slots) at split.off[c].
+template <int EWK>
+__global__ __launch_bounds__(256) void k_rate_groups(RateArgs a, GroupSplit split) {
+  __shared__ uint32_t skey[GROUP_SLOTS];
+  __shared__ unsigned long long sval[GROUP_SLOTS];
+  __shared__ BlockScratch bs;
+  const uint32_t b = blockIdx.x;
+  int c = 0;
+#pragma unroll
+  for (int q = 1; q < GROUP_CLASSES; ++q)
+    if (b >= split.bstart[q]) c = q;
+  RateArgs r = a;
+  r.list = a.list + split.off[c];
+  if (a.mode == MODE_LP) r.cands = a.cands + split.off[c];
+  r.count = split.count[c];
+  const uint64_t blk = b - split.bstart[c];
+  switch (c) {
+    case 0: rate_group<2, EWK>(r, skey, sval, blk); break;
+    case 1: rate_group<4, EWK>(r, skey, sval, blk); break;
+    case 2: rate_group<8, EWK>(r, skey, sval, blk); break;
+    case 3: rate_group<16, EWK>(r, skey, sval, blk); break;
+    case 4: rate_group<32, EWK>(r, skey, sval, blk); break;
+    case 5: rate_group<64, EWK>(r, skey, sval, blk); break;
+    case 6: rate_block<EWK, 9>(r, skey, sval, bs, blk); break;  // whole block per node
+    default: rate_block<EWK, 10>(r, skey, sval, bs, blk); break;
   }
 }
 
@@ -758,7 +775,7 @@ LMGP_D bool lds_add_bounded(unsigned long long* tab, uint32_t K, unsigned long l
 }
 
 template <int EWK>
-__global__ __launch_bounds__(1024) void k_hub_range(HubArgs h, uint32_t* overflow) {
+__global__ __launch_bounds__(1024) void k_hub_range(HubArgs h, uint32_t* ovl, int force_overflow) {
   constexpr int T = BIG_TABLE;
   constexpr int NW = 1024 / WAVE;
   __shared__ unsigned long long tab[T];
@@ -766,25 +783,38 @@ __global__ __launch_bounds__(1024) void k_hub_range(HubArgs h, uint32_t* overflo
   __shared__ int64_t so[NW];
   __shared__ int sfull;
   const RateArgs& a = h.a;
+  if (blockIdx.x >= h.soff[a.count]) return;  // the grid is an upper bound
   const uint32_t i = find_hub(h.soff, a.count, blockIdx.x);
   const uint32_t u = a.list[i];
   if (!hub_active(a, u)) return;
   const uint32_t P = (uint32_t)(h.soff[i + 1] - h.soff[i]);
   const uint32_t j = (uint32_t)(blockIdx.x - h.soff[i]);
   for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
-  if (threadIdx.x == 0) sfull = 0;
+  if (threadIdx.x == 0) sfull = force_overflow;
   __syncthreads();
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   bool ok = true;
-  for (uint64_t e = beg + threadIdx.x; e < end && ok; e += 1024) {
-    const uint32_t K = a.label[a.adj[e]];
-    if (label_range(K, P) != j) continue;
-    ok = lds_add_bounded<T>(tab, K, (unsigned long long)edge_w<EWK>(a.ew, e));
+  constexpr int U = 4;
+  for (uint64_t e0 = beg + threadIdx.x; e0 < end && ok; e0 += (uint64_t)U * 1024) {
+    uint32_t v[U], K[U];
+    int64_t w[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const uint64_t e = e0 + (uint64_t)q * 1024;
+      v[q] = e < end ? a.adj[e] : 0u;
+      w[q] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) K[q] = e0 + (uint64_t)q * 1024 < end ? a.label[v[q]] : EMPTY_KEY;
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+      if (ok && K[q] != EMPTY_KEY && label_range(K[q], P) == j)
+        ok = lds_add_bounded<T>(tab, K[q], (unsigned long long)w[q]);
   }
   if (!ok) sfull = 1;
   __syncthreads();
-  if (sfull) {
-    if (threadIdx.x == 0) atomicOr(overflow, 1u);
+  if (sfull) {  // recomputed by k_hub_repair
+    if (threadIdx.x == 0) ovl[1 + atomicAdd(&ovl[0], 1u)] = blockIdx.x;
     return;
   }
   const GraphDesc gd = a.gd[graph_of(a.gid, u)];
@@ -812,6 +842,93 @@ __global__ __launch_bounds__(1024) void k_hub_range(HubArgs h, uint32_t* overflo
       r_own = so[q] > r_own ? so[q] : r_own;
     }
     h.part[blockIdx.x] = Partial{best.r, best.h, best.K, 0, r_own};
+  }
+}
+
+// A second, independent split of a range's labels (repair passes).
+LMGP_D uint32_t label_subrange(uint32_t K, uint32_t R) {
+  uint32_t x = K * 0x85EBCA77u + 0x27D4EB2Fu;
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  return (uint32_t)(((uint64_t)x * R) >> 32);
+}
+
+// Ranges whose labels did not fit the LDS table: each is recomputed by one
+// block in R2 passes, pass q aggregating the labels of sub-range q of the
+// range (R2 doubles until every pass fits), so the result is exact without a
+// host round trip.  Ranges almost never overflow (about HUB_RANGE entries
+// for 16384 slots); the loop is for exactness.
+template <int EWK>
+__global__ __launch_bounds__(1024) void k_hub_repair(HubArgs h, const uint32_t* ovl) {
+  constexpr int T = BIG_TABLE;
+  constexpr int NW = 1024 / WAVE;
+  __shared__ unsigned long long tab[T];
+  __shared__ Best sb[NW];
+  __shared__ int64_t so[NW];
+  __shared__ int sfull;
+  const RateArgs& a = h.a;
+  const uint32_t nov = ovl[0];
+  for (uint32_t o = blockIdx.x; o < nov; o += gridDim.x) {
+    const uint32_t b = ovl[1 + o];
+    const uint32_t i = find_hub(h.soff, a.count, b);
+    const uint32_t u = a.list[i];
+    const uint32_t P = (uint32_t)(h.soff[i + 1] - h.soff[i]);
+    const uint32_t j = (uint32_t)(b - h.soff[i]);
+    const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+    const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+    const uint32_t own = a.label[u];
+    const int64_t cu = a.nw[u];
+    const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+    Best best{0, 0, 0};
+    int64_t r_own = 0;
+    for (uint32_t R2 = (uint32_t)ceil_div(end - beg, T / 2);; R2 *= 2) {
+      Best bb{0, 0, 0};
+      int64_t ro = 0;
+      bool failed = false;
+      for (uint32_t q2 = 0; q2 < R2 && !failed; ++q2) {
+        for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
+        if (threadIdx.x == 0) sfull = 0;
+        __syncthreads();
+        bool ok = true;
+        for (uint64_t e = beg + threadIdx.x; e < end && ok; e += 1024) {
+          const uint32_t K = a.label[a.adj[e]];
+          if (label_range(K, P) != j || label_subrange(K, R2) != q2) continue;
+          ok = lds_add_bounded<T>(tab, K, (unsigned long long)edge_w<EWK>(a.ew, e));
+        }
+        if (!ok) sfull = 1;
+        __syncthreads();
+        failed = sfull != 0;  // uniform: read after the barrier
+        if (!failed)
+          for (int s = threadIdx.x; s < T; s += 1024) {
+            const unsigned long long v = tab[s];
+            if (v != EMPTY_SLOT)
+              consider(a, (uint32_t)(v >> 32), (int64_t)(v & 0xFFFFFFFFull), own, cu, gd.cap,
+                       pre_u, gd.label_base, bb, ro);
+          }
+        __syncthreads();
+      }
+      if (!failed) {
+        best = bb;
+        r_own = ro;
+        break;
+      }
+    }
+    reduce_best<WAVE>(best, r_own);
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+      sb[w] = best;
+      so[w] = r_own;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < NW; ++q) {
+        if (better(sb[q].r, sb[q].h, sb[q].K, best)) best = sb[q];
+        r_own = so[q] > r_own ? so[q] : r_own;
+      }
+      h.part[b] = Partial{best.r, best.h, best.K, 0, r_own};
+    }
+    __syncthreads();
   }
 }
 
@@ -889,14 +1006,14 @@ void launch_groups_t(const RateArgs& a, const uint32_t* count, const uint32_t* o
                      uint64_t degsum, hipStream_t s) {
   GroupSplit split{};
   uint32_t blocks = 0, total = 0;
-  for (int c = 0; c < 6; ++c) {
+  for (int c = 0; c < GROUP_CLASSES; ++c) {
     split.bstart[c] = blocks;
     split.off[c] = off[c];
     split.count[c] = count[c];
-    blocks += grid_for(count[c], 256 / class_group(c));
+    blocks += c < CLASS_BLOCK ? grid_for(count[c], 256 / class_group(c)) : count[c];
     total += count[c];
   }
-  split.bstart[6] = blocks;
+  split.bstart[GROUP_CLASSES] = blocks;
   if (!blocks) return;
   const char* ph[3] = {"cl:", "rf:", "fv:"};
   ProfLaunch prof((std::string(ph[a.phase]) + "k_rate_groups<" + std::to_string(EWK) + ">").c_str(),
@@ -923,8 +1040,7 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   } else if (cls < CLASS_BIG) {
     const dim3 grid(a.count), blk(256);
     switch (cls - CLASS_BLOCK) {
-      case 0: hipExtLaunchKernelGGL(k_rate_block<EWK, 9>, grid, blk, 0, s, e0, e1, 0, a); break;
-      case 1: hipExtLaunchKernelGGL(k_rate_block<EWK, 10>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 0: case 1: throw InvalidArg("block classes 6, 7 are launched by launch_rate_groups");
       case 2: hipExtLaunchKernelGGL(k_rate_block<EWK, 11>, grid, blk, 0, s, e0, e1, 0, a); break;
       default: hipExtLaunchKernelGGL(k_rate_block<EWK, 12>, grid, blk, 0, s, e0, e1, 0, a); break;
     }
@@ -1027,8 +1143,9 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   const uint32_t c = ra.count;
   ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK, false).c_str(),
                  rate_bytes(EWK, ra.count, ra.degsum), s);
-  // LMGP_HUB_TABLES=global forces the global-table path (used by the tests to
-  // cover the fallback taken when a label range overflows its LDS table)
+  // LMGP_HUB_TABLES=global forces the chunked global-table path (taken when
+  // ratings do not fit 32 bits); =repair makes every label range report an
+  // overflow so that k_hub_repair computes all of them (both used by tests)
   const char* force = std::getenv("LMGP_HUB_TABLES");
   if (ra.few && ra.few <= FEW_LABELS && ra.mode == MODE_LP &&
       !(force && std::strcmp(force, "global") == 0)) {
@@ -1054,29 +1171,27 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   const bool ranges =
       ra.packed && ra.phase != 1 && !(force && std::strcmp(force, "global") == 0);
   if (ranges) {
-    // label-range partitioning in LDS; global tables only if a range overflows
+    // label-range partitioning in LDS; ranges that overflow their table are
+    // recomputed on the device (k_hub_repair), so no host round trip is needed
     DBuf<uint64_t> roff(&pool, s, c + 1);
     exclusive_scan(HubRanges{ra.xadj, ra.list}, c, roff.get(), true, pool, s);
-    uint64_t nr = 0;
-    HIP_CHECK(hipMemcpyAsync(&nr, roff.get() + c, 8, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    // sum over hubs of ceil(d / HUB_RANGE) <= degsum / HUB_RANGE + c
+    const uint64_t nr = ra.degsum / HUB_RANGE + c;
     DBuf<Partial> part(&pool, s, nr);
-    DBuf<uint32_t> ovf(&pool, s, 1);
-    ovf.zero();
+    DBuf<uint32_t> ovl(&pool, s, nr + 1);
+    device_zero(ovl.get(), sizeof(uint32_t), s);
     HubArgs h{};
     h.a = ra;
     h.soff = roff.get();
     h.part = part.get();
-    k_hub_range<EWK><<<(unsigned)nr, 1024, 0, s>>>(h, ovf.get());
+    const int force_ovf = force && std::strcmp(force, "repair") == 0;
+    k_hub_range<EWK><<<(unsigned)nr, 1024, 0, s>>>(h, ovl.get(), force_ovf);
     LAUNCH_CHECK();
-    uint32_t overflow = 0;
-    HIP_CHECK(hipMemcpyAsync(&overflow, ovf.get(), 4, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    if (!overflow) {
-      k_hub_final<<<grid_for(c, 64), 64, 0, s>>>(h);
-      LAUNCH_CHECK();
-      return;
-    }
+    k_hub_repair<EWK><<<64, 1024, 0, s>>>(h, ovl.get());
+    LAUNCH_CHECK();
+    k_hub_final<<<grid_for(c, 64), 64, 0, s>>>(h);
+    LAUNCH_CHECK();
+    return;
   }
   DBuf<uint64_t> toff(&pool, s, c + 1), coff(&pool, s, c + 1), soff(&pool, s, c + 1);
   exclusive_scan(HubTable{ra.xadj, ra.list}, c, toff.get(), true, pool, s);

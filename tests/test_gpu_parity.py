@@ -123,11 +123,12 @@ def test_hub_rows(lib, leaves):
     check_partition(lib, g, 2, 0.03, 3)
 
 
-@pytest.mark.parametrize("tables", ["ranges", "global"])
+@pytest.mark.parametrize("tables", ["ranges", "global", "repair"])
 def test_hub_rating_paths(lib, tables, monkeypatch):
-    # degree 20000 > 8192: label-range LDS rating, or forced global tables
-    if tables == "global":
-        monkeypatch.setenv("LMGP_HUB_TABLES", "global")
+    # degree 20000 > 8192: label-range LDS rating, forced global tables, or
+    # every range recomputed by the overflow repair passes
+    if tables != "ranges":
+        monkeypatch.setenv("LMGP_HUB_TABLES", tables)
     rng = np.random.default_rng(9)
     s = T.star(20000)
     a, b, _ = T.edges_of(s)
