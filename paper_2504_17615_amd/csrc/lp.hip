@@ -262,7 +262,7 @@ LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val
   __syncthreads();
   const uint32_t own = a.label[u];
   int64_t acc = 0;
-  constexpr int U = 4;  // entries per thread whose loads are issued together
+  constexpr int U = 8;  // entries per thread whose loads are issued together
   for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * 256) {
     uint32_t v[U], K[U];
     int64_t w[U];
@@ -290,7 +290,7 @@ LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
   int64_t r_own = 0;
-  constexpr int SB = 4;  // slots per thread whose W gathers are issued together
+  constexpr int SB = 8;  // slots per thread whose W gathers are issued together
   for (int s0 = threadIdx.x; s0 < T; s0 += SB * 256) {
     uint32_t Ks[SB];
     int64_t wk[SB];
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   __syncthreads();
   const uint32_t own = a.label[u];
   int64_t acc = 0;
-  constexpr int U = 4;  // entries per thread whose loads are issued together
+  constexpr int U = 8;  // entries per thread whose loads are issued together
   for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * 1024) {
     uint32_t v[U], K[U];
     int64_t w[U];
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
   int64_t r_own = 0;
-  constexpr int SB = 4;  // slots per thread whose W gathers are issued together
+  constexpr int SB = 8;  // slots per thread whose W gathers are issued together
   for (int s0 = threadIdx.x; s0 < T; s0 += SB * 1024) {
     unsigned long long v[SB];
     int64_t wk[SB];
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a) {
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
   const uint32_t own = a.label[u];
   int64_t acc = 0;
-  constexpr int U = 4;
+  constexpr int U = 8;
   for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * NT) {
     uint32_t v[U], K[U];
     int64_t w[U];
@@ -1589,13 +1589,21 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
     const int64_t room = a.gd[cand_graph(a, u0)].cap - a.W[t];
     // range of the keys: digits above the highest differing bit are shared
     uint64_t mnh = ~0ull, mxh = 0, mnl = ~0ull, mxl = 0;
-    for (uint32_t i = threadIdx.x; i < size; i += SEG_NT) {
-      uint64_t h, l;
-      cand_key(a.cands[in[i]], h, l);
-      mnh = h < mnh ? h : mnh;
-      mxh = h > mxh ? h : mxh;
-      mnl = l < mnl ? l : mnl;
-      mxl = l > mxl ? l : mxl;
+    constexpr int U = 8;  // candidates per thread whose loads are issued together
+    for (uint32_t i0 = threadIdx.x; i0 < size; i0 += U * SEG_NT) {
+      uint32_t ci[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) ci[q] = i0 + q * SEG_NT < size ? in[i0 + q * SEG_NT] : ~0u;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (ci[q] == ~0u) continue;
+        uint64_t h, l;
+        cand_key(a.cands[ci[q]], h, l);
+        mnh = h < mnh ? h : mnh;
+        mxh = h > mxh ? h : mxh;
+        mnl = l < mnl ? l : mnl;
+        mxl = l > mxl ? l : mxl;
+      }
     }
     mnh = block_min<NW>(mnh, sred);
     mxh = block_max<NW>(mxh, sred);
@@ -1612,37 +1620,56 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
       if (threadIdx.x == 0) s_cnt = 0;
       __syncthreads();
       const int sh = 8 * (pos & 7);
-      for (uint32_t i = threadIdx.x; i < cur; i += SEG_NT) {
-        const Cand c = a.cands[in[i]];
-        uint64_t h, l;
-        cand_key(c, h, l);
-        const uint32_t d = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
-        atomicAdd(&whist[d], (unsigned long long)a.nw[c.u]);
+      for (uint32_t i0 = threadIdx.x; i0 < cur; i0 += U * SEG_NT) {
+        uint32_t ci[U], d[U];
+        int64_t w[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) ci[q] = i0 + q * SEG_NT < cur ? in[i0 + q * SEG_NT] : ~0u;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (ci[q] == ~0u) continue;
+          const Cand c = a.cands[ci[q]];
+          uint64_t h, l;
+          cand_key(c, h, l);
+          d[q] = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
+          w[q] = a.nw[c.u];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if (ci[q] != ~0u) atomicAdd(&whist[d[q]], (unsigned long long)w[q]);
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int64_t cum = 0;
-        int dsel = 255;
-        for (int d = 0; d < 256; ++d) {
-          const int64_t w = (int64_t)whist[d];
-          if (cum + w > rem) {
-            dsel = d;
-            break;
-          }
-          cum += w;
+      {
+        // the threshold digit: the first one whose cumulative weight exceeds
+        // rem (one block scan over the 256 bins; the survivors always weigh
+        // more than rem, so exactly one digit qualifies)
+        const uint64_t w = threadIdx.x < 256 ? whist[threadIdx.x] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan<uint64_t, NW>(w, sred, tot);
+        if (threadIdx.x < 256 && (int64_t)ex <= rem && (int64_t)(ex + w) > rem) {
+          s_digit = (int)threadIdx.x;
+          s_rem = rem - (int64_t)ex;
         }
-        s_digit = dsel;
-        s_rem = rem - cum;
       }
       __syncthreads();
       const uint32_t dsel = (uint32_t)s_digit;
-      for (uint32_t i = threadIdx.x; i < cur; i += SEG_NT) {
-        const uint32_t ci = in[i];
-        uint64_t h, l;
-        cand_key(a.cands[ci], h, l);
-        const uint32_t d = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
-        if (d < dsel) a.adm[ci] = 1;
-        else if (d == dsel) out[atomicAdd(&s_cnt, 1u)] = ci;
+      for (uint32_t i0 = threadIdx.x; i0 < cur; i0 += U * SEG_NT) {
+        uint32_t ci[U], d[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) ci[q] = i0 + q * SEG_NT < cur ? in[i0 + q * SEG_NT] : ~0u;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (ci[q] == ~0u) continue;
+          uint64_t h, l;
+          cand_key(a.cands[ci[q]], h, l);
+          d[q] = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (ci[q] == ~0u) continue;
+          if (d[q] < dsel) a.adm[ci[q]] = 1;
+          else if (d[q] == dsel) out[atomicAdd(&s_cnt, 1u)] = ci[q];
+        }
       }
       __syncthreads();
       rem = s_rem;
