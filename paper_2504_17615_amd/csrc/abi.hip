@@ -82,8 +82,13 @@ __global__ void k_check_entries(const uint64_t* xadj, const uint32_t* adj, const
   else if (v == u) bad |= BAD_LOOP;
   const int64_t w = edge_w<EWK>(ew, e);
   if (w <= 0) bad |= BAD_WEIGHT;
+  if (!(bad & BAD_ID) && e > xadj[u] && adj[e - 1] >= v) {
+    // an error in full validation; otherwise only recorded (the initial
+    // bisection may walk ascending rows faster)
+    if (full) bad |= BAD_ORDER;
+    else atomicOr(&err[1], 1u);
+  }
   if (full && !(bad & BAD_ID)) {
-    if (e > xadj[u] && adj[e - 1] >= v) bad |= BAD_ORDER;
     // reverse entry (v, u) with the same weight
     uint64_t lo = xadj[v], hi = xadj[v + 1];
     bool found = false;
@@ -204,7 +209,7 @@ void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
       if (v.nnz) HIP_CHECK(hipMemcpyAsync(g.ew64.get(), v.adjwgt, v.nnz * 8, kind, s));
     }
   }
-  DBuf<uint32_t> err(&pool, s, 1);
+  DBuf<uint32_t> err(&pool, s, 2);  // [0] error bits, [1] some row not ascending
   err.zero();
   // node weights (always materialised as int64)
   DBuf<uint8_t> vtmp;
@@ -264,12 +269,15 @@ void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
     LAUNCH_CHECK();
   }
   int64_t hw = 0;
+  uint32_t unsorted = 0;
   HIP_CHECK(hipMemcpyAsync(&bad, err.get(), 4, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&unsorted, err.get() + 1, 4, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(&g.cV, tot.get(), 8, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(&hw, tot.get() + 1, 8, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   if (bad) throw InvalidArg(describe(bad));
   g.wtot = g.ew_kind == EW_UNIT ? v.nnz : (uint64_t)hw;
+  g.rows_sorted = unsorted == 0;
 }
 
 }  // namespace lmgp

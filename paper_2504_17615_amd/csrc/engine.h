@@ -17,6 +17,7 @@ struct InputGraph {
   int ew_kind = EW_UNIT;
   int64_t cV = 0;
   uint64_t wtot = 0;  // sum of the weights of all entries (bounds every rating)
+  bool rows_sorted = false;  // every row strictly ascending (checked at creation)
   DBuf<uint64_t> xadj;
   DBuf<uint32_t> adj;
   DBuf<int32_t> ew32;
@@ -77,7 +78,8 @@ class Engine {
   // Initial partitioning, refinement and evaluation; writes blocks.
   void partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device);
   std::vector<std::unique_ptr<Level>>& levels() { return levels_; }
-  // Sorts the rows of level i in place if they are not sorted yet.
+  // Sorts the rows of coarse level i (i >= 1) in place if they are not
+  // sorted yet; the input level keeps its given order.
   void ensure_sorted(size_t i);
 
   int64_t t_coarsen_ns = 0, t_initial_ns = 0, t_refine_ns = 0;
@@ -110,9 +112,11 @@ class Engine {
 };
 
 // Recursive bipartitioning of a small host graph (coarsest level).
-void initial_partition_host(uint64_t n, const std::vector<uint64_t>& xadj,
-                            const std::vector<uint32_t>& adj, const std::vector<int64_t>& nw,
-                            uint32_t k, uint64_t seed, uint64_t level, std::vector<uint32_t>& block);
+// xadj holds n + 1 global entry offsets (first = e0), adj global neighbour
+// ids (minus n0 = local); `sorted`: every row is ascending.
+void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* adj,
+                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, uint32_t k,
+                            uint64_t seed, uint64_t level, std::vector<uint32_t>& block);
 
 lmgp_params default_params();
 void check_params(const lmgp_params& p);

@@ -288,6 +288,8 @@ void Engine::build_union(std::vector<Job>& jobs) {
   levels_.clear();
   auto L = std::make_unique<Level>();
   const uint32_t B = (uint32_t)jobs.size();
+  L->sorted = true;
+  for (auto& jb : jobs) L->sorted &= jb.g->rows_sorted;
   L->graphs.resize(B);
   L->nbase.assign(B + 1, 0);
   L->ebase.assign(B + 1, 0);
@@ -735,7 +737,8 @@ void Engine::cluster(Level& L, std::vector<Job>& jobs, std::vector<uint8_t>& act
 
 void Engine::ensure_sorted(size_t i) {
   Level& L = *levels_.at(i);
-  if (L.sorted) return;
+  // the input level keeps the caller's row order (the oracle's order too)
+  if (L.sorted || i == 0) return;
   DBuf<uint32_t> adj, src;
   DBuf<int64_t> ew;
   sort_rows(L.n, L.nnz, L.xadj, L.adj, L.ew, L.ew_kind, packed_ ? 1 : 0, adj, ew, src, pool_, s_);
@@ -925,6 +928,18 @@ void Engine::coarsen(std::vector<Job>& jobs) {
 }
 
 // ------------------------------------------------------------ partitioning --
+namespace {
+struct IpHostBuffers {
+  std::vector<uint64_t> xadj;
+  std::vector<uint32_t> adj;
+  std::vector<int64_t> nw;
+};
+IpHostBuffers& ip_host_buffers() {
+  thread_local IpHostBuffers b;
+  return b;
+}
+}  // namespace
+
 void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device) {
   const uint32_t NJ = (uint32_t)jobs.size();
   std::vector<uint64_t> kbase(NJ + 1, 0);
@@ -940,16 +955,18 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     uint32_t b = 0;
     while (L.graphs[b] != g) ++b;
     const uint64_t n0 = L.nbase[b], n1 = L.nbase[b + 1], e0 = L.ebase[b], e1 = L.ebase[b + 1];
-    std::vector<uint64_t> xadj(n1 - n0 + 1);
-    std::vector<uint32_t> adj(e1 - e0);
-    std::vector<int64_t> nw(n1 - n0);
-    d2h(xadj.data(), L.xadj + n0, n1 - n0 + 1, s_);
-    d2h(adj.data(), L.adj + e0, e1 - e0, s_);
-    d2h(nw.data(), L.nw + n0, n1 - n0, s_);
+    // host copies in buffers kept by the calling thread (no page faults after
+    // the first call); ids and offsets stay global, the bisection subtracts
+    IpHostBuffers& hb = ip_host_buffers();
+    if (hb.xadj.size() < n1 - n0 + 1) hb.xadj.resize(n1 - n0 + 1);
+    if (hb.adj.size() < e1 - e0) hb.adj.resize(e1 - e0);
+    if (hb.nw.size() < n1 - n0) hb.nw.resize(n1 - n0);
+    d2h(hb.xadj.data(), L.xadj + n0, n1 - n0 + 1, s_);
+    d2h(hb.adj.data(), L.adj + e0, e1 - e0, s_);
+    d2h(hb.nw.data(), L.nw + n0, n1 - n0, s_);
     sync(s_);
-    for (auto& x : xadj) x -= e0;
-    for (auto& y : adj) y -= (uint32_t)n0;
-    initial_partition_host(n1 - n0, xadj, adj, nw, jobs[g].k, jobs[g].seed, top + 1, ip[g]);
+    initial_partition_host(n1 - n0, hb.xadj.data(), hb.adj.data(), hb.nw.data(), e0, n0, L.sorted,
+                           jobs[g].k, jobs[g].seed, top + 1, ip[g]);
     for (auto& x : ip[g]) x += (uint32_t)kbase[g];
   }
   t_initial_ns = tm.stop_ns();
@@ -1032,9 +1049,11 @@ namespace {
 
 struct IpState {
   uint64_t n;
-  const std::vector<uint64_t>* xadj;
-  const std::vector<uint32_t>* adj;
-  const std::vector<int64_t>* nw;
+  const uint64_t* xadj;  // entry offsets, relative to e0
+  const uint32_t* adj;   // neighbour ids, relative to n0
+  const int64_t* nw;
+  uint64_t e0, n0;
+  bool sorted;           // rows ascending: unvisited nodes may be walked in id order
   uint64_t seed, level;
   std::vector<uint32_t>* block;
   // stamps: sibling subproblems own disjoint node sets, so they may run on
@@ -1056,7 +1075,7 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   const auto rl = std::memory_order_relaxed;
   const uint32_t k1 = (kS + 1) / 2;
   int64_t cS = 0;
-  for (uint32_t v : S) cS += (*st.nw)[v];
+  for (uint32_t v : S) cS += st.nw[v];
   const int64_t T1 = (int64_t)(((u128)cS * k1 + kS - 1) / kS);
   const uint32_t my = st.stamp.fetch_add(1) + 1;
   const uint64_t pre = chain(st.seed, TAG_IP, {st.level, (uint64_t)off, (uint64_t)kS});
@@ -1067,6 +1086,21 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   }
   std::sort(order.begin(), order.end());
   for (uint32_t v : S) st.part1[v] = 0;
+  // Unvisited members of S as a bitset over node ids.  With sorted rows,
+  // walking it in ascending order and keeping the nodes found in v's row (by
+  // binary search) enqueues exactly what a scan of the row would, in the same
+  // order; it is used when few unvisited nodes remain and v's row is long
+  // (dense coarse graphs).
+  const uint64_t nwords = st.sorted ? (st.n + 63) / 64 : 0;
+  std::vector<uint64_t> unv(nwords, 0);
+  if (st.sorted)
+    for (uint32_t v : S) unv[v >> 6] |= 1ull << (v & 63);
+  uint64_t nunv = S.size();
+  auto visit = [&](uint32_t x) {
+    st.visited[x].store(my, rl);
+    if (st.sorted) unv[x >> 6] &= ~(1ull << (x & 63));
+    --nunv;
+  };
   std::vector<uint32_t> queue;
   queue.reserve(S.size());
   int64_t w1 = 0;
@@ -1076,18 +1110,36 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
     if (ptr == order.size()) break;
     queue.clear();
     size_t head = 0;
-    st.visited[order[ptr].second].store(my, rl);
+    visit(order[ptr].second);
     queue.push_back(order[ptr].second);
     while (head < queue.size() && w1 < T1) {
       const uint32_t v = queue[head++];
-      if (w1 + (*st.nw)[v] > T1) continue;
+      if (w1 + st.nw[v] > T1) continue;
       st.part1[v] = 1;
-      w1 += (*st.nw)[v];
-      for (uint64_t e = (*st.xadj)[v]; e < (*st.xadj)[v + 1]; ++e) {
-        const uint32_t x = (*st.adj)[e];
-        if (st.inset[x].load(rl) == my && st.visited[x].load(rl) != my) {
-          st.visited[x].store(my, rl);
-          queue.push_back(x);
+      w1 += st.nw[v];
+      if (nunv == 0) continue;  // nothing left to enqueue
+      const uint32_t* rb = st.adj + (st.xadj[v] - st.e0);
+      const uint32_t* re = st.adj + (st.xadj[v + 1] - st.e0);
+      const uint64_t deg = (uint64_t)(re - rb);
+      if (st.sorted && nwords + 16 * nunv < deg) {
+        for (uint64_t w = 0; w < nwords; ++w) {
+          uint64_t bits = unv[w];
+          while (bits) {
+            const uint32_t x = (uint32_t)(w * 64 + __builtin_ctzll(bits));
+            bits &= bits - 1;
+            if (std::binary_search(rb, re, (uint32_t)(x + st.n0))) {
+              visit(x);
+              queue.push_back(x);
+            }
+          }
+        }
+      } else {
+        for (const uint32_t* p = rb; p < re; ++p) {
+          const uint32_t x = *p - (uint32_t)st.n0;
+          if (st.inset[x].load(rl) == my && st.visited[x].load(rl) != my) {
+            visit(x);
+            queue.push_back(x);
+          }
         }
       }
     }
@@ -1108,14 +1160,17 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
 
 }  // namespace
 
-void initial_partition_host(uint64_t n, const std::vector<uint64_t>& xadj,
-                            const std::vector<uint32_t>& adj, const std::vector<int64_t>& nw,
-                            uint32_t k, uint64_t seed, uint64_t level, std::vector<uint32_t>& block) {
+void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* adj,
+                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, uint32_t k,
+                            uint64_t seed, uint64_t level, std::vector<uint32_t>& block) {
   IpState st;
   st.n = n;
-  st.xadj = &xadj;
-  st.adj = &adj;
-  st.nw = &nw;
+  st.xadj = xadj;
+  st.adj = adj;
+  st.nw = nw;
+  st.e0 = e0;
+  st.n0 = n0;
+  st.sorted = sorted;
   st.seed = seed;
   st.level = level;
   block.assign(n, 0);

@@ -175,6 +175,35 @@ def test_hub_rows_heavy_weights(lib):
     check_partition(lib, g, 2, 0.03, 3)
 
 
+def _shuffle_rows(g, rng):
+    adj = g.adjncy.copy()
+    w = None if g.adjwgt is None else g.adjwgt.copy()
+    for u in range(g.n):
+        a, b = int(g.xadj[u]), int(g.xadj[u + 1])
+        perm = rng.permutation(b - a) + a
+        adj[a:b] = g.adjncy[perm]
+        if w is not None:
+            w[a:b] = g.adjwgt[perm]
+    return T.G(g.n, g.xadj.copy(), adj, w, g.vwgt)
+
+
+@pytest.mark.parametrize("n", [300, 5000])
+def test_unsorted_input_rows(lib, n):
+    # rows in arbitrary order (accepted without full validation): the
+    # breadth-first bisection visits neighbours in the given row order, which
+    # the oracle follows too; n = 300 with k = 2 partitions the input level
+    # itself, n = 5000 coarsens first (coarse rows are built sorted)
+    rng = np.random.default_rng(n)
+    g = _shuffle_rows(T.random_graph(n, 6 * n, rng, wmax=5, vmax=3), rng)
+    print(f"unsorted rows n={n}", flush=True)
+    dg = lib.create_graph(g)
+    blocks, res = dg.partition(2, 0.03, 7, host_out=True)
+    ob, ores, _ = O.partition(g, 2, 0.03, 7)
+    assert np.array_equal(blocks, ob)
+    assert res["cut"] == ores["cut"]
+    dg.close()
+
+
 def test_tiny_and_degenerate(lib):
     check_partition(lib, T.path(2), 2, 0.03, 1)
     check_partition(lib, T.from_edges(5, [(0, 1)]), 3, 0.03, 1)  # isolated nodes
