@@ -84,7 +84,14 @@ typedef struct {
   uint32_t tau_e_num, tau_e_den; /* edge threshold tau_e = 1/2 (Sec. 4.2, Sec. 5.1)  */
   uint32_t tau_d_num, tau_d_den; /* density threshold tau_d = 1/2                   */
   uint32_t rho_num, rho_den;     /* minimum reduction factor rho = 4               */
-  uint32_t sampler;              /* 0 = weighted threshold sampling, 2 = off       */
+  uint32_t sampler;              /* Sec. 4.2 sparsifier: 0 = weighted threshold
+                                  * sampling, the edges of weight omega_t sampled to
+                                  * exactly m_hat; 1 = uniform random sampling, each
+                                  * edge kept with probability m_hat/|E'|; 2 = off;
+                                  * 3 = weighted threshold sampling with each edge of
+                                  * weight omega_t kept with probability
+                                  * (m_hat - |E'^>|)/|E'^=|.  Coins are
+                                  * H(seed, SPARS, level, a, b) as 64-bit fractions. */
   uint32_t clim;                 /* C = 160: U = c(V)/(C k), stop at C k nodes     */
   uint32_t shrink_num, shrink_den; /* node reduction cap 5/2 = 2.5x (Sec. 4.3)     */
   uint32_t lp_rounds;            /* LP clustering rounds, 5                        */

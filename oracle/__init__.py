@@ -74,7 +74,7 @@ def _load():
         "or_contract": ([vp, vp, vp], vp),
         "or_edge_budget": ([u64, u64, u64, vp], u64),
         "or_budget_triggers": ([u64, u64, vp], ctypes.c_int),
-        "or_sparsify": ([vp, u64, u64, u64, vp], vp),
+        "or_sparsify": ([vp, u64, u64, u64, u32, vp], vp),
         "or_coarsen": ([vp, u32, u64, vp], vp),
         "or_h_levels": ([vp], u32),
         "or_h_info": ([vp, u32, vp], None),
@@ -211,10 +211,12 @@ def budget_triggers(m_prime, m_hat, p: Optional[Params] = None) -> bool:
     return bool(_load().or_budget_triggers(m_prime, m_hat, ctypes.byref(p)))
 
 
-def sparsify(g, m_hat, seed, level):
+def sparsify(g, m_hat, seed, level, sampler=0):
+    """sampler 0: exact-size threshold sampling, 1: uniform random sampling,
+    3: threshold sampling with independent coins for the edges of weight w_t."""
     v = _View(g)
     st = np.zeros(3, np.int64)
-    h = _load().or_sparsify(v.ref, m_hat, seed, level, st.ctypes.data)
+    h = _load().or_sparsify(v.ref, m_hat, seed, level, sampler, st.ctypes.data)
     return _take_graph(h), dict(w_t=int(st[0]), n_gt=int(st[1]), n_eq=int(st[2]))
 
 

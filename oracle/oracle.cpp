@@ -101,7 +101,9 @@ typedef struct {
   uint32_t tau_e_num, tau_e_den;  // edge threshold tau_e (1/2)
   uint32_t tau_d_num, tau_d_den;  // density threshold tau_d (1/2)
   uint32_t rho_num, rho_den;      // minimum reduction factor rho (4)
-  uint32_t sampler;               // 0 = weighted threshold sampling, 2 = off
+  uint32_t sampler;               // 0 = weighted threshold sampling (exact size), 1 = uniform
+                                  // random sampling, 2 = off, 3 = weighted threshold sampling
+                                  // with independent coins for the edges of weight omega_t
   uint32_t clim;                  // C in U = c(V)/(C k) and the stop size C k (160)
   uint32_t shrink_num, shrink_den;  // node reduction cap 5/2 (2.5x)
   uint32_t lp_rounds, ref_rounds, subrounds;  // 5, 5, 4
@@ -460,7 +462,16 @@ struct SparsStats {
   uint64_t n_gt = 0, n_eq = 0;
 };
 
-Graph sparsify(const Graph& g, uint64_t m_hat, uint64_t seed, uint64_t level, SparsStats* st) {
+// Sec. 4.2, Uniform Random Sampling: every edge is kept independently with
+// probability m_hat / |E'|; the mode with coins for E'^= keeps each edge of
+// weight omega_t with probability (m_hat - |E'^>|) / |E'^=| (the paper's
+// literal rule).  Reading: the coin of edge {a<b} is H(SPARS, level, a, b)
+// read as a uniform 64-bit fraction, and the edge is kept iff
+// floor(H * N / 2^64) < r, i.e. with probability r / N up to 2^-64.
+uint64_t mulhi64(uint64_t a, uint64_t b) { return (uint64_t)(((u128)a * b) >> 64); }
+
+Graph sparsify(const Graph& g, uint64_t m_hat, uint64_t seed, uint64_t level, uint32_t sampler,
+               SparsStats* st) {
   struct E {
     uint32_t a, b;
     int64_t w;
@@ -471,7 +482,13 @@ Graph sparsify(const Graph& g, uint64_t m_hat, uint64_t seed, uint64_t level, Sp
       if (a < g.adj[e]) edges.push_back({(uint32_t)a, g.adj[e], g.ew[e]});
   std::vector<uint8_t> keep(edges.size(), 0);
   SparsStats s;
-  if (m_hat > 0 && !edges.empty()) {
+  if (sampler == 1) {
+    const uint64_t mp = edges.size();
+    for (size_t i = 0; i < edges.size(); ++i) {
+      const uint64_t h = H(seed, TAG_SPARS, {level, (uint64_t)edges[i].a, (uint64_t)edges[i].b});
+      if (mulhi64(h, mp) < m_hat) keep[i] = 1;
+    }
+  } else if (m_hat > 0 && !edges.empty()) {
     std::vector<int64_t> ws(edges.size());
     for (size_t i = 0; i < edges.size(); ++i) ws[i] = edges[i].w;
     std::nth_element(ws.begin(), ws.begin() + (m_hat - 1), ws.end(), std::greater<int64_t>());
@@ -487,9 +504,14 @@ Graph sparsify(const Graph& g, uint64_t m_hat, uint64_t seed, uint64_t level, Sp
       }
     }
     uint64_t r = m_hat - s.n_gt;
-    // edge indices increase with (a, b), so (hash, index) orders by (hash, a, b)
-    std::sort(eq.begin(), eq.end());
-    for (uint64_t j = 0; j < r; ++j) keep[eq[j].second] = 1;
+    if (sampler == 3) {
+      for (const auto& q : eq)
+        if (mulhi64(q.first, s.n_eq) < r) keep[q.second] = 1;
+    } else {
+      // edge indices increase with (a, b), so (hash, index) orders by (hash, a, b)
+      std::sort(eq.begin(), eq.end());
+      for (uint64_t j = 0; j < r; ++j) keep[eq[j].second] = 1;
+    }
   }
   if (st) *st = s;
   Graph out;
@@ -613,7 +635,7 @@ Hierarchy coarsen(const Graph& g1, uint32_t k, uint64_t seed, const or_params& p
     li.nclusters_lp = st.nclusters_lp;
     if (budget_triggers(li.m_prime, li.m_hat, p)) {
       SparsStats ss;
-      Graph gs = sparsify(gp, li.m_hat, seed, i + 1, &ss);
+      Graph gs = sparsify(gp, li.m_hat, seed, i + 1, p.sampler, &ss);
       li.triggered = 1;
       li.w_t = ss.w_t;
       li.n_gt = ss.n_gt;
@@ -815,13 +837,14 @@ int or_budget_triggers(uint64_t m_prime, uint64_t m_hat, const or_params* p) {
   return budget_triggers(m_prime, m_hat, *p) ? 1 : 0;
 }
 
-// Sparsify to m_hat; stats_out = {w_t, n_gt, n_eq}.
+// Sparsify to m_hat with the given sampler (0, 1 or 3); stats_out = {w_t,
+// n_gt, n_eq} (zeros for uniform sampling).
 void* or_sparsify(const or_graph* v, uint64_t m_hat, uint64_t seed, uint64_t level,
-                  int64_t* stats_out) {
+                  uint32_t sampler, int64_t* stats_out) {
   Graph g = from_view(v);
   SparsStats s;
   Handle* h = new Handle();
-  h->g = sparsify(g, m_hat, seed, level, &s);
+  h->g = sparsify(g, m_hat, seed, level, sampler, &s);
   stats_out[0] = s.w_t;
   stats_out[1] = (int64_t)s.n_gt;
   stats_out[2] = (int64_t)s.n_eq;

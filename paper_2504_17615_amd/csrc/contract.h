@@ -66,6 +66,7 @@ struct SparsGraph {
   uint64_t e0 = 0, e1 = 0;   // entry range of the graph
   uint64_t m_hat = 0;
   bool triggered = false;
+  uint32_t sampler = 0;      // 0 exact-size threshold, 1 uniform, 3 threshold with coins
   uint64_t pre = 0;          // H(seed, SPARS, level) prefix
   // outputs
   int64_t w_t = 0;

@@ -275,7 +275,8 @@ lmgp_params default_params() {
 
 void check_params(const lmgp_params& p) {
   if (!p.tau_e_den || !p.tau_d_den || !p.rho_den) throw InvalidArg("zero denominator in params");
-  if (p.sampler != 0 && p.sampler != 2) throw InvalidArg("sampler must be 0 (threshold) or 2 (off)");
+  if (p.sampler > 3)
+    throw InvalidArg("sampler must be 0 (threshold), 1 (uniform), 2 (off) or 3 (threshold, coins)");
   if (!p.clim) throw InvalidArg("clim must be positive");
   if (!p.shrink_num) throw InvalidArg("shrink_num must be positive");
   if (!p.subrounds || p.subrounds > 32) throw InvalidArg("subrounds must be in [1, 32]");
@@ -877,6 +878,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
       sg.e1 = C->ebase[c + 1];
       sg.m_hat = m_hat;
       sg.triggered = trig;
+      sg.sampler = p_.sampler;
       sg.pre = chain(jb.seed, TAG_SPARS, {(uint64_t)depth + 1});
       any_trig |= trig;
       ++c;

@@ -100,8 +100,12 @@ struct SparsDesc {
   int64_t w_t;
   uint64_t tkey;
   uint32_t ta, tb;
-  uint32_t mode;  // 0 keep all, 1 keep w >= w_t, 2 keep w > w_t and E^= up to (tkey, ta, tb)
+  // 0 keep all, 1 keep w >= w_t, 2 keep w > w_t and E^= up to (tkey, ta, tb),
+  // 3 keep iff coin < coin_r (uniform sampling), 4 keep w > w_t and E^= edges
+  // whose coin < coin_r; coin = floor(H(SPARS, level, a, b) * coin_n / 2^64)
+  uint32_t mode;
   uint32_t pad;
+  uint64_t coin_n, coin_r;
 };
 
 __global__ void k_keep(const uint32_t* src, const uint32_t* adj, const int64_t* ew,
@@ -110,15 +114,18 @@ __global__ void k_keep(const uint32_t* src, const uint32_t* adj, const int64_t* 
   if (e >= nnz) return;
   const uint32_t u = src[e], v = adj[e];
   const SparsDesc d = sd[graph_of(gid, u)];
+  const uint32_t a = (u < v ? u : v) - (uint32_t)d.node_base;
+  const uint32_t b = (u < v ? v : u) - (uint32_t)d.node_base;
   uint8_t k = 1;
-  if (d.mode != 0) {
+  if (d.mode == 3) {
+    k = __umul64hi(edge_key(d.pre, a, b), d.coin_n) < d.coin_r;
+  } else if (d.mode != 0) {
     const int64_t w = ew[e];
     if (w > d.w_t) k = 1;
     else if (w < d.w_t) k = 0;
     else if (d.mode == 1) k = 1;
+    else if (d.mode == 4) k = __umul64hi(edge_key(d.pre, a, b), d.coin_n) < d.coin_r;
     else {
-      const uint32_t a = (u < v ? u : v) - (uint32_t)d.node_base;
-      const uint32_t b = (u < v ? v : u) - (uint32_t)d.node_base;
       const uint64_t key = edge_key(d.pre, a, b);
       k = key < d.tkey || (key == d.tkey && (a < d.ta || (a == d.ta && b <= d.tb)));
     }
@@ -166,8 +173,16 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
   for (size_t g = 0; g < B; ++g) {
     SparsGraph& sg = graphs[g];
     SparsDesc& d = desc[g];
-    d = SparsDesc{sg.node_base, sg.pre, 0, 0, 0, 0, 0, 0};
+    d = SparsDesc{sg.node_base, sg.pre, 0, 0, 0, 0, 0, 0, 0, 0};
     if (!sg.triggered) continue;
+    if (sg.sampler == 1) {  // uniform: every edge keeps with probability m_hat / |E'|
+      d.mode = 3;
+      d.coin_n = (sg.e1 - sg.e0) / 2;
+      d.coin_r = sg.m_hat;
+      sg.w_t = 0;
+      sg.n_gt = sg.n_eq = 0;
+      continue;
+    }
     if (sg.m_hat == 0) {  // keep nothing: threshold above every weight
       d.mode = 1;
       d.w_t = INT64_MAX;
@@ -214,6 +229,12 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
     const uint64_t r = sg.m_hat - sg.n_gt;
     if (r == sg.n_eq) {
       d.mode = 1;
+      continue;
+    }
+    if (sg.sampler == 3) {  // independent coins for the edges of weight w_t
+      d.mode = 4;
+      d.coin_n = sg.n_eq;
+      d.coin_r = r;
       continue;
     }
     // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t

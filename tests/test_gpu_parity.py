@@ -107,6 +107,15 @@ def test_subround_counts(lib, subrounds):
     check_partition(lib, g, k, eps, seed, subrounds=subrounds)
 
 
+@pytest.mark.parametrize("sampler", [1, 3])
+@pytest.mark.parametrize("name", ["er14", "rmat14"])
+def test_sparsification_samplers(lib, name, sampler):
+    # uniform random sampling and threshold sampling with coins for E^=
+    g, k, eps, seed = gg.workload(name)
+    check_hierarchy(lib, g, 16, seed, sampler=sampler)
+    check_partition(lib, g, k, eps, seed, sampler=sampler)
+
+
 def test_sparsification_off(lib):
     g, k, eps, seed = gg.workload("er14")
     check_hierarchy(lib, g, 16, seed, sampler=2)

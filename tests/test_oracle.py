@@ -169,6 +169,78 @@ def test_equal_weight_sample_is_uniform():
     assert chi2 < stats.chi2.ppf(0.999, len(index) - 1)
 
 
+def _edge_counts(g, trials, **kw):
+    a, b, _ = T.edges_of(g)
+    index = {(x, y): i for i, (x, y) in enumerate(zip(a.tolist(), b.tolist()))}
+    counts = np.zeros(len(index))
+    sizes = []
+    for seed in range(trials):
+        s, _ = O.sparsify(g, seed=seed, **kw)
+        T.check_canonical(s)
+        sa, sb, sw = T.edges_of(s)
+        sizes.append(len(sa))
+        for x, y in zip(sa.tolist(), sb.tolist()):
+            counts[index[(x, y)]] += 1
+    return counts, np.array(sizes)
+
+
+def test_uniform_sampling_special_cases():
+    # Sec. 4.2 uniform random sampling keeps each edge with p = m_hat / |E'|:
+    # p = 1 keeps everything, p = 0 nothing, and kept edges keep their weights
+    rng = np.random.default_rng(21)
+    g = T.random_graph(60, 300, rng, wmax=7, vmax=3)
+    a, b, w = T.edges_of(g)
+    full, st = O.sparsify(g, g.m, seed=5, level=2, sampler=1)
+    assert full.m == g.m and st == dict(w_t=0, n_gt=0, n_eq=0)
+    assert np.array_equal(full.adjncy, g.adjncy) and np.array_equal(full.adjwgt, g.adjwgt)
+    none, _ = O.sparsify(g, 0, seed=5, level=2, sampler=1)
+    assert none.m == 0 and none.n == g.n
+    some, _ = O.sparsify(g, 100, seed=5, level=2, sampler=1)
+    orig = {(x, y): ww for x, y, ww in zip(a.tolist(), b.tolist(), w.tolist())}
+    sa, sb, sw = T.edges_of(some)
+    assert all(orig[(x, y)] == ww for x, y, ww in zip(sa.tolist(), sb.tolist(), sw.tolist()))
+    assert np.array_equal(some.vwgt, T.node_weights(g))
+
+
+def test_uniform_sampling_is_bernoulli():
+    # every edge is kept with frequency p across seeds (chi-square), and the
+    # kept count has mean p |E'| and the binomial spread
+    rng = np.random.default_rng(22)
+    g = T.random_graph(40, 80, rng, wmax=5)
+    m_hat, trials = 30, 1500
+    counts, sizes = _edge_counts(g, trials, m_hat=m_hat, level=4, sampler=1)
+    p = m_hat / g.m
+    expected = trials * p
+    chi2 = float(((counts - expected) ** 2 / (expected * (1 - p))).sum())
+    assert chi2 < stats.chi2.ppf(0.999, g.m)
+    assert abs(sizes.mean() - m_hat) < 5 * np.sqrt(g.m * p * (1 - p) / trials)
+    assert 0.5 < sizes.var() / (g.m * p * (1 - p)) < 1.5
+
+
+def test_threshold_coin_sampling():
+    # the paper-literal threshold rule: E^> kept, lighter edges dropped, each
+    # edge of weight w_t kept with probability (m_hat - |E^>|) / |E^=|
+    rng = np.random.default_rng(23)
+    g = T.random_graph(50, 160, rng, wmax=4)
+    a, b, w = T.edges_of(g)
+    m_hat, trials = 70, 1500
+    w_t = int(np.sort(w)[::-1][m_hat - 1])
+    gt, eq = w > w_t, w == w_t
+    r, n_eq = m_hat - int(gt.sum()), int(eq.sum())
+    _, st = O.sparsify(g, m_hat, seed=0, level=3, sampler=3)
+    assert st == dict(w_t=w_t, n_gt=int(gt.sum()), n_eq=n_eq)
+    counts, sizes = _edge_counts(g, trials, m_hat=m_hat, level=3, sampler=3)
+    assert np.all(counts[gt] == trials) and np.all(counts[w < w_t] == 0)
+    p = r / n_eq
+    ce = counts[eq]
+    chi2 = float(((ce - trials * p) ** 2 / (trials * p * (1 - p))).sum())
+    assert chi2 < stats.chi2.ppf(0.999, n_eq)
+    assert abs((sizes - gt.sum()).mean() - r) < 5 * np.sqrt(n_eq * p * (1 - p) / trials)
+    # r = |E^=| keeps all of E^=: the graph above the threshold weight
+    whole, _ = O.sparsify(g, int(gt.sum()) + n_eq, seed=1, level=3, sampler=3)
+    assert whole.m == int(gt.sum()) + n_eq
+
+
 # ------------------------------------------------------- label propagation --
 def _lp_bruteforce(g, label, W, cap, seed, level, S, tags):
     """One round (S sub-rounds) of the synchronous size-constrained LP rule,
