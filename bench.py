@@ -288,6 +288,87 @@ def bench_serve(args) -> dict:
     }
 
 
+ABLATION_SETTINGS = [
+    # (name, parameter overrides); defaults tau_e = tau_d = 1/2, rho = 4
+    ("off", dict(sampler=2)),
+    ("T-Weight", dict(sampler=0)),
+    ("T-Weight rho=3", dict(sampler=0, rho_num=3)),
+    ("T-Weight coins", dict(sampler=3)),
+    ("UR", dict(sampler=1)),
+    ("UR tau_e=1/4 tau_d=1 rho=2", dict(sampler=1, tau_e_num=1, tau_e_den=4, tau_d_num=1,
+                                        tau_d_den=1, rho_num=2)),
+]
+
+
+def _ablation_graphs():
+    from paper_2504_17615_amd import graphgen as gg
+
+    return {
+        "er20 (ER, avg degree 32)": lambda: gg.er(1 << 20, 1 << 24, seed=1),
+        "rmat20 (R-MAT, edge factor 16)": lambda: gg.rmat(20),
+        "planted20 (1024 groups, f_in 0.8, avg degree 32)":
+            lambda: gg.planted(1 << 20, 1024, avg_degree=32, f_in=0.8),
+        "chunglu20 (power law 2.5, avg degree 32)":
+            lambda: gg.chung_lu(1 << 20, avg_degree=32, gamma=2.5),
+    }
+
+
+def bench_ablation(args) -> dict:
+    """Sparsification ablation and parameter sweep (the paper's Sec. 5
+    questions, on synthetic graphs): per graph and setting the coarsen+refine
+    time, the cut, the first coarse level's edge fraction and the hierarchy
+    size (sum of level edge counts / input edges), relative to no
+    sparsification.  k = 16, eps = 0.03, seed 1."""
+    import torch
+
+    import paper_2504_17615_amd as L
+
+    L.library()
+    k, eps, seed = 16, 0.03, 1
+    rows = []
+    for gname, make in _ablation_graphs().items():
+        g = make()
+        dg = L.create_graph(g)
+        base = None
+        for sname, over in ABLATION_SETTINGS:
+            prm = L.default_params(**over)
+            h = dg.coarsen(k, seed, prm)
+            ms = [h.info(i)["m"] for i in range(h.levels)]
+            trig = [bool(h.info(i)["triggered"]) for i in range(h.levels)]
+            h.close()
+            dg.partition(k, eps, seed, prm, host_out=True)  # warm-up
+            times, cut = [], None
+            for _ in range(args.steps):
+                _, r = dg.partition(k, eps, seed, prm, host_out=True)
+                times.append((r["t_coarsen_ns"] + r["t_refine_ns"]) * 1e-6)
+                cut = r["cut"]
+            t = float(np.median(times))
+            row = {"graph": gname, "setting": sname, "ms": round(t, 2), "cut": cut,
+                   "levels": len(ms), "triggered_levels": int(sum(trig)),
+                   "level1_edge_fraction": round(ms[1] / ms[0], 4) if len(ms) > 1 else None,
+                   "hierarchy_size": round(sum(ms) / ms[0], 4)}
+            if base is None:
+                base = row
+            row["speedup_vs_off"] = round(base["ms"] / t, 3)
+            row["cut_change_vs_off"] = round(cut / base["cut"] - 1, 4)
+            row["hierarchy_vs_off"] = round(row["hierarchy_size"] / base["hierarchy_size"], 4)
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+        dg.close()
+        del g
+        torch.cuda.empty_cache()
+    on = [r for r in rows if r["setting"] != "off"]
+    rt = np.array([1 / r["speedup_vs_off"] for r in on])
+    hs = np.array([r["hierarchy_vs_off"] for r in on])
+    corr = float(np.corrcoef(rt, hs)[0, 1]) if len(on) > 2 else None
+    geo = {s: round(float(np.exp(np.mean([np.log(r["speedup_vs_off"]) for r in on
+                                          if r["setting"] == s]))), 3)
+           for s, _ in ABLATION_SETTINGS[1:]}
+    return {"metric": "sparsification ablation", "unit": "speedup / cut change vs no sparsification",
+            "n_gpus": 1, "data": "synthetic", "k": k, "eps": eps, "seed": seed,
+            "geomean_speedup": geo, "corr_time_vs_hierarchy_size": corr, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,9 +380,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="launch one plain copy of this size first (counter calibration)")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "ablation"],
                     help="single: the headline workload; batch: many small graphs in one "
-                         "batched call; serve: Poisson request stream through the server")
+                         "batched call; serve: Poisson request stream through the server; "
+                         "ablation: sparsification settings against none")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-prefix", type=int, default=256)
     ap.add_argument("--requests", type=int, default=300)
@@ -318,7 +400,8 @@ def main():
         sys.exit(2)
 
     if args.mode != "single":
-        line = bench_batch(args) if args.mode == "batch" else bench_serve(args)
+        line = {"batch": bench_batch, "serve": bench_serve,
+                "ablation": bench_ablation}[args.mode](args)
         print(json.dumps(line), flush=True)
         return
 

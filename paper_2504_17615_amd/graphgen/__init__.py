@@ -44,6 +44,10 @@ def _load():
     lib.gg_er.restype = vp
     lib.gg_rgg.argtypes = [u64, dbl, u64]
     lib.gg_rgg.restype = vp
+    lib.gg_planted.argtypes = [u64, u64, dbl, dbl, u64]
+    lib.gg_planted.restype = vp
+    lib.gg_chung_lu.argtypes = [u64, dbl, dbl, u64]
+    lib.gg_chung_lu.restype = vp
     lib.gg_n.argtypes = [vp]
     lib.gg_n.restype = u64
     lib.gg_nnz.argtypes = [vp]
@@ -114,6 +118,18 @@ def rgg(n: int, r: Optional[float] = None, seed: int = 24) -> Graph:
     if r is None:
         r = rgg_radius(n)
     return _collect(_load().gg_rgg(n, r, seed), f"rgg{n}")
+
+
+def planted(n: int, groups: int, avg_degree: float = 32.0, f_in: float = 0.8,
+            seed: int = 25) -> Graph:
+    """Planted partition: n nodes in `groups` contiguous groups, a fraction
+    f_in of the edge draws inside a group."""
+    return _collect(_load().gg_planted(n, groups, avg_degree, f_in, seed), f"planted{n}_{groups}")
+
+
+def chung_lu(n: int, avg_degree: float = 32.0, gamma: float = 2.5, seed: int = 26) -> Graph:
+    """Chung-Lu graph with power-law expected degrees (exponent gamma)."""
+    return _collect(_load().gg_chung_lu(n, avg_degree, gamma, seed), f"chunglu{n}")
 
 
 # The workloads: (graph factory, k, eps, seed).  Full sizes plus reduced

@@ -22,7 +22,16 @@
 //   rgg   : random geometric graph in [0,1)^2 with radius r; node ids in
 //           cell-major order of a grid with cells of side >= r; edge weight
 //           1 + floor(8 (1 - d/r)) in {1..9}.
-//   er_pairs / planted: not needed by the configurations; omitted.
+//   planted: planted partition (Condon & Karp's planted l-partition model,
+//           drawn as a multigraph): n nodes in b contiguous groups; each of
+//           d n / 2 draws picks u uniformly and v uniformly inside u's group
+//           with probability f_in, else uniformly in the graph; self-loops
+//           dropped, symmetrised, deduplicated.
+//   chung_lu: Chung-Lu graph with a power-law expected-degree sequence
+//           w_i proportional to (i + 1)^(-1 / (gamma - 1)), scaled to average
+//           degree d; each of d n / 2 draws picks both endpoints with
+//           probability proportional to w (inverse CDF on the prefix sums);
+//           self-loops dropped, symmetrised, deduplicated.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -242,6 +251,71 @@ void gen_er(uint64_t n, uint64_t m, uint64_t seed, Csr& out) {
   build_csr(n, src, dst, nullptr, out);
 }
 
+void sym_dedup(uint64_t n, const std::vector<uint64_t>& u, const std::vector<uint64_t>& v,
+               Csr& out) {
+  std::vector<uint64_t> src;
+  std::vector<uint32_t> dst;
+  src.reserve(2 * u.size());
+  dst.reserve(2 * u.size());
+  for (size_t e = 0; e < u.size(); ++e) {
+    if (u[e] == v[e]) continue;
+    src.push_back(u[e]);
+    dst.push_back((uint32_t)v[e]);
+    src.push_back(v[e]);
+    dst.push_back((uint32_t)u[e]);
+  }
+  build_csr(n, src, dst, nullptr, out);
+}
+
+void gen_planted(uint64_t n, uint64_t groups, double avg_degree, double f_in, uint64_t seed,
+                 Csr& out) {
+  const uint64_t draws = (uint64_t)(avg_degree * (double)n / 2.0);
+  const uint64_t t_in = (uint64_t)std::floor(f_in * 4294967296.0);
+  std::vector<uint64_t> su(draws), sv(draws);
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < (int64_t)draws; ++e) {
+    const uint64_t u = bounded(draw(seed, 201, (uint64_t)e), n);
+    uint64_t v;
+    if ((draw(seed, 202, (uint64_t)e) >> 32) < t_in) {
+      const uint64_t g = u * groups / n;                      // u's group
+      const uint64_t lo = (g * n + groups - 1) / groups;      // first node of the group
+      const uint64_t hi = ((g + 1) * n + groups - 1) / groups;
+      v = lo + bounded(draw(seed, 203, (uint64_t)e), hi - lo);
+    } else {
+      v = bounded(draw(seed, 203, (uint64_t)e), n);
+    }
+    su[e] = u;
+    sv[e] = v;
+  }
+  sym_dedup(n, su, sv, out);
+}
+
+void gen_chung_lu(uint64_t n, double avg_degree, double gamma, uint64_t seed, Csr& out) {
+  std::vector<double> cdf(n + 1, 0.0);
+  const double ex = -1.0 / (gamma - 1.0);
+  for (uint64_t i = 0; i < n; ++i) cdf[i + 1] = cdf[i] + std::pow((double)(i + 1), ex);
+  const double total = cdf[n];
+  const uint64_t draws = (uint64_t)(avg_degree * (double)n / 2.0);
+  std::vector<uint64_t> su(draws), sv(draws);
+  auto pick = [&](uint64_t h) {
+    // uniform in [0, total) from the top 53 bits; first i with cdf[i + 1] > x
+    const double x = (double)(h >> 11) * (1.0 / 9007199254740992.0) * total;
+    uint64_t lo = 0, hi = n;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (cdf[mid] <= x) lo = mid;
+      else hi = mid;
+    }
+    return lo;
+  };
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < (int64_t)draws; ++e) {
+    su[e] = pick(draw(seed, 301, (uint64_t)e));
+    sv[e] = pick(draw(seed, 302, (uint64_t)e));
+  }
+  sym_dedup(n, su, sv, out);
+}
+
 // Random geometric graph.  Distances in binary64 with no contraction
 // (this file is compiled with -ffp-contract=off).
 void gen_rgg(uint64_t n, double r, uint64_t seed, Csr& out) {
@@ -345,6 +419,16 @@ void* gg_rmat(uint32_t scale, uint64_t ef, double a, double b, double c, uint64_
 void* gg_er(uint64_t n, uint64_t m, uint64_t seed) {
   Csr* g = new Csr();
   gen_er(n, m, seed, *g);
+  return g;
+}
+void* gg_planted(uint64_t n, uint64_t groups, double avg_degree, double f_in, uint64_t seed) {
+  Csr* g = new Csr();
+  gen_planted(n, groups, avg_degree, f_in, seed, *g);
+  return g;
+}
+void* gg_chung_lu(uint64_t n, double avg_degree, double gamma, uint64_t seed) {
+  Csr* g = new Csr();
+  gen_chung_lu(n, avg_degree, gamma, seed, *g);
   return g;
 }
 void* gg_rgg(uint64_t n, double r, uint64_t seed) {

@@ -47,3 +47,33 @@ def test_workload_table():
     assert (k, eps, seed) == (4, 0.03, 1)
     g, k, eps, seed = gg.workload("rmat12")
     assert k == 64 and g.n == 4096
+
+
+def test_planted_partition_structure():
+    n, groups, f_in = 1 << 14, 32, 0.8
+    g = gg.planted(n, groups, avg_degree=16, f_in=f_in, seed=3)
+    T.check_canonical(g)
+    h = gg.planted(n, groups, avg_degree=16, f_in=f_in, seed=3)
+    assert np.array_equal(g.adjncy, h.adjncy)
+    deg = np.diff(g.xadj.astype(np.int64))
+    src = np.repeat(np.arange(n), deg)
+    same = (src * groups // n) == (g.adjncy.astype(np.int64) * groups // n)
+    # a draw lands inside its group with probability f_in + (1 - f_in) / groups
+    want = f_in + (1 - f_in) / groups
+    assert abs(same.mean() - want) < 0.01
+    assert abs(deg.mean() - 16) < 0.5  # few duplicates at this density
+
+
+def test_chung_lu_degrees_follow_weights():
+    n, d, gamma = 1 << 14, 16.0, 2.5
+    g = gg.chung_lu(n, avg_degree=d, gamma=gamma, seed=4)
+    T.check_canonical(g)
+    deg = np.diff(g.xadj.astype(np.int64))
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-1 / (gamma - 1))
+    expected = 2 * (d * n / 2) * w / w.sum()  # two endpoint draws per edge
+    # low-degree nodes: mean degree close to the expected weight
+    tail = slice(n // 2, n)
+    assert abs(deg[tail].mean() - expected[tail].mean()) < 0.15 * expected[tail].mean()
+    # heavy head (duplicates merge there), decreasing on average
+    assert deg[:16].mean() > 10 * deg.mean()
+    assert deg[: n // 16].mean() > deg[n // 16: n // 4].mean() > deg[n // 4:].mean()
