@@ -393,6 +393,9 @@ def main():
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--hbm-budget-gib", type=int, default=64)
+    ap.add_argument("--tune", default="off",
+                    help="rating class tables: off (default table), auto (autotuned, "
+                         "timed during the warm-up calls) or a table index")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -420,8 +423,10 @@ def main():
     dev = L.create_graph(g)
     del g
     out = torch.empty(dev.n, dtype=torch.int32, device="cuda")
+    tune = {"off": 0, "auto": 1}.get(args.tune)
+    prm = L.default_params(tune=16 + int(args.tune) if tune is None else tune)
     for _ in range(args.warmup):
-        dev.partition(k, eps, seed, out=out)
+        dev.partition(k, eps, seed, prm, out=out)
     torch.cuda.synchronize()
     if not args.no_profile:
         L.profile_read(reset=True)
@@ -430,7 +435,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, res = dev.partition(k, eps, seed, out=out)
+        _, res = dev.partition(k, eps, seed, prm, out=out)
         results.append(res)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -464,7 +469,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "n": dev.n, "m": m, "k": k, "eps": eps, "seed": seed,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "tune": args.tune},
         "phases_ms": {p: round(v, 3) for p, v in ph.items()},
         "wall_edges_per_s": m / wall,
         "cut": results[-1]["cut"],

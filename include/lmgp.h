@@ -99,7 +99,19 @@ typedef struct {
   uint32_t subrounds;            /* synchronous sub-rounds per LP round, 4         */
   uint32_t max_levels;           /* hierarchy depth cap, 64                        */
   uint32_t stop_num, stop_den;   /* stop when stop_den*n' > stop_num*n (19/20)     */
+  uint32_t tune;                 /* degree-class cut-offs of the rating kernels (no
+                                  * effect on any result, only on speed):
+                                  * LMGP_TUNE_OFF (0) = fixed default table;
+                                  * LMGP_TUNE_AUTO (1) = per level, the table timed
+                                  * fastest for the level's (phase, degree histogram),
+                                  * cached for the process (and in the file named by
+                                  * LMGP_TUNE_CACHE if set); LMGP_TUNE_FORCE + p =
+                                  * table p (modulo the number of tables).          */
 } lmgp_params;
+
+#define LMGP_TUNE_OFF 0u
+#define LMGP_TUNE_AUTO 1u
+#define LMGP_TUNE_FORCE 16u
 
 typedef struct lmgp_graph lmgp_graph;
 typedef struct lmgp_hierarchy lmgp_hierarchy;
@@ -141,6 +153,13 @@ typedef struct {
 } lmgp_server_cfg;
 
 void lmgp_default_params(lmgp_params *out);
+
+/* The autotuner's process-wide cache (see lmgp_params.tune): number of cached
+ * (phase, degree histogram) entries and of timed trials so far.  Either
+ * pointer may be NULL. */
+lmgp_status lmgp_tuner_info(uint64_t *entries, uint64_t *trials);
+/* Forgets the process-wide cache (a cache file is left unchanged). */
+void lmgp_tuner_clear(void);
 
 /* Last error message of the calling thread ("" if none). */
 const char *lmgp_last_error(void);

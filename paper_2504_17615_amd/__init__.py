@@ -21,4 +21,6 @@ from ._binding import (  # noqa: F401
     partition_batch,
     profile_enable,
     profile_read,
+    tuner_clear,
+    tuner_info,
 )

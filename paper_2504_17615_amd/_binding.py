@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_uint32) for nm in (
         "tau_e_num", "tau_e_den", "tau_d_num", "tau_d_den", "rho_num", "rho_den", "sampler",
         "clim", "shrink_num", "shrink_den", "lp_rounds", "ref_rounds", "subrounds",
-        "max_levels", "stop_num", "stop_den")]
+        "max_levels", "stop_num", "stop_den", "tune")]
 
 
 class CsrView(ctypes.Structure):
@@ -99,6 +99,8 @@ _SIGS = {
     "lmgp_profile_enable": ([ctypes.c_uint32], ctypes.c_int),
     "lmgp_profile_read": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32],
                           ctypes.c_int),
+    "lmgp_tuner_info": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "lmgp_tuner_clear": ([], None),
 }
 
 
@@ -120,6 +122,17 @@ def profile_read(reset: bool = True) -> dict:
     return {arr[i].name.decode(): dict(launches=int(arr[i].launches),
                                        total_ns=int(arr[i].total_ns), bytes=int(arr[i].bytes))
             for i in range(cnt.value)}
+
+def tuner_info() -> dict:
+    """The autotuner's process-wide cache: cached entries and timed trials."""
+    e, t = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(library().lmgp_tuner_info(ctypes.byref(e), ctypes.byref(t)))
+    return {"entries": int(e.value), "trials": int(t.value)}
+
+
+def tuner_clear():
+    library().lmgp_tuner_clear()
+
 
 EXPORTED = tuple(_SIGS)
 

@@ -5,6 +5,7 @@
 #include <string>
 
 #include "engine.h"
+#include "tuner.h"
 
 
 struct lmgp_hierarchy {
@@ -291,6 +292,15 @@ void lmgp_default_params(lmgp_params* out) {
 }
 
 const char* lmgp_last_error(void) { return g_err.c_str(); }
+
+lmgp_status lmgp_tuner_info(uint64_t* entries, uint64_t* trials) {
+  return guard([&] {
+    if (entries) *entries = Tuner::get().entries();
+    if (trials) *trials = Tuner::get().trials();
+  });
+}
+
+void lmgp_tuner_clear(void) { Tuner::get().clear(); }
 
 lmgp_status lmgp_graph_create(const lmgp_csr_view* view, const lmgp_allocator* alloc, void* stream,
                               lmgp_graph** out) {

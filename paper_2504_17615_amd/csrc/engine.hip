@@ -13,6 +13,7 @@
 #include <initializer_list>
 
 #include "engine.h"
+#include "tuner.h"
 
 namespace lmgp {
 
@@ -270,6 +271,7 @@ lmgp_params default_params() {
   p.lp_rounds = 5, p.ref_rounds = 5, p.subrounds = 4;
   p.max_levels = 64;
   p.stop_num = 19, p.stop_den = 20;
+  p.tune = LMGP_TUNE_OFF;
   return p;
 }
 
@@ -282,6 +284,8 @@ void check_params(const lmgp_params& p) {
   if (!p.subrounds || p.subrounds > 32) throw InvalidArg("subrounds must be in [1, 32]");
   if (!p.max_levels) throw InvalidArg("max_levels must be positive");
   if (!p.stop_den) throw InvalidArg("stop_den must be positive");
+  if (p.tune > LMGP_TUNE_AUTO && p.tune < LMGP_TUNE_FORCE)
+    throw InvalidArg("tune must be 0 (default classes), 1 (autotune) or 16 + preset");
 }
 
 // ----------------------------------------------------------------- union --
@@ -453,6 +457,10 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   // refinement with few labels: demand and segment slots from block-privatised
   // histograms in the admission instead of contended atomics
   const uint32_t few = spec.refine && nlabels <= FEW_LABELS ? (uint32_t)nlabels : 0u;
+  // the rating kernels' class cut-offs: dense per-block rows when few
+  const bool dense = few != 0;
+  const std::vector<CutPreset>& presets = cut_presets(dense);
+  int preset = p_.tune >= LMGP_TUNE_FORCE ? (int)((p_.tune - LMGP_TUNE_FORCE) % presets.size()) : 0;
   const uint64_t tsub = spec.refine ? TAG_RSUB : TAG_SUB;
   const uint64_t ttie = spec.refine ? TAG_RTIE : TAG_TIE;
   const uint64_t tadm = spec.refine ? TAG_RADM : TAG_ADM;
@@ -494,6 +502,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();
+  ba.cuts = presets[preset].cuts;
   // Stop decisions (node-reduction cap after a sub-round, no moves in a
   // round) are taken on the device; the host reads the active flags together
   // with the next round's bucket counts, in one copy per round.
@@ -509,38 +518,96 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       degs[i] = hstate[NB + i];
     }
   };
-  for (uint32_t r = 0; r < R; ++r) {
-    begin_round(r);
-    bool any = false;
-    for (uint32_t b = 0; b < B; ++b) any |= hstate[2 * NB + b] != 0;
-    if (!any) break;
+  auto bucket_offsets = [&]() {
     uint32_t run = 0;
     for (uint32_t i = 0; i < NB; ++i) {
       offs[i] = run;  // the same prefix the device computed into boffs
       run += cnt[i];
     }
+  };
+  auto rating_args = [&](uint32_t sr) {
+    RateArgs ra{};
+    ra.xadj = L.xadj;
+    ra.adj = L.adj;
+    ra.ew = L.ew;
+    ra.nw = L.nw;
+    ra.label = label;
+    ra.W = W;
+    ra.gid = L.gid;
+    ra.gd = dgd.get();
+    ra.mode = MODE_LP;
+    ra.phase = spec.refine ? 1 : 0;
+    ra.packed = packed_ ? 1 : 0;
+    ra.few = few;
+    ra.demand = demand.get();
+    ra.ntgt = ntgt.get();
+    ra.list = list.get() + offs[sr * NCLASS];
+    ra.cands = cands.get();
+    return ra;
+  };
+  // Autotuning: the first round's buckets under the default table give the
+  // level's degree histogram; an unseen one is timed under every table on
+  // the first sub-round (rating only, no tallies) and the fastest is cached.
+  auto autotune = [&]() {
+    uint64_t hist[NCLASS] = {};
+    uint64_t entries = 0;
+    for (uint32_t i = 0; i < NB; ++i) {
+      hist[i % NCLASS] += cnt[i];
+      entries += degs[i];
+    }
+    const std::string key = tune_key(spec.refine ? 1 : 0, dense, L.ew_kind, packed_, hist);
+    Tuner& tuner = Tuner::get();
+    int best = tuner.lookup(key);
+    if (best < 0) {
+      best = 0;
+      if (entries >= TUNE_MIN_ENTRIES) {
+        hipEvent_t e0, e1;
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        float best_ms = 0.f;
+        for (int p = 0; p < (int)presets.size(); ++p) {
+          ba.cuts = presets[p].cuts;
+          begin_round(0);
+          bucket_offsets();
+          launch_bucket_scatter(ba, s_);
+          RateArgs ra = rating_args(0);
+          ra.trial = 1;
+          float ms = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {  // the first one also warms the caches
+            HIP_CHECK(hipEventRecord(e0, s_));
+            rate_classes(ra, &cnt[0], &offs[0], &degs[0], L.ew_kind);
+            HIP_CHECK(hipEventRecord(e1, s_));
+            HIP_CHECK(hipEventSynchronize(e1));
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+          }
+          tuner.note_trial();
+          if (p == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = p;
+          }
+        }
+        HIP_CHECK(hipEventDestroy(e0));
+        HIP_CHECK(hipEventDestroy(e1));
+      }
+      tuner.store(key, best);
+    }
+    preset = best;
+    ba.cuts = presets[preset].cuts;
+    begin_round(0);
+  };
+  for (uint32_t r = 0; r < R; ++r) {
+    begin_round(r);
+    if (r == 0 && p_.tune == LMGP_TUNE_AUTO) autotune();
+    bool any = false;
+    for (uint32_t b = 0; b < B; ++b) any |= hstate[2 * NB + b] != 0;
+    if (!any) break;
+    bucket_offsets();
     launch_bucket_scatter(ba, s_);
     for (uint32_t sr = 0; sr < S; ++sr) {
       uint32_t total = 0;
       for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
       if (total == 0) continue;
-      RateArgs ra{};
-      ra.xadj = L.xadj;
-      ra.adj = L.adj;
-      ra.ew = L.ew;
-      ra.nw = L.nw;
-      ra.label = label;
-      ra.W = W;
-      ra.gid = L.gid;
-      ra.gd = dgd.get();
-      ra.mode = MODE_LP;
-      ra.phase = spec.refine ? 1 : 0;
-      ra.packed = packed_ ? 1 : 0;
-      ra.few = few;
-      ra.demand = demand.get();
-      ra.ntgt = ntgt.get();
-      ra.list = list.get() + offs[sr * NCLASS];
-      ra.cands = cands.get();
+      RateArgs ra = rating_args(sr);
       rate_classes(ra, &cnt[sr * NCLASS], &offs[sr * NCLASS], &degs[sr * NCLASS], L.ew_kind);
       AdmitArgs aa{};
       aa.cands = cands.get();
@@ -619,6 +686,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();
+  ba.cuts = default_cuts();
   bcount.zero();
   launch_bucket_count(ba, s_);
   launch_bucket_offsets(ba, s_);

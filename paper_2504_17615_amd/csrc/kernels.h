@@ -53,6 +53,19 @@ LMGP_HD int degree_class(uint64_t d) {
        : d <= 256 ? 6 : d <= 512 ? 7 : d <= 1024 ? 8 : d <= 2048 ? 9
        : d <= 6144 ? 10 : d <= 8192 ? 11 : 12;
 }
+// A class cut-off table: class c takes the degrees in (ub[c-1], ub[c]], the
+// last class every degree above ub[NCLASS-2].  The default table is the one of
+// degree_class; other tables (chosen by the autotuner) move degrees between
+// kernels that can all hold them, which changes the speed and never a result.
+struct ClassCuts {
+  uint32_t ub[NCLASS - 1];
+};
+LMGP_HD int class_of(uint64_t d, const ClassCuts& c) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < NCLASS - 1; ++i) k += d > c.ub[i];
+  return k;
+}
 LMGP_HD int class_group(int c) { return c < 6 ? (2 << c) : 256; }
 // log2 of the LDS table of a block / big-block class
 LMGP_HD int class_table_log(int c) { return c < CLASS_BIG ? c + 3 : c == CLASS_BIG ? 13 : 14; }
@@ -90,6 +103,8 @@ struct RateArgs {
   int packed;              // every rating fits in 32 bits: use gtab
   uint32_t few;            // labels < few <= FEW_LABELS: demand and ntgt are counted
                            // by the admission (block-privatised), not here
+  uint32_t trial;          // timing trial: candidates are written, demand and ntgt
+                           // are not counted
 };
 
 // Label counts up to this use block-privatised LDS histograms in admission
@@ -130,6 +145,7 @@ struct BucketArgs {
   uint32_t* offs;          // [nbuckets] (offsets pass writes, scatter pass reads)
   uint32_t* fill;          // [nbuckets] (scatter pass)
   uint32_t* list;          // output
+  ClassCuts cuts;          // degree -> class (non-decreasing bounds)
 };
 void launch_bucket_count(const BucketArgs& a, hipStream_t s);
 // offs = exclusive prefix of counts, fill = 0 (one small block on the device).

@@ -102,7 +102,7 @@ LMGP_D void emit(const RateArgs& a, uint32_t idx, uint32_t u, const GraphDesc& g
     c.pad = 0;
     c.gain = best.r - r_own;
     a.cands[i] = c;
-    if (!a.few) {
+    if (!a.few && !a.trial) {
       atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
       atomicAdd(&a.ntgt[best.K], 1u);
     }
@@ -1245,12 +1245,12 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
     // adjacent label weighs at least one), so rating it cannot produce a move
     if (a.nw[u] >= gd.cap) return -1;
     uint32_t sr = subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds);
-    return (int)(sr * NCLASS + degree_class(d));
+    return (int)(sr * NCLASS + class_of(d, a.cuts));
   }
   // 2-hop: light singletons with neighbours
   if (a.csize[a.label[u]] != 1) return -1;
   if (2 * a.nw[u] > gd.cap) return -1;
-  return degree_class(d);
+  return class_of(d, a.cuts);
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {

@@ -93,3 +93,10 @@ def test_null_arguments_are_rejected():
 def test_profile_api_without_device():
     L.profile_enable(False)
     assert isinstance(L.profile_read(reset=True), dict)
+
+
+def test_tuner_api_without_device():
+    p = L.default_params()
+    assert p.tune == 0  # fixed default class table unless asked
+    L.tuner_clear()
+    assert L.tuner_info() == {"entries": 0, "trials": 0}
