@@ -17,6 +17,7 @@ import json
 import os
 import sys
 import time
+from typing import Optional
 
 import numpy as np
 
@@ -74,19 +75,32 @@ def measured_traffic(kernel: str, workload: str):
     return None if k is None else k["hbm_bytes_per_launch"]
 
 
-def roofline(stats: dict, steps: int, wall: float, workload: str) -> dict:
-    """Roofline record of the dominant rating kernel from the event timings.
-
-    Families are '<phase>:<kernel>'; the dominant kernel is the single HIP
-    kernel with the largest summed time over all phases (the hub class,
-    which brackets several kernels, is reported but not chosen)."""
+def _per_kernel(stats: dict) -> dict:
     per_kernel = {}
     for fam, st in stats.items():
         k = per_kernel.setdefault(_kernel_of(fam), {"launches": 0, "total_ns": 0, "bytes": 0})
         for f in ("launches", "total_ns", "bytes"):
             k[f] += st[f]
-    single = {k: v for k, v in per_kernel.items() if k.startswith("k_")}
-    name, st = max(single.items(), key=lambda kv: kv[1]["total_ns"])
+    return per_kernel
+
+
+def dominant_kernel(stats: dict) -> str:
+    """The single HIP kernel with the largest summed time over all phases
+    (the hub class, which brackets several kernels, is not chosen)."""
+    single = {k: v for k, v in _per_kernel(stats).items() if k.startswith("k_")}
+    return max(single.items(), key=lambda kv: kv[1]["total_ns"])[0]
+
+
+def roofline(stats: dict, steps: int, wall: float, workload: str,
+             breakdown: Optional[dict] = None) -> dict:
+    """Roofline record of the dominant rating kernel from the event timings.
+
+    Families are '<phase>:<kernel>'.  `stats` holds the timed region's event
+    timings (all rating launches, or only the dominant kernel's when the
+    breakdown over all of them comes from a separate profiled step)."""
+    per_kernel = _per_kernel(stats)
+    name = dominant_kernel(stats)
+    st = per_kernel[name]
     per_launch_bytes = st["bytes"] / st["launches"]
     per_launch_ns = st["total_ns"] / st["launches"]
     achieved = per_launch_bytes / per_launch_ns  # bytes/ns == GB/s
@@ -95,11 +109,12 @@ def roofline(stats: dict, steps: int, wall: float, workload: str) -> dict:
             "traffic": measured_traffic(name, workload), "launches": st["launches"],
             "avg_launch_us": round(per_launch_ns / 1e3, 2),
             "bytes_per_launch": int(per_launch_bytes)}
-    tot = sum(s["total_ns"] for s in stats.values())
-    tb = sum(s["bytes"] for s in stats.values())
+    bd, bsteps = (stats, steps) if breakdown is None else (breakdown, 1)
+    tot = sum(s["total_ns"] for s in bd.values())
+    tb = sum(s["bytes"] for s in bd.values())
     roof["lp_rate_all"] = {"achieved": round(tb / tot, 1),
                            "frac": round(tb / tot / HBM_PEAK_GBS, 4),
-                           "share_of_step": round(tot / steps / 1e9 / wall, 3)}
+                           "share_of_step": round(tot / bsteps / 1e9 / wall, 3)}
 
     def summary(d):
         return {nm: {"launches": s["launches"],
@@ -108,8 +123,11 @@ def roofline(stats: dict, steps: int, wall: float, workload: str) -> dict:
                      "ms_per_step": round(s["total_ns"] / steps / 1e6, 2)}
                 for nm, s in sorted(d.items(), key=lambda kv: -kv[1]["total_ns"])}
 
-    roof["kernels"] = summary(per_kernel)
-    roof["families"] = summary(stats)
+    if breakdown is not None:
+        roof["breakdown_from"] = "last warm-up step, every rating launch timed"
+        steps = 1
+    roof["kernels"] = summary(_per_kernel(bd))
+    roof["families"] = summary(bd)
     return roof
 
 
@@ -396,6 +414,8 @@ def main():
     ap.add_argument("--tune", default="off",
                     help="rating class tables: off (default table), auto (autotuned, "
                          "timed during the warm-up calls) or a table index")
+    ap.add_argument("--graph-rounds", type=int, default=0, choices=[0, 1],
+                    help="replay the LP rounds of small levels from HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -424,11 +444,26 @@ def main():
     del g
     out = torch.empty(dev.n, dtype=torch.int32, device="cuda")
     tune = {"off": 0, "auto": 1}.get(args.tune)
-    prm = L.default_params(tune=16 + int(args.tune) if tune is None else tune)
-    for _ in range(args.warmup):
+    prm = L.default_params(tune=16 + int(args.tune) if tune is None else tune,
+                           graph_rounds=args.graph_rounds)
+    # The last warm-up call times every rating launch (the per-kernel
+    # breakdown); the timed calls time only the dominant kernel, so that event
+    # timing of the other launches does not slow the measured steps.
+    breakdown = None
+    for i in range(args.warmup):
+        last = i == args.warmup - 1 and not args.no_profile
+        if last:
+            L.profile_filter(None)
+            L.profile_read(reset=True)
+            L.profile_enable(True)
         dev.partition(k, eps, seed, prm, out=out)
+        if last:
+            torch.cuda.synchronize()
+            L.profile_enable(False)
+            breakdown = L.profile_read(reset=True)
     torch.cuda.synchronize()
     if not args.no_profile:
+        L.profile_filter(dominant_kernel(breakdown) if breakdown else None)
         L.profile_read(reset=True)
         L.profile_enable(True)
     results = []
@@ -443,6 +478,7 @@ def main():
     if not args.no_profile:
         L.profile_enable(False)
         stats = L.profile_read(reset=True)
+        L.profile_filter(None)
     K = args.steps
     wall = (t1 - t0) / K
     cr = sum(r["t_coarsen_ns"] + r["t_refine_ns"] for r in results) / K * 1e-9
@@ -450,7 +486,7 @@ def main():
                                                                        "refine")}
     roof = None
     if stats:
-        roof = roofline(stats, K, wall, args.workload)
+        roof = roofline(stats, K, wall, args.workload, breakdown)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_sample)
@@ -469,7 +505,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "n": dev.n, "m": m, "k": k, "eps": eps, "seed": seed,
-                   "parallelism": "single GPU", "tune": args.tune},
+                   "parallelism": "single GPU", "tune": args.tune,
+                   "graph_rounds": args.graph_rounds},
         "phases_ms": {p: round(v, 3) for p, v in ph.items()},
         "wall_edges_per_s": m / wall,
         "cut": results[-1]["cut"],

@@ -107,6 +107,13 @@ typedef struct {
                                   * cached for the process (and in the file named by
                                   * LMGP_TUNE_CACHE if set); LMGP_TUNE_FORCE + p =
                                   * table p (modulo the number of tables).          */
+  uint32_t graph_rounds;         /* 1 = on levels of at most 2^18 nodes (over a batch)
+                                  * with no node rated through global tables, the LP
+                                  * rounds after the first are captured once into a
+                                  * HIP graph and replayed (grids sized from the first
+                                  * round, counts planned on the device); 0 = every
+                                  * round launched kernel by kernel.  No effect on any
+                                  * result, only on launch overhead.                 */
 } lmgp_params;
 
 #define LMGP_TUNE_OFF 0u
@@ -237,6 +244,11 @@ typedef struct {
 } lmgp_kernel_stat;
 
 lmgp_status lmgp_profile_enable(uint32_t on);
+/* Times only the launches of one kernel (the part of a family name after its
+ * phase prefix, e.g. "k_rate_big<2, 13>"); NULL or "" times every profiled
+ * launch.  Event timing adds work to each launch it covers, so timing one
+ * kernel keeps the rest of a timed run undisturbed. */
+lmgp_status lmgp_profile_filter(const char *kernel);
 /* Writes up to `max` entries to `out` (may be NULL), the number of families
  * to *count; reset = 1 clears the accumulated statistics afterwards. */
 lmgp_status lmgp_profile_read(lmgp_kernel_stat *out, uint32_t max, uint32_t *count,

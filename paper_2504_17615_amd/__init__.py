@@ -20,6 +20,7 @@ from ._binding import (  # noqa: F401
     library,
     partition_batch,
     profile_enable,
+    profile_filter,
     profile_read,
     tuner_clear,
     tuner_info,

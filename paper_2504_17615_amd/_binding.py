@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_uint32) for nm in (
         "tau_e_num", "tau_e_den", "tau_d_num", "tau_d_den", "rho_num", "rho_den", "sampler",
         "clim", "shrink_num", "shrink_den", "lp_rounds", "ref_rounds", "subrounds",
-        "max_levels", "stop_num", "stop_den", "tune")]
+        "max_levels", "stop_num", "stop_den", "tune", "graph_rounds")]
 
 
 class CsrView(ctypes.Structure):
@@ -99,6 +99,7 @@ _SIGS = {
     "lmgp_profile_enable": ([ctypes.c_uint32], ctypes.c_int),
     "lmgp_profile_read": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32],
                           ctypes.c_int),
+    "lmgp_profile_filter": ([ctypes.c_char_p], ctypes.c_int),
     "lmgp_tuner_info": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "lmgp_tuner_clear": ([], None),
 }
@@ -111,6 +112,11 @@ class KernelStat(ctypes.Structure):
 
 def profile_enable(on: bool = True):
     _check(library().lmgp_profile_enable(1 if on else 0))
+
+
+def profile_filter(kernel: Optional[str] = None):
+    """Time only the launches of `kernel` (None: every profiled launch)."""
+    _check(library().lmgp_profile_filter(kernel.encode() if kernel else None))
 
 
 def profile_read(reset: bool = True) -> dict:

@@ -13,6 +13,7 @@
 #include <initializer_list>
 
 #include "engine.h"
+#include "profiler.h"
 #include "tuner.h"
 
 namespace lmgp {
@@ -59,7 +60,8 @@ struct LpCtl {
   unsigned long long* round_moves;  // moves of the current round
   unsigned long long* ncl;          // cluster count (clustering) or NULL
   uint32_t* rounds_run;             // rounds in which the graph was active
-  unsigned long long* rstate;       // [2 nb] bucket counters, then [B] active flags
+  unsigned long long* rstate;       // [2 nb] bucket counters, then [B] active flags,
+                                    // then [B] the next round's flags (k_lp_peek)
   uint32_t nb;                      // buckets (sub-rounds x degree classes)
   uint32_t* ovtotal;                // admission overflow counters [2], cleared here
   const uint64_t* pre;              // [round][graph][3]: SUB, TIE, ADM hash prefixes
@@ -85,8 +87,10 @@ __global__ void k_lp_after_sub(LpCtl c) {
 }
 
 // Start of round r: a graph that made no move in round r - 1 stops; the
-// others take round r's hash prefixes.
-__global__ void k_lp_round(LpCtl c, uint32_t r) {
+// others take round r's hash prefixes.  A replayed round takes r from the
+// device counter rdev and advances it.
+__global__ void k_lp_round(LpCtl c, uint32_t r_arg, uint32_t* rdev) {
+  const uint32_t r = rdev ? *rdev : r_arg;
   for (uint32_t b = threadIdx.x; b < c.B; b += blockDim.x) {
     GraphDesc& g = c.gd[b];
     if (r > 0 && g.active && c.round_moves[b] == 0) g.active = 0;
@@ -99,6 +103,32 @@ __global__ void k_lp_round(LpCtl c, uint32_t r) {
     c.rstate[2 * c.nb + b] = g.active;
   }
   for (uint32_t i = threadIdx.x; i < 2 * c.nb; i += blockDim.x) c.rstate[i] = 0;
+  __syncthreads();
+  if (rdev && threadIdx.x == 0) *rdev = r + 1;
+}
+
+// The flags the next round's k_lp_round will compute (without changing any
+// state), for the host to decide whether to run it.
+__global__ void k_lp_peek(LpCtl c) {
+  for (uint32_t b = threadIdx.x; b < c.B; b += blockDim.x)
+    c.rstate[2 * c.nb + c.B + b] = c.gd[b].active && c.round_moves[b] != 0;
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// Levels (unions) up to this many nodes replay their LP rounds from a graph
+// when asked: above it the rounds are long enough to hide their launches.
+constexpr uint64_t REPLAY_MAX_NODES = 1ull << 18;
+
+// Stream on which replayed rounds are captured (capture needs a stream other
+// than the null stream; nothing is executed on it), one per thread and device.
+hipStream_t capture_stream() {
+  static thread_local std::vector<hipStream_t> streams;
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev]) HIP_CHECK(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
 }
 
 
@@ -272,6 +302,7 @@ lmgp_params default_params() {
   p.max_levels = 64;
   p.stop_num = 19, p.stop_den = 20;
   p.tune = LMGP_TUNE_OFF;
+  p.graph_rounds = 0;
   return p;
 }
 
@@ -286,6 +317,7 @@ void check_params(const lmgp_params& p) {
   if (!p.stop_den) throw InvalidArg("stop_den must be positive");
   if (p.tune > LMGP_TUNE_AUTO && p.tune < LMGP_TUNE_FORCE)
     throw InvalidArg("tune must be 0 (default classes), 1 (autotune) or 16 + preset");
+  if (p.graph_rounds > 1) throw InvalidArg("graph_rounds must be 0 or 1");
 }
 
 // ----------------------------------------------------------------- union --
@@ -447,7 +479,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<uint32_t> boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
   // per-round state read by the host in one copy: bucket counts, bucket
   // degree sums, active flags
-  DBuf<unsigned long long> rstate(&pool_, s_, 2 * NB + B);
+  DBuf<unsigned long long> rstate(&pool_, s_, 2 * NB + 2 * B);
   std::vector<unsigned long long> hstate(2 * NB + B);
   demand.zero();
   ntgt.zero();
@@ -507,7 +539,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   // round) are taken on the device; the host reads the active flags together
   // with the next round's bucket counts, in one copy per round.
   auto begin_round = [&](uint32_t r) {
-    k_lp_round<<<1, 256, 0, s_>>>(ctl, r);  // also clears the bucket counters
+    k_lp_round<<<1, 256, 0, s_>>>(ctl, r, nullptr);  // also clears the bucket counters
     LAUNCH_CHECK();
     launch_bucket_count(ba, s_);
     launch_bucket_offsets(ba, s_);
@@ -595,55 +627,177 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     ba.cuts = presets[preset].cuts;
     begin_round(0);
   };
-  for (uint32_t r = 0; r < R; ++r) {
-    begin_round(r);
-    if (r == 0 && p_.tune == LMGP_TUNE_AUTO) autotune();
-    bool any = false;
-    for (uint32_t b = 0; b < B; ++b) any |= hstate[2 * NB + b] != 0;
-    if (!any) break;
-    bucket_offsets();
-    launch_bucket_scatter(ba, s_);
-    for (uint32_t sr = 0; sr < S; ++sr) {
-      uint32_t total = 0;
-      for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
-      if (total == 0) continue;
-      RateArgs ra = rating_args(sr);
-      rate_classes(ra, &cnt[sr * NCLASS], &offs[sr * NCLASS], &degs[sr * NCLASS], L.ew_kind);
-      AdmitArgs aa{};
-      aa.cands = cands.get();
-      aa.max_cands = total;
-      aa.W = W;
-      aa.Wmut = W;
-      aa.nw = L.nw;
-      aa.label = label;
-      aa.gid = L.gid;
-      aa.gd = dgd.get();
-      aa.demand = demand.get();
-      aa.ntgt = ntgt.get();
-      aa.fill = fill.get();
-      aa.segbase = segbase.get();
-      aa.ovtotal = ovtotal.get();
-      aa.ovcount = ovtotal.get() + 1;
-      aa.ovtgts = ovtgts.get();
-      aa.adm = adm.get();
-      aa.cpos = cpos.get();
-      aa.seg = seg.get();
-      aa.csize = csize;
-      aa.moves = (uint64_t*)dmoves.get();
-      aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
-      aa.few = few;
-      launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
-      k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+  auto admit_args = [&]() {
+    AdmitArgs aa{};
+    aa.cands = cands.get();
+    aa.W = W;
+    aa.Wmut = W;
+    aa.nw = L.nw;
+    aa.label = label;
+    aa.gid = L.gid;
+    aa.gd = dgd.get();
+    aa.demand = demand.get();
+    aa.ntgt = ntgt.get();
+    aa.fill = fill.get();
+    aa.segbase = segbase.get();
+    aa.ovtotal = ovtotal.get();
+    aa.ovcount = ovtotal.get() + 1;
+    aa.ovtgts = ovtgts.get();
+    aa.adm = adm.get();
+    aa.cpos = cpos.get();
+    aa.seg = seg.get();
+    aa.csize = csize;
+    aa.moves = (uint64_t*)dmoves.get();
+    aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
+    aa.few = few;
+    return aa;
+  };
+  // Replayed rounds: on a small level the rounds after the first are launch
+  // bound, so one round is captured into a HIP graph and replayed.  Its
+  // launches cannot depend on host-read counts: grids are upper bounds (a
+  // class never holds more nodes than in the first round, as graphs only
+  // stop and node weights are fixed), and the kernels take their counts and
+  // list ranges from the plan k_lp_plan writes on the device.  Hub nodes
+  // (global tables, sized on the host) keep a level on the unplanned path.
+  uint64_t ub[NCLASS] = {};
+  auto plannable = [&]() {
+    for (int c = 0; c < NCLASS; ++c) ub[c] = 0;
+    for (uint32_t i = 0; i < NB; ++i) ub[i % NCLASS] += cnt[i];
+    if (ub[CLASS_GLOBAL]) return false;
+    if (!dense && !packed_ && ub[CLASS_BIG] + ub[CLASS_BIG + 1]) return false;
+    return true;
+  };
+  DBuf<SubPlan> dplan;
+  DBuf<uint32_t> drctr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  auto capture_round = [&]() {
+    dplan.reset(&pool_, s_, S);
+    drctr.reset(&pool_, s_, 1);
+    const hipStream_t cs = capture_stream();
+    const hipStream_t saved = s_;
+    ProfSuspend quiet;
+    uint64_t umax = 0;
+    for (int c = 0; c < NCLASS; ++c) umax += ub[c];
+    HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    s_ = cs;
+    try {
+      k_lp_round<<<1, 256, 0, cs>>>(ctl, 0, drctr.get());
       LAUNCH_CHECK();
+      launch_bucket_count(ba, cs);
+      launch_bucket_offsets(ba, cs);
+      launch_lp_plan(rstate.get(), boffs.get(), S, dense ? 1 : 0, dplan.get(), cs);
+      launch_bucket_scatter(ba, cs);
+      for (uint32_t sr = 0; sr < S; ++sr) {
+        RateArgs ra = rating_args(0);
+        ra.list = list.get();
+        ra.plan = dplan.get() + sr;
+        const int nsmall = dense ? CLASS_BLOCK : GROUP_CLASSES;
+        uint32_t gcnt[GROUP_CLASSES] = {}, goff[GROUP_CLASSES] = {};
+        for (int c = 0; c < nsmall; ++c) gcnt[c] = (uint32_t)ub[c];
+        launch_rate_groups(L.ew_kind, ra, gcnt, goff, 0, cs);
+        auto span = [&](int c0, int c1) {
+          RateArgs r = ra;
+          r.plan_c0 = c0;
+          r.plan_c1 = c1;
+          uint64_t u = 0;
+          for (int c = c0; c <= c1; ++c) u += ub[c];
+          r.count = (uint32_t)u;
+          return r;
+        };
+        if (dense) {
+          launch_rate(CLASS_BLOCK, L.ew_kind, span(CLASS_BLOCK, CLASS_BIG - 1), cs);
+          launch_rate(CLASS_BIG, L.ew_kind, span(CLASS_BIG, CLASS_GLOBAL - 1), cs);
+        } else {
+          for (int c = GROUP_CLASSES; c < CLASS_GLOBAL; ++c)
+            launch_rate(c, L.ew_kind, span(c, c), cs);
+        }
+        AdmitArgs aa = admit_args();
+        aa.plan = dplan.get() + sr;
+        aa.max_cands = (uint32_t)umax;
+        launch_admit(aa, cs);
+        k_lp_after_sub<<<1, 256, 0, cs>>>(ctl);
+        LAUNCH_CHECK();
+      }
+    } catch (...) {
+      s_ = saved;
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
     }
+    s_ = saved;
+    HIP_CHECK(hipStreamEndCapture(cs, &graph));
+    HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    k_set_u32<<<1, 1, 0, s_>>>(drctr.get(), 1);  // the first replayed round
+    LAUNCH_CHECK();
+  };
+  const bool want_replay = p_.graph_rounds && R > 1 && n <= REPLAY_MAX_NODES;
+  bool replay = false;
+  // the active flags the caller gets: those of the last round started (all
+  // clear when the loop stops because no graph is left)
+  std::vector<unsigned long long> hflags(2 * B);
+  bool flags_from_peek = false;
+  try {
+    for (uint32_t r = 0; r < R; ++r) {
+      if (!replay) {
+        begin_round(r);
+        if (r == 0 && p_.tune == LMGP_TUNE_AUTO) autotune();
+        bool any = false;
+        for (uint32_t b = 0; b < B; ++b) any |= hstate[2 * NB + b] != 0;
+        if (!any) break;
+        bucket_offsets();
+        launch_bucket_scatter(ba, s_);
+        for (uint32_t sr = 0; sr < S; ++sr) {
+          uint32_t total = 0;
+          for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
+          if (total == 0) continue;
+          RateArgs ra = rating_args(sr);
+          rate_classes(ra, &cnt[sr * NCLASS], &offs[sr * NCLASS], &degs[sr * NCLASS], L.ew_kind);
+          AdmitArgs aa = admit_args();
+          aa.max_cands = total;
+          launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
+          k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+          LAUNCH_CHECK();
+        }
+        // switch to replay after the first round; the capture waits until a
+        // round is known to follow (a level that stops here pays nothing)
+        if (r == 0 && want_replay && plannable()) replay = true;
+      } else {
+        if (!gexec) capture_round();
+        HIP_CHECK(hipGraphLaunch(gexec, s_));
+      }
+      if (replay && r + 1 < R) {
+        // one copy per round, as on the unplanned path: whether any graph
+        // takes part in the next round
+        k_lp_peek<<<1, 256, 0, s_>>>(ctl);
+        LAUNCH_CHECK();
+        d2h(hflags.data(), rstate.get() + 2 * NB, 2 * B, s_);
+        sync(s_);
+        bool any = false;
+        for (uint32_t b = 0; b < B; ++b) any |= hflags[B + b] != 0;
+        if (!any) {
+          flags_from_peek = true;
+          break;
+        }
+      }
+    }
+  } catch (...) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
   }
   std::vector<unsigned long long> hncl(B);
   d2h(rounds_run.data(), drounds.get(), B, s_);
   if (ncl) d2h(hncl.data(), dncl.get(), B, s_);
+  if (replay && !flags_from_peek) d2h(hflags.data(), rstate.get() + 2 * NB, B, s_);
   sync(s_);
+  if (gexec) HIP_CHECK(hipGraphExecDestroy(gexec));
+  if (graph) HIP_CHECK(hipGraphDestroy(graph));
   if (ncl)
     for (uint32_t b = 0; b < B; ++b) (*ncl)[b] = hncl[b];
-  for (uint32_t b = 0; b < B; ++b) active[b] = hstate[2 * NB + b] != 0;
+  for (uint32_t b = 0; b < B; ++b)
+    active[b] = (!replay ? hstate[2 * NB + b] : flags_from_peek ? hflags[B + b] : hflags[b]) != 0;
 }
 
 // ------------------------------------------------------------ clustering --

@@ -105,6 +105,13 @@ struct RateArgs {
                            // by the admission (block-privatised), not here
   uint32_t trial;          // timing trial: candidates are written, demand and ntgt
                            // are not counted
+  // Planned launch (rounds replayed from a HIP graph): the grid is an upper
+  // bound and the kernel takes its node count and list range from the
+  // device-side plan of its sub-round, for the classes plan_c0..plan_c1 (list
+  // and cands then point at the start of the whole bucket list and of the
+  // sub-round's candidate slots).
+  const struct SubPlan* plan;
+  int plan_c0, plan_c1;
 };
 
 // Label counts up to this use block-privatised LDS histograms in admission
@@ -119,6 +126,21 @@ struct GroupSplit {
   uint32_t off[GROUP_CLASSES];         // list (and candidate slot) offset of each class
   uint32_t count[GROUP_CLASSES];       // nodes of each class
 };
+
+// Launch plan of one LP sub-round, written on the device from the bucket
+// counts and offsets (what the host computes from them otherwise).
+struct SubPlan {
+  GroupSplit gs;              // the merged lane-group launch
+  uint32_t lbase;             // list offset of the sub-round's first bucket
+  uint32_t total;             // nodes listed in the sub-round (candidate slots)
+  uint32_t cnt[NCLASS];       // nodes per class
+  uint32_t off[NCLASS];       // list offset of each class, from lbase
+};
+// Plan of every sub-round: counts/offs are the bucket histogram and its
+// exclusive prefix (S * NCLASS entries); dense: refinement with dense rows
+// (only the lane-group classes go through the merged launch).
+void launch_lp_plan(const unsigned long long* counts, const uint32_t* offs, uint32_t S, int dense,
+                    SubPlan* plan, hipStream_t s);
 
 // One rating launch for a degree class >= CLASS_BLOCK (a.count nodes of a.list).
 void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s);
@@ -176,6 +198,8 @@ struct AdmitArgs {
   uint64_t* moves;         // per graph
   int64_t* ncl_delta;      // per graph (clustering) or NULL
   uint32_t few;            // labels < few <= FEW_LABELS (see RateArgs), else 0
+  const SubPlan* plan;     // planned launch: max_cands is an upper bound, the
+                           // slot count is plan->total
 };
 void launch_admit(const AdmitArgs& a, hipStream_t s);
 

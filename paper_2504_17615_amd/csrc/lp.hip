@@ -154,6 +154,17 @@ LMGP_D int64_t group_sum(int64_t v) {
 // per block, 512 or 1024 slots): all eight share one launch (k_rate_groups).
 constexpr int GROUP_SLOTS = 1024;
 
+// Planned launch: node count and list range from the sub-round's plan.
+LMGP_D void resolve_plan(RateArgs& r) {
+  if (!r.plan) return;
+  const SubPlan& p = *r.plan;
+  uint32_t cnt = 0;
+  for (int c = r.plan_c0; c <= r.plan_c1; ++c) cnt += p.cnt[c];
+  r.count = cnt;
+  r.list = r.list + p.lbase + p.off[r.plan_c0];
+  if (r.cands) r.cands = r.cands + p.off[r.plan_c0];
+}
+
 template <int G, int EWK>
 LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sval,
                        uint64_t blk) {
@@ -322,10 +333,12 @@ LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val
 }
 
 template <int EWK, int LOGT>
-__global__ __launch_bounds__(256) void k_rate_block(RateArgs a) {
+__global__ __launch_bounds__(256) void k_rate_block(RateArgs a0) {
   __shared__ uint32_t key[1 << LOGT];
   __shared__ unsigned long long val[1 << LOGT];
   __shared__ BlockScratch bs;
+  RateArgs a = a0;
+  resolve_plan(a);
   rate_block<EWK, LOGT>(a, key, val, bs, blockIdx.x);
 }
 
@@ -338,15 +351,19 @@ __global__ __launch_bounds__(256) void k_rate_groups(RateArgs a, GroupSplit spli
   __shared__ unsigned long long sval[GROUP_SLOTS];
   __shared__ BlockScratch bs;
   const uint32_t b = blockIdx.x;
+  // planned launch: the split comes from the device and the grid is an upper bound
+  const GroupSplit& sp = a.plan ? a.plan->gs : split;
+  if (b >= sp.bstart[GROUP_CLASSES]) return;
   int c = 0;
 #pragma unroll
   for (int q = 1; q < GROUP_CLASSES; ++q)
-    if (b >= split.bstart[q]) c = q;
+    if (b >= sp.bstart[q]) c = q;
   RateArgs r = a;
-  r.list = a.list + split.off[c];
-  if (a.mode == MODE_LP) r.cands = a.cands + split.off[c];
-  r.count = split.count[c];
-  const uint64_t blk = b - split.bstart[c];
+  r.plan = nullptr;
+  r.list = a.list + (a.plan ? a.plan->lbase : 0u) + sp.off[c];
+  if (a.mode == MODE_LP) r.cands = a.cands + sp.off[c];
+  r.count = sp.count[c];
+  const uint64_t blk = b - sp.bstart[c];
   switch (c) {
     case 0: rate_group<2, EWK>(r, skey, sval, blk); break;
     case 1: rate_group<4, EWK>(r, skey, sval, blk); break;
@@ -404,7 +421,7 @@ LMGP_D void lds_add_packed_n(unsigned long long* tab, uint32_t K, unsigned long 
 // fit a CU), 16384 for degree <= 8192.  Own-label entries are summed in
 // registers.
 template <int EWK, int LOGT>
-__global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
+__global__ __launch_bounds__(1024) void k_rate_big(RateArgs a0) {
   constexpr int NW = 1024 / WAVE;
   constexpr int T = 1 << LOGT;
   constexpr int logt = LOGT;
@@ -412,6 +429,8 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
   __shared__ Best sb[NW];
   __shared__ int64_t so[NW];
   __shared__ int64_t sm[NW];
+  RateArgs a = a0;
+  resolve_plan(a);
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
@@ -489,12 +508,14 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a) {
 // and big-block classes rate into a dense LDS row indexed by the label, with
 // no hashing and no probing; NT threads per node.
 template <int EWK, int NT>
-__global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a) {
+__global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a0) {
   constexpr int NW = NT / WAVE;
   __shared__ unsigned long long tab[FEW_LABELS];
   __shared__ Best sb[NW];
   __shared__ int64_t so[NW];
   __shared__ int64_t sm[NW];
+  RateArgs a = a0;
+  resolve_plan(a);
   const uint64_t idx = blockIdx.x;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
@@ -1018,8 +1039,7 @@ void launch_groups_t(const RateArgs& a, const uint32_t* count, const uint32_t* o
   const char* ph[3] = {"cl:", "rf:", "fv:"};
   ProfLaunch prof((std::string(ph[a.phase]) + "k_rate_groups<" + std::to_string(EWK) + ">").c_str(),
                   rate_bytes(EWK, total, degsum));
-  hipExtLaunchKernelGGL(k_rate_groups<EWK>, dim3(blocks), dim3(256), 0, s, prof.start(),
-                        prof.stop(), 0, a, split);
+  launch_k(k_rate_groups<EWK>, dim3(blocks), dim3(256), s, prof.start(), prof.stop(), a, split);
   LAUNCH_CHECK();
 }
 
@@ -1034,21 +1054,21 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
     throw InvalidArg("lane-group classes are launched by launch_rate_groups");
   } else if (a.few && a.few <= FEW_LABELS && a.mode == MODE_LP && cls < CLASS_GLOBAL) {
     if (cls < CLASS_BIG)
-      hipExtLaunchKernelGGL(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), 0, s, e0, e1, 0, a);
+      launch_k(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), s, e0, e1, a);
     else
-      hipExtLaunchKernelGGL(k_rate_dense<EWK, 1024>, dim3(a.count), dim3(1024), 0, s, e0, e1, 0, a);
+      launch_k(k_rate_dense<EWK, 1024>, dim3(a.count), dim3(1024), s, e0, e1, a);
   } else if (cls < CLASS_BIG) {
     const dim3 grid(a.count), blk(256);
     switch (cls - CLASS_BLOCK) {
       case 0: case 1: throw InvalidArg("block classes 6, 7 are launched by launch_rate_groups");
-      case 2: hipExtLaunchKernelGGL(k_rate_block<EWK, 11>, grid, blk, 0, s, e0, e1, 0, a); break;
-      default: hipExtLaunchKernelGGL(k_rate_block<EWK, 12>, grid, blk, 0, s, e0, e1, 0, a); break;
+      case 2: launch_k(k_rate_block<EWK, 11>, grid, blk, s, e0, e1, a); break;
+      default: launch_k(k_rate_block<EWK, 12>, grid, blk, s, e0, e1, a); break;
     }
   } else if (is_big_class(cls)) {
     if (!a.packed) throw InvalidArg("big-block class needs packed ratings");
     const dim3 grid(a.count), blk(1024);
-    if (cls == CLASS_BIG) hipExtLaunchKernelGGL(k_rate_big<EWK, 13>, grid, blk, 0, s, e0, e1, 0, a);
-    else hipExtLaunchKernelGGL(k_rate_big<EWK, 14>, grid, blk, 0, s, e0, e1, 0, a);
+    if (cls == CLASS_BIG) launch_k(k_rate_big<EWK, 13>, grid, blk, s, e0, e1, a);
+    else launch_k(k_rate_big<EWK, 14>, grid, blk, s, e0, e1, a);
   } else {
     throw InvalidArg("hub class needs launch_rate_hubs");
   }
@@ -1292,6 +1312,36 @@ __global__ void k_bucket_offsets(BucketArgs a) {
   }
 }
 
+// One thread per sub-round: the launch plan the host derives from the bucket
+// counts in an unplanned round (launch_groups_t, rate_classes).
+__global__ void k_lp_plan(const unsigned long long* counts, const uint32_t* offs, uint32_t S,
+                          int dense, SubPlan* plan) {
+  const uint32_t sr = threadIdx.x;
+  if (sr >= S) return;
+  SubPlan p{};
+  const uint32_t* o = offs + sr * NCLASS;
+  p.lbase = o[0];
+  uint32_t total = 0;
+  for (int c = 0; c < NCLASS; ++c) {
+    p.cnt[c] = (uint32_t)counts[sr * NCLASS + c];
+    p.off[c] = o[c] - o[0];
+    total += p.cnt[c];
+  }
+  p.total = total;
+  const int nsmall = dense ? CLASS_BLOCK : GROUP_CLASSES;
+  uint32_t blocks = 0;
+  for (int c = 0; c < GROUP_CLASSES; ++c) {
+    const uint32_t n = c < nsmall ? p.cnt[c] : 0u;
+    p.gs.bstart[c] = blocks;
+    p.gs.off[c] = p.off[c];
+    p.gs.count[c] = n;
+    const uint32_t per = c < CLASS_BLOCK ? 256u / (uint32_t)class_group(c) : 1u;
+    blocks += (n + per - 1) / per;
+  }
+  p.gs.bstart[GROUP_CLASSES] = blocks;
+  plan[sr] = p;
+}
+
 // Each block takes 2048 consecutive nodes, counts them per bucket in LDS and
 // reserves its range of every bucket with one atomic (order inside a bucket
 // does not affect any result).
@@ -1336,7 +1386,7 @@ __global__ __launch_bounds__(256) void k_adm_count_few(AdmitArgs a) {
     sn[t] = 0;
   }
   __syncthreads();
-  const uint32_t nc = a.max_cands;
+  const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
 #pragma unroll
   for (int j = 0; j < ADM_ITEMS; ++j) {
@@ -1361,7 +1411,7 @@ __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
   __shared__ uint32_t cnt[FEW_LABELS], base[FEW_LABELS];
   for (uint32_t t = threadIdx.x; t < a.few; t += 256) cnt[t] = 0;
   __syncthreads();
-  const uint32_t nc = a.max_cands;
+  const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
   uint32_t tg[ADM_ITEMS], lp[ADM_ITEMS];
 #pragma unroll
@@ -1412,7 +1462,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
     }
   }
   __syncthreads();
-  const uint32_t nc = a.max_cands;
+  const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * ADM_ITEMS;
   uint64_t mv = 0;
 #pragma unroll
@@ -1448,7 +1498,7 @@ __global__ void k_adm_reset_few(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
-  const uint32_t nc = a.max_cands;
+  const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc) return;
   const Cand c = a.cands[i];
@@ -1472,7 +1522,7 @@ __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_scatter(AdmitArgs a) {
-  const uint32_t nc = a.max_cands;
+  const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc || a.adm[i]) return;
   const uint32_t t = a.cands[i].tgt;
@@ -1684,7 +1734,7 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
-  const uint32_t nc = a.max_cands;
+  const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t mv = 0;
   int64_t dl = 0;
@@ -1771,6 +1821,13 @@ void launch_bucket_count(const BucketArgs& a, hipStream_t s) {
 void launch_bucket_offsets(const BucketArgs& a, hipStream_t s) {
   if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
   k_bucket_offsets<<<1, 64, 0, s>>>(a);
+  LAUNCH_CHECK();
+}
+
+void launch_lp_plan(const unsigned long long* counts, const uint32_t* offs, uint32_t S, int dense,
+                    SubPlan* plan, hipStream_t s) {
+  if (S > 32 || S * NCLASS > MAX_BUCKETS) throw InvalidArg("too many sub-rounds for a plan");
+  k_lp_plan<<<1, 64, 0, s>>>(counts, offs, S, dense, plan);
   LAUNCH_CHECK();
 }
 

@@ -22,7 +22,12 @@ struct KernelStat {
 class Profiler {
  public:
   static Profiler& get();
-  bool on() const { return on_.load(std::memory_order_relaxed); }
+  bool on() const { return on_.load(std::memory_order_relaxed) && !suspended(); }
+  // Time only the launches of one kernel: `kernel` is the part of a family
+  // name after its phase prefix ("k_rate_big<2, 13>"); empty = every launch.
+  void set_filter(const std::string& kernel);
+  bool wants(const char* family);
+  static bool& suspended();
   void enable(bool v) { on_.store(v); }
   // Record the start of a launch; returns a slot id (or -1 when disabled).
   int begin(const char* name, uint64_t bytes, hipStream_t s);
@@ -47,6 +52,7 @@ class Profiler {
   std::vector<Rec> pending_;
   std::vector<hipEvent_t> free_;
   std::map<std::string, KernelStat> stats_;
+  std::string filter_;
 };
 
 // RAII bracket of one launch.
@@ -54,7 +60,7 @@ class ProfScope {
  public:
   ProfScope(const char* name, uint64_t bytes, hipStream_t s) : s_(s) {
     Profiler& p = Profiler::get();
-    slot_ = p.on() ? p.begin(name, bytes, s) : -1;
+    slot_ = p.on() && p.wants(name) ? p.begin(name, bytes, s) : -1;
   }
   ~ProfScope() {
     if (slot_ >= 0) Profiler::get().end(slot_, s_);
@@ -71,13 +77,34 @@ class ProfLaunch {
  public:
   ProfLaunch(const char* name, uint64_t bytes) {
     Profiler& p = Profiler::get();
-    if (p.on()) p.begin_ext(name, bytes, &a_, &b_);
+    if (p.on() && p.wants(name)) p.begin_ext(name, bytes, &a_, &b_);
   }
   hipEvent_t start() const { return a_; }
   hipEvent_t stop() const { return b_; }
 
  private:
   hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+// Launch that timestamps itself when given events (profiling), else a plain
+// launch (the form a stream capture records).
+template <typename... Args>
+void launch_k(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0,
+              hipEvent_t e1, Args... args) {
+  if (e0) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+    return;
+  }
+  void* ptrs[] = {(void*)&args...};
+  HIP_CHECK(hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, 0, s));
+}
+
+// Suspends profiling on the calling thread (launches recorded into a graph
+// cannot carry event timestamps).
+class ProfSuspend {
+ public:
+  ProfSuspend();
+  ~ProfSuspend();
 };
 
 }  // namespace lmgp

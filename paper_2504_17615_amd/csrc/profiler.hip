@@ -77,12 +77,37 @@ void Profiler::reset() {
   stats_.clear();
 }
 
+void Profiler::set_filter(const std::string& kernel) {
+  std::lock_guard<std::mutex> g(mu_);
+  filter_ = kernel;
+}
+
+bool Profiler::wants(const char* family) {
+  std::lock_guard<std::mutex> g(mu_);
+  if (filter_.empty()) return true;
+  const char* k = std::strchr(family, ':');
+  return filter_ == (k ? k + 1 : family);
+}
+
+bool& Profiler::suspended() {
+  static thread_local bool v = false;
+  return v;
+}
+
+ProfSuspend::ProfSuspend() { Profiler::suspended() = true; }
+ProfSuspend::~ProfSuspend() { Profiler::suspended() = false; }
+
 }  // namespace lmgp
 
 extern "C" {
 
 lmgp_status lmgp_profile_enable(uint32_t on) {
   lmgp::Profiler::get().enable(on != 0);
+  return LMGP_OK;
+}
+
+lmgp_status lmgp_profile_filter(const char* kernel) {
+  lmgp::Profiler::get().set_filter(kernel ? kernel : "");
   return LMGP_OK;
 }
 

@@ -69,3 +69,19 @@ def test_committed_traffic_record_is_well_formed():
     assert os.path.exists(os.path.join(bench.ROOT, rec["source"]))
     for k, v in rec["kernels"].items():
         assert v["hbm_bytes_per_launch"] >= 0 and v["dispatches"] > 0
+
+
+def test_roofline_with_breakdown_from_a_separate_step():
+    # timed region: only the dominant kernel's launches carry events
+    timed = {"cl:k_rate_big<2>": {"launches": 30, "total_ns": 3_000_000, "bytes": 6_000_000_000}}
+    warm = {
+        "cl:k_rate_big<2>": {"launches": 10, "total_ns": 1_000_000, "bytes": 2_000_000_000},
+        "rf:k_rate_block<0>": {"launches": 4, "total_ns": 500_000, "bytes": 100},
+    }
+    assert bench.dominant_kernel(warm) == "k_rate_big<2>"
+    r = bench.roofline(timed, steps=3, wall=0.01, workload="none", breakdown=warm)
+    assert r["kernel"] == "k_rate_big<2>" and r["launches"] == 30
+    assert abs(r["achieved"] - 2000.0) < 0.1
+    assert set(r["kernels"]) == {"k_rate_big<2>", "k_rate_block<0>"}
+    assert r["kernels"]["k_rate_big<2>"]["ms_per_step"] == 1.0  # one warm-up step
+    assert r["lp_rate_all"]["share_of_step"] == round(1.5e6 / 1e9 / 0.01, 3)
