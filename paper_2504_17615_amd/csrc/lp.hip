@@ -416,13 +416,15 @@ LMGP_D void lds_add_packed_n(unsigned long long* tab, uint32_t K, unsigned long 
   }
 }
 
-// One 1024-thread block per node of degree in (2048, 8192], packed LDS table
-// of 2^LOGT slots: 8192 slots for degree <= 6144 (load <= 3/4, two blocks
-// fit a CU), 16384 for degree <= 8192.  Own-label entries are summed in
-// registers.
-template <int EWK, int LOGT>
-__global__ __launch_bounds__(1024) void k_rate_big(RateArgs a0) {
-  constexpr int NW = 1024 / WAVE;
+// One block of NT threads per node, packed LDS table of 2^LOGT slots: 8192
+// slots for degree <= 6144 (load <= 3/4, two 1024-thread blocks fit a CU),
+// 16384 for degree <= 8192; with packed ratings the block classes use it too
+// (2048 slots / 256 threads, 4096 slots / 512 threads: half the LDS of a
+// key + value table, so twice the nodes in flight per CU).  Own-label entries
+// are summed in registers.
+template <int EWK, int LOGT, int NT>
+__global__ __launch_bounds__(NT) void k_rate_big(RateArgs a0) {
+  constexpr int NW = NT / WAVE;
   constexpr int T = 1 << LOGT;
   constexpr int logt = LOGT;
   __shared__ unsigned long long tab[T];
@@ -439,22 +441,22 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a0) {
     return;
   }
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
-  for (int s = threadIdx.x; s < T; s += 1024) tab[s] = EMPTY_SLOT;
+  for (int s = threadIdx.x; s < T; s += NT) tab[s] = EMPTY_SLOT;
   __syncthreads();
   const uint32_t own = a.label[u];
   int64_t acc = 0;
   constexpr int U = 8;  // entries per thread whose loads are issued together
-  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * 1024) {
+  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * NT) {
     uint32_t v[U], K[U];
     int64_t w[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const uint64_t e = e0 + (uint64_t)j * 1024;
+      const uint64_t e = e0 + (uint64_t)j * NT;
       v[j] = e < end ? a.adj[e] : 0u;
       w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * 1024 < end ? a.label[v[j]] : EMPTY_KEY;
+    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * NT < end ? a.label[v[j]] : EMPTY_KEY;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (K[j] == EMPTY_KEY) continue;
@@ -472,11 +474,11 @@ __global__ __launch_bounds__(1024) void k_rate_big(RateArgs a0) {
   Best best{0, 0, 0};
   int64_t r_own = 0;
   constexpr int SB = 8;  // slots per thread whose W gathers are issued together
-  for (int s0 = threadIdx.x; s0 < T; s0 += SB * 1024) {
+  for (int s0 = threadIdx.x; s0 < T; s0 += SB * NT) {
     unsigned long long v[SB];
     int64_t wk[SB];
 #pragma unroll
-    for (int j = 0; j < SB; ++j) v[j] = s0 + j * 1024 < T ? tab[s0 + j * 1024] : EMPTY_SLOT;
+    for (int j = 0; j < SB; ++j) v[j] = s0 + j * NT < T ? tab[s0 + j * NT] : EMPTY_SLOT;
 #pragma unroll
     for (int j = 0; j < SB; ++j) {
       const uint32_t K = (uint32_t)(v[j] >> 32);
@@ -996,7 +998,7 @@ struct HubSlotChunks {
 // Profiler family of a rating launch: phase, degree class, edge-weight type
 // (e.g. "cl_rate_block_i64" for clustering, "rf_" refinement, "fv_" 2-hop
 // favourites).
-std::string rate_name(int phase, int cls, int ewk, bool few) {
+std::string rate_name(int phase, int cls, int ewk, bool few, bool packed) {
   // "<phase>:<kernel>": the kernel part is the HIP kernel's template name, so
   // that event timings line up with a kernel trace; the hub class brackets
   // several kernels and is named rate_hubs
@@ -1006,10 +1008,11 @@ std::string rate_name(int phase, int cls, int ewk, bool few) {
   if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_GLOBAL)
     k = "k_rate_dense<" + std::to_string(w) + ", " + (cls < CLASS_BIG ? "256>" : "1024>");
   else if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
-  else if (cls < CLASS_BIG)
+  else if (cls < CLASS_BIG && !(packed && cls >= CLASS_BLOCK + 2))
     k = "k_rate_block<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ">";
-  else if (is_big_class(cls))
-    k = "k_rate_big<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ">";
+  else if (cls < CLASS_GLOBAL)
+    k = "k_rate_big<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ", " +
+        (cls == CLASS_BLOCK + 2 ? "256>" : cls == CLASS_BLOCK + 3 ? "512>" : "1024>");
   else k = "rate_hubs<" + std::to_string(w) + ">";
   return std::string(ph[phase]) + k;
 }
@@ -1048,7 +1051,8 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (a.count == 0) return;
   // single-kernel classes: the launch timestamps its own start and end
   const bool few = a.few && a.few <= FEW_LABELS && a.mode == MODE_LP;
-  ProfLaunch prof(rate_name(a.phase, cls, EWK, few).c_str(), rate_bytes(EWK, a.count, a.degsum));
+  ProfLaunch prof(rate_name(a.phase, cls, EWK, few, a.packed != 0).c_str(),
+                  rate_bytes(EWK, a.count, a.degsum));
   const hipEvent_t e0 = prof.start(), e1 = prof.stop();
   if (cls < CLASS_BLOCK) {
     throw InvalidArg("lane-group classes are launched by launch_rate_groups");
@@ -1057,6 +1061,11 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
       launch_k(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), s, e0, e1, a);
     else
       launch_k(k_rate_dense<EWK, 1024>, dim3(a.count), dim3(1024), s, e0, e1, a);
+  } else if (cls < CLASS_BIG && a.packed && cls >= CLASS_BLOCK + 2) {
+    if (cls == CLASS_BLOCK + 2)
+      launch_k(k_rate_big<EWK, 11, 256>, dim3(a.count), dim3(256), s, e0, e1, a);
+    else
+      launch_k(k_rate_big<EWK, 12, 512>, dim3(a.count), dim3(512), s, e0, e1, a);
   } else if (cls < CLASS_BIG) {
     const dim3 grid(a.count), blk(256);
     switch (cls - CLASS_BLOCK) {
@@ -1067,8 +1076,8 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   } else if (is_big_class(cls)) {
     if (!a.packed) throw InvalidArg("big-block class needs packed ratings");
     const dim3 grid(a.count), blk(1024);
-    if (cls == CLASS_BIG) launch_k(k_rate_big<EWK, 13>, grid, blk, s, e0, e1, a);
-    else launch_k(k_rate_big<EWK, 14>, grid, blk, s, e0, e1, a);
+    if (cls == CLASS_BIG) launch_k(k_rate_big<EWK, 13, 1024>, grid, blk, s, e0, e1, a);
+    else launch_k(k_rate_big<EWK, 14, 1024>, grid, blk, s, e0, e1, a);
   } else {
     throw InvalidArg("hub class needs launch_rate_hubs");
   }
@@ -1161,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_hub_few_final(HubArgs h, const unsigned
 template <int EWK>
 void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   const uint32_t c = ra.count;
-  ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK, false).c_str(),
+  ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK, false, false).c_str(),
                  rate_bytes(EWK, ra.count, ra.degsum), s);
   // LMGP_HUB_TABLES=global forces the chunked global-table path (taken when
   // ratings do not fit 32 bits); =repair makes every label range report an
