@@ -168,13 +168,14 @@ def bench_batch(args) -> dict:
     dgs = [L.create_graph(g) for _ in range(B)]
     ks, eps, seeds = [4] * B, [0.03] * B, list(range(1, B + 1))
     outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(B)]
+    prm = L.default_params(ip_device=args.ip_device)
     for _ in range(args.warmup):
-        L.partition_batch(dgs, ks, eps, seeds, outs=outs)
+        L.partition_batch(dgs, ks, eps, seeds, prm, outs=outs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = []
     for _ in range(args.steps):
-        _, r = L.partition_batch(dgs, ks, eps, seeds, outs=outs)
+        _, r = L.partition_batch(dgs, ks, eps, seeds, prm, outs=outs)
         res.append(r[0])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
@@ -188,7 +189,7 @@ def bench_batch(args) -> dict:
     t0 = time.perf_counter()
     pcr = 0.0
     for i in range(P):
-        _, r = dgs[i].partition(4, 0.03, seeds[i], out=outs[i])
+        _, r = dgs[i].partition(4, 0.03, seeds[i], prm, out=outs[i])
         pcr += (r["t_coarsen_ns"] + r["t_refine_ns"]) * 1e-9
     torch.cuda.synchronize()
     pwall = (time.perf_counter() - t0) / P
@@ -200,6 +201,9 @@ def bench_batch(args) -> dict:
         "config": {"workload": f"grid128 x {B}", "description": f"{B} 128x128 grids, seeds 1..{B}, "
                    "k=4, eps=0.03, one batched call per step", "graphs": B, "m_total": m_tot},
         "graphs_per_s": B / wall, "wall_edges_per_s": m_tot / wall,
+        "phases_ms": {p: round(sum(r[f"t_{p}_ns"] for r in res) / len(res) * 1e-6, 3)
+                      for p in ("coarsen", "initial", "refine")},
+        "ip_device": args.ip_device,
         "plain": {"graphs": P, "edges_per_s": g.m / (pcr / P), "graphs_per_s": 1.0 / pwall,
                   "ms_per_graph": pwall * 1e3},
         "batch_vs_plain_graphs_per_s": (B / wall) / (1.0 / pwall),
@@ -246,14 +250,15 @@ def bench_serve(args) -> dict:
     t_gen = time.perf_counter() - t_gen
     dgs = [L.create_graph(g) for g, _, _, _ in reqs]
     m_tot = sum(g.m for g, _, _, _ in reqs)
+    prm = L.default_params(ip_device=args.ip_device)
     for i in range(min(8, len(reqs))):
-        dgs[i].partition(reqs[i][1], reqs[i][2], reqs[i][3], host_out=True)
+        dgs[i].partition(reqs[i][1], reqs[i][2], reqs[i][3], prm, host_out=True)
     torch.cuda.synchronize()
     # plain capacity: per-request service times on one stream
     svc = []
     for dg, (g, k, eps, seed) in zip(dgs, reqs):
         t0 = time.perf_counter()
-        dg.partition(k, eps, seed, host_out=True)
+        dg.partition(k, eps, seed, prm, host_out=True)
         svc.append(time.perf_counter() - t0)
     mu = len(reqs) / sum(svc)
     lam = args.load * mu
@@ -264,7 +269,8 @@ def bench_serve(args) -> dict:
     for a, s in zip(arrivals, svc):
         fin = max(fin, a) + s
         plain_lat.append(fin - a)
-    srv = L.Server(hbm_budget_bytes=args.hbm_budget_gib << 30, max_slots=args.slots,
+    srv = L.Server(ip_device=args.ip_device, hbm_budget_bytes=args.hbm_budget_gib << 30,
+                   max_slots=args.slots,
                    max_batch=args.max_batch, streams=args.streams)
     tickets = [None] * len(reqs)
     done = [0.0] * len(reqs)
@@ -416,6 +422,8 @@ def main():
                          "timed during the warm-up calls) or a table index")
     ap.add_argument("--graph-rounds", type=int, default=0, choices=[0, 1],
                     help="replay the LP rounds of small levels from HIP graphs")
+    ap.add_argument("--ip-device", type=int, default=2, choices=[0, 1, 2],
+                    help="initial partitioning: 0 host, 1 device, 2 automatic (default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -445,7 +453,7 @@ def main():
     out = torch.empty(dev.n, dtype=torch.int32, device="cuda")
     tune = {"off": 0, "auto": 1}.get(args.tune)
     prm = L.default_params(tune=16 + int(args.tune) if tune is None else tune,
-                           graph_rounds=args.graph_rounds)
+                           graph_rounds=args.graph_rounds, ip_device=args.ip_device)
     # The last warm-up call times every rating launch (the per-kernel
     # breakdown); the timed calls time only the dominant kernel, so that event
     # timing of the other launches does not slow the measured steps.
@@ -506,7 +514,7 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "n": dev.n, "m": m, "k": k, "eps": eps, "seed": seed,
                    "parallelism": "single GPU", "tune": args.tune,
-                   "graph_rounds": args.graph_rounds},
+                   "graph_rounds": args.graph_rounds, "ip_device": args.ip_device},
         "phases_ms": {p: round(v, 3) for p, v in ph.items()},
         "wall_edges_per_s": m / wall,
         "cut": results[-1]["cut"],

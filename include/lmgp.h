@@ -114,7 +114,19 @@ typedef struct {
                                   * round, counts planned on the device); 0 = every
                                   * round launched kernel by kernel.  No effect on any
                                   * result, only on launch overhead.                 */
+  uint32_t ip_device;            /* initial partitioning (Sec. 4.3's recursive
+                                  * bipartitioning, greedy growing): LMGP_IP_HOST (0)
+                                  * on the host; LMGP_IP_DEVICE (1) on the device, the
+                                  * subproblems of one recursion depth concurrently, one
+                                  * workgroup each; LMGP_IP_AUTO (2, default) on the
+                                  * device when at least 16 graphs of a batch share their
+                                  * coarsest level, else on the host.  Same result
+                                  * either way.                                       */
 } lmgp_params;
+
+#define LMGP_IP_HOST 0u
+#define LMGP_IP_DEVICE 1u
+#define LMGP_IP_AUTO 2u
 
 #define LMGP_TUNE_OFF 0u
 #define LMGP_TUNE_AUTO 1u
@@ -156,7 +168,7 @@ typedef struct {
   uint32_t max_slots;         /* requests resident at once                          */
   uint32_t max_batch;         /* requests fused into one batched run                */
   uint32_t streams;           /* concurrent device streams (worker threads)         */
-  uint32_t pad;
+  uint32_t ip_device;         /* lmgp_params.ip_device of every batched run          */
 } lmgp_server_cfg;
 
 void lmgp_default_params(lmgp_params *out);

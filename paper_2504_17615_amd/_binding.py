@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_uint32) for nm in (
         "tau_e_num", "tau_e_den", "tau_d_num", "tau_d_den", "rho_num", "rho_den", "sampler",
         "clim", "shrink_num", "shrink_den", "lp_rounds", "ref_rounds", "subrounds",
-        "max_levels", "stop_num", "stop_den", "tune", "graph_rounds")]
+        "max_levels", "stop_num", "stop_den", "tune", "graph_rounds", "ip_device")]
 
 
 class CsrView(ctypes.Structure):
@@ -67,7 +67,7 @@ class Result(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("ip_device", ctypes.c_uint32)]
 
 
 _SIGS = {
@@ -387,8 +387,8 @@ class Server:
     """Serving loop: submit partition requests, poll or wait for results."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, max_batch: int = 32,
-                 streams: int = 2):
-        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_batch, streams, 0)
+                 streams: int = 2, ip_device: int = 2):
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_batch, streams, ip_device)
         h = ctypes.c_void_p()
         _check(library().lmgp_server_create(ctypes.byref(cfg), None, ctypes.byref(h)))
         self._h = h

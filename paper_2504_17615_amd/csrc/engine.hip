@@ -13,6 +13,7 @@
 #include <initializer_list>
 
 #include "engine.h"
+#include "initial.h"
 #include "profiler.h"
 #include "tuner.h"
 
@@ -119,6 +120,10 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 // Levels (unions) up to this many nodes replay their LP rounds from a graph
 // when asked: above it the rounds are long enough to hide their launches.
 constexpr uint64_t REPLAY_MAX_NODES = 1ull << 18;
+
+// Graphs sharing a coarsest level from which the automatic choice bisects
+// them on the device.
+constexpr uint32_t IP_DEVICE_MIN_GRAPHS = 16;
 
 // Stream on which replayed rounds are captured (capture needs a stream other
 // than the null stream; nothing is executed on it), one per thread and device.
@@ -303,6 +308,7 @@ lmgp_params default_params() {
   p.stop_num = 19, p.stop_den = 20;
   p.tune = LMGP_TUNE_OFF;
   p.graph_rounds = 0;
+  p.ip_device = LMGP_IP_AUTO;
   return p;
 }
 
@@ -318,6 +324,7 @@ void check_params(const lmgp_params& p) {
   if (p.tune > LMGP_TUNE_AUTO && p.tune < LMGP_TUNE_FORCE)
     throw InvalidArg("tune must be 0 (default classes), 1 (autotune) or 16 + preset");
   if (p.graph_rounds > 1) throw InvalidArg("graph_rounds must be 0 or 1");
+  if (p.ip_device > LMGP_IP_AUTO) throw InvalidArg("ip_device must be 0, 1 or 2");
 }
 
 // ----------------------------------------------------------------- union --
@@ -1170,10 +1177,71 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
   for (uint32_t g = 0; g < NJ; ++g) kbase[g + 1] = kbase[g] + jobs[g].k;
   const uint64_t Ktot = kbase[NJ];
   Timer tm(s_);
-  // initial partitioning of every graph's coarsest level, on the host
+  // initial partitioning of every graph's coarsest level: on the device, all
+  // graphs whose coarsest level is level j at once, or on the host
   tm.start();
   std::vector<std::vector<uint32_t>> ip(NJ);
+  std::vector<DBuf<uint32_t>> ipdev(levels_.size());
+  std::vector<uint8_t> on_dev_ip(NJ, 0);
+  if (p_.ip_device) {
+    for (size_t j = 0; j < levels_.size(); ++j) {
+      Level& L = *levels_[j];
+      const uint32_t B = (uint32_t)L.graphs.size();
+      std::vector<uint32_t> gbase(B, IP_NONE);
+      bool any = false;
+      for (uint32_t b = 0; b < B; ++b) {
+        const uint32_t g = L.graphs[b];
+        if (jobs[g].nlevels - 1 == j) {
+          gbase[b] = (uint32_t)kbase[g];
+          any = true;
+        }
+      }
+      // block ids, node ids and frontier ranks are 32-bit in the device search
+      if (!any || L.nnz >= (1ull << 32) || L.n >= (1ull << 31) || Ktot >= IP_NONE) continue;
+      // automatic choice: the device search gives each subproblem one
+      // workgroup, which pays when many graphs are bisected side by side; a
+      // few large coarsest levels are faster on the host's cores
+      uint32_t taking = 0;
+      for (uint32_t b = 0; b < B; ++b) taking += gbase[b] != IP_NONE;
+      if (p_.ip_device == LMGP_IP_AUTO && taking < IP_DEVICE_MIN_GRAPHS) continue;
+      ipdev[j].reset(&pool_, s_, L.n ? L.n : 1);
+      DBuf<uint32_t> dgb(&pool_, s_, B);
+      h2d(dgb.get(), gbase.data(), B, s_);
+      ip_device_init(L.gid, dgb.get(), L.n, ipdev[j].get(), s_);
+      IpDevice ipd(IpLevel{L.xadj, L.adj, L.nw, L.gid, L.n}, ipdev[j].get(), Ktot, pool_, s_);
+      struct Part {
+        uint32_t b, off, kS;
+      };
+      std::vector<Part> cur;
+      for (uint32_t b = 0; b < B; ++b)
+        if (gbase[b] != IP_NONE) {
+          cur.push_back(Part{b, 0, jobs[L.graphs[b]].k});
+          on_dev_ip[L.graphs[b]] = 1;
+        }
+      while (true) {
+        std::vector<IpSub> subs;
+        std::vector<uint32_t> sob(Ktot, IP_NONE);
+        std::vector<Part> next;
+        for (const Part& q : cur) {
+          if (q.kS <= 1) continue;
+          const Job& jb = jobs[L.graphs[q.b]];
+          const uint32_t k1 = (q.kS + 1) / 2;
+          sob[kbase[L.graphs[q.b]] + q.off] = (uint32_t)subs.size();
+          subs.push_back(IpSub{chain(jb.seed, TAG_IP, {(uint64_t)j + 1, (uint64_t)q.off,
+                                                       (uint64_t)q.kS}),
+                               L.nbase[q.b], q.kS, k1});
+          next.push_back(Part{q.b, q.off, k1});
+          next.push_back(Part{q.b, q.off + k1, q.kS - k1});
+        }
+        if (subs.empty()) break;
+        ipd.depth(subs, sob);
+        cur.swap(next);
+      }
+      ipd.finish();
+    }
+  }
   for (uint32_t g = 0; g < NJ; ++g) {
+    if (on_dev_ip[g]) continue;
     const uint32_t top = jobs[g].nlevels - 1;
     Level& L = *levels_[top];
     uint32_t b = 0;
@@ -1200,10 +1268,13 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
   for (int j = (int)levels_.size() - 1; j >= 0; --j) {
     Level& L = *levels_[j];
     const uint32_t B = (uint32_t)L.graphs.size();
-    DBuf<uint32_t> block(&pool_, s_, L.n ? L.n : 1);
+    DBuf<uint32_t> block;
+    if (ipdev[j].get()) block = std::move(ipdev[j]);  // graphs initially partitioned here
+    else block.reset(&pool_, s_, L.n ? L.n : 1);
     for (uint32_t b = 0; b < B; ++b) {
       const uint32_t g = L.graphs[b];
-      if (jobs[g].nlevels - 1 == (uint32_t)j) h2d(block.get() + L.nbase[b], ip[g].data(), ip[g].size(), s_);
+      if (jobs[g].nlevels - 1 == (uint32_t)j && !on_dev_ip[g])
+        h2d(block.get() + L.nbase[b], ip[g].data(), ip[g].size(), s_);
     }
     if ((size_t)j + 1 < levels_.size()) project_blocks(L.map.get(), upper.get(), L.n, block.get(), s_);
     BW.zero();

@@ -75,7 +75,8 @@ void worker_main(lmgp_server* sv) {
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
   Pool pool(sv->have_alloc ? &sv->alloc : nullptr);
-  const lmgp_params p = default_params();
+  lmgp_params p = default_params();
+  p.ip_device = sv->cfg.ip_device <= LMGP_IP_AUTO ? sv->cfg.ip_device : LMGP_IP_AUTO;
   while (true) {
     std::vector<Request*> batch;
     uint64_t bytes = 0;

@@ -98,5 +98,6 @@ def test_profile_api_without_device():
 def test_tuner_api_without_device():
     p = L.default_params()
     assert p.tune == 0  # fixed default class table unless asked
+    assert p.ip_device == 2 and p.graph_rounds == 0  # automatic initial partitioning
     L.tuner_clear()
     assert L.tuner_info() == {"entries": 0, "trials": 0}
