@@ -109,18 +109,20 @@ LMGP_D void emit(const RateArgs& a, uint32_t idx, uint32_t u, const GraphDesc& g
   }
 }
 
+// Open addressing with linear probing.  The probe loop has a single exit
+// (the slot holding K, claimed or found) and the add follows it, so that a
+// wave's divergent probes cost few scalar mask updates per step.
 template <int T>
 LMGP_D void lds_insert(uint32_t* key, unsigned long long* val, uint32_t K, uint64_t w) {
   constexpr int LOGT = __builtin_ctz(T);
   uint32_t s = (K * 0x9E3779B1u) >> (32 - LOGT);
-  while (true) {
-    uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
-    if (prev == EMPTY_KEY || prev == K) {
-      atomicAdd(&val[s], (unsigned long long)w);
-      return;
-    }
-    s = (s + 1) & (T - 1);
-  }
+  bool hit;
+  do {
+    const uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
+    hit = prev == EMPTY_KEY || prev == K;
+    s = hit ? s : (s + 1) & (T - 1);
+  } while (!hit);
+  atomicAdd(&val[s], (unsigned long long)w);
 }
 
 // Table of 2^logt slots (logt >= 1): runtime-sized variant.
@@ -128,14 +130,13 @@ LMGP_D void lds_insert_n(uint32_t* key, unsigned long long* val, uint32_t K, uin
                          int logt) {
   const uint32_t mask = (1u << logt) - 1;
   uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
-  while (true) {
-    uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
-    if (prev == EMPTY_KEY || prev == K) {
-      atomicAdd(&val[s], (unsigned long long)w);
-      return;
-    }
-    s = (s + 1) & mask;
-  }
+  bool hit;
+  do {
+    const uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
+    hit = prev == EMPTY_KEY || prev == K;
+    s = hit ? s : (s + 1) & mask;
+  } while (!hit);
+  atomicAdd(&val[s], (unsigned long long)w);
 }
 
 template <int G>
@@ -379,41 +380,37 @@ __global__ __launch_bounds__(256) void k_rate_groups(RateArgs a, GroupSplit spli
 constexpr unsigned long long EMPTY_SLOT = ~0ull;  // packed slot: label EMPTY_KEY
 
 // Packed LDS table: label in the high half of a slot, rating in the low half
-// (valid when every rating fits in 32 bits).
+// (valid when every rating fits in 32 bits).  The compare-and-swap claims an
+// empty slot with the first rating or returns the occupant; the loop's only
+// exit is the slot of K, and the add for a found slot follows it.
 template <int T>
 LMGP_D void lds_add_packed(unsigned long long* tab, uint32_t K, unsigned long long w) {
   constexpr int LOGT = __builtin_ctz(T);
+  const unsigned long long mine = ((unsigned long long)K << 32) | w;
   uint32_t s = (K * 0x9E3779B1u) >> (32 - LOGT);
-  while (true) {
-    unsigned long long cur = tab[s];
-    if (cur == EMPTY_SLOT) {
-      cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
-      if (cur == EMPTY_SLOT) return;
-    }
-    if ((uint32_t)(cur >> 32) == K) {
-      atomicAdd(&tab[s], w);
-      return;
-    }
-    s = (s + 1) & (T - 1);
-  }
+  unsigned long long prev;
+  bool hit;
+  do {
+    prev = atomicCAS(&tab[s], EMPTY_SLOT, mine);
+    hit = prev == EMPTY_SLOT || (uint32_t)(prev >> 32) == K;
+    s = hit ? s : (s + 1) & (T - 1);
+  } while (!hit);
+  if (prev != EMPTY_SLOT) atomicAdd(&tab[s], w);
 }
 
 // Runtime-sized variant of lds_add_packed: 2^logt slots.
 LMGP_D void lds_add_packed_n(unsigned long long* tab, uint32_t K, unsigned long long w, int logt) {
   const uint32_t mask = (1u << logt) - 1;
+  const unsigned long long mine = ((unsigned long long)K << 32) | w;
   uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
-  while (true) {
-    unsigned long long cur = tab[s];
-    if (cur == EMPTY_SLOT) {
-      cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
-      if (cur == EMPTY_SLOT) return;
-    }
-    if ((uint32_t)(cur >> 32) == K) {
-      atomicAdd(&tab[s], w);
-      return;
-    }
-    s = (s + 1) & mask;
-  }
+  unsigned long long prev;
+  bool hit;
+  do {
+    prev = atomicCAS(&tab[s], EMPTY_SLOT, mine);
+    hit = prev == EMPTY_SLOT || (uint32_t)(prev >> 32) == K;
+    s = hit ? s : (s + 1) & mask;
+  } while (!hit);
+  if (prev != EMPTY_SLOT) atomicAdd(&tab[s], w);
 }
 
 // One block of NT threads per node, packed LDS table of 2^LOGT slots: 8192
