@@ -374,34 +374,34 @@ __global__ __launch_bounds__(1024) void k_rows_big(ContractArgs a, const uint32_
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)carry;
 }
 
+// Linear probing with a single loop exit (the slot of K), the add after it:
+// divergent probes of a wave then cost few scalar mask updates per step.
 LMGP_D void row_insert(uint32_t* key, unsigned long long* val, uint32_t K, uint64_t w, int logt) {
   const uint32_t mask = (1u << logt) - 1;
   uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
-  while (true) {
+  bool hit;
+  do {
     const uint32_t prev = atomicCAS(&key[s], EMPTY_KEY, K);
-    if (prev == EMPTY_KEY || prev == K) {
-      atomicAdd(&val[s], (unsigned long long)w);
-      return;
-    }
-    s = (s + 1) & mask;
-  }
+    hit = prev == EMPTY_KEY || prev == K;
+    s = hit ? s : (s + 1) & mask;
+  } while (!hit);
+  atomicAdd(&val[s], (unsigned long long)w);
 }
 
+// Packed slots: the compare-and-swap claims an empty slot with the first
+// weight or returns the occupant; a found slot gets the add after the loop.
 LMGP_D void row_insert_packed(unsigned long long* tab, uint32_t K, unsigned long long w, int logt) {
   const uint32_t mask = (1u << logt) - 1;
+  const unsigned long long mine = ((unsigned long long)K << 32) | w;
   uint32_t s = (K * 0x9E3779B1u) >> (32 - logt);
-  while (true) {
-    unsigned long long cur = tab[s];
-    if (cur == ~0ull) {
-      cur = atomicCAS(&tab[s], ~0ull, ((unsigned long long)K << 32) | w);
-      if (cur == ~0ull) return;
-    }
-    if ((uint32_t)(cur >> 32) == K) {
-      atomicAdd(&tab[s], w);
-      return;
-    }
-    s = (s + 1) & mask;
-  }
+  unsigned long long prev;
+  bool hit;
+  do {
+    prev = atomicCAS(&tab[s], ~0ull, mine);
+    hit = prev == ~0ull || (uint32_t)(prev >> 32) == K;
+    s = hit ? s : (s + 1) & mask;
+  } while (!hit);
+  if (prev != ~0ull) atomicAdd(&tab[s], w);
 }
 
 // Hash-aggregated rows: one block of NT threads per coarse row, LDS table of
@@ -602,21 +602,18 @@ __global__ __launch_bounds__(1024) void k_rows_range(ContractArgs a, const uint3
     const uint32_t k = (uint32_t)gkey[e];
     if (k == EMPTY_KEY || key_range(k, R) != j) continue;
     const unsigned long long w = (unsigned long long)gw[e];
+    const unsigned long long mine = ((unsigned long long)k << 32) | w;
     uint32_t sl = (k * 0x9E3779B1u) >> (32 - RANGE_LOGT);
+    unsigned long long prev;
+    bool hit;
     int probe = 0;
-    for (; probe < T; ++probe) {
-      unsigned long long cur = tab[sl];
-      if (cur == ~0ull) {
-        cur = atomicCAS(&tab[sl], ~0ull, ((unsigned long long)k << 32) | w);
-        if (cur == ~0ull) break;
-      }
-      if ((uint32_t)(cur >> 32) == k) {
-        atomicAdd(&tab[sl], w);
-        break;
-      }
-      sl = (sl + 1) & (T - 1);
-    }
-    if (probe == T) s_full = 1;
+    do {  // bounded: a full table reports an overflow
+      prev = atomicCAS(&tab[sl], ~0ull, mine);
+      hit = prev == ~0ull || (uint32_t)(prev >> 32) == k;
+      sl = hit ? sl : (sl + 1) & (T - 1);
+    } while (!hit && ++probe < T);
+    if (hit && prev != ~0ull) atomicAdd(&tab[sl], w);
+    if (!hit) s_full = 1;
   }
   __syncthreads();
   if (s_full) {

@@ -778,20 +778,18 @@ LMGP_D uint32_t label_range(uint32_t K, uint32_t P) {
 template <int T>
 LMGP_D bool lds_add_bounded(unsigned long long* tab, uint32_t K, unsigned long long w) {
   constexpr int LOGT = __builtin_ctz(T);
+  const unsigned long long mine = ((unsigned long long)K << 32) | w;
   uint32_t s = (K * 0x9E3779B1u) >> (32 - LOGT);
-  for (int probe = 0; probe < T; ++probe) {
-    unsigned long long cur = tab[s];
-    if (cur == EMPTY_SLOT) {
-      cur = atomicCAS(&tab[s], EMPTY_SLOT, ((unsigned long long)K << 32) | w);
-      if (cur == EMPTY_SLOT) return true;
-    }
-    if ((uint32_t)(cur >> 32) == K) {
-      atomicAdd(&tab[s], w);
-      return true;
-    }
-    s = (s + 1) & (T - 1);
-  }
-  return false;
+  unsigned long long prev;
+  bool hit;
+  int probe = 0;
+  do {
+    prev = atomicCAS(&tab[s], EMPTY_SLOT, mine);
+    hit = prev == EMPTY_SLOT || (uint32_t)(prev >> 32) == K;
+    s = hit ? s : (s + 1) & (T - 1);
+  } while (!hit && ++probe < T);
+  if (hit && prev != EMPTY_SLOT) atomicAdd(&tab[s], w);
+  return hit;
 }
 
 template <int EWK>
