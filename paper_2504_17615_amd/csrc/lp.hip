@@ -78,6 +78,20 @@ LMGP_D void consider_w(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, i
   if (better(r, h, K, best)) best = Best{r, h, K};
 }
 
+// As consider_w with a single branch (around the tie hash of a candidate that
+// can still win); the lane-group kernels, whose lanes hold few slots each,
+// issue fewer instructions with it.
+LMGP_D void consider_w1(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, int64_t cu,
+                        int64_t cap, int64_t wk, uint64_t pre_u, uint64_t label_base, Best& best,
+                        int64_t& r_own) {
+  r_own = K == own ? r : r_own;
+  const bool cand = K != own && (a.mode != MODE_LP || wk + cu <= cap) && r >= best.r;
+  if (cand) {
+    const uint64_t h = hash_add(pre_u, (uint64_t)K - label_base);
+    if (better(r, h, K, best)) best = Best{r, h, K};
+  }
+}
+
 // Candidate slots are dense: the node at position idx of the rated list owns
 // slot idx and marks it empty (tgt = EMPTY_KEY) when it proposes no move, so
 // that no global counter is needed.
@@ -196,20 +210,18 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   int64_t acc = 0;
   {
     // degree <= 2G: at most two entries per lane, loads issued together
+    // (past the row end the loads repeat the row's first entry, a valid
+    // address, and are masked: no branch around them)
     const uint64_t e0 = beg + gl, e1 = e0 + G;
-    const uint32_t v0 = e0 < end ? a.adj[e0] : 0u, v1 = e1 < end ? a.adj[e1] : 0u;
-    const int64_t w0 = e0 < end ? edge_w<EWK>(a.ew, e0) : 0;
-    const int64_t w1 = e1 < end ? edge_w<EWK>(a.ew, e1) : 0;
-    const uint32_t K0 = e0 < end ? a.label[v0] : EMPTY_KEY;
-    const uint32_t K1 = e1 < end ? a.label[v1] : EMPTY_KEY;
-    if (K0 != EMPTY_KEY) {
-      if (K0 == own) acc += w0;
-      else lds_insert<T>(key, val, K0, (uint64_t)w0);
-    }
-    if (K1 != EMPTY_KEY) {
-      if (K1 == own) acc += w1;
-      else lds_insert<T>(key, val, K1, (uint64_t)w1);
-    }
+    const uint64_t f0 = e0 < end ? e0 : beg, f1 = e1 < end ? e1 : beg;
+    const uint32_t v0 = a.adj[f0], v1 = a.adj[f1];
+    const int64_t w0 = edge_w<EWK>(a.ew, f0), w1 = edge_w<EWK>(a.ew, f1);
+    const uint32_t l0 = a.label[v0], l1 = a.label[v1];
+    const uint32_t K0 = e0 < end ? l0 : EMPTY_KEY;
+    const uint32_t K1 = e1 < end ? l1 : EMPTY_KEY;
+    acc += (K0 != EMPTY_KEY && K0 == own ? w0 : 0) + (K1 != EMPTY_KEY && K1 == own ? w1 : 0);
+    if (K0 != EMPTY_KEY && K0 != own) lds_insert<T>(key, val, K0, (uint64_t)w0);
+    if (K1 != EMPTY_KEY && K1 != own) lds_insert<T>(key, val, K1, (uint64_t)w1);
   }
   acc = group_sum<G>(acc);
   if (gl == 0 && acc > 0) lds_insert<T>(key, val, own, (uint64_t)acc);
@@ -233,8 +245,8 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
 #pragma unroll
     for (int j = 0; j < SPL; ++j)
       if (Ks[j] != EMPTY_KEY)
-        consider_w(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, wk[j], pre_u,
-                   gd.label_base, best, r_own);
+        consider_w1(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, wk[j], pre_u,
+                    gd.label_base, best, r_own);
   }
   reduce_best<G>(best, r_own);
   if (gl == 0 && idx < a.count) {
