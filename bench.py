@@ -109,6 +109,11 @@ def roofline(stats: dict, steps: int, wall: float, workload: str,
             "traffic": measured_traffic(name, workload), "launches": st["launches"],
             "avg_launch_us": round(per_launch_ns / 1e3, 2),
             "bytes_per_launch": int(per_launch_bytes)}
+    if roof["traffic"]:
+        # measured DRAM-side bytes over the same launch time: random label
+        # gathers fetch whole lines, so this is above the algorithmic rate
+        roof["traffic_GBps"] = round(roof["traffic"] / per_launch_ns, 1)
+        roof["traffic_frac"] = round(roof["traffic"] / per_launch_ns / HBM_PEAK_GBS, 4)
     bd, bsteps = (stats, steps) if breakdown is None else (breakdown, 1)
     tot = sum(s["total_ns"] for s in bd.values())
     tb = sum(s["bytes"] for s in bd.values())
