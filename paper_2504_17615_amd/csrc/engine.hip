@@ -117,9 +117,18 @@ __global__ void k_lp_peek(LpCtl c) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+__global__ void k_to_u8(const uint32_t* a, uint64_t n, uint8_t* b) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (uint8_t)a[i];
+}
+
 // Levels (unions) up to this many nodes replay their LP rounds from a graph
 // when asked: above it the rounds are long enough to hide their launches.
 constexpr uint64_t REPLAY_MAX_NODES = 1ull << 18;
+
+// Levels from this size gather refinement labels from a byte copy (with 4
+// bytes per label the array no longer fits the 4 MiB L2 of an XCD).
+constexpr uint64_t LABEL8_MIN_NODES = 1ull << 20;
 
 // Graphs sharing a coarsest level from which the automatic choice bisects
 // them on the device.
@@ -498,6 +507,14 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   const uint32_t few = spec.refine && nlabels <= FEW_LABELS ? (uint32_t)nlabels : 0u;
   // the rating kernels' class cut-offs: dense per-block rows when few
   const bool dense = few != 0;
+  // at most 256 labels on a level whose 4-byte labels outgrow an XCD's L2:
+  // the neighbours' labels are gathered from a byte copy
+  DBuf<uint8_t> label8;
+  if (few && nlabels <= 256 && n >= LABEL8_MIN_NODES) {
+    label8.reset(&pool_, s_, n);
+    k_to_u8<<<grid_for(n, 256), 256, 0, s_>>>(label, n, label8.get());
+    LAUNCH_CHECK();
+  }
   const std::vector<CutPreset>& presets = cut_presets(dense);
   int preset = p_.tune >= LMGP_TUNE_FORCE ? (int)((p_.tune - LMGP_TUNE_FORCE) % presets.size()) : 0;
   const uint64_t tsub = spec.refine ? TAG_RSUB : TAG_SUB;
@@ -582,6 +599,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     ra.ntgt = ntgt.get();
     ra.list = list.get() + offs[sr * NCLASS];
     ra.cands = cands.get();
+    ra.label8 = label8.get();
     return ra;
   };
   // Autotuning: the first round's buckets under the default table give the
@@ -657,6 +675,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.moves = (uint64_t*)dmoves.get();
     aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
     aa.few = few;
+    aa.label8 = label8.get();
     return aa;
   };
   // Replayed rounds: on a small level the rounds after the first are launch

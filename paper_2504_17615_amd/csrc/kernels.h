@@ -112,6 +112,10 @@ struct RateArgs {
   // sub-round's candidate slots).
   const struct SubPlan* plan;
   int plan_c0, plan_c1;
+  // Refinement with at most 256 labels: the labels as bytes, gathered for the
+  // neighbours instead of `label` (a quarter of the footprint: the array of a
+  // large level stays in an XCD's L2).  NULL otherwise.
+  const uint8_t* label8;
 };
 
 // Label counts up to this use block-privatised LDS histograms in admission
@@ -200,6 +204,7 @@ struct AdmitArgs {
   uint32_t few;            // labels < few <= FEW_LABELS (see RateArgs), else 0
   const SubPlan* plan;     // planned launch: max_cands is an upper bound, the
                            // slot count is plan->total
+  uint8_t* label8;         // byte copy of the labels kept in step (or NULL)
 };
 void launch_admit(const AdmitArgs& a, hipStream_t s);
 

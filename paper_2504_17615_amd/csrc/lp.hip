@@ -169,6 +169,11 @@ LMGP_D int64_t group_sum(int64_t v) {
 // per block, 512 or 1024 slots): all eight share one launch (k_rate_groups).
 constexpr int GROUP_SLOTS = 1024;
 
+// Label of a neighbour (the byte copy when the labels fit in one).
+LMGP_D uint32_t nbr_label(const RateArgs& a, uint32_t v) {
+  return a.label8 ? (uint32_t)a.label8[v] : a.label[v];
+}
+
 // Planned launch: node count and list range from the sub-round's plan.
 LMGP_D void resolve_plan(RateArgs& r) {
   if (!r.plan) return;
@@ -216,7 +221,7 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
     const uint64_t f0 = e0 < end ? e0 : beg, f1 = e1 < end ? e1 : beg;
     const uint32_t v0 = a.adj[f0], v1 = a.adj[f1];
     const int64_t w0 = edge_w<EWK>(a.ew, f0), w1 = edge_w<EWK>(a.ew, f1);
-    const uint32_t l0 = a.label[v0], l1 = a.label[v1];
+    const uint32_t l0 = nbr_label(a, v0), l1 = nbr_label(a, v1);
     const uint32_t K0 = e0 < end ? l0 : EMPTY_KEY;
     const uint32_t K1 = e1 < end ? l1 : EMPTY_KEY;
     acc += (K0 != EMPTY_KEY && K0 == own ? w0 : 0) + (K1 != EMPTY_KEY && K1 == own ? w1 : 0);
@@ -1124,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_hub_few_insert(HubArgs h, unsigned long
 #pragma unroll
   for (int j = 0; j < U; ++j) {
     const uint64_t e = beg + (uint64_t)j * 256 + threadIdx.x;
-    if (e < end) atomicAdd(&mt[a.label[v[j]]], (unsigned long long)w[j]);
+    if (e < end) atomicAdd(&mt[nbr_label(a, v[j])], (unsigned long long)w[j]);
   }
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < few; t += 256) {
@@ -1489,6 +1494,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
       const uint32_t own = a.label[c.u];
       const long long cu = a.nw[c.u];
       a.label[c.u] = c.tgt;
+      if (a.label8) a.label8[c.u] = (uint8_t)c.tgt;
       atomicAdd((unsigned long long*)&dw[c.tgt], (unsigned long long)cu);
       atomicAdd((unsigned long long*)&dw[own], (unsigned long long)(-cu));
       if (a.gid) atomicAdd((unsigned long long*)&a.moves[a.gid[c.u]], 1ull);
@@ -1760,6 +1766,7 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
     const uint32_t own = a.label[c.u];
     const int64_t cu = a.nw[c.u];
     a.label[c.u] = t;
+    if (a.label8) a.label8[c.u] = (uint8_t)t;
     const int64_t old_t = (int64_t)atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
     const int64_t old_o =
         (int64_t)atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
