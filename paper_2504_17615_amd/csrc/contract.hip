@@ -552,12 +552,14 @@ __global__ __launch_bounds__(256) void k_rows_gather(ContractArgs a, const uint3
 }
 
 // Rows of more than 12288 entries on the hash path (packed weights): the
-// row's gathered entries are split into R = ceil(deg / 6144) hash ranges of
+// row's gathered entries are split into R = ceil(deg / 12288) hash ranges of
 // their neighbour ids; block j of the row aggregates range j in a packed LDS
-// table of 16384 slots (expected load < 3/8) and appends its distinct
-// entries to the row.  Probing is bounded: a range that does not fit sets
-// `overflow` and the caller rebuilds these rows with the radix sort.
-constexpr int RANGE_ENTRIES = 6144;
+// table of 16384 slots (at most about 3/4 full: a range holds about 12288
+// entries, fewer distinct ones) and appends its distinct entries to the row.
+// Every block reads the whole row, so fewer, fuller ranges read less.
+// Probing is bounded: a range that does not fit sets `overflow` and the
+// caller rebuilds these rows with the radix sort.
+constexpr int RANGE_ENTRIES = 12288;
 constexpr int RANGE_LOGT = 14;
 
 LMGP_D uint32_t key_range(uint32_t k, uint32_t R) {
