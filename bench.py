@@ -47,10 +47,17 @@ def cpu_baseline(sample: str):
     _, res, times = O.partition(g, k, eps, seed)
     wall = time.perf_counter() - t0
     cr = times["coarsen"] + times["refine"]
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         None)
+    except OSError:
+        pass
     return {"value": float(g.m / cr), "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample}: same generator recipe at smaller scale (n={g.n}, m={g.m}), "
                       f"full partition k={k}; coarsen+refine {cr:.2f}s of {wall:.2f}s wall",
-            "cut": res["cut"]}
+            "cut": res["cut"], "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def _kernel_of(family: str) -> str:
@@ -174,9 +181,25 @@ def bench_batch(args) -> dict:
     ks, eps, seeds = [4] * B, [0.03] * B, list(range(1, B + 1))
     outs = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(B)]
     prm = L.default_params(ip_device=args.ip_device)
-    for _ in range(args.warmup):
+    # as in the single-graph mode: the last warm-up call times every rating
+    # launch, the timed calls only the dominant kernel
+    breakdown = None
+    for i in range(args.warmup):
+        last = i == args.warmup - 1 and not args.no_profile
+        if last:
+            L.profile_filter(None)
+            L.profile_read(reset=True)
+            L.profile_enable(True)
         L.partition_batch(dgs, ks, eps, seeds, prm, outs=outs)
+        if last:
+            torch.cuda.synchronize()
+            L.profile_enable(False)
+            breakdown = L.profile_read(reset=True)
     torch.cuda.synchronize()
+    if breakdown:
+        L.profile_filter(dominant_kernel(breakdown))
+        L.profile_read(reset=True)
+        L.profile_enable(True)
     t0 = time.perf_counter()
     res = []
     for _ in range(args.steps):
@@ -184,6 +207,12 @@ def bench_batch(args) -> dict:
         res.append(r[0])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
+    roof = None
+    if breakdown:
+        L.profile_enable(False)
+        stats = L.profile_read(reset=True)
+        L.profile_filter(None)
+        roof = roofline(stats, args.steps, wall, "grid128x%d" % B, breakdown)
     cr = sum(r["t_coarsen_ns"] + r["t_refine_ns"] for r in res) / len(res) * 1e-9
     m_tot = g.m * B
     # plain calls, one graph at a time, on a prefix of the same requests
@@ -209,6 +238,7 @@ def bench_batch(args) -> dict:
         "phases_ms": {p: round(sum(r[f"t_{p}_ns"] for r in res) / len(res) * 1e-6, 3)
                       for p in ("coarsen", "initial", "refine")},
         "ip_device": args.ip_device,
+        "roofline": roof,
         "plain": {"graphs": P, "edges_per_s": g.m / (pcr / P), "graphs_per_s": 1.0 / pwall,
                   "ms_per_graph": pwall * 1e3},
         "batch_vs_plain_graphs_per_s": (B / wall) / (1.0 / pwall),

@@ -28,11 +28,13 @@ constexpr int ROW_A = WAVE;   // <= 64 entries: wave
 constexpr int ROW_B = 2048;   // <= 2048 entries: block, LDS
 constexpr int ROW_C = 8192;   // <= 8192 entries: 1024-thread block, packed LDS words
 constexpr int ROW_D = 16384;  // <= 16384 entries: the same with a 128 KiB LDS array
-constexpr int NROWCLS = 9;
+constexpr int NROWCLS = 12;
 // Row classes.  Sorted: 0 wave, 1 block bitonic, 3/4 big bitonic (packed),
-// 2 radix.  Hash aggregation: 0 wave (sorted anyway), 5 block <= 512 entries,
-// 6 block <= 2048, 7 big <= 6144 and 8 big <= 12288 (packed), 2 radix.
+// 2 radix.  Hash aggregation: lane groups of 16, 32 and 64 lanes for <= 32,
+// <= 64 and <= 128 entries (9, 10, 11), 5 block <= 512 entries, 6 block
+// <= 2048, 7 big <= 6144 and 8 big <= 12288 (packed), 2 radix.
 LMGP_D int row_class(uint64_t d, int packed, int sorted) {
+  if (!sorted && d <= 128) return d <= 32 ? 9 : d <= 64 ? 10 : 11;
   if (d <= ROW_A) return 0;
   if (sorted) {
     if (d <= ROW_B) return 1;
@@ -198,6 +200,112 @@ __global__ __launch_bounds__(256) void k_rows_wave(ContractArgs a, const uint32_
   const uint32_t nd = (uint32_t)__popcll(tmask);
   for (uint64_t i = nd + l; i < deg; i += WAVE) a.tkey[base + i] = EMPTY_KEY;
   if (l == 0) a.ndist[x] = nd;
+}
+
+template <int G, class T>
+LMGP_D T group_inclusive_scan(T v) {
+  const int gl = lane_id() % G;
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const T o = __shfl_up(v, d, G);
+    if (gl >= d) v += o;
+  }
+  return v;
+}
+
+// Rows with at most 2G fine entries (unsorted output): a group of G lanes
+// per row, 256 / G rows per block, an LDS hash table of 4G slots per row;
+// the distinct entries are written in slot order.
+template <int EWK, int G>
+__global__ __launch_bounds__(256) void k_rows_group(ContractArgs a, const uint32_t* rows,
+                                                    uint32_t nrows) {
+  constexpr int T = 4 * G, GPB = 256 / G;
+  __shared__ uint32_t skey[GPB * T];
+  __shared__ unsigned long long sval[GPB * T];
+  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
+  uint32_t* key = skey + grp * T;
+  unsigned long long* val = sval + grp * T;
+  const uint32_t r = blockIdx.x * GPB + grp;
+  const bool valid = r < nrows;
+#pragma unroll
+  for (int i = gl; i < T; i += G) {
+    key[i] = EMPTY_KEY;
+    val[i] = 0;
+  }
+  wave_sync();
+  uint32_t x = 0;
+  uint64_t m0 = 0, m1 = 0;
+  if (valid) {
+    x = rows[r];
+    m0 = a.mstart[x];
+    m1 = a.mstart[x + 1];
+  }
+  // members in chunks of G: lane l takes entries l and l + G of the chunk
+  for (uint64_t mb = m0; mb < m1; mb += G) {
+    const uint64_t mi = mb + gl;
+    uint64_t beg = 0, d = 0;
+    if (mi < m1) {
+      const uint32_t u = a.members[mi];
+      beg = a.xadj[u];
+      d = a.xadj[u + 1] - beg;
+    }
+    const uint64_t incl = group_inclusive_scan<G>(d);
+    const uint64_t excl = incl - d;
+    const uint64_t tot = __shfl(incl, G - 1, G);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint64_t t = (uint64_t)gl + (uint64_t)h * G;
+      // owner: the last member whose exclusive offset is <= t
+      int lo = 0;
+#pragma unroll
+      for (int step = G / 2; step > 0; step >>= 1) {
+        const int c = lo + step;
+        const uint64_t ex = __shfl(excl, c, G);
+        if (mb + (uint64_t)c < m1 && t >= ex) lo = c;
+      }
+      const uint64_t obeg = __shfl(beg, lo, G);
+      const uint64_t oex = __shfl(excl, lo, G);
+      uint32_t k = EMPTY_KEY;
+      int64_t w = 0;
+      if (t < tot) load_entry<EWK>(a, obeg + (t - oex), x, k, w);
+      if (k != EMPTY_KEY) {
+        uint32_t sl = (k * 0x9E3779B1u) >> (32 - __builtin_ctz(T));
+        bool hit;
+        do {
+          const uint32_t prev = atomicCAS(&key[sl], EMPTY_KEY, k);
+          hit = prev == EMPTY_KEY || prev == k;
+          sl = hit ? sl : (sl + 1) & (T - 1);
+        } while (!hit);
+        atomicAdd(&val[sl], (unsigned long long)w);
+      }
+    }
+  }
+  wave_sync();
+  if (!valid) return;
+  // occupied slots -> consecutive outputs (each lane owns 4 slots)
+  constexpr int SPL = T / G;
+  uint32_t kk[SPL];
+  int n = 0;
+#pragma unroll
+  for (int j = 0; j < SPL; ++j) {
+    kk[j] = key[gl * SPL + j];
+    n += kk[j] != EMPTY_KEY;
+  }
+  const int incl = group_inclusive_scan<G>(n);
+  const int nd = __shfl(incl, G - 1, G);
+  const uint64_t base = a.tmpoff[x];
+  uint64_t o = base + (uint64_t)(incl - n);
+#pragma unroll
+  for (int j = 0; j < SPL; ++j)
+    if (kk[j] != EMPTY_KEY) {
+      a.tkey[o] = kk[j];
+      a.tw[o] = (int64_t)val[gl * SPL + j];
+      a.tsrc[o] = x;
+      ++o;
+    }
+  const uint64_t deg = a.degsum[x];
+  for (uint64_t i = (uint64_t)nd + gl; i < deg; i += G) a.tkey[base + i] = EMPTY_KEY;
+  if (gl == 0) a.ndist[x] = (uint32_t)nd;
 }
 
 // Rows with 65..2048 fine entries: one block per row, sort in LDS.
@@ -746,6 +854,18 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
     }
     if (rc[1]) {
       k_rows_block<EWK><<<rc[1], 256, 0, s>>>(a, listB, rc[1]);
+      LAUNCH_CHECK();
+    }
+    if (rc[9]) {
+      k_rows_group<EWK, 16><<<grid_for(rc[9], 16), 256, 0, s>>>(a, list_of(9), rc[9]);
+      LAUNCH_CHECK();
+    }
+    if (rc[10]) {
+      k_rows_group<EWK, 32><<<grid_for(rc[10], 8), 256, 0, s>>>(a, list_of(10), rc[10]);
+      LAUNCH_CHECK();
+    }
+    if (rc[11]) {
+      k_rows_group<EWK, 64><<<grid_for(rc[11], 4), 256, 0, s>>>(a, list_of(11), rc[11]);
       LAUNCH_CHECK();
     }
     if (rc[3]) {
