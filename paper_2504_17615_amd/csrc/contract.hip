@@ -28,13 +28,14 @@ constexpr int ROW_A = WAVE;   // <= 64 entries: wave
 constexpr int ROW_B = 2048;   // <= 2048 entries: block, LDS
 constexpr int ROW_C = 8192;   // <= 8192 entries: 1024-thread block, packed LDS words
 constexpr int ROW_D = 16384;  // <= 16384 entries: the same with a 128 KiB LDS array
-constexpr int NROWCLS = 12;
+constexpr int NROWCLS = 13;
 // Row classes.  Sorted: 0 wave, 1 block bitonic, 3/4 big bitonic (packed),
 // 2 radix.  Hash aggregation: lane groups of 16, 32 and 64 lanes for <= 32,
-// <= 64 and <= 128 entries (9, 10, 11), 5 block <= 512 entries, 6 block
-// <= 2048, 7 big <= 6144 and 8 big <= 12288 (packed), 2 radix.
+// <= 64 and <= 128 entries (9, 10, 11), 12 a 128-thread block <= 256, 5 a
+// 256-thread block <= 512 entries, 6 block <= 2048, 7 big <= 6144 and 8 big
+// <= 12288 (packed), 2 radix.
 LMGP_D int row_class(uint64_t d, int packed, int sorted) {
-  if (!sorted && d <= 128) return d <= 32 ? 9 : d <= 64 ? 10 : 11;
+  if (!sorted && d <= 256) return d <= 32 ? 9 : d <= 64 ? 10 : d <= 128 ? 11 : 12;
   if (d <= ROW_A) return 0;
   if (sorted) {
     if (d <= ROW_B) return 1;
@@ -866,6 +867,11 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
     }
     if (rc[11]) {
       k_rows_group<EWK, 64><<<grid_for(rc[11], 4), 256, 0, s>>>(a, list_of(11), rc[11]);
+      LAUNCH_CHECK();
+    }
+    if (rc[12]) {
+      if (packed) k_rows_hash<EWK, 128, 9, true><<<rc[12], 128, 0, s>>>(a, list_of(12), rc[12]);
+      else k_rows_hash<EWK, 128, 9, false><<<rc[12], 128, 0, s>>>(a, list_of(12), rc[12]);
       LAUNCH_CHECK();
     }
     if (rc[3]) {
