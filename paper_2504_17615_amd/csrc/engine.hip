@@ -117,6 +117,22 @@ __global__ void k_lp_peek(LpCtl c) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+// Pinned host memory for the per-round state copy (copies into pageable
+// memory are staged by the runtime).  One buffer per thread, grown on demand
+// and kept for the thread's life (a few KiB).
+unsigned long long* pinned_state(size_t n) {
+  static thread_local unsigned long long* p = nullptr;
+  static thread_local size_t cap = 0;
+  if (n > cap) {
+    if (p) HIP_CHECK(hipHostFree(p));
+    p = nullptr;
+    cap = 0;
+    HIP_CHECK(hipHostMalloc((void**)&p, n * sizeof(unsigned long long), hipHostMallocDefault));
+    cap = n;
+  }
+  return p;
+}
+
 __global__ void k_to_u8(const uint32_t* a, uint64_t n, uint8_t* b) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (uint8_t)a[i];
@@ -496,7 +512,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   // per-round state read by the host in one copy: bucket counts, bucket
   // degree sums, active flags
   DBuf<unsigned long long> rstate(&pool_, s_, 2 * NB + 2 * B);
-  std::vector<unsigned long long> hstate(2 * NB + B);
+  const size_t nstate = 2 * NB + B;
+  unsigned long long* hstate = pinned_state(nstate);
+  std::memset(hstate, 0, nstate * sizeof(unsigned long long));
   demand.zero();
   ntgt.zero();
   fill.zero();
@@ -567,7 +585,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     LAUNCH_CHECK();
     launch_bucket_count(ba, s_);
     launch_bucket_offsets(ba, s_);
-    d2h(hstate.data(), rstate.get(), hstate.size(), s_);
+    d2h(hstate, rstate.get(), nstate, s_);
     sync(s_);
     for (uint32_t i = 0; i < NB; ++i) {
       cnt[i] = (uint32_t)hstate[i];
