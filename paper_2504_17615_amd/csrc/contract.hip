@@ -50,6 +50,11 @@ LMGP_D int row_class(uint64_t d, int packed, int sorted) {
   return 2;
 }
 
+__global__ void k_gather_u32(const uint32_t* a, const uint64_t* idx, uint64_t n, uint32_t* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[idx[i]];
+}
+
 __global__ void k_map(const uint32_t* label, const uint32_t* cid, const uint32_t* gid,
                       const uint8_t* keep, uint64_t n, uint32_t* map) {
   uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -839,8 +844,7 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
     LAUNCH_CHECK();
   }
   uint32_t rc[NROWCLS] = {};
-  HIP_CHECK(hipMemcpyAsync(rc, rcount.get(), sizeof(rc), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  read_now(rc, rcount.get(), sizeof(rc), s);
   const uint32_t* listA = rlists.get();
   const uint32_t* listB = rlists.get() + nc;
   const uint32_t* listC = rlists.get() + 2 * nc;
@@ -904,8 +908,7 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
       DBuf<uint64_t> goff(&pool, s, rc[2] + 1);
       exclusive_scan(U64AtList{a.degsum, listC}, rc[2], goff.get(), true, pool, s);
       uint64_t gt = 0;
-      HIP_CHECK(hipMemcpyAsync(&gt, goff.get() + rc[2], sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
+      read_now(&gt, goff.get() + rc[2], sizeof(uint64_t), s);
       DBuf<uint64_t> gk(&pool, s, gt), gk2(&pool, s, gt);
       DBuf<int64_t> gwv(&pool, s, gt), gw2(&pool, s, gt);
       k_rows_gather<EWK><<<rc[2], 256, 0, s>>>(a, listC, rc[2], goff.get(), gk.get(), gwv.get());
@@ -914,17 +917,15 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
         DBuf<uint64_t> roff(&pool, s, rc[2] + 1);
         exclusive_scan(RangeCount{a.degsum, listC}, rc[2], roff.get(), true, pool, s);
         uint64_t nr = 0;
-        HIP_CHECK(hipMemcpyAsync(&nr, roff.get() + rc[2], 8, hipMemcpyDeviceToHost, s));
+        read_now(&nr, roff.get() + rc[2], 8, s);
         DBuf<uint32_t> rowfill(&pool, s, rc[2]), ovf(&pool, s, 1);
         rowfill.zero();
         ovf.zero();
-        HIP_CHECK(hipStreamSynchronize(s));
         k_rows_range<<<(unsigned)nr, 1024, 0, s>>>(a, listC, rc[2], goff.get(), gk.get(), gwv.get(),
                                                    roff.get(), rowfill.get(), ovf.get());
         LAUNCH_CHECK();
         uint32_t overflow = 0;
-        HIP_CHECK(hipMemcpyAsync(&overflow, ovf.get(), 4, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
+        read_now(&overflow, ovf.get(), 4, s);
         // LMGP_ROW_RANGES=overflow takes the fallback as if a range had not fit
         // (used by the tests: the radix rows must overwrite the range output)
         const char* force = std::getenv("LMGP_ROW_RANGES");
@@ -973,8 +974,7 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   DBuf<uint32_t> cid(&pool, s, n + 1);
   exclusive_scan(FlagUsed{lcount.get()}, n, cid.get(), true, pool, s);
   uint32_t nc32 = 0;
-  HIP_CHECK(hipMemcpyAsync(&nc32, cid.get() + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  read_now(&nc32, cid.get() + n, sizeof(uint32_t), s);
   const uint64_t nc = nc32;
   out.nc = nc;
   out.map.reset(&pool, s, n);
@@ -987,10 +987,17 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
                                     ccount.get(), in.gid ? out.gid.get() : nullptr);
   LAUNCH_CHECK();
   // graph boundaries of the coarse union
-  out.cid_at_bounds.resize(in.bounds.size());
-  for (size_t i = 0; i < in.bounds.size(); ++i)
-    HIP_CHECK(hipMemcpyAsync(&out.cid_at_bounds[i], cid.get() + in.bounds[i], sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, s));
+  const size_t nbnd = in.bounds.size();
+  out.cid_at_bounds.resize(nbnd);
+  if (nbnd) {  // one gather and one read, whatever the number of graphs
+    DBuf<uint64_t> dbnd(&pool, s, nbnd);
+    DBuf<uint32_t> dval(&pool, s, nbnd);
+    HIP_CHECK(hipMemcpyAsync(dbnd.get(), in.bounds.data(), nbnd * sizeof(uint64_t),
+                             hipMemcpyHostToDevice, s));
+    k_gather_u32<<<grid_for(nbnd, 256), 256, 0, s>>>(cid.get(), dbnd.get(), nbnd, dval.get());
+    LAUNCH_CHECK();
+    read_now(out.cid_at_bounds.data(), dval.get(), nbnd * sizeof(uint32_t), s);
+  }
   cid.clear();
   lcount.clear();
   // members and degree sums
@@ -1008,7 +1015,7 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   DBuf<uint64_t> tmpoff(&pool, s, nc + 1);
   exclusive_scan(ArrayU64{(const uint64_t*)degsum.get()}, nc, tmpoff.get(), true, pool, s);
   uint64_t mt = 0;
-  HIP_CHECK(hipMemcpyAsync(&mt, tmpoff.get() + nc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  read_now(&mt, tmpoff.get() + nc, sizeof(uint64_t), s);
   DBuf<uint32_t> tkey(&pool, s, mt ? mt : 1), tsrc(&pool, s, mt ? mt : 1), ndist(&pool, s, nc + 1);
   DBuf<int64_t> tw(&pool, s, mt ? mt : 1);
   ContractArgs a{};
@@ -1029,8 +1036,7 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   out.xadj.reset(&pool, s, nc + 1);
   exclusive_scan(U32At{ndist.get()}, nc, out.xadj.get(), true, pool, s);
   uint64_t mc = 0;
-  HIP_CHECK(hipMemcpyAsync(&mc, out.xadj.get() + nc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  read_now(&mc, out.xadj.get() + nc, sizeof(uint64_t), s);
   out.nnz = mc;
   out.adj.reset(&pool, s, mc ? mc : 1);
   out.ew.reset(&pool, s, mc ? mc : 1);

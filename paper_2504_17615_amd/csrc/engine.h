@@ -73,6 +73,7 @@ struct Job {
 class Engine {
  public:
   Engine(Pool& pool, hipStream_t s, const lmgp_params& p) : pool_(pool), s_(s), p_(p) {}
+  ~Engine();
   // Builds the hierarchy for all jobs (one union).
   void coarsen(std::vector<Job>& jobs);
   // Initial partitioning, refinement and evaluation; writes blocks.

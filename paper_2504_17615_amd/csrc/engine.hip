@@ -29,15 +29,43 @@ uint64_t chain(uint64_t seed, uint64_t tag, std::initializer_list<uint64_t> xs) 
   return s;
 }
 
+// Small copies go through the thread's page-locked staging arena: an upload
+// is copied into it first, a download lands in it and reaches its
+// destination at the next sync(), which also gives the arena back (the
+// stream has then passed every staged copy).  Every read of a download in
+// this file follows a sync().
+struct PendingRead {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+std::vector<PendingRead>& pending_reads() {
+  static thread_local std::vector<PendingRead> v;
+  return v;
+}
+
 template <class T>
 void h2d(T* dst, const T* src, size_t n, hipStream_t s) {
-  if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  if (!n) return;
+  const size_t bytes = n * sizeof(T);
+  void* p = stage_take(bytes);
+  if (p) std::memcpy(p, src, bytes);
+  HIP_CHECK(hipMemcpyAsync(dst, p ? p : src, bytes, hipMemcpyHostToDevice, s));
 }
 template <class T>
 void d2h(T* dst, const T* src, size_t n, hipStream_t s) {
-  if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  if (!n) return;
+  const size_t bytes = n * sizeof(T);
+  void* p = stage_take(bytes);
+  HIP_CHECK(hipMemcpyAsync(p ? p : (void*)dst, src, bytes, hipMemcpyDeviceToHost, s));
+  if (p) pending_reads().push_back(PendingRead{dst, p, bytes});
 }
-void sync(hipStream_t s) { HIP_CHECK(hipStreamSynchronize(s)); }
+void sync(hipStream_t s) {
+  HIP_CHECK(hipStreamSynchronize(s));
+  for (const PendingRead& r : pending_reads()) std::memcpy(r.dst, r.src, r.bytes);
+  pending_reads().clear();
+  stage_reset(0);
+}
 
 // ------------------------------------------------------------ small kernels --
 __global__ void k_iota(uint32_t* a, uint64_t n) {
@@ -319,6 +347,16 @@ class Timer {
 };
 
 }  // namespace
+
+// A call that ends by an exception may leave staged copies in flight: wait
+// for them before the staging arena is reused.
+Engine::~Engine() {
+  if (!pending_reads().empty() || stage_mark() != 0) {
+    (void)hipStreamSynchronize(s_);
+    pending_reads().clear();
+    stage_reset(0);
+  }
+}
 
 lmgp_params default_params() {
   lmgp_params p;

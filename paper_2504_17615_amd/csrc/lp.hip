@@ -1239,10 +1239,9 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   exclusive_scan(HubChunks{ra.xadj, ra.list}, c, coff.get(), true, pool, s);
   exclusive_scan(HubSlotChunks{ra.xadj, ra.list}, c, soff.get(), true, pool, s);
   uint64_t tot[3] = {0, 0, 0};
-  HIP_CHECK(hipMemcpyAsync(&tot[0], toff.get() + c, 8, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(&tot[1], coff.get() + c, 8, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(&tot[2], soff.get() + c, 8, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  read_now(&tot[0], toff.get() + c, 8, s);
+  read_now(&tot[1], coff.get() + c, 8, s);
+  read_now(&tot[2], soff.get() + c, 8, s);
   DBuf<uint32_t> keys;
   DBuf<int64_t> vals;
   DBuf<unsigned long long> tab;

@@ -157,4 +157,19 @@ class DBuf {
   hipStream_t s_ = nullptr;
 };
 
+// Page-locked staging for the small host <-> device copies of the calling
+// thread (copies from or into pageable memory are staged by the runtime).
+// stage_take returns room for `bytes` (16-byte aligned) or nullptr when the
+// arena is full or the copy is large.  Room is given back by
+// stage_reset(mark) to an earlier stage_mark(), which the caller makes only
+// once the stream has passed every copy that used the room.
+constexpr size_t STAGE_BYTES = 1u << 20;
+constexpr size_t STAGE_MAX_COPY = 16u << 10;
+void* stage_take(size_t bytes);
+size_t stage_mark();
+void stage_reset(size_t mark);
+
+// Reads `bytes` from the device now: the stream is synchronised.
+void read_now(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 }  // namespace lmgp

@@ -1,6 +1,8 @@
 // Primitive kernels: fills and the stable LSD radix sort.
 #include "primitives.h"
 
+#include <cstring>
+
 namespace lmgp {
 
 __global__ void k_zero_u32(uint32_t* p, uint64_t n) {
@@ -157,5 +159,39 @@ template bool radix_sort_pairs<uint64_t>(uint64_t*, uint64_t*, uint64_t*, uint64
                                          int, int, Pool&, hipStream_t);
 template bool radix_sort_pairs<int64_t>(uint64_t*, int64_t*, uint64_t*, int64_t*, uint64_t, int,
                                         int, Pool&, hipStream_t);
+
+namespace {
+struct Stage {
+  char* buf = nullptr;
+  size_t used = 0;
+};
+Stage& stage() {
+  static thread_local Stage st;  // kept for the thread's life (1 MiB)
+  return st;
+}
+}  // namespace
+
+void* stage_take(size_t bytes) {
+  if (bytes == 0 || bytes > STAGE_MAX_COPY) return nullptr;
+  Stage& st = stage();
+  if (!st.buf) HIP_CHECK(hipHostMalloc((void**)&st.buf, STAGE_BYTES, hipHostMallocDefault));
+  const size_t off = (st.used + 15) & ~(size_t)15;
+  if (off + bytes > STAGE_BYTES) return nullptr;
+  st.used = off + bytes;
+  return st.buf + off;
+}
+
+size_t stage_mark() { return stage().used; }
+void stage_reset(size_t mark) { stage().used = mark; }
+
+void read_now(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  const size_t mark = stage_mark();
+  void* p = stage_take(bytes);
+  HIP_CHECK(hipMemcpyAsync(p ? p : dst, src, bytes, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (p) std::memcpy(dst, p, bytes);
+  stage_reset(mark);  // room taken after `mark` is this call's alone
+}
 
 }  // namespace lmgp

@@ -194,8 +194,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
     k_wmax<<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, dmax.get());
     LAUNCH_CHECK();
     unsigned long long wmax = 0;
-    HIP_CHECK(hipMemcpyAsync(&wmax, dmax.get(), sizeof(wmax), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    read_now(&wmax, dmax.get(), sizeof(wmax), s);
     int top = 0;
     while (top < 64 && (wmax >> top) != 0) top += 8;
     // (2 m_hat)-th largest directed weight
@@ -205,9 +204,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
       hist.zero();
       k_whist<<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, shift, prefix, hist.get());
       LAUNCH_CHECK();
-      HIP_CHECK(hipMemcpyAsync(h.data(), hist.get(), 256 * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
+      read_now(h.data(), hist.get(), 256 * sizeof(uint32_t), s);
       uint64_t cum = 0;
       int sel = 0;
       for (int dgt = 255; dgt >= 0; --dgt) {
@@ -243,9 +240,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
                                                  sg.pre, hist.get());
     LAUNCH_CHECK();
     std::vector<uint32_t> kh(4096);
-    HIP_CHECK(hipMemcpyAsync(kh.data(), hist.get(), 4096 * sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    read_now(kh.data(), hist.get(), 4096 * sizeof(uint32_t), s);
     uint64_t cum = 0;
     uint32_t bucket = 0;
     for (uint32_t i = 0; i < 4096; ++i) {
@@ -263,8 +258,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
                                                    sg.pre, bucket, buf.get(), cnt.get(), bsz);
     LAUNCH_CHECK();
     std::vector<EqEntry> hb(bsz);
-    HIP_CHECK(hipMemcpyAsync(hb.data(), buf.get(), bsz * sizeof(EqEntry), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    read_now(hb.data(), buf.get(), bsz * sizeof(EqEntry), s);
     auto less = [](const EqEntry& x, const EqEntry& y) {
       if (x.key != y.key) return x.key < y.key;
       if (x.a != y.a) return x.a < y.a;
@@ -288,8 +282,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
   DBuf<uint64_t> pos(&pool, s, nnz + 1);
   exclusive_scan(U8At{keep.get()}, nnz, pos.get(), true, pool, s);
   uint64_t total = 0;
-  HIP_CHECK(hipMemcpyAsync(&total, pos.get() + nnz, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  read_now(&total, pos.get() + nnz, sizeof(uint64_t), s);
   out.nnz = total;
   out.xadj.reset(&pool, s, n + 1);
   out.adj.reset(&pool, s, total ? total : 1);
