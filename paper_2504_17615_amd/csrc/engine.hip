@@ -161,6 +161,26 @@ unsigned long long* pinned_state(size_t n) {
   return p;
 }
 
+__global__ void k_gather_u64(const uint64_t* a, const uint64_t* idx, uint64_t n, uint64_t* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[idx[i]];
+}
+
+__global__ void k_remap_u32(uint32_t* g, uint64_t n, const uint32_t* map) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = map[g[i]];
+}
+
+// Every graph's blocks to its own output array, as graph-local ids.
+__global__ void k_blocks_out(const uint32_t* block, const uint32_t* gid, uint64_t n,
+                             const uint64_t* nbase, const uint64_t* kbase, uint32_t* const* out) {
+  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t b = graph_of(gid, v);
+  uint32_t* o = out[b];
+  if (o) o[v - nbase[b]] = block[v] - (uint32_t)kbase[b];
+}
+
 __global__ void k_to_u8(const uint32_t* a, uint64_t n, uint8_t* b) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (uint8_t)a[i];
@@ -315,11 +335,6 @@ __global__ void k_union_src(const UnionPart* parts, const uint32_t* const* srcs,
   if (e >= nnz) return;
   const uint32_t g = find_part(eb, B, e);
   src[e] = (uint32_t)(parts[g].nbase + srcs[g][e - parts[g].ebase]);
-}
-
-__global__ void k_to_local(const uint32_t* block, uint64_t n, uint32_t kbase, uint32_t* out) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = block[i] - kbase;
 }
 
 class Timer {
@@ -1136,24 +1151,28 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     C->nbase.push_back(co.nc);
     const uint32_t BC = nkeep;
     C->ebase.resize(BC + 1);
-    for (uint32_t c = 0; c <= BC; ++c) d2h(&C->ebase[c], co.xadj.get() + C->nbase[c], 1, s_);
-    sync(s_);
+    // entry offsets of the graphs: one gather and one read
+    auto read_ebase = [&](const uint64_t* xadj) {
+      DBuf<uint64_t> didx(&pool_, s_, BC + 1), dval(&pool_, s_, BC + 1);
+      h2d(didx.get(), C->nbase.data(), BC + 1, s_);
+      k_gather_u64<<<grid_for(BC + 1, 256), 256, 0, s_>>>(xadj, didx.get(), BC + 1, dval.get());
+      LAUNCH_CHECK();
+      d2h(C->ebase.data(), dval.get(), BC + 1, s_);
+      sync(s_);
+    };
+    read_ebase(co.xadj.get());
     // remap coarse graph ids to positions in the coarse union
     if (BC > 1) {
       std::vector<uint32_t> remap(B);
       for (uint32_t b = 0; b < B; ++b) remap[b] = newpos[b];
       DBuf<uint32_t> drm(&pool_, s_, B);
       h2d(drm.get(), remap.data(), B, s_);
-      struct Remap {};
       // gid values were written as old positions; translate in place
-      auto translate = [&](uint32_t* g, uint64_t nn) {
-        std::vector<uint32_t> hg(nn);
-        d2h(hg.data(), g, nn, s_);
-        sync(s_);
-        for (auto& x : hg) x = remap[x];
-        h2d(g, hg.data(), nn, s_);
-      };
-      translate(co.gid.get(), co.nc);
+      if (co.nc) {
+        k_remap_u32<<<grid_for(co.nc, 256), 256, 0, s_>>>(co.gid.get(), co.nc, drm.get());
+        LAUNCH_CHECK();
+      }
+      sync(s_);  // drm is freed on return
     }
     // budget and sparsification per kept graph
     std::vector<SparsGraph> sgs(BC);
@@ -1196,8 +1215,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
       C->o_adj = std::move(so.adj);
       C->o_ew = std::move(so.ew);
       C->o_src = std::move(so.src);
-      for (uint32_t c = 0; c <= BC; ++c) d2h(&C->ebase[c], C->o_xadj.get() + C->nbase[c], 1, s_);
-      sync(s_);
+      read_ebase(C->o_xadj.get());
     } else {
       C->o_xadj = std::move(co.xadj);
       C->o_adj = std::move(co.adj);
@@ -1373,18 +1391,30 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
   std::vector<int64_t> hcut(B0), hbw(Ktot);
   d2h(hcut.data(), cut.get(), B0, s_);
   d2h(hbw.data(), BW.get(), Ktot, s_);
-  for (uint32_t b = 0; b < B0; ++b) {
-    const uint32_t g = L0.graphs[b];
-    const uint64_t n0 = L0.nbase[b], nn = L0.nbase[b + 1] - n0;
-    if (!block_out || !block_out[g]) continue;
-    if (on_device) {
-      if (nn) {
-        k_to_local<<<grid_for(nn, 256), 256, 0, s_>>>(upper.get() + n0, nn, (uint32_t)kbase[g],
-                                                      block_out[g]);
-        LAUNCH_CHECK();
-      }
-    } else {
-      d2h(block_out[g], upper.get() + n0, nn, s_);
+  // device outputs: one launch for all graphs; host outputs: one copy each
+  DBuf<uint32_t*> douts;
+  DBuf<uint64_t> dnb0, dkb0;
+  if (on_device && block_out && L0.n) {
+    std::vector<uint32_t*> outs(B0, nullptr);
+    std::vector<uint64_t> kb(B0, 0);
+    for (uint32_t b = 0; b < B0; ++b) {
+      outs[b] = block_out[L0.graphs[b]];
+      kb[b] = kbase[L0.graphs[b]];
+    }
+    douts.reset(&pool_, s_, B0);
+    dnb0.reset(&pool_, s_, B0 + 1);
+    dkb0.reset(&pool_, s_, B0);
+    h2d(douts.get(), outs.data(), B0, s_);
+    h2d(dnb0.get(), L0.nbase.data(), B0 + 1, s_);
+    h2d(dkb0.get(), kb.data(), B0, s_);
+    k_blocks_out<<<grid_for(L0.n, 256), 256, 0, s_>>>(upper.get(), L0.gid, L0.n, dnb0.get(),
+                                                      dkb0.get(), douts.get());
+    LAUNCH_CHECK();
+  } else if (!on_device && block_out) {
+    for (uint32_t b = 0; b < B0; ++b) {
+      const uint32_t g = L0.graphs[b];
+      const uint64_t n0 = L0.nbase[b], nn = L0.nbase[b + 1] - n0;
+      if (block_out[g]) d2h(block_out[g], upper.get() + n0, nn, s_);
     }
   }
   sync(s_);
