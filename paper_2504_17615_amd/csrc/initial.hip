@@ -27,8 +27,8 @@ namespace lmgp {
 namespace {
 
 typedef unsigned __int128 u128;
-constexpr int IP_NT = 1024;
-constexpr int IP_NW = IP_NT / WAVE;
+// Subproblems of at most this many nodes on average take 256-thread groups.
+constexpr uint64_t IP_SMALL_SUB = 4096;
 
 struct IpArgs {
   const uint64_t* xadj;
@@ -87,12 +87,19 @@ __global__ void k_ip_subkeys(const uint32_t* sub, const uint32_t* vals, uint64_t
   keys[i] = s == IP_NONE ? nsub : s;
 }
 
+// A subproblem's nodes are touched by its own workgroup only: workgroup-scope
+// atomics and fences suffice (agent scope would make every fence write the
+// XCD's L2 back to memory).
 LMGP_D unsigned long long load_first(const unsigned long long* p) {
-  // written by atomics at the L2: read past the CU's vector cache
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+LMGP_D void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
+// NT threads per subproblem: 256 when subproblems are small (more of them
+// in flight per CU), 1024 for large ones.
+template <int IP_NT>
 __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
+  constexpr int IP_NW = IP_NT / WAVE;
   __shared__ int64_t sm[IP_NW];
   __shared__ uint64_t smu[IP_NW];
   __shared__ uint64_t sdp[IP_NT + 1];
@@ -114,9 +121,9 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
     const uint32_t v = order[i];
     a.visited[v] = 0;
     a.part1[v] = 0;
-    __hip_atomic_store(&a.first[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.first[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  __threadfence();
+  wg_fence();
   if (tid == 0) {
     sh_w1 = 0;
     sh_head = sh_tail = sh_ptr = sh_done = 0;
@@ -300,7 +307,9 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
               ((unsigned long long)iter << 32) | (0xFFFFFFFFull - (uint32_t)t);
           if (a.sub[x] == s) {
             if (pass == 0) {
-              if (!a.visited[x]) atomicMax(&a.first[x], key);
+              if (!a.visited[x])
+                __hip_atomic_fetch_max(&a.first[x], key, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             } else {
               win = load_first(&a.first[x]) == key;
             }
@@ -318,7 +327,7 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
           __syncthreads();  // sdp is refilled for the next tile
         }
       }
-      __threadfence();  // the pass's atomics and stores are complete
+      wg_fence();  // the pass's atomics and stores are visible to the workgroup
       __syncthreads();
     }
     if (tid == 0) sh_tail = t0 + pushed;
@@ -407,7 +416,8 @@ void IpDevice::depth(const std::vector<IpSub>& subs, const std::vector<uint32_t>
   while ((1ull << bits) <= nsub) ++bits;
   const bool sw2 = radix_sort_pairs<uint32_t>(k1, v1, k2, v2, n, 0, bits, pool_, s_);
   a.order = sw2 ? v2 : v1;
-  k_ip_grow<<<nsub, IP_NT, 0, s_>>>(a);
+  if (n <= (uint64_t)nsub * IP_SMALL_SUB) k_ip_grow<256><<<nsub, 256, 0, s_>>>(a);
+  else k_ip_grow<1024><<<nsub, 1024, 0, s_>>>(a);
   LAUNCH_CHECK();
 }
 
