@@ -152,6 +152,14 @@ def library():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2504_17615_amd.build lib`")
+        # One HIP runtime per process: PyTorch loads its own copy of the
+        # runtime by another file name, which would come in as a second
+        # runtime (seeing no device) if it were loaded after this library's.
+        # Loaded first, it also serves this library (same soname).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(lib, name)

@@ -519,8 +519,9 @@ void Engine::rate_classes(RateArgs ra, const uint32_t* cnt, const uint32_t* offs
     gdeg += degs ? degs[c] : 0;
   }
   launch_rate_groups(ew_kind, ra, gcnt, goff, gdeg, s_);
-  if (dense) {  // refinement, few blocks: dense LDS rows, one launch per block size
-    launch_rate(CLASS_BLOCK, ew_kind, span(CLASS_BLOCK, CLASS_BIG - 1), s_);
+  if (dense) {  // refinement, few blocks: dense LDS rows, one launch per row width
+    launch_rate(CLASS_BLOCK, ew_kind, span(CLASS_BLOCK, CLASS_BLOCK + 1), s_);
+    launch_rate(CLASS_BLOCK + 2, ew_kind, span(CLASS_BLOCK + 2, CLASS_BIG - 1), s_);
     launch_rate(CLASS_BIG, ew_kind, span(CLASS_BIG, CLASS_GLOBAL - 1), s_);
   } else {
     for (int c = GROUP_CLASSES; c < CLASS_BIG; ++c) launch_rate(c, ew_kind, span(c, c), s_);
@@ -803,7 +804,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
           return r;
         };
         if (dense) {
-          launch_rate(CLASS_BLOCK, L.ew_kind, span(CLASS_BLOCK, CLASS_BIG - 1), cs);
+          launch_rate(CLASS_BLOCK, L.ew_kind, span(CLASS_BLOCK, CLASS_BLOCK + 1), cs);
+          launch_rate(CLASS_BLOCK + 2, L.ew_kind, span(CLASS_BLOCK + 2, CLASS_BIG - 1), cs);
           launch_rate(CLASS_BIG, L.ew_kind, span(CLASS_BIG, CLASS_GLOBAL - 1), cs);
         } else {
           for (int c = GROUP_CLASSES; c < CLASS_GLOBAL; ++c)

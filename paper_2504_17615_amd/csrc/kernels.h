@@ -121,6 +121,8 @@ struct RateArgs {
 // Label counts up to this use block-privatised LDS histograms in admission
 // (refinement: labels are the k blocks of each graph).
 constexpr uint32_t FEW_LABELS = 1024;
+// Waves (one node each) per block of the smallest dense-row classes.
+constexpr int RW_WAVES = 4;
 
 // Split of one launch over the classes 0..GROUP_CLASSES-1 (lane groups and
 // the two smallest block classes).

@@ -595,6 +595,72 @@ __global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a0) {
   }
 }
 
+// Refinement with few labels, one wavefront per node (the two smallest
+// dense classes): each wave rates its node into a dense LDS row of its own,
+// so no wave waits at a block barrier and one node's evaluation overlaps the
+// other waves' loads.  RW_WAVES rows of `few` counters per block, in
+// dynamic LDS.
+template <int EWK>
+__global__ __launch_bounds__(RW_WAVES * WAVE) void k_rate_rows(RateArgs a0) {
+  extern __shared__ unsigned long long rw_tab[];
+  RateArgs a = a0;
+  resolve_plan(a);
+  const int wv = threadIdx.x / WAVE, ln = lane_id();
+  const uint64_t idx = (uint64_t)blockIdx.x * RW_WAVES + wv;
+  if (idx >= a.count) return;  // whole waves leave: nothing below waits on the block
+  const uint32_t u = a.list[idx];
+  const uint32_t g = graph_of(a.gid, u);
+  if (!a.gd[g].active) {
+    if (ln == 0) no_cand(a, (uint32_t)idx);
+    return;
+  }
+  const uint32_t few = a.few;
+  unsigned long long* tab = rw_tab + (size_t)wv * few;
+  for (uint32_t t = ln; t < few; t += WAVE) tab[t] = 0;
+  wave_sync();
+  const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
+  const uint32_t own = a.label[u];
+  int64_t acc = 0;
+  constexpr int U = 8;
+  for (uint64_t e0 = beg + ln; e0 < end; e0 += (uint64_t)U * WAVE) {
+    uint32_t v[U], K[U];
+    int64_t w[U];
+    // past the row end the loads repeat the row's first entry (these rows are
+    // never empty) and are masked below
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint64_t e = e0 + (uint64_t)j * WAVE;
+      const uint64_t f = e < end ? e : beg;
+      v[j] = a.adj[f];
+      w[j] = edge_w<EWK>(a.ew, f);
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) K[j] = a.label[v[j]];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (e0 + (uint64_t)j * WAVE >= end) continue;
+      if (K[j] == own) acc += w[j];
+      else atomicAdd(&tab[K[j]], (unsigned long long)w[j]);
+    }
+  }
+  acc = group_sum<WAVE>(acc);
+  if (ln == 0 && acc > 0) atomicAdd(&tab[own], (unsigned long long)acc);
+  wave_sync();
+  const GraphDesc gd = a.gd[g];
+  const int64_t cu = a.nw[u];
+  const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
+  Best best{0, 0, 0};
+  int64_t r_own = 0;
+  for (uint32_t t = ln; t < few; t += WAVE) {
+    const int64_t r = (int64_t)tab[t];
+    if (r == 0) continue;  // not adjacent (edge weights are positive)
+    const int64_t wk = t != own ? a.W[t] : 0;
+    consider_w(a, t, r, own, cu, gd.cap, wk, pre_u, gd.label_base, best, r_own);
+  }
+  reduce_best<WAVE>(best, r_own);
+  if (ln == 0) emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
+}
+
 // ------------------------------------------------- hub nodes (degree > 2048) --
 // A hub's rating table lives in global memory; its adjacency is split into
 // chunks of HUB_CHUNK entries rated by separate blocks, and its table into
@@ -1017,7 +1083,9 @@ std::string rate_name(int phase, int cls, int ewk, bool few, bool packed) {
   static const char* ph[3] = {"cl:", "rf:", "fv:"};
   const int w = ewk;
   std::string k;
-  if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_GLOBAL)
+  if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_BLOCK + 2)
+    k = "k_rate_rows<" + std::to_string(w) + ">";
+  else if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_GLOBAL)
     k = "k_rate_dense<" + std::to_string(w) + ", " + (cls < CLASS_BIG ? "256>" : "1024>");
   else if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
   else if (cls < CLASS_BIG && !(packed && cls >= CLASS_BLOCK + 2))
@@ -1069,7 +1137,11 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (cls < CLASS_BLOCK) {
     throw InvalidArg("lane-group classes are launched by launch_rate_groups");
   } else if (a.few && a.few <= FEW_LABELS && a.mode == MODE_LP && cls < CLASS_GLOBAL) {
-    if (cls < CLASS_BIG)
+    if (cls < CLASS_BLOCK + 2)
+      launch_k_lds(k_rate_rows<EWK>, dim3((uint32_t)ceil_div(a.count, RW_WAVES)),
+                   dim3(RW_WAVES * WAVE),
+                   (uint32_t)(RW_WAVES * a.few * sizeof(unsigned long long)), s, e0, e1, a);
+    else if (cls < CLASS_BIG)
       launch_k(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), s, e0, e1, a);
     else
       launch_k(k_rate_dense<EWK, 1024>, dim3(a.count), dim3(1024), s, e0, e1, a);

@@ -49,7 +49,8 @@ class Pool {
       e = hipMalloc(&p, sz);
       if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw OutOfMemory("hipMalloc failed for " + std::to_string(sz) + " bytes");
+        throw OutOfMemory("hipMalloc failed for " + std::to_string(sz) + " bytes: " +
+                          hipGetErrorString(e));
       }
     }
     std::lock_guard<std::mutex> g(mu_);

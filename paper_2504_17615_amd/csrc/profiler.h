@@ -99,6 +99,18 @@ void launch_k(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t s, hip
   HIP_CHECK(hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, 0, s));
 }
 
+// As launch_k, with `lds` bytes of dynamic LDS per block.
+template <typename... Args>
+void launch_k_lds(void (*kernel)(Args...), dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                  hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0) {
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, e0, e1, 0, args...);
+    return;
+  }
+  void* ptrs[] = {(void*)&args...};
+  HIP_CHECK(hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, lds, s));
+}
+
 // Suspends profiling on the calling thread (launches recorded into a graph
 // cannot carry event timestamps).
 class ProfSuspend {

@@ -32,6 +32,8 @@ struct CutPreset {
 
 // The table of degree_class (preset 0 of both kinds).
 ClassCuts default_cuts();
+// The default table of refinement with dense per-block rows.
+ClassCuts dense_cuts();
 // Tables for the hashed rating kernels (dense = false) and for refinement
 // with dense per-block rows (dense = true).
 const std::vector<CutPreset>& cut_presets(bool dense);

@@ -13,6 +13,13 @@ ClassCuts default_cuts() {
   return ClassCuts{{4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 6144, 8192}};
 }
 
+// Dense rows: one wave per node up to degree 512, a 256-thread block per node
+// up to 8192 (classes 10 and 11, the 1024-thread rows, stay empty), hub rows
+// above.
+ClassCuts dense_cuts() {
+  return ClassCuts{{4, 8, 16, 32, 64, 128, 256, 512, 1024, 8192, 8192, 8192}};
+}
+
 const std::vector<CutPreset>& cut_presets(bool dense) {
   // hashed tables: lane groups hold degree <= 2G (two entries per lane) or
   // <= G (one); block tables run at load <= 1/2 or <= 3/4; the largest LDS
@@ -25,15 +32,17 @@ const std::vector<CutPreset>& cut_presets(bool dense) {
       {"big3072", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 3072, 6144, 8192}}},
   };
   // dense rows (refinement, few blocks): the bounds that matter are the end
-  // of the lane groups (class 5), of the 256-thread rows (class 9) and of
-  // the 1024-thread rows (class 11)
+  // of the lane groups (class 5), of the one-wave rows (class 7), of the
+  // 256-thread rows (class 9) and of the 1024-thread rows (class 11)
   static const std::vector<CutPreset> rows = {
-      {"default", default_cuts()},
-      {"rows1024", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 1024, 6144, 8192}}},
-      {"rows4096", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 4096, 6144, 8192}}},
-      {"groups64", {{4, 8, 16, 32, 64, 64, 256, 512, 1024, 2048, 6144, 8192}}},
-      {"wide32768", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 6144, 32768}}},
-      {"rows4096+wide", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 4096, 6144, 32768}}},
+      {"default", dense_cuts()},
+      {"rows256", {{4, 8, 16, 32, 64, 128, 128, 128, 1024, 2048, 6144, 8192}}},
+      {"waves2048", {{4, 8, 16, 32, 64, 128, 1024, 2048, 2048, 2048, 6144, 8192}}},
+      {"rows1024", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 6144, 8192}}},
+      {"waves1024", {{4, 8, 16, 32, 64, 128, 512, 1024, 1024, 8192, 8192, 8192}}},
+      {"waves8192", {{4, 8, 16, 32, 64, 128, 4096, 8192, 8192, 8192, 8192, 8192}}},
+      {"groups64", {{4, 8, 16, 32, 64, 64, 256, 512, 1024, 8192, 8192, 8192}}},
+      {"wide32768", {{4, 8, 16, 32, 64, 128, 256, 512, 1024, 8192, 8192, 32768}}},
   };
   static const bool checked = [] {
     for (const CutPreset& p : hashed)

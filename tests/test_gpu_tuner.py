@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # forced table indices wrap modulo the number of tables of each kind (five
-# hashed, six dense-row tables), so 0..5 covers every table of both kinds
-NTABLES = 6
+# hashed, eight dense-row tables), so 0..7 covers every table of both kinds
+NTABLES = 8
 TUNE_AUTO, TUNE_FORCE = 1, 16
 
 
