@@ -6,6 +6,7 @@
 // graph is the union of one.  Level decisions need a few scalars per level
 // on the host (cluster counts, coarse sizes, edge counts).
 #include <algorithm>
+#include <functional>
 #include <atomic>
 #include <cmath>
 #include <thread>
@@ -1486,50 +1487,96 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
     st.inset[S[i]].store(my, rl);
     order[i] = {hash_add(pre, S[i]), S[i]};
   }
-  std::sort(order.begin(), order.end());
+  // start order: a min-heap, popped lazily (a search usually needs few
+  // starts, so sorting all of S would cost more than the search)
+  std::make_heap(order.begin(), order.end(), std::greater<>());
   for (uint32_t v : S) st.part1[v] = 0;
-  // Unvisited members of S as a bitset over node ids.  With sorted rows,
-  // walking it in ascending order and keeping the nodes found in v's row (by
-  // binary search) enqueues exactly what a scan of the row would, in the same
-  // order; it is used when few unvisited nodes remain and v's row is long
-  // (dense coarse graphs).
-  const uint64_t nwords = st.sorted ? (st.n + 63) / 64 : 0;
+  // Unvisited members of S that a row scan can still find: those with
+  // neighbours (a node with an empty row is in no row of a symmetric graph).
+  // Once none is left, a joined node's row is not scanned at all.  When S is
+  // not much smaller than the level and rows are sorted they are also kept
+  // as a bitset over node ids: walking it in ascending order and keeping the
+  // nodes y adjacent to v (binary search of the shorter of the two rows)
+  // enqueues exactly what a scan of v's row would, in the same order.  The
+  // walk is taken when it costs less than the scan: v's row is long and the
+  // nodes left are few or have short rows (dense coarse graphs, where some
+  // nodes of small degree stay unvisited for long).
+  auto deg_of = [&](uint32_t x) { return st.xadj[x + 1] - st.xadj[x]; };
+  auto bitlen = [](uint64_t d) { return (uint64_t)(64 - __builtin_clzll(d | 1)); };
+  const bool use_bits = st.sorted && (uint64_t)S.size() * 64 >= st.n;
+  const uint64_t nwords = use_bits ? (st.n + 63) / 64 : 0;
   std::vector<uint64_t> unv(nwords, 0);
-  if (st.sorted)
-    for (uint32_t v : S) unv[v >> 6] |= 1ull << (v & 63);
-  uint64_t nunv = S.size();
+  uint64_t nunv = 0, sumlen = 0;  // nodes left, sum of their rows' bit lengths
+  for (uint32_t v : S)
+    if (deg_of(v)) {
+      ++nunv;
+      sumlen += bitlen(deg_of(v));
+      if (use_bits) unv[v >> 6] |= 1ull << (v & 63);
+    }
   auto visit = [&](uint32_t x) {
     st.visited[x].store(my, rl);
-    if (st.sorted) unv[x >> 6] &= ~(1ull << (x & 63));
+    const uint64_t d = deg_of(x);
+    if (!d) return;
+    if (use_bits) unv[x >> 6] &= ~(1ull << (x & 63));
     --nunv;
+    sumlen -= bitlen(d);
   };
   std::vector<uint32_t> queue;
   queue.reserve(S.size());
   int64_t w1 = 0;
-  size_t ptr = 0;
-  while (w1 < T1) {
-    while (ptr < order.size() && st.visited[order[ptr].second].load(rl) == my) ++ptr;
-    if (ptr == order.size()) break;
+  // Members of S not dequeued yet (unvisited or waiting in the queue) by
+  // weight, weights below LIGHT one by one: once the capacity left is below
+  // LIGHT and none of them fits it, no node can join part 1 any more and the
+  // search ends (going on would only visit nodes that do not fit).
+  constexpr int64_t LIGHT = 64;
+  uint32_t light[LIGHT] = {};
+  auto is_light = [&](uint32_t v) { return st.nw[v] >= 0 && st.nw[v] < LIGHT; };
+  for (uint32_t v : S)
+    if (is_light(v)) ++light[st.nw[v]];
+  auto nothing_fits = [&]() {
+    const int64_t R = T1 - w1;
+    if (R >= LIGHT) return false;
+    for (int64_t w = 0; w <= R; ++w)
+      if (light[w]) return false;
+    return true;
+  };
+  bool done = false;
+  while (w1 < T1 && !done && !nothing_fits()) {
+    while (!order.empty() && st.visited[order.front().second].load(rl) == my) {
+      std::pop_heap(order.begin(), order.end(), std::greater<>());
+      order.pop_back();
+    }
+    if (order.empty()) break;
     queue.clear();
     size_t head = 0;
-    visit(order[ptr].second);
-    queue.push_back(order[ptr].second);
+    visit(order.front().second);
+    queue.push_back(order.front().second);
     while (head < queue.size() && w1 < T1) {
       const uint32_t v = queue[head++];
+      if (is_light(v)) --light[st.nw[v]];
       if (w1 + st.nw[v] > T1) continue;
       st.part1[v] = 1;
       w1 += st.nw[v];
+      if (nothing_fits()) {
+        done = true;
+        break;
+      }
       if (nunv == 0) continue;  // nothing left to enqueue
       const uint32_t* rb = st.adj + (st.xadj[v] - st.e0);
       const uint32_t* re = st.adj + (st.xadj[v + 1] - st.e0);
       const uint64_t deg = (uint64_t)(re - rb);
-      if (st.sorted && nwords + 16 * nunv < deg) {
+      if (use_bits && nwords + 2 * std::min(sumlen, nunv * bitlen(deg)) < deg) {
+        const uint32_t vg = (uint32_t)(v + st.n0);
         for (uint64_t w = 0; w < nwords; ++w) {
           uint64_t bits = unv[w];
           while (bits) {
             const uint32_t x = (uint32_t)(w * 64 + __builtin_ctzll(bits));
             bits &= bits - 1;
-            if (std::binary_search(rb, re, (uint32_t)(x + st.n0))) {
+            const uint64_t dx = deg_of(x);
+            const uint32_t* xb = st.adj + (st.xadj[x] - st.e0);
+            const bool found = dx < deg ? std::binary_search(xb, xb + dx, vg)
+                                        : std::binary_search(rb, re, (uint32_t)(x + st.n0));
+            if (found) {
               visit(x);
               queue.push_back(x);
             }
