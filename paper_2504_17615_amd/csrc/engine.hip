@@ -1530,9 +1530,10 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   // search ends (going on would only visit nodes that do not fit).
   constexpr int64_t LIGHT = 64;
   uint32_t light[LIGHT] = {};
-  auto is_light = [&](uint32_t v) { return st.nw[v] >= 0 && st.nw[v] < LIGHT; };
+  // (weights <= 0, which always fit, are counted as 0)
+  auto light_of = [&](uint32_t v) { return st.nw[v] > 0 ? st.nw[v] : 0; };
   for (uint32_t v : S)
-    if (is_light(v)) ++light[st.nw[v]];
+    if (st.nw[v] < LIGHT) ++light[light_of(v)];
   auto nothing_fits = [&]() {
     const int64_t R = T1 - w1;
     if (R >= LIGHT) return false;
@@ -1553,7 +1554,7 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
     queue.push_back(order.front().second);
     while (head < queue.size() && w1 < T1) {
       const uint32_t v = queue[head++];
-      if (is_light(v)) --light[st.nw[v]];
+      if (st.nw[v] < LIGHT) --light[light_of(v)];
       if (w1 + st.nw[v] > T1) continue;
       st.part1[v] = 1;
       w1 += st.nw[v];

@@ -29,6 +29,8 @@ namespace {
 typedef unsigned __int128 u128;
 // Subproblems of at most this many nodes on average take 256-thread groups.
 constexpr uint64_t IP_SMALL_SUB = 4096;
+// Node weights below this are counted one by one for the end-of-search test.
+constexpr int IP_LIGHT = 64;
 
 struct IpArgs {
   const uint64_t* xadj;
@@ -105,6 +107,8 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
   __shared__ uint64_t sdp[IP_NT + 1];
   __shared__ long long sh_w1;
   __shared__ uint32_t sh_head, sh_tail, sh_ptr, sh_done, sh_r0;
+  // nodes not dequeued yet (unvisited or queued) by weight, below IP_LIGHT
+  __shared__ uint32_t sh_light[IP_LIGHT];
   const uint32_t s = blockIdx.x;
   const uint32_t seg = a.segoff[s];
   const uint32_t m = a.segoff[s + 1] - seg;
@@ -117,11 +121,15 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
   uint32_t* jl = a.jl + seg;
   uint64_t* dpre = a.dpre + seg + s;
   const int tid = threadIdx.x, lane = lane_id();
+  for (int w = tid; w < IP_LIGHT; w += IP_NT) sh_light[w] = 0;
+  __syncthreads();
   for (uint32_t i = tid; i < m; i += IP_NT) {
     const uint32_t v = order[i];
     a.visited[v] = 0;
     a.part1[v] = 0;
     __hip_atomic_store(&a.first[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int64_t c = a.nw[v];
+    if (c < IP_LIGHT) atomicAdd(&sh_light[c > 0 ? c : 0], 1u);  // weights <= 0 always fit
   }
   wg_fence();
   if (tid == 0) {
@@ -171,6 +179,7 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
             if (lane == 0) {
               a.visited[vv] = 1;
               if (join) a.part1[vv] = 1;
+              if (cl < IP_LIGHT) --sh_light[cl > 0 ? cl : 0];
             }
             if (join) w1 += cl;
             if (w1 >= T1) {
@@ -243,12 +252,23 @@ __global__ __launch_bounds__(IP_NT) void k_ip_grow(IpArgs a) {
       w1 = sh_w1;
       settled = true;
     }
+    for (uint32_t i = h0 + tid; i < t0; i += IP_NT) {  // the frontier is decided
+      const int64_t c = a.nw[queue[i]];
+      if (c < IP_LIGHT) atomicSub(&sh_light[c > 0 ? c : 0], 1u);
+    }
     if (tid == 0) {
       sh_w1 = w1;
       sh_head = t0;
     }
     __syncthreads();
     if (w1 >= T1) break;
+    // capacity left below IP_LIGHT and no undecided node that light: no node
+    // can join part 1 any more (the rest of the search would only visit)
+    if (T1 - w1 < IP_LIGHT) {
+      bool any = false;
+      for (int64_t w = 0; w <= T1 - w1; ++w) any |= sh_light[w] != 0;
+      if (!any) break;
+    }
     // (3) joined frontier nodes that have neighbours, with their degree prefix
     uint32_t J = 0;
     uint64_t D = 0;

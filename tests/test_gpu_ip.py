@@ -41,10 +41,11 @@ def _shuffle_rows(g, rng):
     return T.G(g.n, g.xadj.copy(), adj, w, g.vwgt)
 
 
-def check(lib, g, k, eps, seed, **kw):
-    print(f"device IP: n={g.n} m={g.nnz // 2} k={k} seed={seed} {kw}", flush=True)
+def check(lib, g, k, eps, seed, ip=1, **kw):
+    where = "device" if ip == 1 else "host"
+    print(f"{where} IP: n={g.n} m={g.nnz // 2} k={k} seed={seed} {kw}", flush=True)
     dg = lib.create_graph(g)
-    blocks, res = dg.partition(k, eps, seed, lib.default_params(ip_device=1, **kw), host_out=True)
+    blocks, res = dg.partition(k, eps, seed, lib.default_params(ip_device=ip, **kw), host_out=True)
     ob, ores, _ = O.partition(g, k, eps, seed, O.params(**kw))
     assert res["cut"] == ores["cut"]
     assert res["max_block_weight"] == ores["max_block_weight"]
@@ -53,11 +54,12 @@ def check(lib, g, k, eps, seed, **kw):
     dg.close()
 
 
+@pytest.mark.parametrize("ip", [1, 0])
 @pytest.mark.parametrize("name", ["grid128", "rmat12", "rmat14", "er12", "er14", "rgg14",
                                   "rgg16", "rmat16"])
-def test_device_ip_workloads(lib, name):
+def test_device_ip_workloads(lib, name, ip):
     g, k, eps, seed = gg.workload(name)
-    check(lib, g, k, eps, seed)
+    check(lib, g, k, eps, seed, ip)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 7, 100, 2000])
@@ -80,13 +82,33 @@ def test_device_ip_sparsified_levels(lib):
     check(lib, g, k, eps, seed, sampler=1)
 
 
-def test_device_ip_degenerate(lib):
-    check(lib, T.path(2), 2, 0.03, 1)
-    check(lib, T.from_edges(5, [(0, 1)]), 3, 0.03, 1)  # isolated nodes
-    check(lib, T.two_cliques(8), 2, 0.03, 3)
-    check(lib, T.from_edges(400, []), 4, 0.03, 2)  # no edges at all
-    check(lib, T.star(5000), 2, 0.03, 3)
-    check(lib, T.star(300), 16, 0.03, 3)
+@pytest.mark.parametrize("ip", [1, 0])
+def test_device_ip_degenerate(lib, ip):
+    check(lib, T.path(2), 2, 0.03, 1, ip)
+    check(lib, T.from_edges(5, [(0, 1)]), 3, 0.03, 1, ip)  # isolated nodes
+    check(lib, T.two_cliques(8), 2, 0.03, 3, ip)
+    check(lib, T.from_edges(400, []), 4, 0.03, 2, ip)  # no edges at all
+    check(lib, T.star(5000), 2, 0.03, 3, ip)
+    check(lib, T.star(300), 16, 0.03, 3, ip)
+
+
+def _core_with_stragglers(rng, core=220, pendants=60, isolated=120):
+    # a clique whose rows are long, nodes of degree one hanging off it, and
+    # isolated nodes: the searches keep a few unvisited nodes of short rows
+    # for long (the host bisection then walks them instead of scanning rows)
+    edges = [(a, b) for a in range(core) for b in range(a + 1, core)]
+    for p in range(pendants):
+        edges.append((int(rng.integers(core)), core + p))
+    n = core + pendants + isolated
+    vw = rng.integers(1, 6, size=n)
+    return T.from_edges(n, edges, vwgt=vw)
+
+
+@pytest.mark.parametrize("ip", [0, 1])
+@pytest.mark.parametrize("k", [2, 5, 16])
+def test_dense_core_with_stragglers(lib, k, ip):
+    g = _core_with_stragglers(np.random.default_rng(40 + k))
+    check(lib, g, k, 0.03, 11, ip)
 
 
 def test_device_ip_unsorted_rows(lib):
