@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
@@ -523,10 +524,15 @@ __global__ __launch_bounds__(NT) void k_rate_big(RateArgs a0) {
 // Refinement with few labels (blocks, at most FEW_LABELS): nodes of the block
 // and big-block classes rate into a dense LDS row indexed by the label, with
 // no hashing and no probing; NT threads per node.
-template <int EWK, int NT>
+// P: ratings fit in 32 bits (RateArgs.packed), the row holds 32-bit counters.
+template <bool P>
+using RowCount = typename std::conditional<P, uint32_t, unsigned long long>::type;
+
+template <int EWK, int NT, bool P>
 __global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a0) {
   constexpr int NW = NT / WAVE;
-  __shared__ unsigned long long tab[FEW_LABELS];
+  using CT = RowCount<P>;
+  __shared__ CT tab[FEW_LABELS];
   __shared__ Best sb[NW];
   __shared__ int64_t so[NW];
   __shared__ int64_t sm[NW];
@@ -561,12 +567,12 @@ __global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a0) {
     for (int j = 0; j < U; ++j) {
       if (K[j] == EMPTY_KEY) continue;
       if (K[j] == own) acc += w[j];
-      else atomicAdd(&tab[K[j]], (unsigned long long)w[j]);
+      else atomicAdd(&tab[K[j]], (CT)w[j]);
     }
   }
   int64_t acc_tot;
   (void)block_exclusive_scan<int64_t, NW>(acc, sm, acc_tot);
-  if (threadIdx.x == 0) tab[own] += (unsigned long long)acc_tot;
+  if (threadIdx.x == 0) tab[own] += (CT)acc_tot;
   __syncthreads();
   const GraphDesc gd = a.gd[graph_of(a.gid, u)];
   const int64_t cu = a.nw[u];
@@ -600,9 +606,11 @@ __global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a0) {
 // so no wave waits at a block barrier and one node's evaluation overlaps the
 // other waves' loads.  RW_WAVES rows of `few` counters per block, in
 // dynamic LDS.
-template <int EWK>
+template <int EWK, bool P>
 __global__ __launch_bounds__(RW_WAVES * WAVE) void k_rate_rows(RateArgs a0) {
-  extern __shared__ unsigned long long rw_tab[];
+  using CT = RowCount<P>;
+  extern __shared__ __align__(8) unsigned char rw_raw[];
+  CT* rw_tab = reinterpret_cast<CT*>(rw_raw);
   RateArgs a = a0;
   resolve_plan(a);
   const int wv = threadIdx.x / WAVE, ln = lane_id();
@@ -615,7 +623,7 @@ __global__ __launch_bounds__(RW_WAVES * WAVE) void k_rate_rows(RateArgs a0) {
     return;
   }
   const uint32_t few = a.few;
-  unsigned long long* tab = rw_tab + (size_t)wv * few;
+  CT* tab = rw_tab + (size_t)wv * few;
   for (uint32_t t = ln; t < few; t += WAVE) tab[t] = 0;
   wave_sync();
   const uint64_t beg = a.xadj[u], end = a.xadj[u + 1];
@@ -640,11 +648,11 @@ __global__ __launch_bounds__(RW_WAVES * WAVE) void k_rate_rows(RateArgs a0) {
     for (int j = 0; j < U; ++j) {
       if (e0 + (uint64_t)j * WAVE >= end) continue;
       if (K[j] == own) acc += w[j];
-      else atomicAdd(&tab[K[j]], (unsigned long long)w[j]);
+      else atomicAdd(&tab[K[j]], (CT)w[j]);
     }
   }
   acc = group_sum<WAVE>(acc);
-  if (ln == 0 && acc > 0) atomicAdd(&tab[own], (unsigned long long)acc);
+  if (ln == 0 && acc > 0) atomicAdd(&tab[own], (CT)acc);
   wave_sync();
   const GraphDesc gd = a.gd[g];
   const int64_t cu = a.nw[u];
@@ -1084,9 +1092,10 @@ std::string rate_name(int phase, int cls, int ewk, bool few, bool packed) {
   const int w = ewk;
   std::string k;
   if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_BLOCK + 2)
-    k = "k_rate_rows<" + std::to_string(w) + ">";
+    k = "k_rate_rows<" + std::to_string(w) + (packed ? ", true>" : ", false>");
   else if (phase == 1 && few && cls >= CLASS_BLOCK && cls < CLASS_GLOBAL)
-    k = "k_rate_dense<" + std::to_string(w) + ", " + (cls < CLASS_BIG ? "256>" : "1024>");
+    k = "k_rate_dense<" + std::to_string(w) + ", " + (cls < CLASS_BIG ? "256, " : "1024, ") +
+        (packed ? "true>" : "false>");
   else if (cls < CLASS_BLOCK) k = "k_rate_group<" + std::to_string(class_group(cls)) + ", " + std::to_string(w) + ">";
   else if (cls < CLASS_BIG && !(packed && cls >= CLASS_BLOCK + 2))
     k = "k_rate_block<" + std::to_string(w) + ", " + std::to_string(class_table_log(cls)) + ">";
@@ -1137,14 +1146,18 @@ void launch_rate_t(int cls, const RateArgs& a, hipStream_t s) {
   if (cls < CLASS_BLOCK) {
     throw InvalidArg("lane-group classes are launched by launch_rate_groups");
   } else if (a.few && a.few <= FEW_LABELS && a.mode == MODE_LP && cls < CLASS_GLOBAL) {
-    if (cls < CLASS_BLOCK + 2)
-      launch_k_lds(k_rate_rows<EWK>, dim3((uint32_t)ceil_div(a.count, RW_WAVES)),
-                   dim3(RW_WAVES * WAVE),
-                   (uint32_t)(RW_WAVES * a.few * sizeof(unsigned long long)), s, e0, e1, a);
-    else if (cls < CLASS_BIG)
-      launch_k(k_rate_dense<EWK, 256>, dim3(a.count), dim3(256), s, e0, e1, a);
-    else
-      launch_k(k_rate_dense<EWK, 1024>, dim3(a.count), dim3(1024), s, e0, e1, a);
+    const dim3 rgrid((uint32_t)ceil_div(a.count, RW_WAVES)), rblk(RW_WAVES * WAVE);
+    const uint32_t rlds = (uint32_t)(RW_WAVES * a.few * (a.packed ? 4 : 8));
+    if (cls < CLASS_BLOCK + 2) {
+      if (a.packed) launch_k_lds(k_rate_rows<EWK, true>, rgrid, rblk, rlds, s, e0, e1, a);
+      else launch_k_lds(k_rate_rows<EWK, false>, rgrid, rblk, rlds, s, e0, e1, a);
+    } else if (cls < CLASS_BIG) {
+      if (a.packed) launch_k(k_rate_dense<EWK, 256, true>, dim3(a.count), dim3(256), s, e0, e1, a);
+      else launch_k(k_rate_dense<EWK, 256, false>, dim3(a.count), dim3(256), s, e0, e1, a);
+    } else {
+      if (a.packed) launch_k(k_rate_dense<EWK, 1024, true>, dim3(a.count), dim3(1024), s, e0, e1, a);
+      else launch_k(k_rate_dense<EWK, 1024, false>, dim3(a.count), dim3(1024), s, e0, e1, a);
+    }
   } else if (cls < CLASS_BIG && a.packed && cls >= CLASS_BLOCK + 2) {
     if (cls == CLASS_BLOCK + 2)
       launch_k(k_rate_big<EWK, 11, 256>, dim3(a.count), dim3(256), s, e0, e1, a);

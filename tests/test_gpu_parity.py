@@ -184,6 +184,27 @@ def test_hub_rows_heavy_weights(lib):
     check_partition(lib, g, 2, 0.03, 3)
 
 
+def test_dense_rows_heavy_weights(lib):
+    # total edge weight >= 2^32: refinement's dense rows (one wave per node,
+    # 256-thread rows) keep 64-bit counters instead of 32-bit ones
+    rng = np.random.default_rng(8)
+    n = 4000
+    edges = set()
+    while len(edges) < 20000:
+        a, b = (int(x) for x in rng.integers(n, size=2))
+        if a != b:
+            edges.add((min(a, b), max(a, b)))
+    for h, d in zip(range(20), np.linspace(150, 3000, 20).astype(int)):
+        for b in rng.choice(n, size=d, replace=False):
+            if int(b) != h:
+                edges.add((min(h, int(b)), max(h, int(b))))
+    e = np.array(sorted(edges))
+    w = rng.integers(1 << 19, 1 << 20, size=len(e))
+    g = T.from_edges(n, e, w)
+    assert int(g.adjwgt.sum()) >= 1 << 32
+    check_partition(lib, g, 8, 0.03, 4)
+
+
 def _shuffle_rows(g, rng):
     adj = g.adjncy.copy()
     w = None if g.adjwgt is None else g.adjwgt.copy()
