@@ -22,6 +22,9 @@ struct ContractIn {
   // order (every consumer on the device is order independent); true: rows
   // sorted by neighbour id
   bool sorted = true;
+  // every coarse edge weight is below 2^31: the coarse weights are stored as
+  // int32 (ew32, ew_kind EW_I32) instead of int64
+  bool narrow = false;
   std::vector<uint64_t> bounds;     // node boundaries of the graphs (B + 1 values)
 };
 
@@ -33,8 +36,11 @@ struct ContractOut {
   DBuf<uint64_t> xadj;
   DBuf<uint32_t> adj;
   DBuf<int64_t> ew;
+  DBuf<int32_t> ew32;
+  int ew_kind = EW_I64;  // which of ew / ew32 holds the coarse weights
   DBuf<uint32_t> src;
   std::vector<uint32_t> cid_at_bounds;  // coarse node boundaries of the graphs
+  const void* weights() const { return ew_kind == EW_I32 ? (const void*)ew32.get() : ew.get(); }
 };
 
 struct ContractArgs {
@@ -78,12 +84,15 @@ struct SparsOut {
   DBuf<uint64_t> xadj;
   DBuf<uint32_t> adj;
   DBuf<int64_t> ew;
+  DBuf<int32_t> ew32;
+  int ew_kind = EW_I64;  // the input's: EW_I64 (ew) or EW_I32 (ew32)
   DBuf<uint32_t> src;
 };
 
-// Sparsify the triggered graphs of a union level in place of a new CSR.
+// Sparsify the triggered graphs of a union level in place of a new CSR.  The
+// weights are int64 (ew_kind EW_I64) or int32 (EW_I32) and keep their width.
 void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
-                    const int64_t* ew, const uint32_t* src, const uint32_t* gid,
+                    const void* ew, int ew_kind, const uint32_t* src, const uint32_t* gid,
                     std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s);
 
 // --------------------------------------------------------------- refinement --

@@ -804,8 +804,9 @@ __global__ void k_rows_finish(ContractArgs a, const uint32_t* rows, uint32_t nro
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)nd;
 }
 
-// Compact the scratch rows into the coarse CSR.
-__global__ void k_rows_copy(ContractArgs a, uint64_t total, uint32_t* cadj, int64_t* cew,
+// Compact the scratch rows into the coarse CSR (weights stored as WT).
+template <typename WT>
+__global__ void k_rows_copy(ContractArgs a, uint64_t total, uint32_t* cadj, WT* cew,
                             uint32_t* csrc, const uint64_t* cxadj) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -814,7 +815,7 @@ __global__ void k_rows_copy(ContractArgs a, uint64_t total, uint32_t* cadj, int6
   const uint32_t x = a.tsrc[e];
   const uint64_t d = cxadj[x] + (e - a.tmpoff[x]);
   cadj[d] = k;
-  cew[d] = a.tw[e];
+  cew[d] = (WT)a.tw[e];
   csrc[d] = x;
 }
 
@@ -1039,11 +1040,17 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   read_now(&mc, out.xadj.get() + nc, sizeof(uint64_t), s);
   out.nnz = mc;
   out.adj.reset(&pool, s, mc ? mc : 1);
-  out.ew.reset(&pool, s, mc ? mc : 1);
   out.src.reset(&pool, s, mc ? mc : 1);
+  out.ew_kind = in.narrow ? EW_I32 : EW_I64;
+  if (in.narrow) out.ew32.reset(&pool, s, mc ? mc : 1);
+  else out.ew.reset(&pool, s, mc ? mc : 1);
   if (mt) {
-    k_rows_copy<<<grid_for(mt, 256), 256, 0, s>>>(a, mt, out.adj.get(), out.ew.get(),
-                                                   out.src.get(), out.xadj.get());
+    if (in.narrow)
+      k_rows_copy<int32_t><<<grid_for(mt, 256), 256, 0, s>>>(a, mt, out.adj.get(), out.ew32.get(),
+                                                             out.src.get(), out.xadj.get());
+    else
+      k_rows_copy<int64_t><<<grid_for(mt, 256), 256, 0, s>>>(a, mt, out.adj.get(), out.ew.get(),
+                                                             out.src.get(), out.xadj.get());
     LAUNCH_CHECK();
   }
   HIP_CHECK(hipStreamSynchronize(s));

@@ -46,6 +46,7 @@ struct Level {
   DBuf<uint64_t> o_xadj;
   DBuf<uint32_t> o_adj;
   DBuf<int64_t> o_ew;
+  DBuf<int32_t> o_ew32;  // coarse edge weights stored narrow (ew_kind EW_I32)
   DBuf<int64_t> o_nw;
   DBuf<uint32_t> o_src;
   DBuf<uint32_t> o_gid;
@@ -102,6 +103,7 @@ class Engine {
                uint32_t level, uint32_t* label, int64_t* W, uint32_t* csize,
                std::vector<uint64_t>& ncl);
   void build_union(std::vector<Job>& jobs);
+  void narrow_weights(Level& L);
   void rate_classes(RateArgs ra, const uint32_t* cnt, const uint32_t* offs,
                     const unsigned long long* degs, int ew_kind);
 
@@ -109,6 +111,7 @@ class Engine {
   hipStream_t s_;
   lmgp_params p_;
   bool packed_ = false;  // all ratings < 2^32: packed hub tables
+  bool narrow_ = false;  // all entry weights < 2^31: coarse weights stored as int32
   std::vector<std::unique_ptr<Level>> levels_;
 };
 

@@ -279,6 +279,12 @@ __global__ void k_pair_merge(const uint32_t* vals, const uint32_t* flag, const u
   csize[lb] -= 1;
 }
 
+// Coarse edge weights known to be below 2^31, stored as int32.
+__global__ void k_narrow_i32(const int64_t* w, uint64_t n, int32_t* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int32_t)w[i];
+}
+
 // Union construction for batches: concatenate graphs with rebased ids.
 struct UnionPart {
   const uint64_t* xadj;
@@ -1073,6 +1079,19 @@ void Engine::ensure_sorted(size_t i) {
   L.ew_kind = EW_I64;
   L.src = L.o_src.get();
   L.sorted = true;
+  narrow_weights(L);
+}
+
+// A coarse level's int64 weights (o_ew) stored as int32 when narrow_.
+void Engine::narrow_weights(Level& L) {
+  L.o_ew32.clear();
+  if (!narrow_ || !L.nnz || L.ew_kind != EW_I64) return;
+  L.o_ew32.reset(&pool_, s_, L.nnz);
+  k_narrow_i32<<<grid_for(L.nnz, 256), 256, 0, s_>>>(L.o_ew.get(), L.nnz, L.o_ew32.get());
+  LAUNCH_CHECK();
+  L.o_ew.clear();
+  L.ew = L.o_ew32.get();
+  L.ew_kind = EW_I32;
 }
 
 // -------------------------------------------------------------- coarsening --
@@ -1084,6 +1103,10 @@ void Engine::coarsen(std::vector<Job>& jobs) {
   // only merges weight, sparsification only drops it)
   packed_ = true;
   for (auto& jb : jobs) packed_ &= jb.g->wtot < (1ull << 32) && jb.g->nnz < (1ull << 32);
+  // the same bound on every coarse edge weight: int32 storage holds them
+  // (a third fewer bytes per entry for every pass over a coarse level)
+  narrow_ = true;
+  for (auto& jb : jobs) narrow_ &= jb.g->wtot < (1ull << 31);
   for (auto& jb : jobs) {
     jb.nlevels = 1;
     jb.info.clear();
@@ -1129,6 +1152,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     ci.adj = L.adj;
     ci.ew = L.ew;
     ci.ew_kind = L.ew_kind;
+    ci.narrow = narrow_;
     ci.label = label.get();
     ci.W = W.get();
     ci.csize = csize.get();
@@ -1211,18 +1235,22 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     }
     if (any_trig) {
       SparsOut so;
-      sparsify_level(co.nc, co.nnz, co.xadj.get(), co.adj.get(), co.ew.get(), co.src.get(),
-                     BC > 1 ? co.gid.get() : nullptr, sgs, so, pool_, s_);
+      sparsify_level(co.nc, co.nnz, co.xadj.get(), co.adj.get(), co.weights(), co.ew_kind,
+                     co.src.get(), BC > 1 ? co.gid.get() : nullptr, sgs, so, pool_, s_);
       C->nnz = so.nnz;
       C->o_xadj = std::move(so.xadj);
       C->o_adj = std::move(so.adj);
       C->o_ew = std::move(so.ew);
+      C->o_ew32 = std::move(so.ew32);
+      C->ew_kind = so.ew_kind;
       C->o_src = std::move(so.src);
       read_ebase(C->o_xadj.get());
     } else {
       C->o_xadj = std::move(co.xadj);
       C->o_adj = std::move(co.adj);
       C->o_ew = std::move(co.ew);
+      C->o_ew32 = std::move(co.ew32);
+      C->ew_kind = co.ew_kind;
       C->o_src = std::move(co.src);
     }
     C->o_nw = std::move(co.nw);
@@ -1230,8 +1258,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     C->sorted = false;
     C->xadj = C->o_xadj.get();
     C->adj = C->o_adj.get();
-    C->ew = C->o_ew.get();
-    C->ew_kind = EW_I64;
+    C->ew = C->ew_kind == EW_I32 ? (const void*)C->o_ew32.get() : (const void*)C->o_ew.get();
     C->nw = C->o_nw.get();
     C->src = C->o_src.get();
     C->gid = BC > 1 ? C->o_gid.get() : nullptr;

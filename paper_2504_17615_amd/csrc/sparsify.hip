@@ -17,13 +17,14 @@ namespace lmgp {
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_wmax(const int64_t* ew, uint64_t e0, uint64_t e1,
+template <typename WT>
+__global__ __launch_bounds__(256) void k_wmax(const WT* ew, uint64_t e0, uint64_t e1,
                                               unsigned long long* out) {
   __shared__ int64_t sm[NWAVE];
   int64_t m = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride)
-    m = ew[e] > m ? ew[e] : m;
+    m = (int64_t)ew[e] > m ? (int64_t)ew[e] : m;
   m = wave_reduce_max(m);
   if (lane_id() == 0) sm[threadIdx.x / WAVE] = m;
   __syncthreads();
@@ -33,7 +34,8 @@ __global__ __launch_bounds__(256) void k_wmax(const int64_t* ew, uint64_t e0, ui
   }
 }
 
-__global__ __launch_bounds__(256) void k_whist(const int64_t* ew, uint64_t e0, uint64_t e1,
+template <typename WT>
+__global__ __launch_bounds__(256) void k_whist(const WT* ew, uint64_t e0, uint64_t e1,
                                                int shift, uint64_t prefix, uint32_t* hist) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(256) void k_whist(const int64_t* ew, uint64_t e0, u
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const int hs = shift + 8;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
-    const uint64_t w = (uint64_t)ew[e];
+    const uint64_t w = (uint64_t)(int64_t)ew[e];
     const bool match = hs >= 64 || (w >> hs) == (prefix >> hs);
     if (match) atomicAdd(&h[(w >> shift) & 0xFF], 1u);
   }
@@ -54,8 +56,9 @@ LMGP_D uint64_t edge_key(uint64_t pre, uint64_t a, uint64_t b) {
 }
 
 // 12-bit histogram of the top bits of the keys of E^= (a < b entries only).
+template <typename WT>
 __global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32_t* adj,
-                                               const int64_t* ew, uint64_t e0, uint64_t e1,
+                                               const WT* ew, uint64_t e0, uint64_t e1,
                                                int64_t w_t, uint64_t base, uint64_t pre,
                                                uint32_t* hist) {
   __shared__ uint32_t h[4096];
@@ -64,7 +67,8 @@ __global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
     const uint32_t a = src[e], b = adj[e];
-    if (a < b && ew[e] == w_t) atomicAdd(&h[edge_key(pre, a - base, b - base) >> 52], 1u);
+    if (a < b && (int64_t)ew[e] == w_t)
+      atomicAdd(&h[edge_key(pre, a - base, b - base) >> 52], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 4096; i += 256)
@@ -76,15 +80,16 @@ struct EqEntry {
   uint32_t a, b;  // local ids
 };
 
+template <typename WT>
 __global__ __launch_bounds__(256) void k_kgather(const uint32_t* src, const uint32_t* adj,
-                                                 const int64_t* ew, uint64_t e0, uint64_t e1,
+                                                 const WT* ew, uint64_t e0, uint64_t e1,
                                                  int64_t w_t, uint64_t base, uint64_t pre,
                                                  uint32_t bucket, EqEntry* out, uint32_t* cnt,
                                                  uint32_t cap) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
     const uint32_t a = src[e], b = adj[e];
-    if (a < b && ew[e] == w_t) {
+    if (a < b && (int64_t)ew[e] == w_t) {
       const uint64_t k = edge_key(pre, a - base, b - base);
       if ((k >> 52) == bucket) {
         const uint32_t p = atomicAdd(cnt, 1u);
@@ -108,7 +113,8 @@ struct SparsDesc {
   uint64_t coin_n, coin_r;
 };
 
-__global__ void k_keep(const uint32_t* src, const uint32_t* adj, const int64_t* ew,
+template <typename WT>
+__global__ void k_keep(const uint32_t* src, const uint32_t* adj, const WT* ew,
                        const uint32_t* gid, const SparsDesc* sd, uint64_t nnz, uint8_t* keep) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
@@ -120,7 +126,7 @@ __global__ void k_keep(const uint32_t* src, const uint32_t* adj, const int64_t* 
   if (d.mode == 3) {
     k = __umul64hi(edge_key(d.pre, a, b), d.coin_n) < d.coin_r;
   } else if (d.mode != 0) {
-    const int64_t w = ew[e];
+    const int64_t w = (int64_t)ew[e];
     if (w > d.w_t) k = 1;
     else if (w < d.w_t) k = 0;
     else if (d.mode == 1) k = 1;
@@ -138,9 +144,10 @@ struct U8At {
   LMGP_D uint64_t operator()(uint64_t i) const { return a[i]; }
 };
 
-__global__ void k_scatter_kept(const uint32_t* src, const uint32_t* adj, const int64_t* ew,
+template <typename WT>
+__global__ void k_scatter_kept(const uint32_t* src, const uint32_t* adj, const WT* ew,
                                const uint8_t* keep, const uint64_t* pos, uint64_t nnz,
-                               uint32_t* osrc, uint32_t* oadj, int64_t* oew) {
+                               uint32_t* osrc, uint32_t* oadj, WT* oew) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz || !keep[e]) return;
   const uint64_t p = pos[e];
@@ -163,9 +170,13 @@ unsigned sweep_grid(uint64_t cnt) {
 
 }  // namespace
 
-void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
-                    const int64_t* ew, const uint32_t* src, const uint32_t* gid,
-                    std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s) {
+namespace {
+
+template <typename WT>
+void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
+                const WT* ew, const uint32_t* src, const uint32_t* gid,
+                std::vector<SparsGraph>& graphs, SparsOut& out, WT* (*alloc_w)(SparsOut&, uint64_t, Pool&, hipStream_t),
+                Pool& pool, hipStream_t s) {
   const size_t B = graphs.size();
   std::vector<SparsDesc> desc(B);
   DBuf<unsigned long long> dmax(&pool, s, 1);
@@ -191,7 +202,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
     }
     const uint64_t e0 = sg.e0, e1 = sg.e1;
     dmax.zero();
-    k_wmax<<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, dmax.get());
+    k_wmax<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, dmax.get());
     LAUNCH_CHECK();
     unsigned long long wmax = 0;
     read_now(&wmax, dmax.get(), sizeof(wmax), s);
@@ -202,7 +213,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
     std::vector<uint32_t> h(256);
     for (int shift = top - 8; shift >= 0; shift -= 8) {
       hist.zero();
-      k_whist<<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, shift, prefix, hist.get());
+      k_whist<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, shift, prefix, hist.get());
       LAUNCH_CHECK();
       read_now(h.data(), hist.get(), 256 * sizeof(uint32_t), s);
       uint64_t cum = 0;
@@ -236,7 +247,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
     }
     // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t
     hist.zero();
-    k_khist<<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
+    k_khist<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
                                                  sg.pre, hist.get());
     LAUNCH_CHECK();
     std::vector<uint32_t> kh(4096);
@@ -254,7 +265,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
     const uint32_t bsz = kh[bucket];
     DBuf<EqEntry> buf(&pool, s, bsz ? bsz : 1);
     cnt.zero();
-    k_kgather<<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
+    k_kgather<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
                                                    sg.pre, bucket, buf.get(), cnt.get(), bsz);
     LAUNCH_CHECK();
     std::vector<EqEntry> hb(bsz);
@@ -276,7 +287,7 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
   HIP_CHECK(hipMemcpyAsync(dd.get(), desc.data(), B * sizeof(SparsDesc), hipMemcpyHostToDevice, s));
   DBuf<uint8_t> keep(&pool, s, nnz ? nnz : 1);
   if (nnz) {
-    k_keep<<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, gid, dd.get(), nnz, keep.get());
+    k_keep<WT><<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, gid, dd.get(), nnz, keep.get());
     LAUNCH_CHECK();
   }
   DBuf<uint64_t> pos(&pool, s, nnz + 1);
@@ -286,16 +297,42 @@ void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32
   out.nnz = total;
   out.xadj.reset(&pool, s, n + 1);
   out.adj.reset(&pool, s, total ? total : 1);
-  out.ew.reset(&pool, s, total ? total : 1);
+  WT* oew = alloc_w(out, total ? total : 1, pool, s);
   out.src.reset(&pool, s, total ? total : 1);
   if (nnz) {
-    k_scatter_kept<<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, keep.get(), pos.get(), nnz,
-                                                       out.src.get(), out.adj.get(), out.ew.get());
+    k_scatter_kept<WT><<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, keep.get(), pos.get(), nnz,
+                                                           out.src.get(), out.adj.get(), oew);
     LAUNCH_CHECK();
   }
   k_row_starts<<<grid_for(n + 1, 256), 256, 0, s>>>(xadj, pos.get(), n, out.xadj.get());
   LAUNCH_CHECK();
   HIP_CHECK(hipStreamSynchronize(s));
+}
+
+int64_t* alloc_w64(SparsOut& o, uint64_t n, Pool& pool, hipStream_t s) {
+  o.ew.reset(&pool, s, n);
+  o.ew_kind = EW_I64;
+  return o.ew.get();
+}
+int32_t* alloc_w32(SparsOut& o, uint64_t n, Pool& pool, hipStream_t s) {
+  o.ew32.reset(&pool, s, n);
+  o.ew_kind = EW_I32;
+  return o.ew32.get();
+}
+
+}  // namespace
+
+void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
+                    const void* ew, int ew_kind, const uint32_t* src, const uint32_t* gid,
+                    std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s) {
+  if (ew_kind == EW_I32)
+    sparsify_t<int32_t>(n, nnz, xadj, adj, (const int32_t*)ew, src, gid, graphs, out, alloc_w32,
+                        pool, s);
+  else if (ew_kind == EW_I64)
+    sparsify_t<int64_t>(n, nnz, xadj, adj, (const int64_t*)ew, src, gid, graphs, out, alloc_w64,
+                        pool, s);
+  else
+    throw InvalidArg("sparsification needs stored edge weights");
 }
 
 }  // namespace lmgp
