@@ -166,7 +166,9 @@ typedef struct {
 typedef struct {
   uint64_t hbm_budget_bytes;  /* admission limit on the summed estimated footprint */
   uint32_t max_slots;         /* requests resident at once                          */
-  uint32_t max_batch;         /* requests fused into one batched run                */
+  uint32_t max_batch;         /* requests fused into one batched run (a run also
+                                 stops before 2^21 directed entries; a request
+                                 above that runs alone)                             */
   uint32_t streams;           /* concurrent device streams (worker threads)         */
   uint32_t ip_device;         /* lmgp_params.ip_device of every batched run          */
 } lmgp_server_cfg;

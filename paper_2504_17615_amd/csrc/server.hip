@@ -3,8 +3,9 @@
 // Requests enter a FIFO queue.  Worker threads (one device stream each) admit
 // requests from the head of the queue while a slot is free and the summed
 // footprint estimate of resident requests stays within the HBM budget, up to
-// max_batch per run, and partition the admitted set as one batched run (all
-// graphs of the run share every kernel launch).  Requests arriving while runs
+// max_batch per run and 2^21 directed entries per run (a larger request runs
+// alone), and partition the admitted set as one batched run (all graphs of
+// the run share every kernel launch).  Requests arriving while runs
 // are on the device are admitted by the next free worker as soon as slots and
 // memory free up, so their work overlaps with the runs in flight.  Every
 // result is identical to a plain lmgp_partition call (per-graph rules only).
@@ -48,6 +49,9 @@ uint64_t request_footprint(uint64_t n, uint64_t nnz) {
   return 4096 + n * 160 + nnz * 64;
 }
 
+// Directed entries above which a run takes no further request.
+constexpr uint64_t RUN_ENTRIES = 1ull << 21;
+
 }  // namespace lmgp
 
 struct lmgp_server {
@@ -90,11 +94,18 @@ void worker_main(lmgp_server* sv) {
                sv->resident_bytes + r->footprint <= sv->cfg.hbm_budget_bytes;
       });
       if (sv->stop) break;
+      uint64_t entries = 0;
       while (!sv->queue.empty() && batch.size() < sv->cfg.max_batch) {
         Request* r = sv->queue.front();
         if (sv->resident >= sv->cfg.max_slots ||
             sv->resident_bytes + r->footprint > sv->cfg.hbm_budget_bytes)
           break;
+        // a run ends where the next request would take it past RUN_ENTRIES
+        // (a large request runs alone): every graph of a run waits for the
+        // run's last one, so a small request should not wait for a large one
+        const uint64_t e = r->graph->g.nnz;
+        if (!batch.empty() && entries + e > RUN_ENTRIES) break;
+        entries += e;
         sv->queue.pop_front();
         sv->resident++;
         sv->resident_bytes += r->footprint;
