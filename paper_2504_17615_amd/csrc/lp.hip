@@ -1961,9 +1961,11 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
   LAUNCH_CHECK();
   k_adm_scatter<<<g, 256, 0, s>>>(a);
   LAUNCH_CHECK();
-  // one wave per small segment, one block per segment above 64 candidates
+  // one wave per small segment, one block per segment above 64 candidates;
+  // one block per CU at most (most launches find no segment at all, and
+  // dispatching more blocks was most of their cost)
   unsigned gs = grid_for(a.max_cands, SEG_NT / WAVE);
-  if (gs > 1024) gs = 1024;
+  if (gs > 256) gs = 256;
   k_adm_seg<<<gs, SEG_NT, 0, s>>>(a);
   LAUNCH_CHECK();
   // apply (clearing the per-target scratch as it goes)
