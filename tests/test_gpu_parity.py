@@ -184,6 +184,19 @@ def test_hub_rows_heavy_weights(lib):
     check_partition(lib, g, 2, 0.03, 3)
 
 
+def test_packed_wide_coarse_weights(lib):
+    # 2^31 <= total edge weight < 2^32: ratings still fit 32 bits (packed
+    # tables, 32-bit dense rows) while coarse weights stay int64
+    rng = np.random.default_rng(12)
+    g = T.random_graph(3000, 20000, rng)
+    w = rng.integers(50000, 60000, size=g.nnz // 2)
+    a, b, _ = T.edges_of(g)
+    g = T.from_edges(g.n, np.stack([a, b], 1), w)
+    assert (1 << 31) <= int(g.adjwgt.sum()) < (1 << 32)
+    check_hierarchy(lib, g, 8, 6)
+    check_partition(lib, g, 8, 0.03, 6)
+
+
 def test_dense_rows_heavy_weights(lib):
     # total edge weight >= 2^32: refinement's dense rows (one wave per node,
     # 256-thread rows) keep 64-bit counters instead of 32-bit ones
