@@ -99,6 +99,13 @@ template <>
 LMGP_D int64_t edge_w<EW_I64>(const void* ew, uint64_t e) {
   return ((const int64_t*)ew)[e];
 }
+// The weights of a row starting at entry `beg` (NULL for unit weights), read
+// with 32-bit offsets by edge_w.
+template <int K>
+LMGP_D const void* edge_row(const void* ew, uint64_t beg) {
+  return K == EW_I32 ? (const void*)((const int32_t*)ew + beg)
+       : K == EW_I64 ? (const void*)((const int64_t*)ew + beg) : nullptr;
+}
 
 LMGP_HD uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 

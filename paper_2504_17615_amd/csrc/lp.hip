@@ -461,17 +461,22 @@ __global__ __launch_bounds__(NT) void k_rate_big(RateArgs a0) {
   const uint32_t own = a.label[u];
   int64_t acc = 0;
   constexpr int U = 8;  // entries per thread whose loads are issued together
-  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * NT) {
+  // 32-bit offsets into the row (a block-uniform base): the loads take a
+  // scalar base and one vector offset
+  const uint32_t deg = (uint32_t)(end - beg);
+  const uint32_t* arow = a.adj + beg;
+  const void* wrow = edge_row<EWK>(a.ew, beg);
+  for (uint32_t o0 = threadIdx.x; o0 < deg; o0 += (uint32_t)(U * NT)) {
     uint32_t v[U], K[U];
     int64_t w[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const uint64_t e = e0 + (uint64_t)j * NT;
-      v[j] = e < end ? a.adj[e] : 0u;
-      w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+      const uint32_t o = o0 + (uint32_t)(j * NT);
+      v[j] = o < deg ? arow[o] : 0u;
+      w[j] = o < deg ? edge_w<EWK>(wrow, o) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * NT < end ? a.label[v[j]] : EMPTY_KEY;
+    for (int j = 0; j < U; ++j) K[j] = o0 + (uint32_t)(j * NT) < deg ? a.label[v[j]] : EMPTY_KEY;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (K[j] == EMPTY_KEY) continue;
@@ -552,17 +557,20 @@ __global__ __launch_bounds__(NT) void k_rate_dense(RateArgs a0) {
   const uint32_t own = a.label[u];
   int64_t acc = 0;
   constexpr int U = 8;
-  for (uint64_t e0 = beg + threadIdx.x; e0 < end; e0 += (uint64_t)U * NT) {
+  const uint32_t deg = (uint32_t)(end - beg);
+  const uint32_t* arow = a.adj + beg;
+  const void* wrow = edge_row<EWK>(a.ew, beg);
+  for (uint32_t o0 = threadIdx.x; o0 < deg; o0 += (uint32_t)(U * NT)) {
     uint32_t v[U], K[U];
     int64_t w[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const uint64_t e = e0 + (uint64_t)j * NT;
-      v[j] = e < end ? a.adj[e] : 0u;
-      w[j] = e < end ? edge_w<EWK>(a.ew, e) : 0;
+      const uint32_t o = o0 + (uint32_t)(j * NT);
+      v[j] = o < deg ? arow[o] : 0u;
+      w[j] = o < deg ? edge_w<EWK>(wrow, o) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < U; ++j) K[j] = e0 + (uint64_t)j * NT < end ? a.label[v[j]] : EMPTY_KEY;
+    for (int j = 0; j < U; ++j) K[j] = o0 + (uint32_t)(j * NT) < deg ? a.label[v[j]] : EMPTY_KEY;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (K[j] == EMPTY_KEY) continue;
