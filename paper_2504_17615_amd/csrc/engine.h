@@ -112,15 +112,21 @@ class Engine {
   lmgp_params p_;
   bool packed_ = false;  // all ratings < 2^32: packed hub tables
   bool narrow_ = false;  // all entry weights < 2^31: coarse weights stored as int32
+  // Whether the graphs whose coarsest level is level j are bisected on the
+  // device (which needs sorted rows) rather than on the host.
+  bool ip_on_device(const std::vector<Job>& jobs, size_t j) const;
   std::vector<std::unique_ptr<Level>> levels_;
 };
 
 // Recursive bipartitioning of a small host graph (coarsest level).
 // xadj holds n + 1 global entry offsets (first = e0), adj global neighbour
-// ids (minus n0 = local); `sorted`: every row is ascending.
+// ids (minus n0 = local); `sorted`: every row is stored ascending; `asc`: the
+// neighbours a row scan finds are enqueued in ascending order (as if sorted)
+// rather than in stored order.
 void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* adj,
-                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, uint32_t k,
-                            uint64_t seed, uint64_t level, std::vector<uint32_t>& block);
+                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, bool asc,
+                            uint32_t k, uint64_t seed, uint64_t level,
+                            std::vector<uint32_t>& block);
 
 lmgp_params default_params();
 void check_params(const lmgp_params& p);

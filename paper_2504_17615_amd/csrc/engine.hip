@@ -1275,10 +1275,34 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     }
     levels_.push_back(std::move(C));
   }
-  // the initial partitioning visits neighbours in ascending order: sort the
-  // coarsest level of every graph (coarse rows are built in hash order)
-  for (auto& jb : jobs) ensure_sorted(jb.nlevels - 1);
+  // The initial partitioning visits neighbours in ascending order; coarse
+  // rows are built in hash order.  The device search expands rows in stored
+  // order, so a coarsest level bisected there is sorted here.  The host search
+  // can order what each row scan finds itself; it does so on dense coarsest
+  // levels (average degree >= 64), whose sort would cost the device far more
+  // than the host's few short sorts, and gets sparse ones sorted.
+  for (size_t j = 1; j < levels_.size(); ++j) {
+    bool coarsest = false;
+    for (uint32_t g : levels_[j]->graphs) coarsest |= jobs[g].nlevels - 1 == j;
+    if (coarsest && (ip_on_device(jobs, j) || levels_[j]->nnz < 64 * levels_[j]->n))
+      ensure_sorted(j);
+  }
   t_coarsen_ns = tm.stop_ns();
+}
+
+bool Engine::ip_on_device(const std::vector<Job>& jobs, size_t j) const {
+  if (!p_.ip_device || j >= levels_.size()) return false;
+  const Level& L = *levels_[j];
+  uint64_t Ktot = 0;
+  for (const Job& jb : jobs) Ktot += jb.k;
+  uint32_t taking = 0;
+  for (uint32_t g : L.graphs) taking += jobs[g].nlevels - 1 == j;
+  // block ids, node ids and frontier ranks are 32-bit in the device search
+  if (!taking || L.nnz >= (1ull << 32) || L.n >= (1ull << 31) || Ktot >= IP_NONE) return false;
+  // automatic choice: the device search gives each subproblem one workgroup,
+  // which pays when many graphs are bisected side by side; a few large
+  // coarsest levels are faster on the host's cores
+  return p_.ip_device != LMGP_IP_AUTO || taking >= IP_DEVICE_MIN_GRAPHS;
 }
 
 // ------------------------------------------------------------ partitioning --
@@ -1319,14 +1343,8 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
           any = true;
         }
       }
-      // block ids, node ids and frontier ranks are 32-bit in the device search
-      if (!any || L.nnz >= (1ull << 32) || L.n >= (1ull << 31) || Ktot >= IP_NONE) continue;
-      // automatic choice: the device search gives each subproblem one
-      // workgroup, which pays when many graphs are bisected side by side; a
-      // few large coarsest levels are faster on the host's cores
-      uint32_t taking = 0;
-      for (uint32_t b = 0; b < B; ++b) taking += gbase[b] != IP_NONE;
-      if (p_.ip_device == LMGP_IP_AUTO && taking < IP_DEVICE_MIN_GRAPHS) continue;
+      if (!any || !ip_on_device(jobs, j)) continue;
+      ensure_sorted(j);  // (done by coarsen; the input level keeps its order)
       ipdev[j].reset(&pool_, s_, L.n ? L.n : 1);
       DBuf<uint32_t> dgb(&pool_, s_, B);
       h2d(dgb.get(), gbase.data(), B, s_);
@@ -1380,8 +1398,10 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     d2h(hb.adj.data(), L.adj + e0, e1 - e0, s_);
     d2h(hb.nw.data(), L.nw + n0, n1 - n0, s_);
     sync(s_);
+    // coarse levels: neighbours in ascending order (the oracle's coarse rows
+    // are sorted); the input level: in the caller's order
     initial_partition_host(n1 - n0, hb.xadj.data(), hb.adj.data(), hb.nw.data(), e0, n0, L.sorted,
-                           jobs[g].k, jobs[g].seed, top + 1, ip[g]);
+                           top > 0 || L.sorted, jobs[g].k, jobs[g].seed, top + 1, ip[g]);
     for (auto& x : ip[g]) x += (uint32_t)kbase[g];
   }
   t_initial_ns = tm.stop_ns();
@@ -1483,7 +1503,9 @@ struct IpState {
   const uint32_t* adj;   // neighbour ids, relative to n0
   const int64_t* nw;
   uint64_t e0, n0;
-  bool sorted;           // rows ascending: unvisited nodes may be walked in id order
+  bool sorted;           // rows stored in ascending order
+  bool asc;              // a row's neighbours are enqueued in ascending order (coarse
+                         // levels: the oracle's rows are sorted); else in stored order
   uint64_t seed, level;
   std::vector<uint32_t>* block;
   // stamps: sibling subproblems own disjoint node sets, so they may run on
@@ -1521,23 +1543,27 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   // Unvisited members of S that a row scan can still find: those with
   // neighbours (a node with an empty row is in no row of a symmetric graph).
   // Once none is left, a joined node's row is not scanned at all.  When S is
-  // not much smaller than the level and rows are sorted they are also kept
-  // as a bitset over node ids: walking it in ascending order and keeping the
-  // nodes y adjacent to v (binary search of the shorter of the two rows)
-  // enqueues exactly what a scan of v's row would, in the same order.  The
-  // walk is taken when it costs less than the scan: v's row is long and the
-  // nodes left are few or have short rows (dense coarse graphs, where some
-  // nodes of small degree stay unvisited for long).
+  // not much smaller than the level they are also kept as a bitset over node
+  // ids, which a row scan tests instead of the stamps.  With ascending enqueue
+  // order, walking the bitset in ascending order and keeping the nodes y
+  // adjacent to v enqueues exactly what a scan of v's row would; adjacency is
+  // a binary search of the shorter of the two rows when rows are stored
+  // sorted, else a scan of y's row.  The walk is taken when it costs less
+  // than the scan: v's row is long and the nodes left are few or have short
+  // rows (dense coarse graphs, where some nodes of small degree stay
+  // unvisited for long).
   auto deg_of = [&](uint32_t x) { return st.xadj[x + 1] - st.xadj[x]; };
   auto bitlen = [](uint64_t d) { return (uint64_t)(64 - __builtin_clzll(d | 1)); };
-  const bool use_bits = st.sorted && (uint64_t)S.size() * 64 >= st.n;
+  const bool use_bits = (uint64_t)S.size() * 64 >= st.n;
   const uint64_t nwords = use_bits ? (st.n + 63) / 64 : 0;
   std::vector<uint64_t> unv(nwords, 0);
-  uint64_t nunv = 0, sumlen = 0;  // nodes left, sum of their rows' bit lengths
+  // nodes left, sums of their rows' bit lengths and lengths
+  uint64_t nunv = 0, sumlen = 0, sumdeg = 0;
   for (uint32_t v : S)
     if (deg_of(v)) {
       ++nunv;
       sumlen += bitlen(deg_of(v));
+      sumdeg += deg_of(v);
       if (use_bits) unv[v >> 6] |= 1ull << (v & 63);
     }
   auto visit = [&](uint32_t x) {
@@ -1547,7 +1573,11 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
     if (use_bits) unv[x >> 6] &= ~(1ull << (x & 63));
     --nunv;
     sumlen -= bitlen(d);
+    sumdeg -= d;
   };
+  // a scan of an unsorted row enqueues what it finds in ascending order
+  const bool sort_found = st.asc && !st.sorted;
+  std::vector<uint32_t> found;
   std::vector<uint32_t> queue;
   queue.reserve(S.size());
   int64_t w1 = 0;
@@ -1593,7 +1623,9 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
       const uint32_t* rb = st.adj + (st.xadj[v] - st.e0);
       const uint32_t* re = st.adj + (st.xadj[v + 1] - st.e0);
       const uint64_t deg = (uint64_t)(re - rb);
-      if (use_bits && nwords + 2 * std::min(sumlen, nunv * bitlen(deg)) < deg) {
+      const uint64_t walk_cost =
+          st.sorted ? 2 * std::min(sumlen, nunv * bitlen(deg)) : 2 * sumdeg;
+      if (use_bits && st.asc && nwords + walk_cost < deg) {
         const uint32_t vg = (uint32_t)(v + st.n0);
         for (uint64_t w = 0; w < nwords; ++w) {
           uint64_t bits = unv[w];
@@ -1602,21 +1634,37 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
             bits &= bits - 1;
             const uint64_t dx = deg_of(x);
             const uint32_t* xb = st.adj + (st.xadj[x] - st.e0);
-            const bool found = dx < deg ? std::binary_search(xb, xb + dx, vg)
-                                        : std::binary_search(rb, re, (uint32_t)(x + st.n0));
-            if (found) {
+            bool adj;
+            if (!st.sorted) adj = std::find(xb, xb + dx, vg) != xb + dx;
+            else if (dx < deg) adj = std::binary_search(xb, xb + dx, vg);
+            else adj = std::binary_search(rb, re, (uint32_t)(x + st.n0));
+            if (adj) {
               visit(x);
               queue.push_back(x);
             }
           }
         }
       } else {
-        for (const uint32_t* p = rb; p < re; ++p) {
-          const uint32_t x = *p - (uint32_t)st.n0;
-          if (st.inset[x].load(rl) == my && st.visited[x].load(rl) != my) {
-            visit(x);
-            queue.push_back(x);
+        found.clear();
+        auto take = [&](uint32_t x) {
+          visit(x);
+          if (sort_found) found.push_back(x);
+          else queue.push_back(x);
+        };
+        if (use_bits) {
+          for (const uint32_t* p = rb; p < re; ++p) {
+            const uint32_t x = *p - (uint32_t)st.n0;
+            if ((unv[x >> 6] >> (x & 63)) & 1) take(x);
           }
+        } else {
+          for (const uint32_t* p = rb; p < re; ++p) {
+            const uint32_t x = *p - (uint32_t)st.n0;
+            if (st.inset[x].load(rl) == my && st.visited[x].load(rl) != my) take(x);
+          }
+        }
+        if (sort_found) {
+          if (found.size() > 1) std::sort(found.begin(), found.end());
+          queue.insert(queue.end(), found.begin(), found.end());
         }
       }
     }
@@ -1638,7 +1686,8 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
 }  // namespace
 
 void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* adj,
-                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, uint32_t k,
+                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, bool asc,
+                            uint32_t k,
                             uint64_t seed, uint64_t level, std::vector<uint32_t>& block) {
   IpState st;
   st.n = n;
@@ -1648,6 +1697,7 @@ void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* ad
   st.e0 = e0;
   st.n0 = n0;
   st.sorted = sorted;
+  st.asc = asc;
   st.seed = seed;
   st.level = level;
   block.assign(n, 0);
