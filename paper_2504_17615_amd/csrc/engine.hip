@@ -1578,6 +1578,13 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
   // a scan of an unsorted row enqueues what it finds in ascending order
   const bool sort_found = st.asc && !st.sorted;
   std::vector<uint32_t> found;
+  // Once the rows of the nodes left hold no more entries than the row about
+  // to be scanned, they are indexed by neighbour: (x, y) for every entry x of
+  // the row of a left node y, sorted.  A joined node v then enqueues the
+  // unvisited y of its pairs, in ascending order: exactly the left nodes in
+  // v's row, as a scan would find them.  No row is scanned after that.
+  std::vector<std::pair<uint32_t, uint32_t>> watch;
+  bool watching = false;
   std::vector<uint32_t> queue;
   queue.reserve(S.size());
   int64_t w1 = 0;
@@ -1623,6 +1630,30 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
       const uint32_t* rb = st.adj + (st.xadj[v] - st.e0);
       const uint32_t* re = st.adj + (st.xadj[v + 1] - st.e0);
       const uint64_t deg = (uint64_t)(re - rb);
+      if (!watching && use_bits && st.asc && sumdeg <= deg) {
+        watch.clear();
+        watch.reserve(sumdeg);
+        for (uint64_t w = 0; w < nwords; ++w)
+          for (uint64_t bits = unv[w]; bits; bits &= bits - 1) {
+            const uint32_t y = (uint32_t)(w * 64 + __builtin_ctzll(bits));
+            const uint32_t* yb = st.adj + (st.xadj[y] - st.e0);
+            const uint32_t* ye = st.adj + (st.xadj[y + 1] - st.e0);
+            for (const uint32_t* p = yb; p < ye; ++p) watch.emplace_back(*p - (uint32_t)st.n0, y);
+          }
+        std::sort(watch.begin(), watch.end());
+        watching = true;
+      }
+      if (watching) {
+        auto it = std::lower_bound(watch.begin(), watch.end(), std::make_pair(v, 0u));
+        for (; it != watch.end() && it->first == v; ++it) {
+          const uint32_t y = it->second;
+          if ((unv[y >> 6] >> (y & 63)) & 1) {
+            visit(y);
+            queue.push_back(y);
+          }
+        }
+        continue;
+      }
       const uint64_t walk_cost =
           st.sorted ? 2 * std::min(sumlen, nunv * bitlen(deg)) : 2 * sumdeg;
       if (use_bits && st.asc && nwords + walk_cost < deg) {
