@@ -1307,15 +1307,45 @@ bool Engine::ip_on_device(const std::vector<Job>& jobs, size_t j) const {
 
 // ------------------------------------------------------------ partitioning --
 namespace {
+// Page-locked host copies of a coarsest level for the host bisection: the
+// device writes them directly (a pageable destination is staged through a
+// bounce buffer and copied again by the CPU).  Buffer sets are pooled across
+// calls and threads, grown on demand and kept until the process ends.
 struct IpHostBuffers {
-  std::vector<uint64_t> xadj;
-  std::vector<uint32_t> adj;
-  std::vector<int64_t> nw;
+  uint64_t* xadj = nullptr;
+  uint32_t* adj = nullptr;
+  int64_t* nw = nullptr;
+  size_t cx = 0, ca = 0, cn = 0;
 };
-IpHostBuffers& ip_host_buffers() {
-  thread_local IpHostBuffers b;
-  return b;
+template <typename T>
+T* pinned_grow(T*& p, size_t& cap, size_t n) {
+  if (n > cap) {
+    if (p) HIP_CHECK(hipHostFree(p));
+    p = nullptr;
+    cap = 0;
+    HIP_CHECK(hipHostMalloc((void**)&p, (n ? n : 1) * sizeof(T), hipHostMallocDefault));
+    cap = n;
+  }
+  return p;
 }
+std::mutex ip_pool_mu;
+std::vector<IpHostBuffers*> ip_pool;
+struct IpBuffersLease {
+  IpHostBuffers* b;
+  IpBuffersLease() {
+    std::lock_guard<std::mutex> g(ip_pool_mu);
+    if (ip_pool.empty()) {
+      b = new IpHostBuffers;
+    } else {
+      b = ip_pool.back();
+      ip_pool.pop_back();
+    }
+  }
+  ~IpBuffersLease() {
+    std::lock_guard<std::mutex> g(ip_pool_mu);
+    ip_pool.push_back(b);
+  }
+};
 }  // namespace
 
 void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device) {
@@ -1390,18 +1420,19 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     const uint64_t n0 = L.nbase[b], n1 = L.nbase[b + 1], e0 = L.ebase[b], e1 = L.ebase[b + 1];
     // host copies in buffers kept by the calling thread (no page faults after
     // the first call); ids and offsets stay global, the bisection subtracts
-    IpHostBuffers& hb = ip_host_buffers();
-    if (hb.xadj.size() < n1 - n0 + 1) hb.xadj.resize(n1 - n0 + 1);
-    if (hb.adj.size() < e1 - e0) hb.adj.resize(e1 - e0);
-    if (hb.nw.size() < n1 - n0) hb.nw.resize(n1 - n0);
-    d2h(hb.xadj.data(), L.xadj + n0, n1 - n0 + 1, s_);
-    d2h(hb.adj.data(), L.adj + e0, e1 - e0, s_);
-    d2h(hb.nw.data(), L.nw + n0, n1 - n0, s_);
+    IpBuffersLease lease;
+    IpHostBuffers& hb = *lease.b;
+    uint64_t* hx = pinned_grow(hb.xadj, hb.cx, n1 - n0 + 1);
+    uint32_t* ha = pinned_grow(hb.adj, hb.ca, e1 - e0);
+    int64_t* hn = pinned_grow(hb.nw, hb.cn, n1 - n0);
+    d2h(hx, L.xadj + n0, n1 - n0 + 1, s_);
+    d2h(ha, L.adj + e0, e1 - e0, s_);
+    d2h(hn, L.nw + n0, n1 - n0, s_);
     sync(s_);
     // coarse levels: neighbours in ascending order (the oracle's coarse rows
     // are sorted); the input level: in the caller's order
-    initial_partition_host(n1 - n0, hb.xadj.data(), hb.adj.data(), hb.nw.data(), e0, n0, L.sorted,
-                           top > 0 || L.sorted, jobs[g].k, jobs[g].seed, top + 1, ip[g]);
+    initial_partition_host(n1 - n0, hx, ha, hn, e0, n0, L.sorted, top > 0 || L.sorted,
+                           jobs[g].k, jobs[g].seed, top + 1, ip[g]);
     for (auto& x : ip[g]) x += (uint32_t)kbase[g];
   }
   t_initial_ns = tm.stop_ns();
