@@ -123,10 +123,11 @@ class Engine {
 // ids (minus n0 = local); `sorted`: every row is stored ascending; `asc`: the
 // neighbours a row scan finds are enqueued in ascending order (as if sorted)
 // rather than in stored order.
-void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* adj,
-                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, bool asc,
-                            uint32_t k, uint64_t seed, uint64_t level,
-                            std::vector<uint32_t>& block);
+// A: uint32_t, or uint16_t for graphs of at most 2^16 nodes.
+template <typename A>
+void initial_partition_host(uint64_t n, const uint64_t* xadj, const A* adj, const int64_t* nw,
+                            uint64_t e0, uint64_t n0, bool sorted, bool asc, uint32_t k,
+                            uint64_t seed, uint64_t level, std::vector<uint32_t>& block);
 
 lmgp_params default_params();
 void check_params(const lmgp_params& p);

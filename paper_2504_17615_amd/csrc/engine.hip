@@ -1314,9 +1314,17 @@ namespace {
 struct IpHostBuffers {
   uint64_t* xadj = nullptr;
   uint32_t* adj = nullptr;
+  uint16_t* adj16 = nullptr;
   int64_t* nw = nullptr;
-  size_t cx = 0, ca = 0, cn = 0;
+  size_t cx = 0, ca = 0, ca16 = 0, cn = 0;
 };
+
+// Neighbour ids of a graph's entries as 16-bit local ids (graphs of at most
+// 2^16 nodes): half the bytes to copy to the host.
+__global__ void k_local_u16(const uint32_t* adj, uint64_t m, uint32_t n0, uint16_t* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = (uint16_t)(adj[i] - n0);
+}
 template <typename T>
 T* pinned_grow(T*& p, size_t& cap, size_t n) {
   if (n > cap) {
@@ -1423,16 +1431,31 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     IpBuffersLease lease;
     IpHostBuffers& hb = *lease.b;
     uint64_t* hx = pinned_grow(hb.xadj, hb.cx, n1 - n0 + 1);
-    uint32_t* ha = pinned_grow(hb.adj, hb.ca, e1 - e0);
     int64_t* hn = pinned_grow(hb.nw, hb.cn, n1 - n0);
     d2h(hx, L.xadj + n0, n1 - n0 + 1, s_);
-    d2h(ha, L.adj + e0, e1 - e0, s_);
     d2h(hn, L.nw + n0, n1 - n0, s_);
-    sync(s_);
     // coarse levels: neighbours in ascending order (the oracle's coarse rows
     // are sorted); the input level: in the caller's order
-    initial_partition_host(n1 - n0, hx, ha, hn, e0, n0, L.sorted, top > 0 || L.sorted,
-                           jobs[g].k, jobs[g].seed, top + 1, ip[g]);
+    const bool asc = top > 0 || L.sorted;
+    if (n1 - n0 <= (1u << 16)) {
+      DBuf<uint16_t> a16(&pool_, s_, e1 > e0 ? e1 - e0 : 1);
+      if (e1 > e0) {
+        k_local_u16<<<grid_for(e1 - e0, 256), 256, 0, s_>>>(L.adj + e0, e1 - e0, (uint32_t)n0,
+                                                            a16.get());
+        LAUNCH_CHECK();
+      }
+      uint16_t* ha = pinned_grow(hb.adj16, hb.ca16, e1 - e0);
+      d2h(ha, a16.get(), e1 - e0, s_);
+      sync(s_);
+      initial_partition_host<uint16_t>(n1 - n0, hx, ha, hn, e0, 0, L.sorted, asc, jobs[g].k,
+                                       jobs[g].seed, top + 1, ip[g]);
+    } else {
+      uint32_t* ha = pinned_grow(hb.adj, hb.ca, e1 - e0);
+      d2h(ha, L.adj + e0, e1 - e0, s_);
+      sync(s_);
+      initial_partition_host<uint32_t>(n1 - n0, hx, ha, hn, e0, n0, L.sorted, asc, jobs[g].k,
+                                       jobs[g].seed, top + 1, ip[g]);
+    }
     for (auto& x : ip[g]) x += (uint32_t)kbase[g];
   }
   t_initial_ns = tm.stop_ns();
@@ -1528,10 +1551,11 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
 // exhausted.
 namespace {
 
+template <typename A>
 struct IpState {
   uint64_t n;
   const uint64_t* xadj;  // entry offsets, relative to e0
-  const uint32_t* adj;   // neighbour ids, relative to n0
+  const A* adj;          // neighbour ids, relative to n0
   const int64_t* nw;
   uint64_t e0, n0;
   bool sorted;           // rows stored in ascending order
@@ -1549,7 +1573,8 @@ struct IpState {
 
 constexpr int IP_PAR_DEPTH = 4;  // up to 16 concurrent subproblems
 
-void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t off, int depth) {
+template <typename A>
+void grow_bisect(IpState<A>& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t off, int depth) {
   if (S.empty()) return;
   if (kS == 1) {
     for (uint32_t v : S) (*st.block)[v] = off;
@@ -1658,8 +1683,8 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
         break;
       }
       if (nunv == 0) continue;  // nothing left to enqueue
-      const uint32_t* rb = st.adj + (st.xadj[v] - st.e0);
-      const uint32_t* re = st.adj + (st.xadj[v + 1] - st.e0);
+      const A* rb = st.adj + (st.xadj[v] - st.e0);
+      const A* re = st.adj + (st.xadj[v + 1] - st.e0);
       const uint64_t deg = (uint64_t)(re - rb);
       if (!watching && use_bits && st.asc && sumdeg <= deg) {
         watch.clear();
@@ -1667,9 +1692,9 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
         for (uint64_t w = 0; w < nwords; ++w)
           for (uint64_t bits = unv[w]; bits; bits &= bits - 1) {
             const uint32_t y = (uint32_t)(w * 64 + __builtin_ctzll(bits));
-            const uint32_t* yb = st.adj + (st.xadj[y] - st.e0);
-            const uint32_t* ye = st.adj + (st.xadj[y + 1] - st.e0);
-            for (const uint32_t* p = yb; p < ye; ++p) watch.emplace_back(*p - (uint32_t)st.n0, y);
+            const A* yb = st.adj + (st.xadj[y] - st.e0);
+            const A* ye = st.adj + (st.xadj[y + 1] - st.e0);
+            for (const A* p = yb; p < ye; ++p) watch.emplace_back((uint32_t)*p - (uint32_t)st.n0, y);
           }
         std::sort(watch.begin(), watch.end());
         watching = true;
@@ -1695,7 +1720,7 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
             const uint32_t x = (uint32_t)(w * 64 + __builtin_ctzll(bits));
             bits &= bits - 1;
             const uint64_t dx = deg_of(x);
-            const uint32_t* xb = st.adj + (st.xadj[x] - st.e0);
+            const A* xb = st.adj + (st.xadj[x] - st.e0);
             bool adj;
             if (!st.sorted) adj = std::find(xb, xb + dx, vg) != xb + dx;
             else if (dx < deg) adj = std::binary_search(xb, xb + dx, vg);
@@ -1714,13 +1739,13 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
           else queue.push_back(x);
         };
         if (use_bits) {
-          for (const uint32_t* p = rb; p < re; ++p) {
-            const uint32_t x = *p - (uint32_t)st.n0;
+          for (const A* p = rb; p < re; ++p) {
+            const uint32_t x = (uint32_t)*p - (uint32_t)st.n0;
             if ((unv[x >> 6] >> (x & 63)) & 1) take(x);
           }
         } else {
-          for (const uint32_t* p = rb; p < re; ++p) {
-            const uint32_t x = *p - (uint32_t)st.n0;
+          for (const A* p = rb; p < re; ++p) {
+            const uint32_t x = (uint32_t)*p - (uint32_t)st.n0;
             if (st.inset[x].load(rl) == my && st.visited[x].load(rl) != my) take(x);
           }
         }
@@ -1747,11 +1772,11 @@ void grow_bisect(IpState& st, std::vector<uint32_t>& S, uint32_t kS, uint32_t of
 
 }  // namespace
 
-void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* adj,
-                            const int64_t* nw, uint64_t e0, uint64_t n0, bool sorted, bool asc,
-                            uint32_t k,
+template <typename A>
+void initial_partition_host(uint64_t n, const uint64_t* xadj, const A* adj, const int64_t* nw,
+                            uint64_t e0, uint64_t n0, bool sorted, bool asc, uint32_t k,
                             uint64_t seed, uint64_t level, std::vector<uint32_t>& block) {
-  IpState st;
+  IpState<A> st;
   st.n = n;
   st.xadj = xadj;
   st.adj = adj;
@@ -1775,5 +1800,14 @@ void initial_partition_host(uint64_t n, const uint64_t* xadj, const uint32_t* ad
   for (uint64_t v = 0; v < n; ++v) S[v] = (uint32_t)v;
   grow_bisect(st, S, k, 0, 0);
 }
+
+template void initial_partition_host<uint32_t>(uint64_t, const uint64_t*, const uint32_t*,
+                                               const int64_t*, uint64_t, uint64_t, bool, bool,
+                                               uint32_t, uint64_t, uint64_t,
+                                               std::vector<uint32_t>&);
+template void initial_partition_host<uint16_t>(uint64_t, const uint64_t*, const uint16_t*,
+                                               const int64_t*, uint64_t, uint64_t, bool, bool,
+                                               uint32_t, uint64_t, uint64_t,
+                                               std::vector<uint32_t>&);
 
 }  // namespace lmgp
