@@ -344,12 +344,17 @@ __global__ __launch_bounds__(256) void k_rows_block(ContractArgs a, const uint32
     const uint64_t ex = block_exclusive_scan(d, sm, tot);
     mex[threadIdx.x] = (mi < m1) ? ex : ~0ull;
     mbeg[threadIdx.x] = beg;
+    // members in this chunk: the owner search needs only log2 of that many
+    // steps (mex is ~0 past them)
+    const uint64_t nmem = m1 - mb < (uint64_t)blockDim.x ? m1 - mb : (uint64_t)blockDim.x;
+    int top = 0;
+    for (int q = 1; (uint64_t)q < nmem; q <<= 1) top = q;
     __syncthreads();
     const uint64_t pos = s_pos;
     for (uint64_t t = threadIdx.x; t < tot; t += 256) {
       int lo = 0;
-      for (int step = 128; step > 0; step >>= 1)
-        if (lo + step < 256 && mex[lo + step] <= t) lo += step;
+      for (int step = top; step > 0; step >>= 1)
+        if (mex[lo + step] <= t) lo += step;
       uint32_t k;
       int64_t w;
       load_entry<EWK>(a, mbeg[lo] + (t - mex[lo]), x, k, w);
@@ -434,11 +439,16 @@ __global__ __launch_bounds__(1024) void k_rows_big(ContractArgs a, const uint32_
     const uint64_t ex = block_exclusive_scan<uint64_t, NW>(d, sm, tot);
     mex[threadIdx.x] = (mi < m1) ? ex : ~0ull;
     mbeg[threadIdx.x] = beg;
+    // members in this chunk: the owner search needs only log2 of that many
+    // steps (mex is ~0 past them)
+    const uint64_t nmem = m1 - mb < (uint64_t)blockDim.x ? m1 - mb : (uint64_t)blockDim.x;
+    int top = 0;
+    for (int q = 1; (uint64_t)q < nmem; q <<= 1) top = q;
     __syncthreads();
     const uint64_t pos = s_pos;
     for (uint64_t t = threadIdx.x; t < tot; t += NT) {
       int lo = 0;
-      for (int step = NT / 2; step > 0; step >>= 1)
+      for (int step = top; step > 0; step >>= 1)
         if (mex[lo + step] <= t) lo += step;
       uint32_t k;
       int64_t w;
@@ -559,6 +569,11 @@ __global__ __launch_bounds__(NT) void k_rows_hash(ContractArgs a, const uint32_t
     const uint64_t ex = block_exclusive_scan<uint64_t, NW>(d, sm, tot);
     mex[threadIdx.x] = (mi < m1) ? ex : ~0ull;
     mbeg[threadIdx.x] = beg;
+    // members in this chunk: the owner search needs only log2 of that many
+    // steps (mex is ~0 past them)
+    const uint64_t nmem = m1 - mb < (uint64_t)blockDim.x ? m1 - mb : (uint64_t)blockDim.x;
+    int top = 0;
+    for (int q = 1; (uint64_t)q < nmem; q <<= 1) top = q;
     __syncthreads();
     constexpr int U = 4;
     for (uint64_t t0 = threadIdx.x; t0 < tot; t0 += (uint64_t)U * NT) {
@@ -571,7 +586,7 @@ __global__ __launch_bounds__(NT) void k_rows_hash(ContractArgs a, const uint32_t
         w[j] = 0;
         if (t < tot) {
           int lo = 0;
-          for (int step = NT / 2; step > 0; step >>= 1)
+          for (int step = top; step > 0; step >>= 1)
             if (mex[lo + step] <= t) lo += step;
           load_entry<EWK>(a, mbeg[lo] + (t - mex[lo]), x, k[j], w[j]);
         }
@@ -647,12 +662,17 @@ __global__ __launch_bounds__(256) void k_rows_gather(ContractArgs a, const uint3
     const uint64_t ex = block_exclusive_scan(d, sm, tot);
     mex[threadIdx.x] = (mi < m1) ? ex : ~0ull;
     mbeg[threadIdx.x] = beg;
+    // members in this chunk: the owner search needs only log2 of that many
+    // steps (mex is ~0 past them)
+    const uint64_t nmem = m1 - mb < (uint64_t)blockDim.x ? m1 - mb : (uint64_t)blockDim.x;
+    int top = 0;
+    for (int q = 1; (uint64_t)q < nmem; q <<= 1) top = q;
     __syncthreads();
     const uint64_t pos = s_pos;
     for (uint64_t t = threadIdx.x; t < tot; t += 256) {
       int lo = 0;
-      for (int step = 128; step > 0; step >>= 1)
-        if (lo + step < 256 && mex[lo + step] <= t) lo += step;
+      for (int step = top; step > 0; step >>= 1)
+        if (mex[lo + step] <= t) lo += step;
       uint32_t k;
       int64_t w;
       load_entry<EWK>(a, mbeg[lo] + (t - mex[lo]), x, k, w);
