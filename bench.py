@@ -462,8 +462,8 @@ def main():
                     help="initial partitioning: 0 host, 1 device, 2 automatic (default)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     if args.mode != "single":
