@@ -95,6 +95,33 @@ def test_server_results_equal_solo(lib, solo, budget_mib, slots, batch, streams)
     srv.close()
 
 
+def test_server_run_cap_equals_solo(lib, solo):
+    # a request above 2^21 directed entries runs alone; the small ones around
+    # it are batched together: every result is still the solo one
+    g = gg.rmat(17)
+    assert g.nnz > (1 << 21)
+    big = lib.create_graph(g)
+    bb, br = big.partition(16, 0.03, 11, host_out=True)
+    ob, ores, _ = O.partition(g, 16, 0.03, 11)
+    assert np.array_equal(bb, ob) and br["cut"] == ores["cut"]
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=16, max_batch=8, streams=2)
+    print("server with a request above the run cap", flush=True)
+    tickets = []
+    for rep in range(2):
+        for i in (0, 1, 2):
+            tickets.append((i, srv.submit(*solo[i][:4])))
+        tickets.append((-1, srv.submit(big, 16, 0.03, 11)))
+        for i in (4, 5, 6):
+            tickets.append((i, srv.submit(*solo[i][:4])))
+    for i, t in tickets:
+        out, res = srv.wait(t)
+        want, wres = (bb, br) if i < 0 else (solo[i][4], solo[i][5])
+        assert np.array_equal(out, want), i
+        assert _same(res, wres), (i, res, wres)
+    srv.close()
+    big.close()
+
+
 def test_server_rejects_request_beyond_budget(lib, solo):
     srv = lib.Server(hbm_budget_bytes=1 << 20, max_slots=2, max_batch=2, streams=1)
     dg = solo[7][0]  # rmat14: footprint estimate well above 1 MiB
