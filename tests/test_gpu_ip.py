@@ -148,3 +148,11 @@ def test_automatic_choice_in_a_large_batch(lib):
         assert np.array_equal(outs[i].cpu().numpy().view(np.uint32), ob), i
     for d in dgs:
         d.close()
+
+
+def test_host_ip_wide_ids(lib):
+    # more than 2^16 nodes at the bisected level: the host copy keeps 32-bit
+    # neighbour ids (smaller levels travel as 16-bit local ids)
+    g = gg.rmat(17)
+    assert g.n > (1 << 16)
+    check(lib, g, 1000, 0.03, 5, 0)  # k = 1000: 160 k >= n, no coarsening
