@@ -646,6 +646,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     LAUNCH_CHECK();
     launch_bucket_count(ba, s_);
     launch_bucket_offsets(ba, s_);
+    // the lists too, before the host waits: the scatter needs only the
+    // device's offsets, and the first rating launch then follows the wait
+    launch_bucket_scatter(ba, s_);
     d2h(hstate, rstate.get(), nstate, s_);
     sync(s_);
     for (uint32_t i = 0; i < NB; ++i) {
@@ -705,7 +708,6 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
           ba.cuts = presets[p].cuts;
           begin_round(0);
           bucket_offsets();
-          launch_bucket_scatter(ba, s_);
           RateArgs ra = rating_args(0);
           ra.trial = 1;
           float ms = 0.f;
@@ -853,7 +855,6 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
         for (uint32_t b = 0; b < B; ++b) any |= hstate[2 * NB + b] != 0;
         if (!any) break;
         bucket_offsets();
-        launch_bucket_scatter(ba, s_);
         for (uint32_t sr = 0; sr < S; ++sr) {
           uint32_t total = 0;
           for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
@@ -950,6 +951,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   bcount.zero();
   launch_bucket_count(ba, s_);
   launch_bucket_offsets(ba, s_);
+  launch_bucket_scatter(ba, s_);  // before the wait, as in run_lp
   std::vector<unsigned long long> hcnt(2 * NCLASS);
   std::vector<uint32_t> cnt(NCLASS), offs(NCLASS);
   d2h(hcnt.data(), bcount.get(), 2 * NCLASS, s_);
@@ -960,7 +962,6 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
     offs[c] = run;
     run += cnt[c];
   }
-  launch_bucket_scatter(ba, s_);
   RateArgs ra{};
   ra.xadj = L.xadj;
   ra.adj = L.adj;
