@@ -451,7 +451,7 @@ def main():
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--max-batch", type=int, default=8)
-    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--hbm-budget-gib", type=int, default=64)
     ap.add_argument("--tune", default="off",
                     help="rating class tables: off (default table), auto (autotuned, "

@@ -395,7 +395,7 @@ class Server:
     """Serving loop: submit partition requests, poll or wait for results."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, max_batch: int = 32,
-                 streams: int = 2, ip_device: int = 2):
+                 streams: int = 4, ip_device: int = 2):
         cfg = ServerConfig(hbm_budget_bytes, max_slots, max_batch, streams, ip_device)
         h = ctypes.c_void_p()
         _check(library().lmgp_server_create(ctypes.byref(cfg), None, ctypes.byref(h)))
