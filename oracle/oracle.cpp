@@ -25,7 +25,7 @@
 //     block weight limit L_max (Sec. 2 and Sec. 3).
 //
 // Where the paper leaves a choice open the oracle takes one fixed reading
-// (visit order, tie-breaking, admission under concurrent moves, pairing in
+// (visit order, tie-breaking, admission under concurrent moves, packing in
 // 2-hop clustering, rounding, exact-size sampling, the bipartitioner).  Each
 // reading is stated at the point where it is used.
 //
@@ -302,16 +302,19 @@ uint64_t count_clusters(const std::vector<uint32_t>& label, uint64_t n) {
 // the weight limit allows.  Isolated nodes are clustered with each other
 // (paragraph after Theorem 1's proof).
 //
-// Readings: only light singletons take part (2 c(v) <= U, the clusters the
-// proof of Theorem 1 calls C_1), so that every pair fits the weight limit and
-// at most one light singleton per favourite stays unmerged.  Favourite =
-// adjacent cluster with the largest rating, ties by smaller
-// H(FAV, level, v, K) then smaller K; isolated singletons share the favourite
-// ISO (after all labels).  Light singletons are ordered by
-// (fav, hi32(H(TWOHOP, level, v)), v); inside each favourite segment the
-// positions (2j, 2j+1) form a pair (label(b) := label(a)).  Pairs are taken in
-// that global order and at most |C| - ceil(shrink_den * n / shrink_num) are
-// merged (the 2.5x cap, Sec. 4.3).  Returns the number of merges.
+// Readings: every singleton lighter than U takes part (a node of weight >= U
+// fits with no other node).  Favourite = adjacent cluster with the largest
+// rating, ties by smaller H(FAV, level, v, K) then smaller K; isolated
+// singletons share the favourite ISO (after all labels).  Singletons are
+// ordered by (fav, c(v), hi32(H(TWOHOP, level, v)), v) and each favourite
+// segment is packed next-fit in that order: a node joins the group opened
+// last if the group's weight plus c(v) stays <= U, otherwise it opens a new
+// group (label of a joiner := label of its group's first node).  Ascending
+// weight keeps Theorem 1's premise: a light singleton (c <= U/2) is left
+// alone only when every later node of its segment is heavier than U/2, so at
+// most one light singleton per favourite stays unmerged.  Joins are taken in
+// that global order and at most |C| - ceil(shrink_den * n / shrink_num) of
+// them are applied (the 2.5x cap, Sec. 4.3).  Returns the number of joins.
 uint64_t two_hop(const Graph& g, std::vector<uint32_t>& label, uint64_t nclusters, int64_t U,
                  uint64_t seed, uint64_t level, uint32_t shrink_num, uint32_t shrink_den) {
   const uint64_t n = g.n;
@@ -319,6 +322,7 @@ uint64_t two_hop(const Graph& g, std::vector<uint32_t>& label, uint64_t ncluster
   for (uint64_t u = 0; u < n; ++u) size[label[u]]++;
   struct S {
     uint32_t fav;
+    int64_t c;
     uint32_t h;
     uint32_t v;
   };
@@ -327,7 +331,7 @@ uint64_t two_hop(const Graph& g, std::vector<uint32_t>& label, uint64_t ncluster
   std::vector<uint32_t> touched;
   for (uint64_t v = 0; v < n; ++v) {
     if (size[label[v]] != 1) continue;
-    if (2 * g.nw[v] > U) continue;  // heavy singleton: not paired
+    if (g.nw[v] >= U) continue;  // fits with no other node
     uint32_t fav = ISO;
     if (g.deg(v) > 0) {
       touched.clear();
@@ -356,10 +360,11 @@ uint64_t two_hop(const Graph& g, std::vector<uint32_t>& label, uint64_t ncluster
       for (uint32_t K : touched) rating[K] = 0;
     }
     uint32_t h = (uint32_t)(H(seed, TAG_TWOHOP, {level, v}) >> 32);
-    singles.push_back({fav, h, (uint32_t)v});
+    singles.push_back({fav, g.nw[v], h, (uint32_t)v});
   }
   std::sort(singles.begin(), singles.end(), [](const S& a, const S& b) {
     if (a.fav != b.fav) return a.fav < b.fav;
+    if (a.c != b.c) return a.c < b.c;
     if (a.h != b.h) return a.h < b.h;
     return a.v < b.v;
   });
@@ -367,14 +372,20 @@ uint64_t two_hop(const Graph& g, std::vector<uint32_t>& label, uint64_t ncluster
   uint64_t floor_clusters = (uint64_t)(((u128)shrink_den * n + shrink_num - 1) / shrink_num);
   uint64_t P = nclusters > floor_clusters ? nclusters - floor_clusters : 0;
   uint64_t merged = 0;
-  for (size_t i = 0; i < singles.size();) {
+  for (size_t i = 0; i < singles.size() && merged < P;) {
     size_t j = i;
     while (j < singles.size() && singles[j].fav == singles[i].fav) ++j;
-    for (size_t p = i; p + 1 < j; p += 2) {
-      uint32_t a = singles[p].v, b = singles[p + 1].v;
-      if (merged >= P) break;
-      label[b] = label[a];
-      ++merged;
+    uint32_t leader = singles[i].v;
+    int64_t group_w = singles[i].c;
+    for (size_t p = i + 1; p < j && merged < P; ++p) {
+      if (group_w + singles[p].c <= U) {  // joins the open group
+        label[singles[p].v] = label[leader];
+        group_w += singles[p].c;
+        ++merged;
+      } else {  // opens a new group
+        leader = singles[p].v;
+        group_w = singles[p].c;
+      }
     }
     i = j;
   }

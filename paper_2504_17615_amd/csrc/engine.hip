@@ -211,7 +211,8 @@ hipStream_t capture_stream() {
 }
 
 
-// 2-hop: light singletons (and their sort keys).
+// 2-hop: singletons lighter than their graph's cap (a node of weight >= cap
+// fits with no other node), their sort keys and next-fit groups.
 struct SingletonFlag {
   const uint32_t* label;
   const uint32_t* csize;
@@ -220,62 +221,144 @@ struct SingletonFlag {
   const GraphDesc* gd;
   LMGP_D uint64_t operator()(uint64_t v) const {
     const GraphDesc& d = gd[graph_of(gid, v)];
-    return d.active && csize[label[v]] == 1 && 2 * nw[v] <= d.cap;
+    return d.active && csize[label[v]] == 1 && nw[v] < d.cap;
   }
 };
 
+// Segment key of a singleton: 2 * favourite, or for an isolated node
+// 2 * (last node of its graph) + 1, which orders ISO after every label of the
+// graph and before the next graph's labels.
+LMGP_D uint64_t favkey_of(const SingletonFlag& f, const uint64_t* xadj, const uint32_t* fav,
+                          uint64_t v) {
+  const GraphDesc& d = f.gd[graph_of(f.gid, v)];
+  const uint32_t fv = xadj[v + 1] > xadj[v] ? fav[v] : EMPTY_KEY;
+  return fv != EMPTY_KEY ? 2ull * fv : 2ull * (d.node_base + d.nodes - 1) + 1;
+}
+
+// key = favkey << fshift | c(v) << 32 | hi32 H(TWOHOP, level, v); fshift = 0
+// leaves the favourite for a second (stable) sort.  vals in ascending v order,
+// so equal keys stay ordered by id.
 __global__ void k_twohop_keys(SingletonFlag f, const uint64_t* xadj, const uint32_t* fav,
-                              const uint32_t* pos, uint64_t n, uint64_t* keys, uint32_t* vals) {
+                              const uint32_t* pos, uint64_t n, int fshift, uint64_t* keys,
+                              uint32_t* vals) {
   const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || !f(v)) return;
   const GraphDesc& d = f.gd[graph_of(f.gid, v)];
-  const uint64_t deg = xadj[v + 1] - xadj[v];
-  const uint32_t fv = deg ? fav[v] : EMPTY_KEY;
-  const uint64_t favkey = fv != EMPTY_KEY ? 2ull * fv : 2ull * (d.node_base + d.nodes - 1) + 1;
   const uint64_t h = hash_add(d.pre_two, v - d.node_base) >> 32;
-  keys[pos[v]] = (favkey << 32) | h;
+  uint64_t key = ((uint64_t)f.nw[v] << 32) | h;
+  if (fshift) key |= favkey_of(f, xadj, fav, v) << fshift;
+  keys[pos[v]] = key;
   vals[pos[v]] = (uint32_t)v;
 }
 
-__global__ void k_seg_first(const uint64_t* keys, uint64_t ns, uint32_t* first) {
+__global__ void k_twohop_favkeys(SingletonFlag f, const uint64_t* xadj, const uint32_t* fav,
+                                 const uint32_t* vals, uint64_t ns, uint64_t* keys) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < ns) keys[p] = favkey_of(f, xadj, fav, vals[p]);
+}
+
+// One past the last position of every favourite segment, by segment key.
+__global__ void k_seg_last(const uint64_t* keys, int sshift, uint64_t ns, uint32_t* last) {
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ns) return;
-  const uint64_t fk = keys[p] >> 32;
-  if (p == 0 || (keys[p - 1] >> 32) != fk) first[fk] = (uint32_t)p;
+  const uint64_t fk = keys[p] >> sshift;
+  if (p + 1 == ns || (keys[p + 1] >> sshift) != fk) last[fk] = (uint32_t)(p + 1);
 }
 
-__global__ void k_pair_flags(const uint64_t* keys, const uint32_t* vals, uint64_t ns,
-                             const uint32_t* first, const uint32_t* gid, uint32_t* flag,
-                             unsigned long long* pairs) {
+struct SortedWeight {
+  const uint32_t* vals;
+  const int64_t* nw;
+  LMGP_D uint64_t operator()(uint64_t p) const { return (uint64_t)nw[vals[p]]; }
+};
+
+constexpr uint32_t NO_NEXT = 0xFFFFFFFFu;
+
+// nxt[p]: where the next group starts if a next-fit group opens at p, i.e. the
+// first q > p of p's segment with c(p..q) > cap (E = exclusive prefix sums of
+// the sorted weights); NO_NEXT if the rest of the segment fits.  Every weight
+// is >= 1, so q <= p + cap.
+__global__ void k_nextfit(const uint64_t* keys, int sshift, const uint32_t* last, const uint64_t* E,
+                          const uint32_t* vals, const uint32_t* gid, const GraphDesc* gd,
+                          uint64_t ns, uint32_t* nxt) {
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool lead = false;
+  if (p >= ns) return;
+  const uint64_t end = last[keys[p] >> sshift];
+  const uint64_t cap = (uint64_t)gd[graph_of(gid, vals[p])].cap;
+  const uint64_t hi = cap < end - p ? p + 1 + cap : end;
+  const uint64_t base = E[p];
+  uint64_t a = p + 1, b = hi;
+  while (a < b) {
+    const uint64_t mid = (a + b) >> 1;
+    if (E[mid + 1] - base > cap) b = mid;
+    else a = mid + 1;
+  }
+  nxt[p] = a < hi ? (uint32_t)a : NO_NEXT;
+}
+
+// Pointer doubling: J2 = J o J.
+__global__ void k_jump(const uint32_t* J, uint64_t ns, uint32_t* J2) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const uint32_t q = J[p];
+  J2[p] = q == NO_NEXT ? NO_NEXT : J[q];
+}
+
+__global__ void k_mark_seg_first(const uint64_t* keys, int sshift, uint64_t ns, uint8_t top,
+                                 uint8_t* mark) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  mark[p] = (p == 0 || (keys[p - 1] >> sshift) != (keys[p] >> sshift)) ? top : 0;
+}
+
+// Group starts are the positions J^t(segment first), t < 2^K.  Expansion from
+// the top table down: positions marked before this pass (mark >= k + 2) also
+// mark their 2^k-th successor with k + 1, which this pass does not expand.
+__global__ void k_expand(const uint32_t* Jk, uint64_t ns, uint32_t k, uint8_t* mark) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns || mark[p] < k + 2) return;
+  const uint32_t q = Jk[p];
+  if (q != NO_NEXT && mark[q] == 0) mark[q] = (uint8_t)(k + 1);
+}
+
+// Scan value: a group start counts in the low half, a joiner in the high half.
+struct StartJoin {
+  const uint8_t* mark;
+  LMGP_D uint64_t operator()(uint64_t p) const { return mark[p] ? 1ull : (1ull << 32); }
+};
+
+__global__ void k_group_heads(const uint8_t* mark, const uint64_t* sj, uint64_t ns,
+                              const uint32_t* vals, const uint32_t* gid, uint32_t* head,
+                              unsigned long long* joins) {
+  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool join = false;
   if (p < ns) {
-    const uint64_t fk = keys[p] >> 32;
-    const uint64_t pos = p - first[fk];
-    lead = (pos % 2 == 0) && p + 1 < ns && (keys[p + 1] >> 32) == fk;
-    flag[p] = lead;
-    if (lead && gid) atomicAdd(&pairs[gid[vals[p]]], 1ull);
+    if (mark[p]) head[(uint32_t)sj[p]] = (uint32_t)p;
+    join = !mark[p];
+    if (join && gid) atomicAdd(&joins[gid[vals[p]]], 1ull);
   }
   if (!gid) {  // one graph: one atomic per wave
-    const uint64_t c = __popcll(__ballot(lead));
-    if (lane_id() == 0 && c) atomicAdd(&pairs[0], (unsigned long long)c);
+    const uint64_t c = __popcll(__ballot(join));
+    if (lane_id() == 0 && c) atomicAdd(&joins[0], (unsigned long long)c);
   }
 }
 
-__global__ void k_pair_merge(const uint32_t* vals, const uint32_t* flag, const uint32_t* rank,
-                             uint64_t ns, const uint32_t* gid, const uint64_t* base,
-                             const uint64_t* cap, uint32_t* label, int64_t* W, const int64_t* nw,
-                             uint32_t* csize) {
+// A joiner takes its group head's label while its rank among its graph's
+// joiners is below the graph's cap (joins in sorted order).
+__global__ void k_group_merge(const uint32_t* vals, const uint8_t* mark, const uint64_t* sj,
+                              const uint32_t* head, uint64_t ns, const uint32_t* gid,
+                              const uint64_t* base, const uint64_t* cap, uint32_t* label,
+                              int64_t* W, const int64_t* nw, uint32_t* csize) {
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ns || !flag[p]) return;
-  const uint32_t a = vals[p], b = vals[p + 1];
-  const uint32_t g = graph_of(gid, a);
-  if ((uint64_t)rank[p] - base[g] >= cap[g]) return;
+  if (p >= ns || mark[p]) return;
+  const uint32_t b = vals[p];
+  const uint32_t g = graph_of(gid, b);
+  if ((sj[p] >> 32) - base[g] >= cap[g]) return;
+  const uint32_t a = vals[head[(uint32_t)sj[p] - 1]];
   const uint32_t la = label[a], lb = label[b];
   label[b] = la;
-  W[la] += nw[b];
+  atomicAdd((unsigned long long*)&W[la], (unsigned long long)nw[b]);
   W[lb] -= nw[b];
-  csize[la] += 1;
+  atomicAdd(&csize[la], 1u);
   csize[lb] -= 1;
 }
 
@@ -928,7 +1011,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   }
   DBuf<GraphDesc> dgd(&pool_, s_, B);
   h2d(dgd.get(), gd.data(), B, s_);
-  // favourites of light singletons with neighbours
+  // favourites of the singletons with neighbours
   DBuf<unsigned long long> bcount(&pool_, s_, 2 * NCLASS);  // counts, then degree sums
   DBuf<uint32_t> boffs(&pool_, s_, NCLASS), bfill(&pool_, s_, NCLASS);
   DBuf<uint32_t> list(&pool_, s_, n), fav(&pool_, s_, n);
@@ -977,7 +1060,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ra.fav = fav.get();
   ra.list = list.get();
   rate_classes(ra, cnt.data(), offs.data(), hcnt.data() + NCLASS, L.ew_kind);
-  // order light singletons by (favourite, hash, id)
+  // order the singletons by (favourite, weight, hash, id)
   SingletonFlag sf{label, csize, L.nw, L.gid, dgd.get()};
   DBuf<uint32_t> pos(&pool_, s_, n + 1);
   exclusive_scan(sf, n, pos.get(), true, pool_, s_);
@@ -986,34 +1069,74 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   sync(s_);
   const uint64_t ns = ns32;
   if (ns < 2) return;
+  int kb = 1;  // bits of a segment key (< 2n + 2)
+  while ((1ull << kb) <= 2 * n + 1) ++kb;
+  int64_t maxcap = 1;
+  uint64_t groups = 1;  // next-fit groups per segment: fewer than 2 c(V) / U + 1
+  for (uint32_t b = 0; b < B; ++b) {
+    if (!which[b]) continue;
+    const Job& jb = jobs[L.graphs[b]];
+    maxcap = std::max(maxcap, jb.U);
+    groups = std::max<uint64_t>(groups, (uint64_t)(2 * (u128)jb.g->cV / (u128)jb.U) + 2);
+  }
+  int wb = 1;  // bits of a weight below the cap
+  while (wb < 62 && (1ll << wb) <= maxcap - 1) ++wb;
+  const bool one_key = kb + wb + 32 <= 64;
+  const int sshift = one_key ? 32 + wb : 0;
   DBuf<uint64_t> keys(&pool_, s_, ns), keys2(&pool_, s_, ns);
   DBuf<uint32_t> vals(&pool_, s_, ns), vals2(&pool_, s_, ns);
-  k_twohop_keys<<<grid_for(n, 256), 256, 0, s_>>>(sf, L.xadj, fav.get(), pos.get(), n, keys.get(),
-                                                  vals.get());
-  LAUNCH_CHECK();
-  int kb = 1;
-  while ((1ull << kb) <= 2 * n + 1) ++kb;
-  const bool sw = radix_sort_pairs<uint32_t>(keys.get(), vals.get(), keys2.get(), vals2.get(), ns,
-                                             0, 32 + kb, pool_, s_);
-  const uint64_t* sk = sw ? keys2.get() : keys.get();
-  const uint32_t* sv = sw ? vals2.get() : vals.get();
-  DBuf<uint32_t> first(&pool_, s_, 2 * n + 2), flag(&pool_, s_, ns), rank(&pool_, s_, ns + 1);
-  DBuf<unsigned long long> pairs(&pool_, s_, B);
-  pairs.zero();
   const unsigned gs = grid_for(ns, 256);
-  k_seg_first<<<gs, 256, 0, s_>>>(sk, ns, first.get());
+  k_twohop_keys<<<grid_for(n, 256), 256, 0, s_>>>(sf, L.xadj, fav.get(), pos.get(), n, sshift,
+                                                  keys.get(), vals.get());
   LAUNCH_CHECK();
-  k_pair_flags<<<gs, 256, 0, s_>>>(sk, sv, ns, first.get(), L.gid, flag.get(), pairs.get());
+  bool sw = radix_sort_pairs<uint32_t>(keys.get(), vals.get(), keys2.get(), vals2.get(), ns, 0,
+                                       one_key ? kb + wb + 32 : wb + 32, pool_, s_);
+  uint64_t* sk = sw ? keys2.get() : keys.get();
+  uint32_t* sv = sw ? vals2.get() : vals.get();
+  if (!one_key) {  // then stably by favourite
+    uint64_t* ok = sw ? keys.get() : keys2.get();
+    uint32_t* ov = sw ? vals.get() : vals2.get();
+    k_twohop_favkeys<<<gs, 256, 0, s_>>>(sf, L.xadj, fav.get(), sv, ns, sk);
+    LAUNCH_CHECK();
+    if (radix_sort_pairs<uint32_t>(sk, sv, ok, ov, ns, 0, kb, pool_, s_)) sk = ok, sv = ov;
+  }
+  // next-fit groups of each favourite segment
+  DBuf<uint32_t> last(&pool_, s_, 2 * n + 2);
+  DBuf<uint64_t> E(&pool_, s_, ns + 1);
+  k_seg_last<<<gs, 256, 0, s_>>>(sk, sshift, ns, last.get());
   LAUNCH_CHECK();
-  exclusive_scan(ArrayU32{flag.get()}, ns, rank.get(), true, pool_, s_);
-  std::vector<unsigned long long> hp(B);
-  d2h(hp.data(), pairs.get(), B, s_);
+  exclusive_scan(SortedWeight{sv, L.nw}, ns, E.get(), true, pool_, s_);
+  uint32_t K = 0;  // doubling levels: 2^K > groups - 1
+  while (K < 32 && (1ull << K) < std::min<uint64_t>(ns, groups)) ++K;
+  DBuf<uint32_t> J(&pool_, s_, (size_t)std::max<uint32_t>(K, 1) * ns);
+  k_nextfit<<<gs, 256, 0, s_>>>(sk, sshift, last.get(), E.get(), sv, L.gid, dgd.get(), ns, J.get());
+  LAUNCH_CHECK();
+  for (uint32_t k = 1; k < K; ++k) {
+    k_jump<<<gs, 256, 0, s_>>>(J.get() + (size_t)(k - 1) * ns, ns, J.get() + (size_t)k * ns);
+    LAUNCH_CHECK();
+  }
+  DBuf<uint8_t> mark(&pool_, s_, ns);
+  k_mark_seg_first<<<gs, 256, 0, s_>>>(sk, sshift, ns, (uint8_t)(K + 1), mark.get());
+  LAUNCH_CHECK();
+  for (uint32_t k = K; k-- > 0;) {
+    k_expand<<<gs, 256, 0, s_>>>(J.get() + (size_t)k * ns, ns, k, mark.get());
+    LAUNCH_CHECK();
+  }
+  DBuf<uint64_t> sj(&pool_, s_, ns + 1);
+  exclusive_scan(StartJoin{mark.get()}, ns, sj.get(), true, pool_, s_);
+  DBuf<uint32_t> head(&pool_, s_, ns);
+  DBuf<unsigned long long> joins(&pool_, s_, B);
+  joins.zero();
+  k_group_heads<<<gs, 256, 0, s_>>>(mark.get(), sj.get(), ns, sv, L.gid, head.get(), joins.get());
+  LAUNCH_CHECK();
+  std::vector<unsigned long long> hj(B);
+  d2h(hj.data(), joins.get(), B, s_);
   sync(s_);
   std::vector<uint64_t> base(B), cap(B);
   uint64_t acc = 0;
   for (uint32_t b = 0; b < B; ++b) {
     base[b] = acc;
-    acc += hp[b];
+    acc += hj[b];
     const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
     const uint64_t floor_cl = (uint64_t)(((u128)p_.shrink_den * nb + p_.shrink_num - 1) / p_.shrink_num);
     cap[b] = ncl[b] > floor_cl ? ncl[b] - floor_cl : 0;
@@ -1022,10 +1145,10 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   DBuf<uint64_t> dbase(&pool_, s_, B), dcap(&pool_, s_, B);
   h2d(dbase.get(), base.data(), B, s_);
   h2d(dcap.get(), cap.data(), B, s_);
-  k_pair_merge<<<gs, 256, 0, s_>>>(sv, flag.get(), rank.get(), ns, L.gid, dbase.get(), dcap.get(),
-                                   label, W, L.nw, csize);
+  k_group_merge<<<gs, 256, 0, s_>>>(sv, mark.get(), sj.get(), head.get(), ns, L.gid, dbase.get(),
+                                    dcap.get(), label, W, L.nw, csize);
   LAUNCH_CHECK();
-  for (uint32_t b = 0; b < B; ++b) ncl[b] -= std::min<uint64_t>(hp[b], cap[b]);
+  for (uint32_t b = 0; b < B; ++b) ncl[b] -= std::min<uint64_t>(hj[b], cap[b]);
   sync(s_);
 }
 

@@ -1380,9 +1380,9 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
     uint32_t sr = subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds);
     return (int)(sr * NCLASS + class_of(d, a.cuts));
   }
-  // 2-hop: light singletons with neighbours
+  // 2-hop: singletons lighter than the cap, with neighbours
   if (a.csize[a.label[u]] != 1) return -1;
-  if (2 * a.nw[u] > gd.cap) return -1;
+  if (a.nw[u] >= gd.cap) return -1;
   return class_of(d, a.cuts);
 }
 

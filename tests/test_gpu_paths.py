@@ -1,0 +1,185 @@
+"""GPU parity on paths the default workloads do not reach.
+
+* 2-hop clustering by next-fit packing (Sec. 4.1): weighted singletons, many
+  isolated nodes, and node weights wide enough that the (favourite, weight,
+  hash) sort key needs two sorting passes;
+* the sparsification parameters of the paper's parameter study (Sec. 5.1):
+  rho = 3 and (tau_e, tau_d, rho) = (1/4, 1, 2);
+* device memory from PyTorch's caching allocator through the C ABI's
+  allocator callback, and an allocator that fails (LMGP_ENOMEM, with the
+  library usable afterwards).
+
+Every comparison is bit-exact against the CPU oracle.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_17615_amd import graphgen as gg
+from tests import graphs as T
+from tests.test_gpu_parity import check_hierarchy, check_partition
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_17615_amd as L
+
+    L.library()
+    return L
+
+
+# ------------------------------------------------------------------ 2-hop --
+def _hubs_with_isolated(n, hubs, iso_frac, rng, vmax):
+    edges = set()
+    for v in range(hubs, n):
+        if rng.random() < iso_frac:
+            continue
+        edges.add((int(rng.integers(0, hubs)), v))
+    vw = rng.integers(1, vmax + 1, size=n) if vmax > 1 else None
+    return T.from_edges(n, sorted(edges), vwgt=vw)
+
+
+@pytest.mark.parametrize("case", ["unit", "weighted", "isolated"])
+def test_two_hop_packing(lib, case):
+    rng = np.random.default_rng(21)
+    if case == "unit":  # one hub per 200 leaves: the leaves' favourite segments
+        g = _hubs_with_isolated(20000, 100, 0.0, rng, 1)
+    elif case == "weighted":  # weights 1..9 against U = c(V) / (160 k)
+        g = _hubs_with_isolated(20000, 40, 0.1, rng, 9)
+    else:  # mostly isolated nodes: one long ISO segment per level
+        g = _hubs_with_isolated(30000, 10, 0.8, rng, 3)
+    oh = check_hierarchy(lib, g, 2, 5)
+    assert any(i["twohop"] for i in oh.info)
+    check_partition(lib, g, 2, 0.03, 5)
+
+
+def test_two_hop_two_pass_sort(lib):
+    # node weights ~2^26: U = c(V) / 320 needs 31 bits, so favourite,
+    # weight and hash do not fit one 64-bit key
+    rng = np.random.default_rng(3)
+    g = _hubs_with_isolated(6000, 20, 0.3, rng, 1)
+    g = T.G(g.n, g.xadj, g.adjncy, None, rng.integers(1 << 26, 1 << 27, size=g.n))
+    U = int(g.vwgt.sum()) // (160 * 2)
+    assert U.bit_length() + (2 * g.n + 1).bit_length() + 32 > 64
+    oh = check_hierarchy(lib, g, 2, 9)
+    assert any(i["twohop"] for i in oh.info)
+    check_partition(lib, g, 2, 0.03, 9)
+
+
+# ------------------------------------------- parameter study (Sec. 5.1) --
+SWEEP = [dict(rho_num=3, rho_den=1),
+         dict(tau_e_num=1, tau_e_den=4, tau_d_num=1, tau_d_den=1, rho_num=2, rho_den=1)]
+
+
+@pytest.mark.parametrize("kw", SWEEP, ids=["rho3", "te4_td1_rho2"])
+@pytest.mark.parametrize("name", ["er14", "rmat14"])
+def test_sparsification_parameters(lib, name, kw):
+    g, k, eps, seed = gg.workload(name)
+    oh = check_hierarchy(lib, g, 16, seed, **kw)
+    assert any(i["triggered"] for i in oh.info)
+    check_partition(lib, g, k, eps, seed, **kw)
+
+
+# ---------------------------------------------------------- allocators --
+def test_torch_allocator_parity(lib):
+    g, k, eps, seed = gg.workload("rmat14")
+    before = torch.cuda.memory_allocated()
+    dg = lib.create_graph(g, validate=True, torch_allocator=True)
+    assert torch.cuda.memory_allocated() > before  # the graph lives in torch's pool
+    h = dg.coarsen(k, seed)
+    oh = O.coarsen(g, k, seed)
+    assert h.levels == len(oh.levels)
+    for i in range(1, h.levels):
+        lv = h.copy_level(i)
+        assert np.array_equal(lv["adjncy"], oh.levels[i].adjncy), i
+        assert np.array_equal(lv["adjwgt"], oh.levels[i].adjwgt), i
+    h.close()
+    blocks, res = dg.partition(k, eps, seed, host_out=True)
+    ob, ores, _ = O.partition(g, k, eps, seed)
+    assert np.array_equal(blocks, ob) and res["cut"] == ores["cut"]
+    dg.close()
+    torch.cuda.synchronize()
+
+
+class _FailingAllocator:
+    """PyTorch's caching allocator that returns NULL after `budget` calls."""
+
+    def __init__(self, budget):
+        self.budget = budget
+        self.calls = 0
+        dev = torch.cuda.current_device()
+
+        def _alloc(ctx, nbytes, stream):
+            self.calls += 1
+            if self.budget is not None and self.calls > self.budget:
+                return None
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+
+        def _free(ctx, ptr, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        from paper_2504_17615_amd._binding import Allocator
+
+        self._a = Allocator.ALLOC(_alloc)
+        self._f = Allocator.FREE(_free)
+        self.struct = Allocator(None, self._a, self._f)
+
+
+def _create(lib, g, alloc):
+    from paper_2504_17615_amd._binding import CsrView
+
+    xa = np.ascontiguousarray(g.xadj, np.uint64)
+    adj = np.ascontiguousarray(g.adjncy, np.uint32)
+    view = CsrView(g.n, adj.shape[0], xa.ctypes.data, adj.ctypes.data, None, None, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    st = lib.library().lmgp_graph_create(ctypes.byref(view), ctypes.byref(alloc.struct),
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                         ctypes.byref(h))
+    return st, h
+
+
+def test_allocator_failure_reports_enomem(lib):
+    g, k, eps, seed = gg.workload("grid128")  # five levels: many allocations per call
+    api = lib.library()
+    # the first allocation fails: graph_create reports ENOMEM, writes no handle
+    st, h = _create(lib, g, _FailingAllocator(0))
+    assert st == 2 and not h.value
+    assert b"NULL" in api.lmgp_last_error()
+    # a graph created, then partitions whose allocations fail part-way
+    alloc = _FailingAllocator(None)
+    st, h = _create(lib, g, alloc)
+    assert st == 0
+    ob, ores, _ = O.partition(g, k, eps, seed)
+    out = np.empty(g.n, np.uint32)
+    from paper_2504_17615_amd._binding import Result
+
+    res = Result()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    alloc.calls = 0
+    assert api.lmgp_partition(h, k, eps, seed, None, stream, out.ctypes.data, 0,
+                              ctypes.byref(res)) == 0
+    total = alloc.calls  # allocations of one whole call (a fixed sequence)
+    assert total > 10
+    for extra in (0, 1, total // 2, total - 1):
+        alloc.budget, alloc.calls = extra, 0
+        st = api.lmgp_partition(h, k, eps, seed, None,
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                out.ctypes.data, 0, ctypes.byref(res))
+        assert st == 2, (extra, st)
+    # the same graph partitions correctly once memory is available again
+    alloc.budget = None
+    st = api.lmgp_partition(h, k, eps, seed, None,
+                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                            out.ctypes.data, 0, ctypes.byref(res))
+    assert st == 0
+    assert np.array_equal(out, ob) and res.cut == ores["cut"]
+    api.lmgp_graph_destroy(h)
+    torch.cuda.synchronize()

@@ -242,48 +242,108 @@ def test_threshold_coin_sampling():
 
 
 # ------------------------------------------------------- label propagation --
-def _lp_bruteforce(g, label, W, cap, seed, level, S, tags):
-    """One round (S sub-rounds) of the synchronous size-constrained LP rule,
-    evaluated from scratch with Python containers (tiny graphs only)."""
+def _lp_bruteforce(g, label, W, cap, seed, level, S, tags, rounds=1, shrink=None,
+                   stop_at_round_end=False):
+    """Synchronous size-constrained LP rule (Sec. 3) evaluated from scratch with
+    Python containers (tiny graphs only): `rounds` rounds of S sub-rounds,
+    stopping after a round without moves.  With shrink = (num, den) the
+    2.5x node-reduction cap (Sec. 4.3) stops LP once num*|C| <= den*n after a
+    sub-round (or, with stop_at_round_end, only after the round: a wrong
+    reading that the pins must tell apart).  Returns (label, W, rounds run,
+    (round, sub-round) at which the stop condition first held or None)."""
     label = [int(x) for x in label]
     W = [int(x) for x in W]
     nw = T.node_weights(g)
     xadj = g.xadj.astype(np.int64)
     ew = np.ones(g.nnz, np.int64) if g.adjwgt is None else g.adjwgt
-    r = 0
-    for s in range(S):
-        cands = []
-        for u in range(g.n):
-            if xadj[u + 1] == xadj[u]:
-                continue
-            if ((O.H(seed, tags[0], level, r, u) >> 32) * S) >> 32 != s:
-                continue
+    fired, rounds_run = None, 0
+    for r in range(rounds):
+        rounds_run = r + 1
+        moved, stop = 0, False
+        for s in range(S):
+            cands = []
+            for u in range(g.n):
+                if xadj[u + 1] == xadj[u]:
+                    continue
+                if ((O.H(seed, tags[0], level, r, u) >> 32) * S) >> 32 != s:
+                    continue
+                rating = {}
+                for e in range(xadj[u], xadj[u + 1]):
+                    K = label[int(g.adjncy[e])]
+                    rating[K] = rating.get(K, 0) + int(ew[e])
+                own = label[u]
+                feas = [K for K in rating if K != own and W[K] + nw[u] <= cap]
+                if not feas:
+                    continue
+                best = min(feas, key=lambda K: (-rating[K], O.H(seed, tags[1], level, r, u, K), K))
+                if rating[best] > rating.get(own, 0):
+                    gain = rating[best] - rating.get(own, 0)
+                    cands.append((best, -gain, O.H(seed, tags[2], level, r, u) >> 32, u))
+            cands.sort()
+            admitted = []
+            for tgt, grp in itertools.groupby(cands, key=lambda c: c[0]):
+                acc = 0
+                for c in grp:
+                    if acc + nw[c[3]] > cap - W[tgt]:
+                        break
+                    acc += nw[c[3]]
+                    admitted.append(c)
+            for tgt, _, _, u in admitted:
+                W[label[u]] -= nw[u]
+                W[tgt] += nw[u]
+                label[u] = tgt
+            moved += len(admitted)
+            if shrink is not None and shrink[0] * len(set(label)) <= shrink[1] * g.n:
+                fired = fired or (r, s)
+                stop = True
+                if not stop_at_round_end:
+                    break
+        if stop or moved == 0:
+            break
+    return np.array(label, np.uint32), np.array(W, np.int64), rounds_run, fired
+
+
+def _two_hop_bruteforce(g, label, U, seed, level, shrink=(5, 2)):
+    """2-hop clustering (Sec. 4.1) with the merge cap (Sec. 4.3), from scratch:
+    singletons lighter than U, favourite = best-rated adjacent cluster (ties
+    by H(FAV), then id; isolated nodes share one favourite after all labels),
+    ordered by (favourite, c, hi32 H(TWOHOP), id), each favourite's run packed
+    next-fit under U, at most |C| - ceil(2n/5) joins in that order.
+    shrink = None lifts the cap.  Returns (label, joins)."""
+    label = [int(x) for x in label]
+    nw = T.node_weights(g)
+    xadj = g.xadj.astype(np.int64)
+    ew = np.ones(g.nnz, np.int64) if g.adjwgt is None else g.adjwgt
+    size = np.bincount(label, minlength=g.n)
+    ncl = int((size > 0).sum())
+    singles = []
+    for v in range(g.n):
+        if size[label[v]] != 1 or nw[v] >= U:
+            continue
+        fav = 2**32 - 1
+        if xadj[v + 1] > xadj[v]:
             rating = {}
-            for e in range(xadj[u], xadj[u + 1]):
+            for e in range(xadj[v], xadj[v + 1]):
                 K = label[int(g.adjncy[e])]
                 rating[K] = rating.get(K, 0) + int(ew[e])
-            own = label[u]
-            feas = [K for K in rating if K != own and W[K] + nw[u] <= cap]
-            if not feas:
-                continue
-            best = min(feas, key=lambda K: (-rating[K], O.H(seed, tags[1], level, r, u, K), K))
-            if rating[best] > rating.get(own, 0):
-                gain = rating[best] - rating.get(own, 0)
-                cands.append((best, -gain, O.H(seed, tags[2], level, r, u) >> 32, u))
-        cands.sort()
-        admitted = []
-        for tgt, grp in itertools.groupby(cands, key=lambda c: c[0]):
-            acc = 0
-            for c in grp:
-                if acc + nw[c[3]] > cap - W[tgt]:
-                    break
-                acc += nw[c[3]]
-                admitted.append(c)
-        for tgt, _, _, u in admitted:
-            W[label[u]] -= nw[u]
-            W[tgt] += nw[u]
-            label[u] = tgt
-    return np.array(label, np.uint32), np.array(W, np.int64)
+            fav = min(rating, key=lambda K: (-rating[K], O.H(seed, O.TAGS["FAV"], level, v, K), K))
+        singles.append((fav, int(nw[v]), O.H(seed, O.TAGS["TWOHOP"], level, v) >> 32, v))
+    singles.sort()
+    P = ncl if shrink is None else max(0, ncl + (-shrink[1] * g.n // shrink[0]))
+    joins = 0
+    for _, grp in itertools.groupby(singles, key=lambda s: s[0]):
+        grp = list(grp)
+        lead, gw = grp[0][3], grp[0][1]
+        for _, c, _, v in grp[1:]:
+            if joins >= P:
+                break
+            if gw + c <= U:
+                label[v] = label[lead]
+                gw += c
+                joins += 1
+            else:
+                lead, gw = v, c
+    return np.array(label, np.uint32), joins
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -297,7 +357,7 @@ def test_lp_round_matches_bruteforce(seed, S):
     label0 = np.arange(n, dtype=np.uint32)
     W0 = nw.copy()
     tags = (O.TAGS["SUB"], O.TAGS["TIE"], O.TAGS["ADM"])
-    want_l, want_w = _lp_bruteforce(g, label0, W0, cap, seed, 1, S, tags)
+    want_l, want_w, _, _ = _lp_bruteforce(g, label0, W0, cap, seed, 1, S, tags)
     got_l, got_w, _, _ = O.label_propagation(g, label0, W0, cap, seed, 1, rounds=1, subrounds=S)
     assert np.array_equal(got_l, want_l)
     assert np.array_equal(got_w, want_w)
@@ -307,7 +367,7 @@ def test_lp_round_matches_bruteforce(seed, S):
     BW = np.bincount(blocks, weights=nw, minlength=k).astype(np.int64)
     lmax = int(BW.max()) + 2
     rt = (O.TAGS["RSUB"], O.TAGS["RTIE"], O.TAGS["RADM"])
-    want_l, want_w = _lp_bruteforce(g, blocks, BW, lmax, seed, 2, S, rt)
+    want_l, want_w, _, _ = _lp_bruteforce(g, blocks, BW, lmax, seed, 2, S, rt)
     got_l, got_w, _, _ = O.label_propagation(g, blocks, BW, lmax, seed, 2, refine_tags=True,
                                              rounds=1, subrounds=S)
     assert np.array_equal(got_l, want_l)
@@ -359,35 +419,146 @@ def test_theorem1_cluster_bound(name):
     _clusters_ok(g, label, U)
 
 
-def test_star_two_hop_pairs_leaves():
-    # Star with 101 leaves and U = 3: the hub's cluster fills up; every other
-    # leaf is a singleton whose only adjacent cluster is the hub's, so 2-hop
-    # clustering pairs them.
-    g, U = T.star(101), 3
+def test_star_two_hop_packs_leaves():
+    # Star with 100 leaves and U = 3: the hub's cluster fills up to U; every
+    # other leaf is a singleton whose only adjacent cluster is the hub's, so
+    # 2-hop clustering packs the 98 left into groups of U = 3: 32 groups of
+    # three and one pair.
+    g, U = T.star(100), 3
     label, st = O.cluster(g, U, seed=4, level=1, p=_theorem1_params())
     assert st["twohop"] == 1
-    sizes = np.bincount(np.bincount(label, minlength=g.n))
     hub_cluster = np.sum(label == label[0])
     assert hub_cluster == U
-    assert sizes[2] == (g.n - U) // 2  # leaves in pairs
-    assert sizes[1] <= 1
+    sizes = np.bincount(np.bincount(label, minlength=g.n), minlength=4)
+    assert (sizes[1], sizes[2], sizes[3]) == (0, 1, 32 + 1)
 
 
-def test_isolated_nodes_are_paired():
-    g = T.from_edges(12, [(0, 1), (1, 2), (2, 3)])  # nodes 4..11 isolated
-    label, st = O.cluster(g, 4, seed=1, level=1, p=_theorem1_params())
-    iso = label[4:]
-    assert len(np.unique(iso)) == 4
+def _isolated(n, vwgt=None):
+    return T.G(n, np.zeros(n + 1, np.uint64), np.zeros(0, np.uint32), None,
+               None if vwgt is None else np.asarray(vwgt, np.int64))
 
 
-def test_node_reduction_cap():
-    # Sec. 4.3: at most 2.5x fewer nodes per step (checked at sub-round
-    # granularity by LP, exactly by the 2-hop pair cap)
-    g = gg.grid(64, 64)
-    label, st = O.cluster(g, 50, seed=2, level=1)
-    assert st["nclusters"] >= int(np.ceil(2 * g.n / 5)) or not st["twohop"]
-    if st["twohop"]:
+# Only isolated nodes of unit weight: LP never moves (isolated nodes are never
+# active), |C| = n, so 2-hop runs on one favourite (ISO).  Next-fit packing
+# under U forms groups of U nodes; the cap allows |C| - ceil(2n/5) joins.
+# Cluster sizes by hand for n = 10 (cap: 10 - 4 = 6 joins):
+#   U = 4:   groups 4, 4 use 3 + 3 joins -> [1, 1, 4, 4]; without cap [2, 4, 4]
+#   U = 3:   groups 3, 3, 3 use 6 joins  -> [1, 3, 3, 3]; without cap the same
+#   U = 100: 6 joins into the first group -> [1, 1, 1, 7]; without cap [10]
+# One join more or fewer than the cap changes the capped U = 4 and U = 100 sizes.
+@pytest.mark.parametrize("U,capped,sizes", [
+    (4, True, [1, 1, 4, 4]), (4, False, [2, 4, 4]),
+    (3, True, [1, 3, 3, 3]), (3, False, [1, 3, 3, 3]),
+    (100, True, [1, 1, 1, 7]), (100, False, [10]),
+])
+def test_two_hop_cap_on_isolated_nodes(U, capped, sizes):
+    g = _isolated(10)
+    p = O.params() if capped else _theorem1_params()
+    label, st = O.cluster(g, U, seed=3, level=2, p=p)
+    assert st["twohop"] == 1 and st["nclusters_lp"] == 10
+    assert sorted(np.bincount(label)[np.bincount(label) > 0].tolist()) == sizes
+    assert st["nclusters"] == len(sizes)
+    if capped:
         assert st["nclusters"] >= int(np.ceil(2 * g.n / 5))
+
+
+def test_two_hop_packs_in_ascending_weight_order():
+    # Isolated nodes of weights 5, 1, 1, 2, 3, 4 with U = 6, no cap.  In
+    # ascending weight order next-fit packing gives {1, 1, 2} (adding 3 would
+    # exceed 6), {3}, {4}, {5}: cluster weights [3, 4, 4, 5].  (Descending or
+    # id order would give other groups: 5 | 4 | 3 2 1 | 1, or 5 1 | 1 2 3 | 4.)
+    g = _isolated(6, vwgt=[5, 1, 1, 2, 3, 4])
+    label, st = O.cluster(g, 6, seed=8, level=1, p=_theorem1_params())
+    W = np.bincount(label, weights=[5, 1, 1, 2, 3, 4], minlength=6)
+    assert sorted(W[W > 0].astype(int).tolist()) == [3, 4, 4, 5]
+    assert label[1] == label[2] == label[3]
+    # a node of weight >= U fits with nobody and stays out
+    g = _isolated(4, vwgt=[6, 1, 2, 3])
+    label, _ = O.cluster(g, 6, seed=8, level=1, p=_theorem1_params())
+    assert label[0] == 0 and label[1] == label[2] == label[3]
+
+
+# Tiny graphs where LP's 2.5x stop first holds in the middle of round 1 (found
+# by search with the brute force; each case re-checks that property), so a
+# stop taken only at the end of the round gives other labels.
+@pytest.mark.parametrize("seed", [0, 2, 3, 4, 5, 10, 11])
+def test_lp_subround_stop_matches_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(20, 50))
+    g = T.random_graph(n, int(rng.integers(2 * n, 4 * n)), rng, wmax=2, vmax=2)
+    U = int(rng.integers(4, 10))
+    nw = T.node_weights(g)
+    tags = (O.TAGS["SUB"], O.TAGS["TIE"], O.TAGS["ADM"])
+    lab0 = np.arange(n, dtype=np.uint32)
+    want, _, rounds, fired = _lp_bruteforce(g, lab0, nw, U, seed, 1, 4, tags, rounds=5,
+                                            shrink=(5, 2))
+    assert fired is not None and fired[1] < 3  # the stop fired before the last sub-round
+    late, _, _, _ = _lp_bruteforce(g, lab0, nw, U, seed, 1, 4, tags, rounds=5, shrink=(5, 2),
+                                   stop_at_round_end=True)
+    assert not np.array_equal(late, want)
+    got, _, r, _ = O.label_propagation(g, lab0, nw, U, seed, 1, rounds=5, subrounds=4,
+                                       shrink_stop=True)
+    assert np.array_equal(got, want) and r == rounds
+    # the clustering step reports the same rounds and cluster count
+    _, st = O.cluster(g, U, seed=seed, level=1)
+    assert st["lp_rounds"] == rounds and st["nclusters_lp"] == len(np.unique(want))
+
+
+def _hub_graph(seed):
+    # 1..3 hubs, every other node a leaf of one hub or isolated (a quarter)
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(20, 60))
+    hubs = int(rng.integers(1, 4))
+    edges = set()
+    for v in range(hubs, n):
+        if rng.random() < 0.25:
+            continue
+        edges.add((int(rng.integers(0, hubs)), v))
+    g = T.from_edges(n, sorted(edges), vwgt=rng.integers(1, 4, size=n))
+    return g, int(rng.integers(3, 12))
+
+
+@pytest.mark.parametrize("seed", range(26))
+def test_cluster_step_matches_bruteforce(seed):
+    # LP (with the sub-round stop) then 2-hop (with the join cap) against the
+    # brute force; in most cases the cap binds, and then exactly
+    # |C| - ceil(2n/5) joins are made.
+    g, U = _hub_graph(seed)
+    if g.nnz == 0:
+        pytest.skip("no edges drawn")
+    nw = T.node_weights(g)
+    tags = (O.TAGS["SUB"], O.TAGS["TIE"], O.TAGS["ADM"])
+    lab, _, rounds, _ = _lp_bruteforce(g, np.arange(g.n, dtype=np.uint32), nw, U, seed, 1, 4,
+                                       tags, rounds=5, shrink=(5, 2))
+    ncl = len(np.unique(lab))
+    want = lab
+    if 2 * ncl > g.n:
+        want, joins = _two_hop_bruteforce(g, lab, U, seed, 1)
+        _, avail = _two_hop_bruteforce(g, lab, U, seed, 1, shrink=None)
+        P = ncl - int(np.ceil(2 * g.n / 5))
+        assert joins == min(P, avail)
+    got, st = O.cluster(g, U, seed=seed, level=1)
+    assert np.array_equal(got, want)
+    assert st["lp_rounds"] == rounds and st["nclusters_lp"] == ncl
+    assert st["nclusters"] == len(np.unique(want))
+
+
+def test_cap_binds_in_most_hub_cases():
+    # guards the cases above against becoming vacuous
+    binds = 0
+    for seed in range(26):
+        g, U = _hub_graph(seed)
+        if g.nnz == 0:
+            continue
+        nw = T.node_weights(g)
+        lab, _, _, _ = _lp_bruteforce(g, np.arange(g.n, dtype=np.uint32), nw, U, seed, 1, 4,
+                                      (O.TAGS["SUB"], O.TAGS["TIE"], O.TAGS["ADM"]), rounds=5,
+                                      shrink=(5, 2))
+        ncl = len(np.unique(lab))
+        if 2 * ncl > g.n:
+            _, avail = _two_hop_bruteforce(g, lab, U, seed, 1, shrink=None)
+            binds += ncl - int(np.ceil(2 * g.n / 5)) < avail
+    assert binds >= 15
 
 
 # ---------------------------------------------------------------- hierarchy --
