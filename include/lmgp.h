@@ -220,6 +220,31 @@ lmgp_status lmgp_partition(lmgp_graph *g, uint32_t k, double eps, uint64_t seed,
                            const lmgp_params *params, void *stream, uint32_t *block_out,
                            uint32_t block_on_device, lmgp_result *res);
 
+/* Allocation-free variant of lmgp_partition, for callers that cannot
+ * allocate device memory (code that must not call hipMalloc, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, result and
+ * errors as lmgp_partition, with these differences:
+ *   - every device buffer the call needs comes from a fixed scratch array of
+ *     LMGP_NOALLOC_SCRATCH_BYTES that the library's code object holds on each
+ *     GPU it runs on (resident until the process ends); the call makes no
+ *     device or page-locked host allocation and no allocator callback; its
+ *     host copies go through pageable memory;
+ *   - graphs above LMGP_NOALLOC_MAX_NODES nodes or LMGP_NOALLOC_MAX_ENTRIES
+ *     directed entries are rejected with LMGP_EINVAL before any work; a run
+ *     whose buffers still do not fit the array fails with LMGP_ENOMEM;
+ *   - params.tune and params.graph_rounds are ignored (taken as 0);
+ *   - all calls on one GPU share its array, which keeps the last call's
+ *     contents (every buffer is initialised by the call that uses it): calls
+ *     on one device from several threads are serialised by the library, and
+ *     each returns only after its stream has finished with the array.
+ * The graph itself (lmgp_graph_create) and block_out are the caller's. */
+#define LMGP_NOALLOC_SCRATCH_BYTES (256ull << 20)
+#define LMGP_NOALLOC_MAX_NODES (1ull << 19)
+#define LMGP_NOALLOC_MAX_ENTRIES (1ull << 22)
+lmgp_status lmgp_partition_noalloc(lmgp_graph *g, uint32_t k, double eps, uint64_t seed,
+                                   const lmgp_params *params, void *stream, uint32_t *block_out,
+                                   uint32_t block_on_device, lmgp_result *res);
+
 /* Partitions `count` graphs as one batched run: every kernel launch covers
  * all graphs of the batch.  Outputs are identical to `count` separate
  * lmgp_partition calls.  k, eps, seed, block_out and res are arrays of

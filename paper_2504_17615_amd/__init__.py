@@ -7,6 +7,9 @@ engine.  Importing the package does not load the library; the first call does,
 and raises if it has not been built (``paper_2504_17615_amd.build``).
 """
 from ._binding import (  # noqa: F401
+    NOALLOC_MAX_ENTRIES,
+    NOALLOC_MAX_NODES,
+    NOALLOC_SCRATCH_BYTES,
     LmgpError,
     Params,
     LevelInfo,

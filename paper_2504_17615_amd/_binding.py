@@ -14,6 +14,11 @@ LIB_PATH = os.path.join(_HERE, "liblmgp.so")
 _lib = None
 _lock = threading.Lock()
 
+# Limits of lmgp_partition_noalloc (LMGP_NOALLOC_* in include/lmgp.h).
+NOALLOC_SCRATCH_BYTES = 256 << 20
+NOALLOC_MAX_NODES = 1 << 19
+NOALLOC_MAX_ENTRIES = 1 << 22
+
 
 class LmgpError(RuntimeError):
     def __init__(self, status: int, msg: str):
@@ -87,6 +92,9 @@ _SIGS = {
     "lmgp_partition": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                         ctypes.c_void_p], ctypes.c_int),
+    "lmgp_partition_noalloc": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_double,
+                                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
     "lmgp_partition_batch": ([ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_void_p,
                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                              ctypes.c_void_p], ctypes.c_int),
@@ -261,9 +269,11 @@ class DeviceGraph:
         return int(tw.value)
 
     def partition(self, k: int, eps: float = 0.03, seed: int = 1, params: Optional[Params] = None,
-                  stream=None, out=None, host_out: bool = False):
+                  stream=None, out=None, host_out: bool = False, noalloc: bool = False):
         """Returns (blocks, result dict).  blocks is a torch uint32-compatible
-        int32 tensor on the device (or a numpy uint32 array if host_out)."""
+        int32 tensor on the device (or a numpy uint32 array if host_out).
+        noalloc=True calls lmgp_partition_noalloc (the library's fixed scratch
+        array instead of any allocation; `out` or host_out avoid torch's)."""
         res = Result()
         if host_out:
             blocks = np.empty(self.n, np.uint32)
@@ -273,9 +283,9 @@ class DeviceGraph:
             blocks = out if out is not None else torch.empty(self.n, dtype=torch.int32,
                                                              device="cuda")
             ptr, on_dev = blocks.data_ptr(), 1
-        _check(library().lmgp_partition(self._h, k, eps, seed,
-                                        ctypes.byref(params) if params is not None else None,
-                                        _stream_ptr(stream), ptr, on_dev, ctypes.byref(res)))
+        fn = library().lmgp_partition_noalloc if noalloc else library().lmgp_partition
+        _check(fn(self._h, k, eps, seed, ctypes.byref(params) if params is not None else None,
+                  _stream_ptr(stream), ptr, on_dev, ctypes.byref(res)))
         return blocks, res.as_dict()
 
     def coarsen(self, k: int, seed: int = 1, params: Optional[Params] = None, stream=None):

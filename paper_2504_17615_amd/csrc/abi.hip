@@ -2,6 +2,7 @@
 // this boundary; failures become an lmgp_status plus a thread-local message.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "engine.h"
@@ -281,11 +282,92 @@ void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
   g.rows_sorted = unsorted == 0;
 }
 
+// ------------------------------------------------- allocation-free calls --
+// Device scratch of lmgp_partition_noalloc: each GPU the library runs on holds
+// its own copy from the library's load until the process ends.  Host code
+// never passes the symbol itself (a host-side stand-in): it uses the address
+// that hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) unsigned char scratch[LMGP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+
+struct ScratchSlot {
+  void* ptr = nullptr;  // device address of `scratch` on this device
+  std::mutex call_mu;   // calls on one device share its array: one at a time
+};
+
+// The calling device's slot; the first call on a device (that device current)
+// looks up the array's address.
+ScratchSlot& scratch_slot() {
+  static std::mutex mu;
+  static ScratchSlot slots[MAX_DEVICES];
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw InvalidArg("device index out of range");
+  std::lock_guard<std::mutex> g(mu);
+  ScratchSlot& slot = slots[dev];
+  if (!slot.ptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw HipError(e, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    slot.ptr = p;
+  }
+  return slot;
+}
+
+// Waits for the stream before the call gives the scratch array back (also
+// when the call ends by an exception with work in flight).
+struct StreamDrain {
+  hipStream_t s;
+  ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
+}  // namespace
+
 }  // namespace lmgp
 
 using namespace lmgp;
 
 extern "C" {
+
+lmgp_status lmgp_partition_noalloc(lmgp_graph* g, uint32_t k, double eps, uint64_t seed,
+                                   const lmgp_params* params, void* stream, uint32_t* block_out,
+                                   uint32_t block_on_device, lmgp_result* res) {
+  return guard([&] {
+    if (!g) throw InvalidArg("NULL graph");
+    if (!block_out) throw InvalidArg("block_out is NULL");
+    if (g->g.n > LMGP_NOALLOC_MAX_NODES || g->g.nnz > LMGP_NOALLOC_MAX_ENTRIES)
+      throw InvalidArg("graph too large for lmgp_partition_noalloc: n = " +
+                       std::to_string(g->g.n) + " (max " + std::to_string(LMGP_NOALLOC_MAX_NODES) +
+                       "), nnz = " + std::to_string(g->g.nnz) + " (max " +
+                       std::to_string(LMGP_NOALLOC_MAX_ENTRIES) + ")");
+    lmgp_params p = params ? *params : default_params();
+    check_params(p);
+    p.tune = LMGP_TUNE_OFF;  // no timing trials
+    p.graph_rounds = 0;      // no stream capture
+    std::vector<Job> jobs;
+    jobs.push_back(make_job(&g->g, k, eps, seed, p));
+    ScratchSlot& slot = scratch_slot();
+    std::lock_guard<std::mutex> lock(slot.call_mu);
+    StreamDrain drain{(hipStream_t)stream};
+    NoAllocScope no_alloc;
+    Pool arena(slot.ptr, LMGP_NOALLOC_SCRATCH_BYTES);
+    Engine e(arena, (hipStream_t)stream, p);
+    e.coarsen(jobs);
+    uint32_t* outs[1] = {block_out};
+    e.partition(jobs, outs, block_on_device != 0);
+    if (res) {
+      *res = jobs[0].res;
+      res->t_coarsen_ns = e.t_coarsen_ns;
+      res->t_initial_ns = e.t_initial_ns;
+      res->t_refine_ns = e.t_refine_ns;
+      res->t_total_ns = e.t_coarsen_ns + e.t_initial_ns + e.t_refine_ns;
+    }
+  });
+}
 
 void lmgp_default_params(lmgp_params* out) {
   if (out) *out = default_params();

@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cmath>
 #include <thread>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 
@@ -152,6 +153,11 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 unsigned long long* pinned_state(size_t n) {
   static thread_local unsigned long long* p = nullptr;
   static thread_local size_t cap = 0;
+  if (no_alloc_mode()) {  // pageable: no page-locked allocation
+    static thread_local std::vector<unsigned long long> v;
+    if (v.size() < n) v.resize(n);
+    return v.data();
+  }
   if (n > cap) {
     if (p) HIP_CHECK(hipHostFree(p));
     p = nullptr;
@@ -1441,6 +1447,7 @@ struct IpHostBuffers {
   uint16_t* adj16 = nullptr;
   int64_t* nw = nullptr;
   size_t cx = 0, ca = 0, ca16 = 0, cn = 0;
+  bool pageable = false;  // plain host memory (allocation-free calls), not pooled
 };
 
 // Neighbour ids of a graph's entries as 16-bit local ids (graphs of at most
@@ -1450,12 +1457,20 @@ __global__ void k_local_u16(const uint32_t* adj, uint64_t m, uint32_t n0, uint16
   if (i < m) out[i] = (uint16_t)(adj[i] - n0);
 }
 template <typename T>
-T* pinned_grow(T*& p, size_t& cap, size_t n) {
+T* pinned_grow(T*& p, size_t& cap, size_t n, bool pageable) {
   if (n > cap) {
-    if (p) HIP_CHECK(hipHostFree(p));
+    if (p) {
+      if (pageable) std::free(p);
+      else HIP_CHECK(hipHostFree(p));
+    }
     p = nullptr;
     cap = 0;
-    HIP_CHECK(hipHostMalloc((void**)&p, (n ? n : 1) * sizeof(T), hipHostMallocDefault));
+    if (pageable) {
+      p = (T*)std::malloc((n ? n : 1) * sizeof(T));
+      if (!p) throw OutOfMemory("host buffer of " + std::to_string(n * sizeof(T)) + " bytes");
+    } else {
+      HIP_CHECK(hipHostMalloc((void**)&p, (n ? n : 1) * sizeof(T), hipHostMallocDefault));
+    }
     cap = n;
   }
   return p;
@@ -1465,6 +1480,11 @@ std::vector<IpHostBuffers*> ip_pool;
 struct IpBuffersLease {
   IpHostBuffers* b;
   IpBuffersLease() {
+    if (no_alloc_mode()) {
+      b = new IpHostBuffers;
+      b->pageable = true;
+      return;
+    }
     std::lock_guard<std::mutex> g(ip_pool_mu);
     if (ip_pool.empty()) {
       b = new IpHostBuffers;
@@ -1474,6 +1494,14 @@ struct IpBuffersLease {
     }
   }
   ~IpBuffersLease() {
+    if (b->pageable) {
+      std::free(b->xadj);
+      std::free(b->adj);
+      std::free(b->adj16);
+      std::free(b->nw);
+      delete b;
+      return;
+    }
     std::lock_guard<std::mutex> g(ip_pool_mu);
     ip_pool.push_back(b);
   }
@@ -1554,8 +1582,8 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     // the first call); ids and offsets stay global, the bisection subtracts
     IpBuffersLease lease;
     IpHostBuffers& hb = *lease.b;
-    uint64_t* hx = pinned_grow(hb.xadj, hb.cx, n1 - n0 + 1);
-    int64_t* hn = pinned_grow(hb.nw, hb.cn, n1 - n0);
+    uint64_t* hx = pinned_grow(hb.xadj, hb.cx, n1 - n0 + 1, hb.pageable);
+    int64_t* hn = pinned_grow(hb.nw, hb.cn, n1 - n0, hb.pageable);
     d2h(hx, L.xadj + n0, n1 - n0 + 1, s_);
     d2h(hn, L.nw + n0, n1 - n0, s_);
     // coarse levels: neighbours in ascending order (the oracle's coarse rows
@@ -1568,13 +1596,13 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
                                                             a16.get());
         LAUNCH_CHECK();
       }
-      uint16_t* ha = pinned_grow(hb.adj16, hb.ca16, e1 - e0);
+      uint16_t* ha = pinned_grow(hb.adj16, hb.ca16, e1 - e0, hb.pageable);
       d2h(ha, a16.get(), e1 - e0, s_);
       sync(s_);
       initial_partition_host<uint16_t>(n1 - n0, hx, ha, hn, e0, 0, L.sorted, asc, jobs[g].k,
                                        jobs[g].seed, top + 1, ip[g]);
     } else {
-      uint32_t* ha = pinned_grow(hb.adj, hb.ca, e1 - e0);
+      uint32_t* ha = pinned_grow(hb.adj, hb.ca, e1 - e0, hb.pageable);
       d2h(ha, L.adj + e0, e1 - e0, s_);
       sync(s_);
       initial_partition_host<uint32_t>(n1 - n0, hx, ha, hn, e0, n0, L.sorted, asc, jobs[g].k,

@@ -2,6 +2,8 @@
 // PyTorch caching allocator, passed through the C ABI) or a stream-ordered
 // caching pool of hipMalloc'd blocks.
 #pragma once
+#include <algorithm>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -14,17 +16,39 @@ namespace lmgp {
 // Zero device memory with a kernel on stream s (graph-capture safe).
 void device_zero(void* p, size_t bytes, hipStream_t s);
 
+// True while the calling thread runs an allocation-free call: host copies
+// then go through pageable memory (no page-locked buffers are allocated).
+bool& no_alloc_mode();
+
+struct NoAllocScope {
+  bool prev;
+  NoAllocScope() : prev(no_alloc_mode()) { no_alloc_mode() = true; }
+  ~NoAllocScope() { no_alloc_mode() = prev; }
+};
+
 class Pool {
  public:
   explicit Pool(const lmgp_allocator* user) {
     if (user) user_ = *user, have_user_ = true;
   }
+  // Arena over caller-provided device memory [base, base + bytes): first-fit
+  // ranges of 256-byte granules, nothing is ever allocated or freed on the
+  // device.  A range freed by the host is handed out again only to later
+  // allocations; all work of one arena is ordered on one stream, so reuse
+  // follows the stream order.
+  Pool(void* base, size_t bytes) : arena_base_((char*)base), arena_bytes_(bytes & ~(size_t)255) {
+    if (arena_bytes_) arena_free_[0] = arena_bytes_;
+  }
   ~Pool() { release(); }
   Pool(const Pool&) = delete;
   Pool& operator=(const Pool&) = delete;
 
+  // Highest arena offset handed out so far (arena mode).
+  size_t arena_high_water() const { return arena_high_; }
+
   void* alloc(size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 1;
+    if (arena_base_) return arena_alloc(bytes);
     if (have_user_) {
       void* p = user_.alloc(user_.ctx, bytes, (void*)s);
       if (!p) throw OutOfMemory("caller allocator returned NULL for " + std::to_string(bytes) + " bytes");
@@ -61,6 +85,10 @@ class Pool {
 
   void free(void* p, hipStream_t s) {
     if (!p) return;
+    if (arena_base_) {
+      arena_release(p);
+      return;
+    }
     if (have_user_) {
       user_.free(user_.ctx, p, (void*)s);
       return;
@@ -89,7 +117,7 @@ class Pool {
   }
 
   void release() {
-    if (have_user_) return;
+    if (have_user_ || arena_base_) return;
     std::lock_guard<std::mutex> g(mu_);
     for (void* p : owned_)
       if (p) (void)hipFree(p);
@@ -99,6 +127,45 @@ class Pool {
   }
 
  private:
+  void* arena_alloc(size_t bytes) {
+    const size_t sz = (bytes + 255) & ~(size_t)255;
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto it = arena_free_.begin(); it != arena_free_.end(); ++it) {
+      if (it->second < sz) continue;
+      const size_t off = it->first, len = it->second;
+      arena_free_.erase(it);
+      if (len > sz) arena_free_[off + sz] = len - sz;
+      arena_used_[off] = sz;
+      arena_high_ = std::max(arena_high_, off + sz);
+      return arena_base_ + off;
+    }
+    throw OutOfMemory("scratch arena of " + std::to_string(arena_bytes_) +
+                      " bytes exhausted (a request of " + std::to_string(sz) + " bytes)");
+  }
+  void arena_release(void* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto u = arena_used_.find((size_t)((char*)p - arena_base_));
+    if (u == arena_used_.end()) return;
+    size_t off = u->first, len = u->second;
+    arena_used_.erase(u);
+    auto next = arena_free_.lower_bound(off);
+    if (next != arena_free_.end() && next->first == off + len) {
+      len += next->second;
+      next = arena_free_.erase(next);
+    }
+    if (next != arena_free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    arena_free_[off] = len;
+  }
+
+  char* arena_base_ = nullptr;
+  size_t arena_bytes_ = 0, arena_high_ = 0;
+  std::map<size_t, size_t> arena_free_, arena_used_;  // offset -> length
   struct Key {
     hipStream_t s;
     size_t sz;

@@ -171,8 +171,13 @@ Stage& stage() {
 }
 }  // namespace
 
+bool& no_alloc_mode() {
+  static thread_local bool on = false;
+  return on;
+}
+
 void* stage_take(size_t bytes) {
-  if (bytes == 0 || bytes > STAGE_MAX_COPY) return nullptr;
+  if (bytes == 0 || bytes > STAGE_MAX_COPY || no_alloc_mode()) return nullptr;
   Stage& st = stage();
   if (!st.buf) HIP_CHECK(hipHostMalloc((void**)&st.buf, STAGE_BYTES, hipHostMallocDefault));
   const size_t off = (st.used + 15) & ~(size_t)15;
