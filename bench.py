@@ -8,7 +8,11 @@ every level and the cut/balance evaluation (one lmgp_partition call).
 
 metric: input edges/s through coarsen+refine = m / (T_coarsen + T_refine),
 with T measured by events on the library's stream (the initial bipartitioning
-and the whole-call wall time are reported beside it).  Prints one JSON line.
+and the whole-call wall time are reported beside it).  The headline workload
+is the largest single-GPU configuration (random geometric graph, n = 2^24);
+the same line carries a record for the Erdos-Renyi graph (n = 2^22), the
+configuration on which sparsification fires on most levels, and the CPU
+oracle timed on the headline graph itself.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -37,27 +41,52 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(sample: str):
-    """The CPU oracle (single-threaded) on a bounded sample of the workload."""
-    import oracle as O
-    from paper_2504_17615_amd import graphgen as gg
-
-    g, k, eps, seed = gg.workload(sample)
-    t0 = time.perf_counter()
-    _, res, times = O.partition(g, k, eps, seed)
-    wall = time.perf_counter() - t0
-    cr = times["coarsen"] + times["refine"]
-    model = None
+def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                         None)
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                        None)
     except OSError:
-        pass
-    return {"value": float(g.m / cr), "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}: same generator recipe at smaller scale (n={g.n}, m={g.m}), "
-                      f"full partition k={k}; coarsen+refine {cr:.2f}s of {wall:.2f}s wall",
-            "cut": res["cut"], "cpu_model": model, "host_cpus": os.cpu_count()}
+        return None
+
+
+def cpu_threads() -> int:
+    """Host threads for the all-cores oracle run: the process's CPU share
+    (OMP_NUM_THREADS when set), at most 16."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env and env.isdigit() else (len(os.sched_getaffinity(0))
+                                                 if hasattr(os, "sched_getaffinity")
+                                                 else os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+def cpu_baseline(g, name: str, k: int, eps: float, seed: int, single: bool = True) -> dict:
+    """The CPU oracle on the timed graph itself: one full partition with all
+    host threads of the process (OpenMP), and optionally one single-threaded.
+    The rate is m / (coarsen + refine), the GPU metric's definition."""
+    import oracle as O
+
+    def run(threads):
+        used = O.set_threads(threads)
+        t0 = time.perf_counter()
+        _, res, times = O.partition(g, k, eps, seed)
+        wall = time.perf_counter() - t0
+        O.set_threads(1)
+        cr = times["coarsen"] + times["refine"]
+        return used, res, cr, wall
+
+    T = cpu_threads()
+    used, res, cr, wall = run(T)
+    out = {"value": float(g.m / cr), "unit": "edges/s", "cores": used, "kind": "oracle",
+           "sample": f"{name} itself (n={g.n}, m={g.m}), one full partition k={k} with "
+                     f"{used} OpenMP threads; coarsen+refine {cr:.2f} s of {wall:.2f} s wall",
+           "cut": res["cut"], "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    if single:
+        _, res1, cr1, wall1 = run(1)
+        out["single_thread"] = {"value": float(g.m / cr1), "cores": 1,
+                                "coarsen_refine_s": round(cr1, 2), "wall_s": round(wall1, 2)}
+        assert res1 == res, "oracle result depends on the thread count"
+    return out
 
 
 def _kernel_of(family: str) -> str:
@@ -122,8 +151,9 @@ def roofline(stats: dict, steps: int, wall: float, workload: str,
         roof["traffic_GBps"] = round(roof["traffic"] / per_launch_ns, 1)
         roof["traffic_frac"] = round(roof["traffic"] / per_launch_ns / HBM_PEAK_GBS, 4)
     bd, bsteps = (stats, steps) if breakdown is None else (breakdown, 1)
-    tot = sum(s["total_ns"] for s in bd.values())
-    tb = sum(s["bytes"] for s in bd.values())
+    rating = {k: v for k, v in bd.items() if "rate" in k and v["total_ns"]}
+    tot = max(1, sum(s["total_ns"] for s in rating.values()))
+    tb = sum(s["bytes"] for s in rating.values())
     roof["lp_rate_all"] = {"achieved": round(tb / tot, 1),
                            "frac": round(tb / tot / HBM_PEAK_GBS, 4),
                            "share_of_step": round(tot / bsteps / 1e9 / wall, 3)}
@@ -136,11 +166,44 @@ def roofline(stats: dict, steps: int, wall: float, workload: str,
                 for nm, s in sorted(d.items(), key=lambda kv: -kv[1]["total_ns"])}
 
     if breakdown is not None:
-        roof["breakdown_from"] = "last warm-up step, every rating launch timed"
+        roof["breakdown_from"] = "last warm-up step, every profiled launch timed"
         steps = 1
     roof["kernels"] = summary(_per_kernel(bd))
     roof["families"] = summary(bd)
     return roof
+
+
+COARSEN_PHASES = ("cl", "fv", "ct", "sp")  # clustering, 2-hop, contraction, sparsification
+
+
+def phase_figures(bd: dict, wall: float) -> dict:
+    """From a profiled step's families ('<phase>:<kernel or step>'): the
+    dominant family of the coarsening phases and of refinement, each with
+    its algorithmic rate against the HBM peak, and the whole profiled step
+    (every family with bytes) as one algorithmic rate."""
+    fam = {k: v for k, v in bd.items() if v["total_ns"] and v["bytes"]}
+
+    def best(pred):
+        c = {k: v for k, v in fam.items() if pred(k.split(":", 1)[0])}
+        if not c:
+            return None
+        k, v = max(c.items(), key=lambda kv: kv[1]["total_ns"])
+        gbs = v["bytes"] / v["total_ns"]
+        return {"family": k, "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "ms_per_step": round(v["total_ns"] / 1e6, 3), "launches": v["launches"]}
+
+    tot_ns = sum(v["total_ns"] for v in fam.values())
+    tot_b = sum(v["bytes"] for v in fam.values())
+    syncs = bd.get("host:stream_syncs", {}).get("launches")
+    return {
+        "coarsen_dominant": best(lambda ph: ph in COARSEN_PHASES),
+        "refine_dominant": best(lambda ph: ph == "rf"),
+        "step_algorithmic": {"achieved": round(tot_b / max(1, tot_ns), 1),
+                             "frac": round(tot_b / max(1, tot_ns) / HBM_PEAK_GBS, 4),
+                             "covered_ms": round(tot_ns / 1e6, 3),
+                             "share_of_step": round(tot_ns / 1e9 / wall, 3)},
+        "host_syncs_per_call": syncs,
+    }
 
 
 def copy_calibration(mib: int):
@@ -434,9 +497,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", default="rmat20")
+    ap.add_argument("--workload", default="rgg24", choices=sorted(WORKLOADS))
+    ap.add_argument("--also", default="er22", choices=sorted(WORKLOADS) + ["none"],
+                    help="second workload reported in the same line (default: the graph on "
+                         "which sparsification fires)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-single", action="store_true",
+                    help="skip the single-threaded oracle run (the all-cores one stays)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="launch one plain copy of this size first (counter calibration)")
@@ -475,27 +542,64 @@ def main():
     import torch
 
     import paper_2504_17615_amd as L
-    from paper_2504_17615_amd import graphgen as gg
 
     L.library()
     if args.copy_calib_mib:
         copy_calibration(args.copy_calib_mib)
-    t_gen = time.perf_counter()
-    g, k, eps, seed = gg.workload(args.workload)
-    t_gen = time.perf_counter() - t_gen
-    m = g.m
-    dev = L.create_graph(g)
-    del g
-    out = torch.empty(dev.n, dtype=torch.int32, device="cuda")
     tune = {"off": 0, "auto": 1}.get(args.tune)
     prm = L.default_params(tune=16 + int(args.tune) if tune is None else tune,
                            graph_rounds=args.graph_rounds, ip_device=args.ip_device)
-    # The last warm-up call times every rating launch (the per-kernel
-    # breakdown); of the timed calls, the last one times the dominant kernel
-    # only, so that event timing slows the measured steps as little as it can.
+    head, g = run_workload(L, torch, args.workload, args.steps, args.warmup, prm, args)
+    line = {
+        "metric": "input edges/s through coarsen+refine",
+        "value": head["value"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": dict(head["config"], parallelism="single GPU", tune=args.tune,
+                       graph_rounds=args.graph_rounds, ip_device=args.ip_device),
+    }
+    for f in ("phases_ms", "wall_edges_per_s", "cut", "max_block_weight", "lmax", "levels",
+              "hierarchy", "roofline", "phase_roofline", "gen_s"):
+        line[f] = head[f]
+    if args.also != "none" and args.also != args.workload:
+        also, g2 = run_workload(L, torch, args.also, max(2, args.steps // 2), args.warmup, prm,
+                                args)
+        del g2
+        line[args.also] = also
+    cpu = None
+    if not args.no_cpu_baseline:
+        k, eps, seed = head["config"]["k"], head["config"]["eps"], head["config"]["seed"]
+        cpu = cpu_baseline(g, args.workload, k, eps, seed, single=not args.no_cpu_single)
+    line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def run_workload(L, torch, name, steps, warmup, prm, args):
+    """Warm-up calls (the last one times every profiled launch: the
+    breakdown), then `steps` timed calls of which the last event-times every
+    launch of the dominant kernel.  Returns (record, host graph)."""
+    from paper_2504_17615_amd import graphgen as gg
+
+    t_gen = time.perf_counter()
+    g, k, eps, seed = gg.workload(name)
+    t_gen = time.perf_counter() - t_gen
+    m = g.m
+    dev = L.create_graph(g)
+    out = torch.empty(dev.n, dtype=torch.int32, device="cuda")
+    h = dev.coarsen(k, seed, prm)
+    hier = [h.info(i) for i in range(h.levels)]
+    h.close()
     breakdown = None
-    for i in range(args.warmup):
-        last = i == args.warmup - 1 and not args.no_profile
+    for i in range(warmup):
+        last = i == warmup - 1 and not args.no_profile
         if last:
             L.profile_filter(None)
             L.profile_read(reset=True)
@@ -512,10 +616,10 @@ def main():
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         # every launch of the dominant kernel in the last timed step is
         # event-timed (the timing's own cost stays out of the other steps)
-        if not args.no_profile and i == args.steps - 1:
+        if not args.no_profile and i == steps - 1:
             L.profile_enable(True)
         _, res = dev.partition(k, eps, seed, prm, out=out)
         results.append(res)
@@ -526,45 +630,33 @@ def main():
         L.profile_enable(False)
         stats = L.profile_read(reset=True)
         L.profile_filter(None)
-    K = args.steps
-    wall = (t1 - t0) / K
-    cr = sum(r["t_coarsen_ns"] + r["t_refine_ns"] for r in results) / K * 1e-9
-    ph = {p: sum(r[f"t_{p}_ns"] for r in results) / K * 1e-6 for p in ("coarsen", "initial",
-                                                                       "refine")}
-    roof = None
-    if stats:
-        roof = roofline(stats, K, wall, args.workload, breakdown)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_sample)
-    line = {
-        "metric": "input edges/s through coarsen+refine",
+    dev.close()
+    del out
+    torch.cuda.empty_cache()
+    wall = (t1 - t0) / steps
+    cr = sum(r["t_coarsen_ns"] + r["t_refine_ns"] for r in results) / steps * 1e-9
+    ph = {p: sum(r[f"t_{p}_ns"] for r in results) / steps * 1e-6
+          for p in ("coarsen", "initial", "refine")}
+    rec = {
         "value": m / cr,
-        "unit": "edges/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
         "ms_per_step": wall * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
-                   "n": dev.n, "m": m, "k": k, "eps": eps, "seed": seed,
-                   "parallelism": "single GPU", "tune": args.tune,
-                   "graph_rounds": args.graph_rounds, "ip_device": args.ip_device},
+        "steps": steps,
+        "config": {"workload": name, "description": WORKLOADS[name], "n": g.n, "m": m, "k": k,
+                   "eps": eps, "seed": seed},
         "phases_ms": {p: round(v, 3) for p, v in ph.items()},
         "wall_edges_per_s": m / wall,
         "cut": results[-1]["cut"],
         "max_block_weight": results[-1]["max_block_weight"],
         "lmax": results[-1]["lmax"],
         "levels": results[-1]["levels"],
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        "hierarchy": {"m": [x["m"] for x in hier], "n": [x["n"] for x in hier],
+                      "triggered": [x["triggered"] for x in hier],
+                      "edges_ratio": round(sum(x["m"] for x in hier) / max(1, hier[0]["m"]), 3)},
+        "roofline": roofline(stats, steps, wall, name, breakdown) if stats else None,
+        "phase_roofline": phase_figures(breakdown, wall) if breakdown else None,
         "gen_s": round(t_gen, 2),
     }
-    print(json.dumps(line), flush=True)
+    return rec, g
 
 
 if __name__ == "__main__":

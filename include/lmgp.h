@@ -171,6 +171,9 @@ typedef struct {
                                  above that runs alone)                             */
   uint32_t streams;           /* concurrent device streams (worker threads)         */
   uint32_t ip_device;         /* lmgp_params.ip_device of every batched run          */
+  uint32_t join_runs;         /* 1: a request that finds every stream busy joins a
+                                 run still coarsening at its next level (requests
+                                 with sorted rows and the run's parameters)        */
 } lmgp_server_cfg;
 
 void lmgp_default_params(lmgp_params *out);
@@ -264,10 +267,32 @@ lmgp_status lmgp_server_create(const lmgp_server_cfg *cfg, const lmgp_allocator 
  * exceeds the whole budget. */
 lmgp_status lmgp_server_submit(lmgp_server *s, lmgp_graph *g, uint32_t k, double eps,
                                uint64_t seed, uint32_t *block_out, uint64_t *ticket);
+/* As lmgp_server_submit, with the request's own parameters (NULL =
+ * defaults; params.ip_device is taken from the server configuration).  Only
+ * requests with identical parameters share a batched run.  EINVAL for
+ * invalid parameters. */
+lmgp_status lmgp_server_submit_params(lmgp_server *s, lmgp_graph *g, uint32_t k, double eps,
+                                      uint64_t seed, const lmgp_params *params,
+                                      uint32_t *block_out, uint64_t *ticket);
 /* ENOTREADY until the request is done; then fills res (latency fields:
  * t_total_ns = submit-to-completion). */
 lmgp_status lmgp_server_poll(lmgp_server *s, uint64_t ticket, lmgp_result *res);
 lmgp_status lmgp_server_wait(lmgp_server *s, uint64_t ticket, lmgp_result *res);
+/* Counters of a server since its creation.  peak_pool_bytes is the largest
+ * device memory in use by one worker's run (library pool; 0 with a caller
+ * allocator), beside the largest summed footprint estimate of the resident
+ * requests that admission used. */
+typedef struct {
+  uint64_t completed;              /* requests finished (including failed)        */
+  uint64_t failed;                 /* requests finished with an error             */
+  uint64_t runs;                   /* batched runs started                        */
+  uint64_t max_run_requests;       /* largest number of requests in one run       */
+  uint64_t retried_alone;          /* requests re-run alone after a run's ENOMEM  */
+  uint64_t joined;                 /* requests that joined a run in flight        */
+  uint64_t peak_resident_estimate; /* bytes, admission's summed estimate          */
+  uint64_t peak_pool_bytes;        /* bytes, measured peak in use of one worker   */
+} lmgp_server_stats;
+lmgp_status lmgp_server_stats_read(lmgp_server *s, lmgp_server_stats *out);
 void lmgp_server_destroy(lmgp_server *s);
 
 /* Measurement support.  When enabled (process-wide), launches of the main

@@ -61,6 +61,7 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     vp, u64, u32, i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64
     sig = {
+        "or_set_threads": ([ctypes.c_int], ctypes.c_int),
         "or_hash": ([u64, u64, u32, vp], u64),
         "or_mix": ([u64], u64),
         "or_default_params": ([vp], None),
@@ -139,6 +140,12 @@ def params(**kw) -> Params:
     for k, v in kw.items():
         setattr(p, k, v)
     return p
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel steps (1 = single-threaded, the
+    default); returns the number in effect."""
+    return int(_load().or_set_threads(int(n)))
 
 
 def H(seed: int, tag: int, *xs: int) -> int:

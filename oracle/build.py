@@ -9,7 +9,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build() -> str:
     tmp = LIB + ".tmp"
-    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", SRC, "-o", tmp]
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", SRC,
+           "-o", tmp]
     print("+", " ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)

@@ -5,9 +5,14 @@
 // this file; only the tests, the smoke check and the benchmark's CPU-baseline
 // leg do.  It shares no code, header, table or helper with the GPU library.
 //
-// It is deliberately plain and slow: single-threaded, std::sort /
-// std::nth_element as the only library steps, every quantity recomputed from
-// its definition.  It follows the paper's steps in the paper's order:
+// It is deliberately plain and slow: std::sort / std::nth_element as the only
+// library steps, every quantity recomputed from its definition.  It runs
+// single-threaded unless or_set_threads asks for more: then the per-node
+// rating pass of label propagation, the rows of a contraction and the cut sum
+// are spread over OpenMP threads.  Every parallel step only reads state fixed
+// before it and its outputs are merged in a fixed order (or sorted by a total
+// order), so results do not depend on the thread count.  It follows the
+// paper's steps in the paper's order:
 //
 //   * size-constrained label propagation (Sec. 3, KaMinPar paragraph; the
 //     clustering rule of Sec. 4.1), with the cluster weight limit
@@ -40,7 +45,21 @@
 #include <initializer_list>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
+
+int g_threads = 1;  // OpenMP threads of the parallel steps (1 = plain loops)
+
+int thread_id() {
+#ifdef _OPENMP
+  return omp_get_thread_num();
+#else
+  return 0;
+#endif
+}
 
 typedef unsigned __int128 u128;
 
@@ -198,8 +217,10 @@ uint32_t subround_of(uint64_t seed, uint64_t tag, uint64_t level, uint64_t r, ui
 uint32_t label_propagation(const Graph& g, std::vector<uint32_t>& label, std::vector<int64_t>& W,
                            const LpSetup& cfg, uint64_t* moves_total) {
   const uint64_t n = g.n;
-  std::vector<int64_t> rating(W.size(), 0);
-  std::vector<uint32_t> touched;
+  const int T = g_threads;
+  std::vector<std::vector<int64_t>> ratings(T, std::vector<int64_t>(W.size(), 0));
+  std::vector<std::vector<uint32_t>> touch(T);
+  std::vector<std::vector<Cand>> tcands(T);
   uint64_t moves = 0;
   uint32_t rounds_run = 0;
   bool stop = false;
@@ -207,9 +228,12 @@ uint32_t label_propagation(const Graph& g, std::vector<uint32_t>& label, std::ve
     rounds_run = r + 1;
     uint64_t moved_this_round = 0;
     for (uint32_t s = 0; s < cfg.subrounds && !stop; ++s) {
-      // --- rating phase: state frozen at the start of the sub-round
-      std::vector<Cand> cands;
+      // --- rating phase: state frozen at the start of the sub-round; each
+      // thread rates its share of the nodes into its own table
+#pragma omp parallel for num_threads(T) schedule(dynamic, 1024)
       for (uint64_t u = 0; u < n; ++u) {
+        std::vector<int64_t>& rating = ratings[thread_id()];
+        std::vector<uint32_t>& touched = touch[thread_id()];
         if (g.deg(u) == 0) continue;
         if (subround_of(cfg.seed, cfg.tag_sub, cfg.level, r, u, cfg.subrounds) != s) continue;
         touched.clear();
@@ -242,9 +266,14 @@ uint32_t label_propagation(const Graph& g, std::vector<uint32_t>& label, std::ve
         }
         if (have && best_r > r_own) {
           uint32_t hadm = (uint32_t)(H(cfg.seed, cfg.tag_adm, {cfg.level, (uint64_t)r, u}) >> 32);
-          cands.push_back({(uint32_t)u, best, best_r - r_own, hadm});
+          tcands[thread_id()].push_back({(uint32_t)u, best, best_r - r_own, hadm});
         }
         for (uint32_t K : touched) rating[K] = 0;
+      }
+      std::vector<Cand> cands;
+      for (auto& tc : tcands) {
+        cands.insert(cands.end(), tc.begin(), tc.end());
+        tc.clear();
       }
       // --- admission: per target, the longest prefix of (gain desc, hadm asc,
       // u asc) order with W_start(K) + sum c <= cap (departures not credited)
@@ -420,28 +449,42 @@ Graph contract(const Graph& g, const std::vector<uint32_t>& label, std::vector<u
     std::vector<uint64_t> fill(mstart.begin(), mstart.end() - 1);
     for (uint64_t u = 0; u < n; ++u) members[fill[map[u]]++] = (uint32_t)u;
   }
-  c.xadj.assign(nc + 1, 0);
-  std::vector<std::pair<uint32_t, int64_t>> row;
-  for (uint64_t x = 0; x < nc; ++x) {
-    row.clear();
-    for (uint64_t i = mstart[x]; i < mstart[x + 1]; ++i) {
-      uint32_t u = members[i];
-      for (uint64_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e) {
-        uint32_t y = map[g.adj[e]];
-        if (y != x) row.push_back({y, g.ew[e]});
+  // coarse rows in T contiguous ranges of x, each range built by one thread
+  // into its own arrays, joined in range order
+  const int T = g_threads;
+  std::vector<std::vector<uint32_t>> radj(T);
+  std::vector<std::vector<int64_t>> rew(T);
+  std::vector<uint64_t> rowlen(nc, 0);
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+  for (int t = 0; t < T; ++t) {
+    std::vector<std::pair<uint32_t, int64_t>> row;
+    for (uint64_t x = nc * t / T; x < nc * (t + 1) / T; ++x) {
+      row.clear();
+      for (uint64_t i = mstart[x]; i < mstart[x + 1]; ++i) {
+        uint32_t u = members[i];
+        for (uint64_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e) {
+          uint32_t y = map[g.adj[e]];
+          if (y != x) row.push_back({y, g.ew[e]});
+        }
+      }
+      std::sort(row.begin(), row.end(),
+                [](const auto& a, const auto& b) { return a.first < b.first; });
+      for (size_t i = 0; i < row.size();) {
+        size_t j = i;
+        int64_t w = 0;
+        while (j < row.size() && row[j].first == row[i].first) w += row[j++].second;
+        radj[t].push_back(row[i].first);
+        rew[t].push_back(w);
+        rowlen[x]++;
+        i = j;
       }
     }
-    std::sort(row.begin(), row.end(),
-              [](const auto& a, const auto& b) { return a.first < b.first; });
-    for (size_t i = 0; i < row.size();) {
-      size_t j = i;
-      int64_t w = 0;
-      while (j < row.size() && row[j].first == row[i].first) w += row[j++].second;
-      c.adj.push_back(row[i].first);
-      c.ew.push_back(w);
-      i = j;
-    }
-    c.xadj[x + 1] = c.adj.size();
+  }
+  c.xadj.assign(nc + 1, 0);
+  for (uint64_t x = 0; x < nc; ++x) c.xadj[x + 1] = c.xadj[x] + rowlen[x];
+  for (int t = 0; t < T; ++t) {
+    c.adj.insert(c.adj.end(), radj[t].begin(), radj[t].end());
+    c.ew.insert(c.ew.end(), rew[t].begin(), rew[t].end());
   }
   return c;
 }
@@ -751,6 +794,7 @@ int64_t balance_limit(int64_t cV, uint32_t k, double eps) {
 void evaluate(const Graph& g, const std::vector<uint32_t>& block, uint32_t k, int64_t* cut,
               int64_t* maxbw) {
   int64_t c = 0;
+#pragma omp parallel for num_threads(g_threads) reduction(+ : c)
   for (uint64_t u = 0; u < g.n; ++u)
     for (uint64_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e)
       if (u < g.adj[e] && block[u] != block[g.adj[e]]) c += g.ew[e];
@@ -769,6 +813,18 @@ struct Handle {
 
 // =========================================================== C interface ===
 extern "C" {
+
+// Threads of the parallel steps (1 = single-threaded, the default); returns
+// the number in effect (1 when built without OpenMP).
+int or_set_threads(int threads) {
+#ifdef _OPENMP
+  g_threads = threads < 1 ? 1 : threads;
+#else
+  (void)threads;
+  g_threads = 1;
+#endif
+  return g_threads;
+}
 
 uint64_t or_hash(uint64_t seed, uint64_t tag, uint32_t nx, const uint64_t* xs) {
   uint64_t s = mix(seed);

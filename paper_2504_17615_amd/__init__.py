@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     LevelInfo,
     Result,
     ServerConfig,
+    ServerStats,
     DeviceGraph,
     Hierarchy,
     Server,

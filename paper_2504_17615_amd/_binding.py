@@ -72,7 +72,16 @@ class Result(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("streams", ctypes.c_uint32),
-                ("ip_device", ctypes.c_uint32)]
+                ("ip_device", ctypes.c_uint32), ("join_runs", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(nm, ctypes.c_uint64) for nm in (
+        "completed", "failed", "runs", "max_run_requests", "retried_alone", "joined",
+        "peak_resident_estimate", "peak_pool_bytes")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 _SIGS = {
@@ -101,6 +110,10 @@ _SIGS = {
     "lmgp_server_create": ([ctypes.c_void_p] * 3, ctypes.c_int),
     "lmgp_server_submit": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_double,
                             ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "lmgp_server_submit_params": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "lmgp_server_stats_read": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "lmgp_server_poll": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "lmgp_server_wait": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p], ctypes.c_int),
     "lmgp_server_destroy": ([ctypes.c_void_p], None),
@@ -405,20 +418,32 @@ class Server:
     """Serving loop: submit partition requests, poll or wait for results."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, max_batch: int = 32,
-                 streams: int = 4, ip_device: int = 2):
-        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_batch, streams, ip_device)
+                 streams: int = 4, ip_device: int = 2, join_runs: bool = True):
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, max_batch, streams, ip_device,
+                           1 if join_runs else 0)
         h = ctypes.c_void_p()
         _check(library().lmgp_server_create(ctypes.byref(cfg), None, ctypes.byref(h)))
         self._h = h
         self._pending = {}
 
-    def submit(self, graph: DeviceGraph, k: int, eps: float = 0.03, seed: int = 1) -> int:
+    def submit(self, graph: DeviceGraph, k: int, eps: float = 0.03, seed: int = 1,
+               params: Optional[Params] = None) -> int:
         out = np.empty(graph.n, np.uint32)
         t = ctypes.c_uint64()
-        _check(library().lmgp_server_submit(self._h, graph.handle, k, eps, seed,
-                                            out.ctypes.data, ctypes.byref(t)))
+        if params is None:
+            _check(library().lmgp_server_submit(self._h, graph.handle, k, eps, seed,
+                                                out.ctypes.data, ctypes.byref(t)))
+        else:
+            _check(library().lmgp_server_submit_params(self._h, graph.handle, k, eps, seed,
+                                                       ctypes.byref(params), out.ctypes.data,
+                                                       ctypes.byref(t)))
         self._pending[int(t.value)] = (out, graph)
         return int(t.value)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(library().lmgp_server_stats_read(self._h, ctypes.byref(st)))
+        return st.as_dict()
 
     def poll(self, ticket: int):
         r = Result()

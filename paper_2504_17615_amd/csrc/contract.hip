@@ -19,6 +19,7 @@
 #include <cstring>
 
 #include "contract.h"
+#include "profiler.h"
 
 namespace lmgp {
 
@@ -954,7 +955,6 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
         if (!overflow) {
           k_rows_range_finish<<<rc[2], 256, 0, s>>>(a, listC, rowfill.get());
           LAUNCH_CHECK();
-          HIP_CHECK(hipStreamSynchronize(s));  // keep scratch alive until done
           return;
         }
         // a range did not fit: sort these rows instead (overwrites them)
@@ -972,7 +972,6 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
       LAUNCH_CHECK();
       k_rows_finish<<<rc[2], 256, 0, s>>>(a, listC, rc[2], goff.get(), hpos.get());
       LAUNCH_CHECK();
-      HIP_CHECK(hipStreamSynchronize(s));  // keep scratch alive until done
     }
   };
   switch (ew_kind) {
@@ -987,7 +986,10 @@ void build_rows(const ContractArgs& a, uint64_t nc, int packed, bool sorted, int
 void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStream_t s) {
   const uint64_t n = in.n;
   const unsigned gn = grid_for(n, 256);
-  // coarse ids
+  const uint64_t bw = in.ew_kind == EW_UNIT ? 0 : in.ew_kind == EW_I32 ? 4 : 8;
+  // coarse ids: label read and counted, flags scanned, map written, cluster
+  // weights gathered (per node 4 + 4 + 8 + 4 + 4 + 8 B)
+  ProfScope prof_remap("ct:remap", 32 * n, s);
   DBuf<uint32_t> lcount(&pool, s, n ? n : 1);
   lcount.zero();
   k_label_count<<<gn, 256, 0, s>>>(in.label, in.gid, in.keep, n, lcount.get());
@@ -1021,7 +1023,11 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   }
   cid.clear();
   lcount.clear();
-  // members and degree sums
+  prof_remap.add_bytes(24 * nc);  // coarse weights, counts, graph ids
+  prof_remap.end();
+  // members and degree sums: per node its map entry and two offsets read, its
+  // member slot written; per coarse node offsets and sums
+  ProfScope prof_members("ct:members", 24 * n + 24 * nc, s);
   DBuf<uint64_t> mstart(&pool, s, nc + 1);
   exclusive_scan(U32At{ccount.get()}, nc, mstart.get(), true, pool, s);
   ccount.clear();
@@ -1052,6 +1058,11 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   a.tw = tw.get();
   a.tsrc = tsrc.get();
   a.ndist = ndist.get();
+  prof_members.end();
+  // rows: every member entry's neighbour, its map entry and weight read; the
+  // distinct neighbours written to scratch (id, weight, row) and counted
+  const uint64_t fine_entries = mt;
+  ProfScope prof_rows("ct:rows", (8 + bw) * fine_entries + 8 * n + 16 * nc, s);
   build_rows(a, nc, in.packed, in.sorted, in.ew_kind, pool, s);
   // coarse CSR
   out.xadj.reset(&pool, s, nc + 1);
@@ -1059,6 +1070,11 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   uint64_t mc = 0;
   read_now(&mc, out.xadj.get() + nc, sizeof(uint64_t), s);
   out.nnz = mc;
+  prof_rows.add_bytes(16 * mc);
+  prof_rows.end();
+  // copy: scratch entries read (id, weight, row), coarse adjacency, weight and
+  // row written
+  ProfScope prof_copy("ct:copy", (16 + 8 + (in.narrow ? 4 : 8)) * mc + 8 * nc, s);
   out.adj.reset(&pool, s, mc ? mc : 1);
   out.src.reset(&pool, s, mc ? mc : 1);
   out.ew_kind = in.narrow ? EW_I32 : EW_I64;
@@ -1073,7 +1089,8 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
                                                              out.src.get(), out.xadj.get());
     LAUNCH_CHECK();
   }
-  HIP_CHECK(hipStreamSynchronize(s));
+  // no wait here: scratch freed on return goes back to a stream-ordered pool
+  // (reused only by later work on this stream)
 }
 
 namespace {
@@ -1118,7 +1135,6 @@ void sort_rows(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* a
   a.tsrc = out_src.get();
   a.ndist = ndist.get();
   build_rows(a, n, packed, true, ew_kind, pool, s);
-  HIP_CHECK(hipStreamSynchronize(s));
 }
 
 }  // namespace lmgp

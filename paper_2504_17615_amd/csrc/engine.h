@@ -1,5 +1,6 @@
 // Host orchestration of the multilevel pipeline on one GPU.
 #pragma once
+#include <functional>
 #include <memory>
 #include <vector>
 
@@ -66,6 +67,11 @@ struct Job {
   int64_t U = 1;
   int64_t lmax = 0;
   uint32_t nlevels = 1;  // levels of this graph's hierarchy
+  // Union level holding this graph's input: 0, or the depth at which the
+  // graph joined a run already in flight.  Its own level i (1-based, the
+  // index every hash uses) is union level d0 + i - 1.
+  uint32_t d0 = 0;
+  uint32_t top() const { return d0 + nlevels - 1; }  // union level of its coarsest graph
   std::vector<lmgp_level_info> info;
   std::vector<uint32_t> block;  // host copy of the final blocks (when requested)
   lmgp_result res{};
@@ -77,6 +83,14 @@ class Engine {
   ~Engine();
   // Builds the hierarchy for all jobs (one union).
   void coarsen(std::vector<Job>& jobs);
+  // Optional: asked before every level after the first; the jobs it returns
+  // join the run, their input graphs appended to the union level about to be
+  // clustered (each must pass can_join).  coarsen appends them to `jobs`.
+  std::function<std::vector<Job>()> admit;
+  // Whether a graph may join this run in flight: rows sorted (its input level
+  // then needs no order of its own) and edge weights within the widths the run
+  // stores (packed ratings, narrow coarse weights).
+  bool can_join(const InputGraph& g) const;
   // Initial partitioning, refinement and evaluation; writes blocks.
   void partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool on_device);
   std::vector<std::unique_ptr<Level>>& levels() { return levels_; }
@@ -99,10 +113,14 @@ class Engine {
               uint32_t* label, int64_t* W, size_t nlabels, uint32_t* csize,
               const std::vector<uint64_t>& label_base, std::vector<uint64_t>* ncl,
               std::vector<uint32_t>& rounds_run);
+  void finish_level(std::vector<Job>& jobs, size_t j, const uint32_t* block,
+                    const std::vector<uint64_t>& kbase, uint32_t* const* block_out,
+                    bool on_device);
   void two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t>& which,
                uint32_t level, uint32_t* label, int64_t* W, uint32_t* csize,
                std::vector<uint64_t>& ncl);
   void build_union(std::vector<Job>& jobs);
+  void extend_union(std::vector<Job>& jobs, size_t first);
   void narrow_weights(Level& L);
   void rate_classes(RateArgs ra, const uint32_t* cnt, const uint32_t* offs,
                     const unsigned long long* degs, int ew_kind);

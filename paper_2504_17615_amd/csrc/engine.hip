@@ -63,6 +63,7 @@ void d2h(T* dst, const T* src, size_t n, hipStream_t s) {
   if (p) pending_reads().push_back(PendingRead{dst, p, bytes});
 }
 void sync(hipStream_t s) {
+  Profiler::get().count("host:stream_syncs");
   HIP_CHECK(hipStreamSynchronize(s));
   for (const PendingRead& r : pending_reads()) std::memcpy(r.dst, r.src, r.bytes);
   pending_reads().clear();
@@ -433,6 +434,40 @@ __global__ void k_union_src(const UnionPart* parts, const uint32_t* const* srcs,
   src[e] = (uint32_t)(parts[g].nbase + srcs[g][e - parts[g].ebase]);
 }
 
+// Extension of a union level by graphs that join a run in flight: part 0 is
+// the level itself (its graph ids kept), parts 1.. are input graphs (graph id
+// B0 + part - 1); entry weights converted to the level's stored type WT.
+__global__ void k_extend_nodes(const UnionPart* parts, const uint64_t* nb, uint32_t P, uint64_t n,
+                               const uint32_t* gid0, uint32_t B0, uint64_t* xadj, int64_t* nw,
+                               uint32_t* gid) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t p = find_part(nb, P, i);
+  const UnionPart pt = parts[p];
+  const uint64_t li = i - pt.nbase;
+  xadj[i] = pt.ebase + pt.xadj[li];
+  nw[i] = pt.nw[li];
+  gid[i] = p == 0 ? (gid0 ? gid0[li] : 0u) : B0 + p - 1;
+  if (i == n - 1) xadj[n] = pt.ebase + pt.xadj[li + 1];
+}
+
+template <typename WT>
+__global__ void k_extend_entries(const UnionPart* parts, const uint32_t* const* srcs,
+                                 const uint64_t* eb, uint32_t P, uint64_t nnz, uint32_t* adj,
+                                 WT* ew, uint32_t* src) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t p = find_part(eb, P, e);
+  const UnionPart pt = parts[p];
+  const uint64_t le = e - pt.ebase;
+  adj[e] = (uint32_t)(pt.nbase + pt.adj[le]);
+  src[e] = (uint32_t)(pt.nbase + srcs[p][le]);
+  int64_t w = 1;
+  if (pt.ew_kind == EW_I32) w = ((const int32_t*)pt.ew)[le];
+  else if (pt.ew_kind == EW_I64) w = ((const int64_t*)pt.ew)[le];
+  ew[e] = (WT)w;
+}
+
 class Timer {
  public:
   explicit Timer(hipStream_t s) : s_(s) {
@@ -584,6 +619,96 @@ void Engine::build_union(std::vector<Job>& jobs) {
   levels_.push_back(std::move(L));
 }
 
+bool Engine::can_join(const InputGraph& g) const {
+  if (!g.rows_sorted || g.n == 0) return false;
+  if (packed_ && !(g.wtot < (1ull << 32) && g.nnz < (1ull << 32))) return false;
+  if (narrow_ && !(g.wtot < (1ull << 31))) return false;
+  return true;
+}
+
+// The jobs [first, jobs.size()) join at the current top union level: a new
+// level made of the current one (ids unchanged, so the finer level's map
+// stays valid) followed by their input graphs replaces it.
+void Engine::extend_union(std::vector<Job>& jobs, size_t first) {
+  Level& L = *levels_.back();
+  const uint32_t B0 = (uint32_t)L.graphs.size();
+  const uint32_t Bn = (uint32_t)(jobs.size() - first);
+  const uint32_t P = 1 + Bn;
+  const uint32_t d = (uint32_t)levels_.size() - 1;
+  auto N = std::make_unique<Level>();
+  N->sorted = L.sorted;  // joined inputs have sorted rows (can_join)
+  N->graphs = L.graphs;
+  N->nbase = L.nbase;
+  N->ebase = L.ebase;
+  std::vector<UnionPart> parts(P);
+  std::vector<const uint32_t*> srcs(P);
+  std::vector<uint64_t> pnb(P + 1, 0), peb(P + 1, 0);
+  parts[0] = UnionPart{L.xadj, L.adj, L.ew, L.ew_kind, L.nw, 0, 0, L.n, L.nnz};
+  srcs[0] = L.src;
+  pnb[1] = L.n;
+  peb[1] = L.nnz;
+  for (uint32_t q = 0; q < Bn; ++q) {
+    Job& jb = jobs[first + q];
+    const InputGraph& g = *jb.g;
+    jb.d0 = d;
+    jb.nlevels = 1;
+    jb.info.clear();
+    lmgp_level_info i0{};
+    i0.n = g.n;
+    i0.m = g.nnz / 2;
+    i0.m_prime = i0.m;
+    jb.info.push_back(i0);
+    parts[1 + q] = UnionPart{g.xadj.get(), g.adj.get(), g.ew(), g.ew_kind, g.nw.get(),
+                             pnb[1 + q], peb[1 + q], g.n, g.nnz};
+    srcs[1 + q] = g.src.get();
+    pnb[2 + q] = pnb[1 + q] + g.n;
+    peb[2 + q] = peb[1 + q] + g.nnz;
+    N->graphs.push_back((uint32_t)(first + q));
+    N->nbase.push_back(pnb[2 + q]);
+    N->ebase.push_back(peb[2 + q]);
+  }
+  N->n = pnb[P];
+  N->nnz = peb[P];
+  DBuf<UnionPart> dparts(&pool_, s_, P);
+  DBuf<const uint32_t*> dsrcs(&pool_, s_, P);
+  DBuf<uint64_t> dnb(&pool_, s_, P + 1), deb(&pool_, s_, P + 1);
+  h2d(dparts.get(), parts.data(), P, s_);
+  h2d(dsrcs.get(), srcs.data(), P, s_);
+  h2d(dnb.get(), pnb.data(), P + 1, s_);
+  h2d(deb.get(), peb.data(), P + 1, s_);
+  N->o_xadj.reset(&pool_, s_, N->n + 1);
+  N->o_nw.reset(&pool_, s_, N->n ? N->n : 1);
+  N->o_gid.reset(&pool_, s_, N->n ? N->n : 1);
+  N->o_adj.reset(&pool_, s_, N->nnz ? N->nnz : 1);
+  N->o_src.reset(&pool_, s_, N->nnz ? N->nnz : 1);
+  if (narrow_) N->o_ew32.reset(&pool_, s_, N->nnz ? N->nnz : 1);
+  else N->o_ew.reset(&pool_, s_, N->nnz ? N->nnz : 1);
+  k_extend_nodes<<<grid_for(N->n, 256), 256, 0, s_>>>(dparts.get(), dnb.get(), P, N->n, L.gid, B0,
+                                                      N->o_xadj.get(), N->o_nw.get(),
+                                                      N->o_gid.get());
+  LAUNCH_CHECK();
+  if (N->nnz) {
+    if (narrow_)
+      k_extend_entries<int32_t><<<grid_for(N->nnz, 256), 256, 0, s_>>>(
+          dparts.get(), dsrcs.get(), deb.get(), P, N->nnz, N->o_adj.get(), N->o_ew32.get(),
+          N->o_src.get());
+    else
+      k_extend_entries<int64_t><<<grid_for(N->nnz, 256), 256, 0, s_>>>(
+          dparts.get(), dsrcs.get(), deb.get(), P, N->nnz, N->o_adj.get(), N->o_ew.get(),
+          N->o_src.get());
+    LAUNCH_CHECK();
+  }
+  N->xadj = N->o_xadj.get();
+  N->adj = N->o_adj.get();
+  N->ew_kind = narrow_ ? EW_I32 : EW_I64;
+  N->ew = narrow_ ? (const void*)N->o_ew32.get() : (const void*)N->o_ew.get();
+  N->nw = N->o_nw.get();
+  N->src = N->o_src.get();
+  N->gid = N->o_gid.get();
+  sync(s_);  // the host tables above are freed on return
+  levels_.back() = std::move(N);
+}
+
 // -------------------------------------------------------------- LP driver --
 // Rates the nodes of one sub-round: ra.list (and ra.cands) point at the
 // first degree class; cnt/offs/degs per class, offs absolute in the list.
@@ -695,9 +820,10 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     for (uint32_t b = 0; b < B; ++b) {
       const Job& jb = jobs[L.graphs[b]];
       uint64_t* q = &pre[((size_t)r * B + b) * 3];
-      q[0] = chain(jb.seed, tsub, {spec.level, r});
-      q[1] = chain(jb.seed, ttie, {spec.level, r});
-      q[2] = chain(jb.seed, tadm, {spec.level, r});
+      const uint64_t lv = spec.level - jb.d0;  // the graph's own level index
+      q[0] = chain(jb.seed, tsub, {lv, r});
+      q[1] = chain(jb.seed, ttie, {lv, r});
+      q[2] = chain(jb.seed, tadm, {lv, r});
     }
   DBuf<uint64_t> dpre(&pool_, s_, pre.size() ? pre.size() : 1);
   DBuf<unsigned long long> dround(&pool_, s_, B), dncl(&pool_, s_, B);
@@ -731,13 +857,18 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   // round) are taken on the device; the host reads the active flags together
   // with the next round's bucket counts, in one copy per round.
   auto begin_round = [&](uint32_t r) {
-    k_lp_round<<<1, 256, 0, s_>>>(ctl, r, nullptr);  // also clears the bucket counters
-    LAUNCH_CHECK();
-    launch_bucket_count(ba, s_);
-    launch_bucket_offsets(ba, s_);
-    // the lists too, before the host waits: the scatter needs only the
-    // device's offsets, and the first rating launch then follows the wait
-    launch_bucket_scatter(ba, s_);
+    {
+      // every node's offsets and weight read twice (count, scatter), its
+      // list slot written
+      ProfScope prof(spec.refine ? "rf:bucket" : "cl:bucket", 52 * n, s_);
+      k_lp_round<<<1, 256, 0, s_>>>(ctl, r, nullptr);  // also clears the bucket counters
+      LAUNCH_CHECK();
+      launch_bucket_count(ba, s_);
+      launch_bucket_offsets(ba, s_);
+      // the lists too, before the host waits: the scatter needs only the
+      // device's offsets, and the first rating launch then follows the wait
+      launch_bucket_scatter(ba, s_);
+    }
     d2h(hstate, rstate.get(), nstate, s_);
     sync(s_);
     for (uint32_t i = 0; i < NB; ++i) {
@@ -952,9 +1083,14 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
           rate_classes(ra, &cnt[sr * NCLASS], &offs[sr * NCLASS], &degs[sr * NCLASS], L.ew_kind);
           AdmitArgs aa = admit_args();
           aa.max_cands = total;
-          launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
-          k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
-          LAUNCH_CHECK();
+          {
+            // per candidate slot: the slot (24 B) read by classification,
+            // scatter and apply, its target's demand and weight (16 B)
+            ProfScope prof(spec.refine ? "rf:admission" : "cl:admission", 88ull * total, s_);
+            launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
+            k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+            LAUNCH_CHECK();
+          }
         }
         // switch to replay after the first round; the capture waits until a
         // round is known to follow (a level that stops here pays nothing)
@@ -1010,8 +1146,8 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
     gd[b].nodes = L.nbase[b + 1] - L.nbase[b];
     gd[b].label_base = L.nbase[b];
     gd[b].cap = jb.U;
-    gd[b].pre_tie = chain(jb.seed, TAG_FAV, {level});
-    gd[b].pre_two = chain(jb.seed, TAG_TWOHOP, {level});
+    gd[b].pre_tie = chain(jb.seed, TAG_FAV, {(uint64_t)(level - jb.d0)});
+    gd[b].pre_two = chain(jb.seed, TAG_TWOHOP, {(uint64_t)(level - jb.d0)});
     gd[b].active = which[b];
     gd[b].subrounds = 1;
   }
@@ -1089,6 +1225,10 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   while (wb < 62 && (1ll << wb) <= maxcap - 1) ++wb;
   const bool one_key = kb + wb + 32 <= 64;
   const int sshift = one_key ? 32 + wb : 0;
+  // per singleton: key and id written, read and written per 8-bit sort pass,
+  // weight, prefix sum, successor, K jump tables, marks, scan and merge
+  const int passes = one_key ? (kb + wb + 39) / 8 : (wb + 39) / 8 + (kb + 7) / 8;
+  ProfScope prof_pack("fv:twohop_pack", (uint64_t)ns * (24ull * passes + 64), s_);
   DBuf<uint64_t> keys(&pool_, s_, ns), keys2(&pool_, s_, ns);
   DBuf<uint32_t> vals(&pool_, s_, ns), vals2(&pool_, s_, ns);
   const unsigned gs = grid_for(ns, 256);
@@ -1114,6 +1254,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   exclusive_scan(SortedWeight{sv, L.nw}, ns, E.get(), true, pool_, s_);
   uint32_t K = 0;  // doubling levels: 2^K > groups - 1
   while (K < 32 && (1ull << K) < std::min<uint64_t>(ns, groups)) ++K;
+  prof_pack.add_bytes((uint64_t)ns * 17 * K);
   DBuf<uint32_t> J(&pool_, s_, (size_t)std::max<uint32_t>(K, 1) * ns);
   k_nextfit<<<gs, 256, 0, s_>>>(sk, sshift, last.get(), E.get(), sv, L.gid, dgd.get(), ns, J.get());
   LAUNCH_CHECK();
@@ -1247,6 +1388,14 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     jb.info.push_back(i0);
   }
   while (true) {
+    if (admit && levels_.size() >= 2) {  // graphs joining the run in flight
+      std::vector<Job> more = admit();
+      if (!more.empty()) {
+        const size_t first = jobs.size();
+        for (Job& jb : more) jobs.push_back(std::move(jb));
+        extend_union(jobs, first);
+      }
+    }
     Level& L = *levels_.back();
     const uint32_t B = (uint32_t)L.graphs.size();
     const uint32_t depth = (uint32_t)levels_.size();
@@ -1255,7 +1404,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     for (uint32_t b = 0; b < B; ++b) {
       const Job& jb = jobs[L.graphs[b]];
       const uint64_t nb = L.nbase[b + 1] - L.nbase[b];
-      active[b] = ((u128)nb > (u128)p_.clim * jb.k) && depth < p_.max_levels;
+      active[b] = ((u128)nb > (u128)p_.clim * jb.k) && depth - jb.d0 < p_.max_levels;
       any |= active[b] != 0;
     }
     if (!any) break;
@@ -1359,7 +1508,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
       sg.m_hat = m_hat;
       sg.triggered = trig;
       sg.sampler = p_.sampler;
-      sg.pre = chain(jb.seed, TAG_SPARS, {(uint64_t)depth + 1});
+      sg.pre = chain(jb.seed, TAG_SPARS, {(uint64_t)(depth + 1 - jb.d0)});
       any_trig |= trig;
       ++c;
     }
@@ -1413,7 +1562,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
   // than the host's few short sorts, and gets sparse ones sorted.
   for (size_t j = 1; j < levels_.size(); ++j) {
     bool coarsest = false;
-    for (uint32_t g : levels_[j]->graphs) coarsest |= jobs[g].nlevels - 1 == j;
+    for (uint32_t g : levels_[j]->graphs) coarsest |= jobs[g].top() == j;
     if (coarsest && (ip_on_device(jobs, j) || levels_[j]->nnz < 64 * levels_[j]->n))
       ensure_sorted(j);
   }
@@ -1426,7 +1575,7 @@ bool Engine::ip_on_device(const std::vector<Job>& jobs, size_t j) const {
   uint64_t Ktot = 0;
   for (const Job& jb : jobs) Ktot += jb.k;
   uint32_t taking = 0;
-  for (uint32_t g : L.graphs) taking += jobs[g].nlevels - 1 == j;
+  for (uint32_t g : L.graphs) taking += jobs[g].top() == j;
   // block ids, node ids and frontier ranks are 32-bit in the device search
   if (!taking || L.nnz >= (1ull << 32) || L.n >= (1ull << 31) || Ktot >= IP_NONE) return false;
   // automatic choice: the device search gives each subproblem one workgroup,
@@ -1528,7 +1677,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
       bool any = false;
       for (uint32_t b = 0; b < B; ++b) {
         const uint32_t g = L.graphs[b];
-        if (jobs[g].nlevels - 1 == j) {
+        if (jobs[g].top() == j) {
           gbase[b] = (uint32_t)kbase[g];
           any = true;
         }
@@ -1558,7 +1707,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
           const Job& jb = jobs[L.graphs[q.b]];
           const uint32_t k1 = (q.kS + 1) / 2;
           sob[kbase[L.graphs[q.b]] + q.off] = (uint32_t)subs.size();
-          subs.push_back(IpSub{chain(jb.seed, TAG_IP, {(uint64_t)j + 1, (uint64_t)q.off,
+          subs.push_back(IpSub{chain(jb.seed, TAG_IP, {(uint64_t)(j + 1 - jb.d0), (uint64_t)q.off,
                                                        (uint64_t)q.kS}),
                                L.nbase[q.b], q.kS, k1});
           next.push_back(Part{q.b, q.off, k1});
@@ -1573,7 +1722,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
   }
   for (uint32_t g = 0; g < NJ; ++g) {
     if (on_dev_ip[g]) continue;
-    const uint32_t top = jobs[g].nlevels - 1;
+    const uint32_t top = jobs[g].top();
     Level& L = *levels_[top];
     uint32_t b = 0;
     while (L.graphs[b] != g) ++b;
@@ -1588,7 +1737,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     d2h(hn, L.nw + n0, n1 - n0, s_);
     // coarse levels: neighbours in ascending order (the oracle's coarse rows
     // are sorted); the input level: in the caller's order
-    const bool asc = top > 0 || L.sorted;
+    const bool asc = top > jobs[g].d0 || L.sorted;
     if (n1 - n0 <= (1u << 16)) {
       DBuf<uint16_t> a16(&pool_, s_, e1 > e0 ? e1 - e0 : 1);
       if (e1 > e0) {
@@ -1600,13 +1749,13 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
       d2h(ha, a16.get(), e1 - e0, s_);
       sync(s_);
       initial_partition_host<uint16_t>(n1 - n0, hx, ha, hn, e0, 0, L.sorted, asc, jobs[g].k,
-                                       jobs[g].seed, top + 1, ip[g]);
+                                       jobs[g].seed, jobs[g].nlevels, ip[g]);
     } else {
       uint32_t* ha = pinned_grow(hb.adj, hb.ca, e1 - e0, hb.pageable);
       d2h(ha, L.adj + e0, e1 - e0, s_);
       sync(s_);
       initial_partition_host<uint32_t>(n1 - n0, hx, ha, hn, e0, n0, L.sorted, asc, jobs[g].k,
-                                       jobs[g].seed, top + 1, ip[g]);
+                                       jobs[g].seed, jobs[g].nlevels, ip[g]);
     }
     for (auto& x : ip[g]) x += (uint32_t)kbase[g];
   }
@@ -1622,7 +1771,7 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     else block.reset(&pool_, s_, L.n ? L.n : 1);
     for (uint32_t b = 0; b < B; ++b) {
       const uint32_t g = L.graphs[b];
-      if (jobs[g].nlevels - 1 == (uint32_t)j && !on_dev_ip[g])
+      if (jobs[g].top() == (uint32_t)j && !on_dev_ip[g])
         h2d(block.get() + L.nbase[b], ip[g].data(), ip[g].size(), s_);
     }
     if ((size_t)j + 1 < levels_.size()) project_blocks(L.map.get(), upper.get(), L.n, block.get(), s_);
@@ -1634,16 +1783,28 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
     std::vector<uint32_t> rounds;
     LpSpec spec{true, (uint32_t)j + 1, p_.ref_rounds};
     run_lp(L, jobs, spec, active, block.get(), BW.get(), Ktot, nullptr, lb, nullptr, rounds);
+    // graphs whose input graph is this level: cut, balance, output
+    bool inputs_here = false;
+    for (uint32_t g : L.graphs) inputs_here |= jobs[g].d0 == (uint32_t)j;
+    if (inputs_here) finish_level(jobs, (size_t)j, block.get(), kbase, block_out, on_device);
     upper = std::move(block);
   }
-  // evaluation on the input graphs
-  Level& L0 = *levels_[0];
+  t_refine_ns = tm.stop_ns();
+}
+
+// Cut, block weights and output blocks of the graphs whose input graph is
+// union level j (d0 == j), from that level's blocks.
+void Engine::finish_level(std::vector<Job>& jobs, size_t j, const uint32_t* block,
+                          const std::vector<uint64_t>& kbase, uint32_t* const* block_out,
+                          bool on_device) {
+  Level& L0 = *levels_[j];
   const uint32_t B0 = (uint32_t)L0.graphs.size();
-  DBuf<int64_t> cut(&pool_, s_, B0);
+  const uint64_t Ktot = kbase.back();
+  DBuf<int64_t> cut(&pool_, s_, B0), BW(&pool_, s_, Ktot ? Ktot : 1);
   cut.zero();
-  edge_cut(L0.src, L0.adj, L0.ew, L0.ew_kind, upper.get(), L0.gid, L0.nnz, cut.get(), s_);
+  edge_cut(L0.src, L0.adj, L0.ew, L0.ew_kind, block, L0.gid, L0.nnz, cut.get(), s_);
   BW.zero();
-  block_weights(upper.get(), L0.nw, L0.n, BW.get(), Ktot, s_);
+  block_weights(block, L0.nw, L0.n, BW.get(), Ktot, s_);
   std::vector<int64_t> hcut(B0), hbw(Ktot);
   d2h(hcut.data(), cut.get(), B0, s_);
   d2h(hbw.data(), BW.get(), Ktot, s_);
@@ -1653,31 +1814,32 @@ void Engine::partition(std::vector<Job>& jobs, uint32_t* const* block_out, bool 
   if (on_device && block_out && L0.n) {
     std::vector<uint32_t*> outs(B0, nullptr);
     std::vector<uint64_t> kb(B0, 0);
-    for (uint32_t b = 0; b < B0; ++b) {
-      outs[b] = block_out[L0.graphs[b]];
-      kb[b] = kbase[L0.graphs[b]];
-    }
+    for (uint32_t b = 0; b < B0; ++b)
+      if (jobs[L0.graphs[b]].d0 == j) {
+        outs[b] = block_out[L0.graphs[b]];
+        kb[b] = kbase[L0.graphs[b]];
+      }
     douts.reset(&pool_, s_, B0);
     dnb0.reset(&pool_, s_, B0 + 1);
     dkb0.reset(&pool_, s_, B0);
     h2d(douts.get(), outs.data(), B0, s_);
     h2d(dnb0.get(), L0.nbase.data(), B0 + 1, s_);
     h2d(dkb0.get(), kb.data(), B0, s_);
-    k_blocks_out<<<grid_for(L0.n, 256), 256, 0, s_>>>(upper.get(), L0.gid, L0.n, dnb0.get(),
+    k_blocks_out<<<grid_for(L0.n, 256), 256, 0, s_>>>(block, L0.gid, L0.n, dnb0.get(),
                                                       dkb0.get(), douts.get());
     LAUNCH_CHECK();
   } else if (!on_device && block_out) {
     for (uint32_t b = 0; b < B0; ++b) {
       const uint32_t g = L0.graphs[b];
       const uint64_t n0 = L0.nbase[b], nn = L0.nbase[b + 1] - n0;
-      if (block_out[g]) d2h(block_out[g], upper.get() + n0, nn, s_);
+      if (jobs[g].d0 == j && block_out[g]) d2h(block_out[g], block + n0, nn, s_);
     }
   }
   sync(s_);
-  t_refine_ns = tm.stop_ns();
   for (uint32_t b = 0; b < B0; ++b) {
     const uint32_t g = L0.graphs[b];
     Job& jb = jobs[g];
+    if (jb.d0 != j) continue;
     if (!on_device && block_out && block_out[g]) {
       const uint64_t nn = L0.nbase[b + 1] - L0.nbase[b];
       for (uint64_t i = 0; i < nn; ++i) block_out[g][i] -= (uint32_t)kbase[g];

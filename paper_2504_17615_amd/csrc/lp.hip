@@ -1116,10 +1116,11 @@ std::string rate_name(int phase, int cls, int ewk, bool few, bool packed) {
 
 // Algorithmic bytes of rating `count` nodes with `degsum` entries: per node the
 // two offsets, its list slot, label and weight (32 B); per entry the neighbour
-// id, its label and the edge weight (if stored).
-uint64_t rate_bytes(int ewk, uint64_t count, uint64_t degsum) {
+// id, its label (`label_bytes`: 1 where the kernel gathers the byte copy of
+// the blocks, else 4) and the edge weight (if stored).
+uint64_t rate_bytes(int ewk, uint64_t count, uint64_t degsum, uint64_t label_bytes = 4) {
   const uint64_t bw = ewk == EW_UNIT ? 0 : ewk == EW_I32 ? 4 : 8;
-  return 32 * count + (8 + bw) * degsum;
+  return 32 * count + (4 + label_bytes + bw) * degsum;
 }
 
 template <int EWK>
@@ -1138,7 +1139,7 @@ void launch_groups_t(const RateArgs& a, const uint32_t* count, const uint32_t* o
   if (!blocks) return;
   const char* ph[3] = {"cl:", "rf:", "fv:"};
   ProfLaunch prof((std::string(ph[a.phase]) + "k_rate_groups<" + std::to_string(EWK) + ">").c_str(),
-                  rate_bytes(EWK, total, degsum));
+                  rate_bytes(EWK, total, degsum, a.label8 ? 1 : 4));
   launch_k(k_rate_groups<EWK>, dim3(blocks), dim3(256), s, prof.start(), prof.stop(), a, split);
   LAUNCH_CHECK();
 }
@@ -1276,7 +1277,7 @@ template <int EWK>
 void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
   const uint32_t c = ra.count;
   ProfScope prof(rate_name(ra.phase, CLASS_GLOBAL, EWK, false, false).c_str(),
-                 rate_bytes(EWK, ra.count, ra.degsum), s);
+                 rate_bytes(EWK, ra.count, ra.degsum, ra.label8 ? 1 : 4), s);
   // LMGP_HUB_TABLES=global forces the chunked global-table path (taken when
   // ratings do not fit 32 bits); =repair makes every label range report an
   // overflow so that k_hub_repair computes all of them (both used by tests)

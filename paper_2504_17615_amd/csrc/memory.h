@@ -46,6 +46,15 @@ class Pool {
   // Highest arena offset handed out so far (arena mode).
   size_t arena_high_water() const { return arena_high_; }
 
+  // Bytes handed out and not yet freed (caching-pool mode), and their peak
+  // since the last reset_peak().
+  size_t in_use() const { return in_use_; }
+  size_t peak_in_use() const { return peak_; }
+  void reset_peak() {
+    std::lock_guard<std::mutex> g(mu_);
+    peak_ = in_use_;
+  }
+
   void* alloc(size_t bytes, hipStream_t s) {
     if (bytes == 0) bytes = 1;
     if (arena_base_) return arena_alloc(bytes);
@@ -62,6 +71,7 @@ class Pool {
         void* p = fl.back();
         fl.pop_back();
         sizes_[p] = sz;
+        note_alloc(sz);
         return p;
       }
     }
@@ -80,6 +90,7 @@ class Pool {
     std::lock_guard<std::mutex> g(mu_);
     sizes_[p] = sz;
     owned_.push_back(p);
+    note_alloc(sz);
     return p;
   }
 
@@ -97,6 +108,7 @@ class Pool {
     auto it = sizes_.find(p);
     if (it == sizes_.end()) return;
     free_[Key{s, it->second}].push_back(p);
+    in_use_ -= it->second;
     sizes_.erase(it);
   }
 
@@ -127,6 +139,10 @@ class Pool {
   }
 
  private:
+  void note_alloc(size_t sz) {  // mu_ held
+    in_use_ += sz;
+    if (in_use_ > peak_) peak_ = in_use_;
+  }
   void* arena_alloc(size_t bytes) {
     const size_t sz = (bytes + 255) & ~(size_t)255;
     std::lock_guard<std::mutex> g(mu_);
@@ -163,6 +179,7 @@ class Pool {
     arena_free_[off] = len;
   }
 
+  size_t in_use_ = 0, peak_ = 0;
   char* arena_base_ = nullptr;
   size_t arena_bytes_ = 0, arena_high_ = 0;
   std::map<size_t, size_t> arena_free_, arena_used_;  // offset -> length

@@ -1,5 +1,6 @@
 // Primitive kernels: fills and the stable LSD radix sort.
 #include "primitives.h"
+#include "profiler.h"
 
 #include <cstring>
 
@@ -191,6 +192,7 @@ void stage_reset(size_t mark) { stage().used = mark; }
 
 void read_now(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
+  Profiler::get().count("host:stream_syncs");
   const size_t mark = stage_mark();
   void* p = stage_take(bytes);
   HIP_CHECK(hipMemcpyAsync(p ? p : dst, src, bytes, hipMemcpyDeviceToHost, s));

@@ -35,6 +35,11 @@ class Profiler {
   // hands out the two events to pass to it.
   void begin_ext(const char* name, uint64_t bytes, hipEvent_t* a, hipEvent_t* b);
   void end(int slot, hipStream_t s);
+  // Adds bytes to a started launch record (sizes known only later).
+  void add_bytes(int slot, uint64_t bytes);
+  // Counts an event of the host (e.g. a stream synchronisation) under `name`:
+  // launches = count, no time or bytes.
+  void count(const char* name);
   // Resolve recorded events (synchronises them) and accumulate.
   void collect();
   std::map<std::string, KernelStat> read(bool reset);
@@ -62,8 +67,14 @@ class ProfScope {
     Profiler& p = Profiler::get();
     slot_ = p.on() && p.wants(name) ? p.begin(name, bytes, s) : -1;
   }
-  ~ProfScope() {
+  ~ProfScope() { end(); }
+  void add_bytes(uint64_t b) {
+    if (slot_ >= 0) Profiler::get().add_bytes(slot_, b);
+  }
+  // Ends the bracket before the scope does.
+  void end() {
     if (slot_ >= 0) Profiler::get().end(slot_, s_);
+    slot_ = -1;
   }
 
  private:

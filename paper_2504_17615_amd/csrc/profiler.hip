@@ -43,6 +43,17 @@ void Profiler::end(int slot, hipStream_t s) {
   HIP_CHECK(hipEventRecord(pending_[slot].b, s));
 }
 
+void Profiler::add_bytes(int slot, uint64_t bytes) {
+  std::lock_guard<std::mutex> g(mu_);
+  if (slot >= 0 && (size_t)slot < pending_.size()) pending_[slot].bytes += bytes;
+}
+
+void Profiler::count(const char* name) {
+  if (!on()) return;
+  std::lock_guard<std::mutex> g(mu_);
+  stats_[name].launches++;
+}
+
 void Profiler::collect() {
   std::lock_guard<std::mutex> g(mu_);
   for (Rec& r : pending_) {

@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "contract.h"
+#include "profiler.h"
 
 namespace lmgp {
 
@@ -36,7 +37,9 @@ __global__ __launch_bounds__(256) void k_wmax(const WT* ew, uint64_t e0, uint64_
 
 template <typename WT>
 __global__ __launch_bounds__(256) void k_whist(const WT* ew, uint64_t e0, uint64_t e1,
-                                               int shift, uint64_t prefix, uint32_t* hist) {
+                                               int shift, uint64_t prefix,
+                                               unsigned long long* hist) {
+  // a block counts fewer than 2^32 entries; the device-wide bins are 64-bit
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(256) void k_whist(const WT* ew, uint64_t e0, uint64
     if (match) atomicAdd(&h[(w >> shift) & 0xFF], 1u);
   }
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
 LMGP_D uint64_t edge_key(uint64_t pre, uint64_t a, uint64_t b) {
@@ -60,7 +63,7 @@ template <typename WT>
 __global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32_t* adj,
                                                const WT* ew, uint64_t e0, uint64_t e1,
                                                int64_t w_t, uint64_t base, uint64_t pre,
-                                               uint32_t* hist) {
+                                               unsigned long long* hist) {
   __shared__ uint32_t h[4096];
   for (int i = threadIdx.x; i < 4096; i += 256) h[i] = 0;
   __syncthreads();
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 4096; i += 256)
-    if (h[i]) atomicAdd(&hist[i], h[i]);
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
 struct EqEntry {
@@ -84,15 +87,15 @@ template <typename WT>
 __global__ __launch_bounds__(256) void k_kgather(const uint32_t* src, const uint32_t* adj,
                                                  const WT* ew, uint64_t e0, uint64_t e1,
                                                  int64_t w_t, uint64_t base, uint64_t pre,
-                                                 uint32_t bucket, EqEntry* out, uint32_t* cnt,
-                                                 uint32_t cap) {
+                                                 uint32_t bucket, EqEntry* out,
+                                                 unsigned long long* cnt, uint64_t cap) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
     const uint32_t a = src[e], b = adj[e];
     if (a < b && (int64_t)ew[e] == w_t) {
       const uint64_t k = edge_key(pre, a - base, b - base);
       if ((k >> 52) == bucket) {
-        const uint32_t p = atomicAdd(cnt, 1u);
+        const uint64_t p = atomicAdd(cnt, 1ull);
         if (p < cap) out[p] = EqEntry{k, a - (uint32_t)base, b - (uint32_t)base};
       }
     }
@@ -180,7 +183,7 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
   const size_t B = graphs.size();
   std::vector<SparsDesc> desc(B);
   DBuf<unsigned long long> dmax(&pool, s, 1);
-  DBuf<uint32_t> hist(&pool, s, 4096), cnt(&pool, s, 1);
+  DBuf<unsigned long long> hist(&pool, s, 4096), cnt(&pool, s, 1);
   for (size_t g = 0; g < B; ++g) {
     SparsGraph& sg = graphs[g];
     SparsDesc& d = desc[g];
@@ -208,14 +211,17 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
     read_now(&wmax, dmax.get(), sizeof(wmax), s);
     int top = 0;
     while (top < 64 && (wmax >> top) != 0) top += 8;
+    // the weight of every entry per 8-bit digit pass, with the host's digit
+    // choice between passes
+    ProfScope prof_sel("sp:select", sizeof(WT) * (e1 - e0) * (top / 8), s);
     // (2 m_hat)-th largest directed weight
     uint64_t R = 2 * sg.m_hat, gt = 0, eq = 0, prefix = 0;
-    std::vector<uint32_t> h(256);
+    std::vector<unsigned long long> h(256);
     for (int shift = top - 8; shift >= 0; shift -= 8) {
       hist.zero();
       k_whist<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, shift, prefix, hist.get());
       LAUNCH_CHECK();
-      read_now(h.data(), hist.get(), 256 * sizeof(uint32_t), s);
+      read_now(h.data(), hist.get(), 256 * sizeof(unsigned long long), s);
       uint64_t cum = 0;
       int sel = 0;
       for (int dgt = 255; dgt >= 0; --dgt) {
@@ -230,6 +236,7 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
       prefix |= (uint64_t)sel << shift;
       eq = h[sel];
     }
+    prof_sel.end();
     sg.w_t = (int64_t)prefix;
     sg.n_gt = gt / 2;
     sg.n_eq = eq / 2;
@@ -245,13 +252,15 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
       d.coin_r = r;
       continue;
     }
-    // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t
+    // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t:
+    // row, neighbour and weight of every entry in two passes
+    ProfScope prof_hs("sp:hash_select", 2 * (8 + sizeof(WT)) * (e1 - e0), s);
     hist.zero();
     k_khist<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
                                                  sg.pre, hist.get());
     LAUNCH_CHECK();
-    std::vector<uint32_t> kh(4096);
-    read_now(kh.data(), hist.get(), 4096 * sizeof(uint32_t), s);
+    std::vector<unsigned long long> kh(4096);
+    read_now(kh.data(), hist.get(), 4096 * sizeof(unsigned long long), s);
     uint64_t cum = 0;
     uint32_t bucket = 0;
     for (uint32_t i = 0; i < 4096; ++i) {
@@ -262,7 +271,7 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
       cum += kh[i];
     }
     const uint64_t rin = r - cum;  // rank inside the bucket (1-based)
-    const uint32_t bsz = kh[bucket];
+    const uint64_t bsz = kh[bucket];
     DBuf<EqEntry> buf(&pool, s, bsz ? bsz : 1);
     cnt.zero();
     k_kgather<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
@@ -282,7 +291,12 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
     d.ta = t.a;
     d.tb = t.b;
   }
-  // keep flags, positions, compaction
+  // keep flags, positions, compaction: every entry read (row, neighbour,
+  // weight) and flagged, positions scanned, the kept ones written
+  uint64_t kept_est = 0;
+  for (const SparsGraph& sg : graphs) kept_est += sg.triggered ? 2 * sg.m_hat : sg.e1 - sg.e0;
+  ProfScope prof_cp("sp:compact", (8 + sizeof(WT) + 1 + 8) * nnz + (8 + sizeof(WT)) * kept_est +
+                                      16 * (n + 1), s);
   DBuf<SparsDesc> dd(&pool, s, B);
   HIP_CHECK(hipMemcpyAsync(dd.get(), desc.data(), B * sizeof(SparsDesc), hipMemcpyHostToDevice, s));
   DBuf<uint8_t> keep(&pool, s, nnz ? nnz : 1);

@@ -1,6 +1,7 @@
 // Uncoarsening helpers: projection of blocks to the finer level (Sec. 2),
 // block weights c(V_i) and the edge cut cut(Pi) = sum_{i<j} omega(E_ij).
 #include "contract.h"
+#include "profiler.h"
 
 namespace lmgp {
 
@@ -63,6 +64,8 @@ __global__ __launch_bounds__(256) void k_cut(const uint32_t* src, const uint32_t
 void project_blocks(const uint32_t* map, const uint32_t* cblock, uint64_t n, uint32_t* block,
                     hipStream_t s) {
   if (!n) return;
+  // map[u] and block[u] read and written per node, the coarse block gathered
+  ProfScope prof("rf:project", 12 * n, s);
   k_project<<<grid_for(n, 256), 256, 0, s>>>(map, cblock, n, block);
   LAUNCH_CHECK();
 }
@@ -72,6 +75,7 @@ void block_weights(const uint32_t* block, const int64_t* nw, uint64_t n, int64_t
   if (!n) return;
   unsigned g = grid_for(n, 256);
   if (g > 1024) g = 1024;
+  ProfScope prof("ev:block_weights", 12 * n, s);  // block + node weight per node
   k_block_weights<<<g, 256, 0, s>>>(block, nw, n, BW, K);
   LAUNCH_CHECK();
 }
@@ -82,6 +86,9 @@ void edge_cut(const uint32_t* src, const uint32_t* adj, const void* ew, int ew_k
   if (!nnz) return;
   unsigned g = grid_for(nnz, 256);
   if (g > 4096) g = 4096;
+  // per entry: row, neighbour, its block (4 B each) and the stored weight
+  const uint64_t bw = ew_kind == EW_UNIT ? 0 : ew_kind == EW_I32 ? 4 : 8;
+  ProfScope prof("ev:cut", (12 + bw) * nnz, s);
   switch (ew_kind) {
     case EW_UNIT: k_cut<EW_UNIT><<<g, 256, 0, s>>>(src, adj, ew, block, gid, nnz, cut); break;
     case EW_I32: k_cut<EW_I32><<<g, 256, 0, s>>>(src, adj, ew, block, gid, nnz, cut); break;

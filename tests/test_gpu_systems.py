@@ -79,7 +79,7 @@ def test_batch_of_one_equals_plain(lib, solo):
 
 
 @pytest.mark.parametrize("budget_mib,slots,batch,streams", [(4096, 16, 8, 2), (64, 8, 4, 2),
-                                                            (4096, 4, 1, 1)])
+                                                            (4096, 4, 1, 1), (4096, 16, 8, 4)])
 def test_server_results_equal_solo(lib, solo, budget_mib, slots, batch, streams):
     srv = lib.Server(hbm_budget_bytes=budget_mib << 20, max_slots=slots, max_batch=batch,
                      streams=streams)
@@ -104,7 +104,7 @@ def test_server_run_cap_equals_solo(lib, solo):
     bb, br = big.partition(16, 0.03, 11, host_out=True)
     ob, ores, _ = O.partition(g, 16, 0.03, 11)
     assert np.array_equal(bb, ob) and br["cut"] == ores["cut"]
-    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=16, max_batch=8, streams=2)
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=16, max_batch=8, streams=4)
     print("server with a request above the run cap", flush=True)
     tickets = []
     for rep in range(2):
@@ -120,6 +120,56 @@ def test_server_run_cap_equals_solo(lib, solo):
         assert _same(res, wres), (i, res, wres)
     srv.close()
     big.close()
+
+
+def test_server_joins_run_in_flight(lib, solo):
+    # one stream: once a large request's run has started, the requests that
+    # arrive join it at its next level boundary (no stream is free); each
+    # result is still the solo one
+    import time
+
+    g = gg.rmat(17)
+    big = lib.create_graph(g)
+    bb, br = big.partition(16, 0.03, 11, host_out=True)
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=32, max_batch=8, streams=1)
+    print("server: requests joining a run in flight", flush=True)
+    tickets = [(-1, srv.submit(big, 16, 0.03, 11))]
+    t0 = time.perf_counter()
+    while srv.stats()["runs"] < 1 and time.perf_counter() - t0 < 10:
+        time.sleep(0.0001)
+    for i in range(len(solo)):
+        tickets.append((i, srv.submit(*solo[i][:4])))
+    for i, t in tickets:
+        out, res = srv.wait(t)
+        want, wres = (bb, br) if i < 0 else (solo[i][4], solo[i][5])
+        assert np.array_equal(out, want), i
+        assert _same(res, wres), (i, res, wres)
+    st = srv.stats()
+    print("server stats", st, flush=True)
+    assert st["joined"] >= 1 and st["completed"] == len(tickets) and st["failed"] == 0
+    # the admission estimate covers what one run held on the device
+    assert 0 < st["peak_pool_bytes"] <= st["peak_resident_estimate"]
+    srv.close()
+    big.close()
+
+
+def test_server_per_request_params(lib, solo):
+    # requests with their own parameters (samplers, rho) in one stream of
+    # submissions: each equals the plain call with those parameters
+    dg, k, eps, seed = solo[1][:4]
+    settings = [None, dict(sampler=1), dict(rho_num=3), dict(sampler=2), None, dict(sampler=1)]
+    want = []
+    for kw in settings:
+        prm = lib.default_params(**(kw or {}))
+        want.append(dg.partition(k, eps, seed, prm, host_out=True))
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=16, max_batch=8, streams=2)
+    tickets = [srv.submit(dg, k, eps, seed, None if kw is None else lib.default_params(**kw))
+               for kw in settings]
+    for t, (wb, wr) in zip(tickets, want):
+        out, res = srv.wait(t)
+        assert np.array_equal(out, wb)
+        assert _same(res, wr)
+    srv.close()
 
 
 def test_server_rejects_request_beyond_budget(lib, solo):

@@ -743,3 +743,24 @@ def test_deterministic():
     assert np.array_equal(b1, b2) and r1 == r2
     b3, r3, _ = O.partition(g, k, eps, seed + 1)
     assert not np.array_equal(b1, b3)
+
+
+@pytest.mark.parametrize("name", ["grid128", "rmat14", "er14", "rgg16"])
+def test_thread_count_does_not_change_results(name):
+    # the OpenMP steps (rating pass, contraction rows, cut sum) merge their
+    # outputs in a fixed order: 1 and 4 threads give the same bytes
+    g, k, eps, seed = gg.workload(name)
+    try:
+        assert O.set_threads(1) == 1
+        b1, r1, _ = O.partition(g, k, eps, seed)
+        h1 = O.coarsen(g, k, seed)
+        if O.set_threads(4) == 1:
+            pytest.skip("oracle built without OpenMP")
+        b4, r4, _ = O.partition(g, k, eps, seed)
+        h4 = O.coarsen(g, k, seed)
+    finally:
+        O.set_threads(1)
+    assert np.array_equal(b1, b4) and r1 == r4
+    assert len(h1.levels) == len(h4.levels) and h1.info == h4.info
+    for a, b in zip(h1.levels, h4.levels):
+        assert np.array_equal(a.adjncy, b.adjncy) and np.array_equal(a.adjwgt, b.adjwgt)
