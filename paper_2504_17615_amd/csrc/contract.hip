@@ -71,6 +71,14 @@ __global__ void k_label_count(const uint32_t* label, const uint32_t* gid, const 
   if (keep[graph_of(gid, u)]) atomicAdd(&lcount[label[u]], 1u);
 }
 
+// The same counts from the member counts the clustering kept (labels are node
+// ids of their own graph, so K's graph is K's): a streaming pass, no atomics.
+__global__ void k_label_count_sizes(const uint32_t* csize, const uint32_t* gid,
+                                    const uint8_t* keep, uint64_t n, uint32_t* lcount) {
+  const uint64_t K = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K < n) lcount[K] = keep[graph_of(gid, K)] ? csize[K] : 0u;
+}
+
 // For every used label K: coarse weight, member count, graph.
 __global__ void k_coarse_nodes(const int64_t* W, const uint32_t* lcount, const uint32_t* cid,
                                const uint32_t* gid, uint64_t n, int64_t* cnw, uint32_t* ccount,
@@ -991,8 +999,12 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   // weights gathered (per node 4 + 4 + 8 + 4 + 4 + 8 B)
   ProfScope prof_remap("ct:remap", 32 * n, s);
   DBuf<uint32_t> lcount(&pool, s, n ? n : 1);
-  lcount.zero();
-  k_label_count<<<gn, 256, 0, s>>>(in.label, in.gid, in.keep, n, lcount.get());
+  if (in.csize) {
+    if (n) k_label_count_sizes<<<gn, 256, 0, s>>>(in.csize, in.gid, in.keep, n, lcount.get());
+  } else {
+    lcount.zero();
+    k_label_count<<<gn, 256, 0, s>>>(in.label, in.gid, in.keep, n, lcount.get());
+  }
   LAUNCH_CHECK();
   DBuf<uint32_t> cid(&pool, s, n + 1);
   exclusive_scan(FlagUsed{lcount.get()}, n, cid.get(), true, pool, s);

@@ -148,6 +148,39 @@ __global__ void k_lp_peek(LpCtl c) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+// Refinement: a node whose neighbours all share its block has no other block
+// with a positive rating, so it can produce no move.  flag[u] = 1 for the
+// other nodes (flag zeroed before), from the entries; `count` gets the number
+// of flagged nodes.
+__global__ void k_boundary(const uint32_t* src, const uint32_t* adj, uint64_t nnz,
+                           const uint32_t* block, const uint8_t* block8, uint8_t* flag) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const uint32_t u = src[e], v = adj[e];
+  const uint32_t bu = block8 ? block8[u] : block[u], bv = block8 ? block8[v] : block[v];
+  if (bu != bv) flag[u] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_count_flags(const uint8_t* flag, uint64_t n,
+                                                     unsigned long long* count) {
+  uint64_t c = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    c += flag[i] != 0;
+  c = wave_reduce_sum(c);
+  if (lane_id() == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+// After a sub-round: every neighbour of a node that moved may have become a
+// boundary node; flag it (flags only grow within a level).
+__global__ void k_mark_moved(const Cand* cands, const uint8_t* adm, uint32_t nc,
+                             const uint64_t* xadj, const uint32_t* adj, uint8_t* flag) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc || !adm[i]) return;
+  const uint32_t u = cands[i].u;
+  for (uint64_t e = xadj[u]; e < xadj[u + 1]; ++e) flag[adj[e]] = 1;
+}
+
 // Pinned host memory for the per-round state copy (copies into pageable
 // memory are staged by the runtime).  One buffer per thread, grown on demand
 // and kept for the thread's life (a few KiB).
@@ -193,6 +226,11 @@ __global__ void k_to_u8(const uint32_t* a, uint64_t n, uint8_t* b) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (uint8_t)a[i];
 }
+
+// Refinement levels from this size rate only their boundary nodes (when at
+// most half of the nodes are on the boundary).  Below it, one bucketing pass
+// and one host wait per round cost less than a pass and a wait per sub-round.
+constexpr uint64_t BOUNDARY_MIN_NODES = 1ull << 21;
 
 // Levels (unions) up to this many nodes replay their LP rounds from a graph
 // when asked: above it the rounds are long enough to hide their launches.
@@ -808,6 +846,34 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     k_to_u8<<<grid_for(n, 256), 256, 0, s_>>>(label, n, label8.get());
     LAUNCH_CHECK();
   }
+  // refinement of a large level: only nodes with a neighbour in another block
+  // can move, so only those (and the neighbours of nodes that moved since)
+  // are bucketed and rated, one sub-round at a time.  Exact: every node left
+  // out has all its neighbours in its own block.  Used when at most half of
+  // the nodes are on the boundary.
+  DBuf<uint8_t> bflag;
+  bool bmode = false;
+  // LMGP_BOUNDARY_MIN_NODES overrides the size threshold (tests use it to run
+  // the mode on small levels)
+  const char* bmin_env = std::getenv("LMGP_BOUNDARY_MIN_NODES");
+  const uint64_t bmin = bmin_env ? std::strtoull(bmin_env, nullptr, 10) : BOUNDARY_MIN_NODES;
+  if (spec.refine && n >= bmin && L.nnz && !(p_.graph_rounds && n <= REPLAY_MAX_NODES)) {
+    ProfScope prof("rf:boundary", (8 + (label8.get() ? 2 : 8)) * L.nnz + 2 * n, s_);
+    bflag.reset(&pool_, s_, n);
+    bflag.zero();
+    k_boundary<<<grid_for(L.nnz, 256), 256, 0, s_>>>(L.src, L.adj, L.nnz, label, label8.get(),
+                                                      bflag.get());
+    LAUNCH_CHECK();
+    DBuf<unsigned long long> bcount(&pool_, s_, 1);
+    bcount.zero();
+    unsigned g = grid_for(n, 256);
+    k_count_flags<<<g > 1024 ? 1024 : g, 256, 0, s_>>>(bflag.get(), n, bcount.get());
+    LAUNCH_CHECK();
+    unsigned long long nb = 0;
+    read_now(&nb, bcount.get(), sizeof(nb), s_);
+    bmode = 2 * nb <= n;
+    if (!bmode) bflag.clear();
+  }
   const std::vector<CutPreset>& presets = cut_presets(dense);
   int preset = p_.tune >= LMGP_TUNE_FORCE ? (int)((p_.tune - LMGP_TUNE_FORCE) % presets.size()) : 0;
   const uint64_t tsub = spec.refine ? TAG_RSUB : TAG_SUB;
@@ -853,6 +919,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.fill = bfill.get();
   ba.list = list.get();
   ba.cuts = presets[preset].cuts;
+  ba.only = bmode ? bflag.get() : nullptr;
+  ba.only_sub = 0;
   // Stop decisions (node-reduction cap after a sub-round, no moves in a
   // round) are taken on the device; the host reads the active flags together
   // with the next round's bucket counts, in one copy per round.
@@ -870,6 +938,24 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       launch_bucket_scatter(ba, s_);
     }
     d2h(hstate, rstate.get(), nstate, s_);
+    sync(s_);
+    for (uint32_t i = 0; i < NB; ++i) {
+      cnt[i] = (uint32_t)hstate[i];
+      degs[i] = hstate[NB + i];
+    }
+  };
+  // boundary mode: the lists of sub-round sr (> 0) are built after the
+  // moves of the sub-rounds before it (flags have grown since)
+  auto begin_sub = [&](uint32_t sr) {
+    {
+      ProfScope prof("rf:bucket", 2 * n + 52 * (uint64_t)L.nnz / 8, s_);
+      device_zero(rstate.get(), 2 * NB * sizeof(unsigned long long), s_);
+      ba.only_sub = sr;
+      launch_bucket_count(ba, s_);
+      launch_bucket_offsets(ba, s_);
+      launch_bucket_scatter(ba, s_);
+    }
+    d2h(hstate, rstate.get(), 2 * NB, s_);
     sync(s_);
     for (uint32_t i = 0; i < NB; ++i) {
       cnt[i] = (uint32_t)hstate[i];
@@ -1069,6 +1155,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   try {
     for (uint32_t r = 0; r < R; ++r) {
       if (!replay) {
+        ba.only_sub = 0;
         begin_round(r);
         if (r == 0 && p_.tune == LMGP_TUNE_AUTO) autotune();
         bool any = false;
@@ -1076,6 +1163,10 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
         if (!any) break;
         bucket_offsets();
         for (uint32_t sr = 0; sr < S; ++sr) {
+          if (bmode && sr > 0) {
+            begin_sub(sr);
+            bucket_offsets();
+          }
           uint32_t total = 0;
           for (int c = 0; c < NCLASS; ++c) total += cnt[sr * NCLASS + c];
           if (total == 0) continue;
@@ -1089,6 +1180,11 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
             ProfScope prof(spec.refine ? "rf:admission" : "cl:admission", 88ull * total, s_);
             launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
             k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+            LAUNCH_CHECK();
+          }
+          if (bmode) {  // the next sub-round (or round) buckets from the grown flags
+            k_mark_moved<<<grid_for(total, 256), 256, 0, s_>>>(cands.get(), adm.get(), total,
+                                                              L.xadj, L.adj, bflag.get());
             LAUNCH_CHECK();
           }
         }

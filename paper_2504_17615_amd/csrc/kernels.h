@@ -174,6 +174,10 @@ struct BucketArgs {
   uint32_t* fill;          // [nbuckets] (scatter pass)
   uint32_t* list;          // output
   ClassCuts cuts;          // degree -> class (non-decreasing bounds)
+  // mode 0, refinement of boundary nodes only: when `only` is set, a node is
+  // bucketed only if only[u] != 0 and its sub-round is only_sub
+  const uint8_t* only;
+  uint32_t only_sub;
 };
 void launch_bucket_count(const BucketArgs& a, hipStream_t s);
 // offs = exclusive prefix of counts, fill = 0 (one small block on the device).

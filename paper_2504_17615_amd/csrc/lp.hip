@@ -1369,6 +1369,8 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
 
 // ------------------------------------------------------------- bucketing --
 LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
+  // boundary refinement: interior nodes cost one byte
+  if (a.mode == 0 && a.only && !a.only[u]) return -1;
   const uint32_t g = graph_of(a.gid, u);
   const GraphDesc& gd = a.gd[g];
   if (!gd.active) return -1;
@@ -1379,6 +1381,7 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
     // adjacent label weighs at least one), so rating it cannot produce a move
     if (a.nw[u] >= gd.cap) return -1;
     uint32_t sr = subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds);
+    if (a.only && sr != a.only_sub) return -1;
     return (int)(sr * NCLASS + class_of(d, a.cuts));
   }
   // 2-hop: singletons lighter than the cap, with neighbours
@@ -1390,7 +1393,7 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
 __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
   __shared__ uint32_t h[MAX_BUCKETS];
   __shared__ unsigned long long hd[MAX_BUCKETS];
-  for (uint32_t i = threadIdx.x; i < MAX_BUCKETS; i += 256) {
+  for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256) {
     h[i] = 0;
     hd[i] = 0;
   }
@@ -1463,7 +1466,7 @@ constexpr int BK_ITEMS = 8;
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
   __shared__ uint32_t cnt[MAX_BUCKETS], base[MAX_BUCKETS];
-  for (uint32_t i = threadIdx.x; i < MAX_BUCKETS; i += 256) cnt[i] = 0;
+  for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256) cnt[i] = 0;
   __syncthreads();
   const uint64_t b0 = (uint64_t)blockIdx.x * 256 * BK_ITEMS;
   int bk[BK_ITEMS];

@@ -183,3 +183,25 @@ def test_allocator_failure_reports_enomem(lib):
     assert np.array_equal(out, ob) and res.cut == ores["cut"]
     api.lmgp_graph_destroy(h)
     torch.cuda.synchronize()
+
+
+# ------------------------------------------- refinement of boundary nodes --
+@pytest.mark.parametrize("case", ["grid400_k8", "rgg17_k16", "rgg18_k256"])
+def test_refinement_boundary_mode(lib, case, monkeypatch):
+    # refinement levels with few boundary nodes rate only those (and the
+    # neighbours of nodes that moved): results equal the oracle's, which
+    # rates every node.  The size threshold is lowered to 2^12 nodes here
+    monkeypatch.setenv("LMGP_BOUNDARY_MIN_NODES", str(1 << 12))
+    if case == "grid400_k8":
+        g, k = gg.grid(400, 400), 8
+    elif case == "rgg17_k16":
+        g, k = gg.rgg(1 << 17), 16
+    else:
+        g, k = gg.rgg(1 << 18), 256
+    check_partition(lib, g, k, 0.03, 3)
+
+
+def test_refinement_boundary_mode_default_threshold(lib):
+    # 2^21 nodes: the input level is refined in boundary mode by default
+    g = gg.rgg(1 << 21)
+    check_partition(lib, g, 64, 0.03, 5)
