@@ -19,14 +19,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-TAGS = dict(SUB=1, TIE=2, ADM=3, FAV=4, TWOHOP=5, SPARS=6, IP=7, RSUB=8, RTIE=9, RADM=10)
+TAGS = dict(SUB=1, TIE=2, ADM=3, FAV=4, TWOHOP=5, SPARS=6, IP=7, RSUB=8, RTIE=9, RADM=10,
+            FFSTART=11, FFDRAW=12, FFBREAK=13, FFCLAIM=14)
 
 
 class Params(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_uint32) for nm in (
         "tau_e_num", "tau_e_den", "tau_d_num", "tau_d_den", "rho_num", "rho_den", "sampler",
         "clim", "shrink_num", "shrink_den", "lp_rounds", "ref_rounds", "subrounds",
-        "max_levels", "stop_num", "stop_den")]
+        "max_levels", "stop_num", "stop_den", "ff_p_num", "ff_p_den", "ff_nu_num",
+        "ff_nu_den")]
 
 
 class CGraph(ctypes.Structure):
@@ -72,10 +74,11 @@ def _load():
         "or_g_copy": ([vp, vp, vp, vp, vp], None),
         "or_cluster": ([vp, i64, u64, u64, vp, vp, vp], None),
         "or_label_propagation": ([vp, vp, vp, u64, i64, u64, u64, u32, u32, u32, u32, vp], u32),
+        "or_fire_scores": ([vp, u64, u64, u32, u32, u32, u32, u32, vp, vp], None),
         "or_contract": ([vp, vp, vp], vp),
         "or_edge_budget": ([u64, u64, u64, vp], u64),
         "or_budget_triggers": ([u64, u64, vp], ctypes.c_int),
-        "or_sparsify": ([vp, u64, u64, u64, u32, vp], vp),
+        "or_sparsify": ([vp, u64, u64, u64, u32, vp, vp], vp),
         "or_coarsen": ([vp, u32, u64, vp], vp),
         "or_h_levels": ([vp], u32),
         "or_h_info": ([vp, u32, vp], None),
@@ -200,6 +203,19 @@ def label_propagation(g, label, W, cap, seed, level, refine_tags=False, rounds=5
     return lab, w, int(r), int(moves.value)
 
 
+def fire_scores(g, seed, level, weighted=True, p=(3, 5), nu=(1, 2)):
+    """(Weighted) Forest Fire burn score of every entry; returns (scores,
+    dict(fires=..., burns=...))."""
+    if not all(0 <= x < 1 << 32 for x in (*p, *nu)):
+        raise ValueError("fire parameters are 32-bit rationals")
+    v = _View(g)
+    sc = np.empty(v.adjncy.shape[0], np.int64)
+    st = np.zeros(2, np.uint64)
+    _load().or_fire_scores(v.ref, seed, level, int(weighted), p[0], p[1], nu[0], nu[1],
+                           sc.ctypes.data, st.ctypes.data)
+    return sc, dict(fires=int(st[0]), burns=int(st[1]))
+
+
 def contract(g, label):
     v = _View(g)
     lab = np.ascontiguousarray(label, np.uint32)
@@ -218,12 +234,15 @@ def budget_triggers(m_prime, m_hat, p: Optional[Params] = None) -> bool:
     return bool(_load().or_budget_triggers(m_prime, m_hat, ctypes.byref(p)))
 
 
-def sparsify(g, m_hat, seed, level, sampler=0):
+def sparsify(g, m_hat, seed, level, sampler=0, p: Optional[Params] = None):
     """sampler 0: exact-size threshold sampling, 1: uniform random sampling,
-    3: threshold sampling with independent coins for the edges of weight w_t."""
+    3: threshold sampling with independent coins for the edges of weight w_t,
+    4 / 5: exact-size threshold sampling on (Weighted) Forest Fire scores
+    (fire parameters from p, defaults if None)."""
     v = _View(g)
     st = np.zeros(3, np.int64)
-    h = _load().or_sparsify(v.ref, m_hat, seed, level, sampler, st.ctypes.data)
+    h = _load().or_sparsify(v.ref, m_hat, seed, level, sampler,
+                            ctypes.byref(p) if p is not None else None, st.ctypes.data)
     return _take_graph(h), dict(w_t=int(st[0]), n_gt=int(st[1]), n_eq=int(st[2]))
 
 

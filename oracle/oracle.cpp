@@ -79,7 +79,8 @@ uint64_t H(uint64_t seed, uint64_t tag, std::initializer_list<uint64_t> xs) {
 
 enum : uint64_t {
   TAG_SUB = 1, TAG_TIE = 2, TAG_ADM = 3, TAG_FAV = 4, TAG_TWOHOP = 5, TAG_SPARS = 6,
-  TAG_IP = 7, TAG_RSUB = 8, TAG_RTIE = 9, TAG_RADM = 10
+  TAG_IP = 7, TAG_RSUB = 8, TAG_RTIE = 9, TAG_RADM = 10,
+  TAG_FFSTART = 11, TAG_FFDRAW = 12, TAG_FFBREAK = 13, TAG_FFCLAIM = 14
 };
 
 const uint32_t ISO = 0xFFFFFFFFu;  // favourite of an isolated node: after every label
@@ -122,12 +123,16 @@ typedef struct {
   uint32_t rho_num, rho_den;      // minimum reduction factor rho (4)
   uint32_t sampler;               // 0 = weighted threshold sampling (exact size), 1 = uniform
                                   // random sampling, 2 = off, 3 = weighted threshold sampling
-                                  // with independent coins for the edges of weight omega_t
+                                  // with independent coins for the edges of weight omega_t,
+                                  // 4 / 5 = threshold sampling over Forest Fire / Weighted
+                                  // Forest Fire burn scores (exact size)
   uint32_t clim;                  // C in U = c(V)/(C k) and the stop size C k (160)
   uint32_t shrink_num, shrink_den;  // node reduction cap 5/2 (2.5x)
   uint32_t lp_rounds, ref_rounds, subrounds;  // 5, 5, 4
   uint32_t max_levels;            // 64
   uint32_t stop_num, stop_den;    // stop when stop_den*n' > stop_num*n (19/20)
+  uint32_t ff_p_num, ff_p_den;    // Forest Fire: break probability after a burn (3/5)
+  uint32_t ff_nu_num, ff_nu_den;  // Forest Fire: burn ratio nu (1/2)
 } or_params;
 
 typedef struct {
@@ -524,16 +529,131 @@ struct SparsStats {
 // floor(H * N / 2^64) < r, i.e. with probability r / N up to 2^-64.
 uint64_t mulhi64(uint64_t a, uint64_t b) { return (uint64_t)(((u128)a * b) >> 64); }
 
+// Sec. 4.2, (Weighted) Forest Fire sampling, and the appendix's WFF
+// algorithm: fires start at random nodes; a node reached by a fire burns a
+// geometric number of its not-yet-visited neighbours (a break with
+// probability p after each burn), each drawn with probability proportional
+// to its edge weight among the unvisited ones (Weighted), or uniformly; every
+// burn adds one to the edge's score; fires are scheduled while the burns so
+// far are at most nu |E|.
+// Readings (deterministic, for a data-parallel fire):
+//  * fire f starts at floor(H(FFSTART, level, f) * n / 2^64); its visited set
+//    starts empty (the start node is not in it, as in the appendix);
+//  * a fire advances one frontier at a time: every node u of frontier l
+//    draws against the visited set as it was when frontier l began; its j-th
+//    draw picks, in ascending neighbour order, the entry at which the summed
+//    weight of the still-candidate entries exceeds
+//    floor(H(FFDRAW, level, f, l, u, j) * W / 2^64) (W = their total; unit
+//    weights for Forest Fire), removes it from u's candidates and breaks
+//    iff H(FFBREAK, level, f, l, u, j) < floor(p 2^64);
+//  * several frontier nodes may draw the same neighbour v: the draw with the
+//    smallest (floor(H(FFCLAIM, level, f, l, v, u) / 2^32), u) burns, the
+//    others burn nothing; v joins the visited set and the next frontier;
+//  * fire f runs iff the burns of fires 0..f-1 are at most nu |E| (exact
+//    rational test), so the result does not depend on how many fires run
+//    side by side;
+//  * the score of an undirected edge is the number of burns of either of its
+//    two entries.
+// Returns the score of every entry (equal for the two entries of an edge).
+struct FireStats {
+  uint64_t fires = 0, burns = 0;
+};
+
+void default_params(or_params* p);
+
+std::vector<int64_t> fire_scores(const Graph& g, uint64_t seed, uint64_t level, bool weighted,
+                                 const or_params& p, FireStats* fs) {
+  const uint64_t n = g.n, m = g.m();
+  std::vector<int64_t> burns(g.adj.size(), 0);
+  FireStats st;
+  if (n == 0 || m == 0) {
+    if (fs) *fs = st;
+    return burns;
+  }
+  // break iff H < floor(p 2^64); p >= 1 always breaks
+  const bool always = p.ff_p_num >= p.ff_p_den;
+  const uint64_t pthr = always ? 0 : (uint64_t)(((u128)p.ff_p_num << 64) / p.ff_p_den);
+  std::vector<uint8_t> visited(n);
+  for (uint64_t f = 0; (u128)st.burns * p.ff_nu_den <= (u128)p.ff_nu_num * m; ++f) {
+    std::fill(visited.begin(), visited.end(), 0);
+    std::vector<uint32_t> frontier{(uint32_t)mulhi64(H(seed, TAG_FFSTART, {level, f}), n)};
+    for (uint64_t l = 0; !frontier.empty(); ++l) {
+      // draws of every frontier node against the visited set of this frontier
+      struct Claim {
+        uint64_t key;  // the claim hash's upper 32 bits
+        uint32_t u;
+        uint64_t e;
+      };
+      std::vector<std::pair<uint32_t, Claim>> claims;  // (v, claim)
+      for (uint32_t u : frontier) {
+        std::vector<uint64_t> cand;  // entries of u's row to unvisited nodes, row order
+        for (uint64_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e)
+          if (!visited[g.adj[e]]) cand.push_back(e);
+        for (uint64_t j = 0; !cand.empty(); ++j) {
+          int64_t W = 0;
+          for (uint64_t e : cand) W += weighted ? g.ew[e] : 1;
+          const uint64_t R = mulhi64(H(seed, TAG_FFDRAW, {level, f, l, (uint64_t)u, j}), (uint64_t)W);
+          size_t pick = 0;
+          for (int64_t acc = 0; pick < cand.size(); ++pick) {
+            acc += weighted ? g.ew[cand[pick]] : 1;
+            if ((uint64_t)acc > R) break;
+          }
+          const uint64_t e = cand[pick];
+          const uint32_t v = g.adj[e];
+          claims.push_back(
+              {v, Claim{H(seed, TAG_FFCLAIM, {level, f, l, (uint64_t)v, (uint64_t)u}) >> 32, u, e}});
+          cand.erase(cand.begin() + pick);
+          if (always || H(seed, TAG_FFBREAK, {level, f, l, (uint64_t)u, j}) < pthr) break;
+        }
+      }
+      // one burn per claimed node: the smallest (key, u)
+      std::sort(claims.begin(), claims.end(), [](const auto& a, const auto& b) {
+        if (a.first != b.first) return a.first < b.first;
+        if (a.second.key != b.second.key) return a.second.key < b.second.key;
+        return a.second.u < b.second.u;
+      });
+      std::vector<uint32_t> next;
+      for (size_t i = 0; i < claims.size(); ++i) {
+        if (i > 0 && claims[i].first == claims[i - 1].first) continue;
+        burns[claims[i].second.e] += 1;
+        st.burns += 1;
+        visited[claims[i].first] = 1;
+        next.push_back(claims[i].first);
+      }
+      frontier.swap(next);
+    }
+    st.fires = f + 1;
+  }
+  // score of an edge: burns of both its entries (rows are sorted)
+  std::vector<int64_t> score(g.adj.size(), 0);
+  for (uint64_t u = 0; u < n; ++u)
+    for (uint64_t e = g.xadj[u]; e < g.xadj[u + 1]; ++e) {
+      const uint32_t v = g.adj[e];
+      const auto first = g.adj.begin() + g.xadj[v], last = g.adj.begin() + g.xadj[v + 1];
+      const uint64_t r = (uint64_t)(std::lower_bound(first, last, (uint32_t)u) - g.adj.begin());
+      score[e] = burns[e] + burns[r];
+    }
+  if (fs) *fs = st;
+  return score;
+}
+
 Graph sparsify(const Graph& g, uint64_t m_hat, uint64_t seed, uint64_t level, uint32_t sampler,
-               SparsStats* st) {
+               SparsStats* st, const or_params* fp = nullptr, FireStats* fst = nullptr) {
+  // selection key of an edge: its weight, or its fire score (samplers 4, 5)
   struct E {
     uint32_t a, b;
-    int64_t w;
+    int64_t w, key;
   };
+  std::vector<int64_t> score;
+  if (sampler == 4 || sampler == 5) {
+    or_params dp;
+    if (!fp) default_params(&dp);
+    score = fire_scores(g, seed, level, sampler == 5, fp ? *fp : dp, fst);
+  }
   std::vector<E> edges;
   for (uint64_t a = 0; a < g.n; ++a)
     for (uint64_t e = g.xadj[a]; e < g.xadj[a + 1]; ++e)
-      if (a < g.adj[e]) edges.push_back({(uint32_t)a, g.adj[e], g.ew[e]});
+      if (a < g.adj[e]) edges.push_back({(uint32_t)a, g.adj[e], g.ew[e], score.empty() ? g.ew[e] : score[e]});
   std::vector<uint8_t> keep(edges.size(), 0);
   SparsStats s;
   if (sampler == 1) {
@@ -544,15 +664,15 @@ Graph sparsify(const Graph& g, uint64_t m_hat, uint64_t seed, uint64_t level, ui
     }
   } else if (m_hat > 0 && !edges.empty()) {
     std::vector<int64_t> ws(edges.size());
-    for (size_t i = 0; i < edges.size(); ++i) ws[i] = edges[i].w;
+    for (size_t i = 0; i < edges.size(); ++i) ws[i] = edges[i].key;
     std::nth_element(ws.begin(), ws.begin() + (m_hat - 1), ws.end(), std::greater<int64_t>());
     s.w_t = ws[m_hat - 1];
     std::vector<std::pair<uint64_t, size_t>> eq;  // (hash, edge index); edges listed by (a, b)
     for (size_t i = 0; i < edges.size(); ++i) {
-      if (edges[i].w > s.w_t) {
+      if (edges[i].key > s.w_t) {
         keep[i] = 1;
         s.n_gt++;
-      } else if (edges[i].w == s.w_t) {
+      } else if (edges[i].key == s.w_t) {
         s.n_eq++;
         eq.push_back({H(seed, TAG_SPARS, {level, (uint64_t)edges[i].a, (uint64_t)edges[i].b}), i});
       }
@@ -622,6 +742,8 @@ void default_params(or_params* p) {
   p->lp_rounds = 5; p->ref_rounds = 5; p->subrounds = 4;
   p->max_levels = 64;
   p->stop_num = 19; p->stop_den = 20;
+  p->ff_p_num = 3; p->ff_p_den = 5;
+  p->ff_nu_num = 1; p->ff_nu_den = 2;
 }
 
 int64_t cluster_limit(int64_t cV, uint32_t k, const or_params& p) {
@@ -689,7 +811,7 @@ Hierarchy coarsen(const Graph& g1, uint32_t k, uint64_t seed, const or_params& p
     li.nclusters_lp = st.nclusters_lp;
     if (budget_triggers(li.m_prime, li.m_hat, p)) {
       SparsStats ss;
-      Graph gs = sparsify(gp, li.m_hat, seed, i + 1, p.sampler, &ss);
+      Graph gs = sparsify(gp, li.m_hat, seed, i + 1, p.sampler, &ss, &p);
       li.triggered = 1;
       li.w_t = ss.w_t;
       li.n_gt = ss.n_gt;
@@ -887,6 +1009,22 @@ uint32_t or_label_propagation(const or_graph* v, uint32_t* label, int64_t* W, ui
   return r;
 }
 
+// (Weighted) Forest Fire scores of every entry of a graph (canonical rows);
+// stats_out = {fires run, burns}.
+void or_fire_scores(const or_graph* v, uint64_t seed, uint64_t level, uint32_t weighted,
+                    uint32_t p_num, uint32_t p_den, uint32_t nu_num, uint32_t nu_den,
+                    int64_t* scores_out, uint64_t* stats_out) {
+  Graph g = from_view(v);
+  or_params p;
+  default_params(&p);
+  p.ff_p_num = p_num, p.ff_p_den = p_den, p.ff_nu_num = nu_num, p.ff_nu_den = nu_den;
+  FireStats fs;
+  std::vector<int64_t> sc = fire_scores(g, seed, level, weighted != 0, p, &fs);
+  std::memcpy(scores_out, sc.data(), sc.size() * sizeof(int64_t));
+  stats_out[0] = fs.fires;
+  stats_out[1] = fs.burns;
+}
+
 // Contract a clustering; returns a graph handle, map_out[n].
 void* or_contract(const or_graph* v, const uint32_t* label, uint32_t* map_out) {
   Graph g = from_view(v);
@@ -904,14 +1042,15 @@ int or_budget_triggers(uint64_t m_prime, uint64_t m_hat, const or_params* p) {
   return budget_triggers(m_prime, m_hat, *p) ? 1 : 0;
 }
 
-// Sparsify to m_hat with the given sampler (0, 1 or 3); stats_out = {w_t,
-// n_gt, n_eq} (zeros for uniform sampling).
+// Sparsify to m_hat with the given sampler (0, 1, 3, or 4 / 5 for the
+// (Weighted) Forest Fire scores under p's fire parameters, defaults when p
+// is NULL); stats_out = {w_t, n_gt, n_eq} (zeros for uniform sampling).
 void* or_sparsify(const or_graph* v, uint64_t m_hat, uint64_t seed, uint64_t level,
-                  uint32_t sampler, int64_t* stats_out) {
+                  uint32_t sampler, const or_params* p, int64_t* stats_out) {
   Graph g = from_view(v);
   SparsStats s;
   Handle* h = new Handle();
-  h->g = sparsify(g, m_hat, seed, level, sampler, &s);
+  h->g = sparsify(g, m_hat, seed, level, sampler, &s, p);
   stats_out[0] = s.w_t;
   stats_out[1] = (int64_t)s.n_gt;
   stats_out[2] = (int64_t)s.n_eq;

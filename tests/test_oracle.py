@@ -764,3 +764,219 @@ def test_thread_count_does_not_change_results(name):
     assert len(h1.levels) == len(h4.levels) and h1.info == h4.info
     for a, b in zip(h1.levels, h4.levels):
         assert np.array_equal(a.adjncy, b.adjncy) and np.array_equal(a.adjwgt, b.adjwgt)
+
+
+# ---------------------------------------------------- (Weighted) Forest Fire --
+def _fire_bruteforce(g, seed, level, weighted, p, nu):
+    """The Forest Fire reading of the oracle, from scratch with Python
+    containers: per-fire visited sets, frontier-synchronous draws, claims
+    resolved by the smallest (hi32 H(FFCLAIM), u), fires while the burns so
+    far are at most nu |E|.  Returns (entry scores, fires, burns)."""
+    n, m = g.n, g.nnz // 2
+    xadj = g.xadj.astype(np.int64)
+    ew = np.ones(g.nnz, np.int64) if g.adjwgt is None else np.asarray(g.adjwgt, np.int64)
+    pthr = 1 << 64 if p[0] >= p[1] else (p[0] << 64) // p[1]  # p >= 1 always breaks
+    burns = np.zeros(g.nnz, np.int64)
+    total = 0
+    f = 0
+    while total * nu[1] <= nu[0] * m and m > 0:
+        visited = set()
+        frontier = [(O.H(seed, O.TAGS["FFSTART"], level, f) * n) >> 64]
+        lvl = 0
+        while frontier:
+            claims = []
+            for u in frontier:
+                cand = [e for e in range(xadj[u], xadj[u + 1]) if int(g.adjncy[e]) not in visited]
+                j = 0
+                while cand:
+                    W = sum(int(ew[e]) if weighted else 1 for e in cand)
+                    R = (O.H(seed, O.TAGS["FFDRAW"], level, f, lvl, u, j) * W) >> 64
+                    acc, pick = 0, 0
+                    for pick, e in enumerate(cand):
+                        acc += int(ew[e]) if weighted else 1
+                        if acc > R:
+                            break
+                    e = cand.pop(pick)
+                    v = int(g.adjncy[e])
+                    claims.append((v, O.H(seed, O.TAGS["FFCLAIM"], level, f, lvl, v, u) >> 32, u, e))
+                    brk = O.H(seed, O.TAGS["FFBREAK"], level, f, lvl, u, j) < pthr
+                    j += 1
+                    if brk:
+                        break
+            claims.sort()
+            nxt = []
+            for i, (v, _, _, e) in enumerate(claims):
+                if i and claims[i - 1][0] == v:
+                    continue
+                burns[e] += 1
+                total += 1
+                visited.add(v)
+                nxt.append(v)
+            frontier = nxt
+            lvl += 1
+        f += 1
+    score = burns.copy()
+    for u in range(n):
+        for e in range(xadj[u], xadj[u + 1]):
+            v = int(g.adjncy[e])
+            r = xadj[v] + int(np.searchsorted(g.adjncy[xadj[v]:xadj[v + 1]], u))
+            score[e] = burns[e] + burns[r]
+    return score, f, total
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("weighted", [True, False])
+def test_fire_scores_match_bruteforce(seed, weighted):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(15, 60))
+    g = T.random_graph(n, int(rng.integers(n, 3 * n)), rng, wmax=7)
+    p = [(3, 5), (1, 3), (1, 1)][seed % 3]
+    nu = [(1, 2), (2, 1)][seed % 2]
+    want, fires, burns = _fire_bruteforce(g, seed, 4, weighted, p, nu)
+    got, st = O.fire_scores(g, seed, 4, weighted, p, nu)
+    assert np.array_equal(got, want)
+    assert st == dict(fires=fires, burns=burns)
+    # every burn counts once for its edge, on both entries
+    assert got.sum() == 2 * burns
+
+
+def test_fire_schedule_stops_at_the_burn_budget():
+    # fires run while the burns so far are <= nu |E|: the last fire started
+    # at or below the budget and ended above it (or the budget is never hit)
+    g, _, _, _ = gg.workload("rmat12")
+    for nu in [(1, 10), (1, 2), (3, 2)]:
+        _, st = O.fire_scores(g, 7, 2, True, (3, 5), nu)
+        _, fewer = O.fire_scores(g, 7, 2, True, (3, 5),
+                                 (st["burns"] * nu[1] - 1, nu[1] * g.m))  # a hair below
+        assert st["burns"] * nu[1] > nu[0] * g.m
+        assert fewer["fires"] <= st["fires"]
+
+
+def test_weighted_fire_draw_frequencies():
+    # star with leaf weights 1..8, p = 1 (one draw per reached node) and
+    # nu |E| < 1 (one fire).  A fire that starts at leaf j burns (j, centre);
+    # the centre, whose only visited neighbour set is {centre}, then draws one
+    # leaf i with probability w_i / sum(w) (Weighted Forest Fire) or 1/8
+    # (Forest Fire); leaf i has no unvisited neighbour left.  Over many seeds
+    # the centre's draws follow those probabilities (chi-square).
+    leaves = 8
+    w = np.arange(1, leaves + 1, dtype=np.int64)
+    g = T.from_edges(leaves + 1, [(0, i) for i in range(1, leaves + 1)], w)
+    for weighted in (True, False):
+        counts = np.zeros(leaves, np.int64)
+        starts = 0
+        for seed in range(4000):
+            start = (O.H(seed, O.TAGS["FFSTART"], 1, 0) * g.n) >> 64
+            if start == 0:
+                continue
+            sc, st = O.fire_scores(g, seed, 1, weighted, (1, 1), (1, 100))
+            assert st == dict(fires=1, burns=2)
+            row = sc[g.xadj[0]:g.xadj[1]].copy()
+            row[start - 1] -= 1  # the start leaf's own burn
+            assert row.sum() == 1 and row.min() == 0
+            counts += row
+            starts += 1
+        prob = w / w.sum() if weighted else np.full(leaves, 1 / leaves)
+        exp = starts * prob
+        chi2 = float(((counts - exp) ** 2 / exp).sum())
+        assert chi2 < stats.chi2.ppf(0.999, leaves - 1), (weighted, counts, exp)
+    # and the two rules tell each other apart: uniform draws fail the weighted law
+    assert counts[-1] < starts * (w[-1] / w.sum()) * 0.8
+
+
+@pytest.mark.parametrize("sampler", [4, 5])
+@pytest.mark.parametrize("seed", range(4))
+def test_fire_sparsify_keeps_the_top_scored_edges(sampler, seed):
+    # threshold sampling on fire scores: the m_hat edges first in
+    # (score desc, H(SPARS, level, a, b), a, b) order, from the brute-force
+    # scores above
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(20, 50))
+    g = T.random_graph(n, int(rng.integers(2 * n, 4 * n)), rng, wmax=5)
+    level = 3
+    score, _, _ = _fire_bruteforce(g, seed, level, sampler == 5, (3, 5), (1, 2))
+    a, b, _ = T.edges_of(g)
+    xadj = g.xadj.astype(np.int64)
+    sc = []
+    for x, y in zip(a, b):
+        e = xadj[x] + int(np.searchsorted(g.adjncy[xadj[x]:xadj[x + 1]], y))
+        sc.append(int(score[e]))
+    order = sorted(range(len(a)), key=lambda i: (-sc[i], O.H(seed, O.TAGS["SPARS"], level,
+                                                             int(a[i]), int(b[i])),
+                                                 int(a[i]), int(b[i])))
+    for m_hat in (0, 1, g.m // 3, g.m - 1, g.m):
+        out, st = O.sparsify(g, m_hat, seed, level, sampler)
+        want = {(int(a[i]), int(b[i])) for i in order[:m_hat]}
+        oa, ob, _ = T.edges_of(out)
+        assert set(zip(oa.tolist(), ob.tolist())) == want
+        if m_hat:
+            assert st["w_t"] == sc[order[m_hat - 1]]
+        T.check_canonical(out)
+
+
+@pytest.mark.parametrize("sampler", [4, 5])
+def test_fire_hierarchy_invariants(sampler):
+    g = gg.er(1 << 14, 1 << 18, seed=5)
+    p = O.params(sampler=sampler)
+    h = O.coarsen(g, 16, 1, p)
+    trig = 0
+    for i, lv in enumerate(h.levels):
+        T.check_canonical(lv)
+        if i and h.info[i]["triggered"]:
+            trig += 1
+            assert lv.m == h.info[i]["m_hat"]
+    assert trig >= 1
+
+
+def test_fire_schedule_runs_a_fire_at_equality():
+    # a fire starts when the burns so far equal nu |E| exactly
+    g, _, _, _ = gg.workload("rmat12")
+    _, one = O.fire_scores(g, 3, 2, True, (3, 5), (1, 1 << 30))
+    assert one["fires"] == 1
+    b1 = one["burns"]
+    _, st = O.fire_scores(g, 3, 2, True, (3, 5), (b1, g.m))  # budget = b1 exactly
+    assert st["fires"] >= 2
+    _, below = O.fire_scores(g, 3, 2, True, (3, 5), (b1 - 1, g.m))
+    assert below["fires"] == 1
+
+
+def _claim_collision(seed, level, n, v, skip):
+    """Two node ids u1 < u2 (not in skip) whose claims on v at fire 0,
+    frontier 1 have equal upper 32 hash bits while u1's full hash is the
+    larger (so only the rule's u tie-break picks u1), or None."""
+    seen = {}
+    for u in range(n):
+        if u in skip:
+            continue
+        h = O.H(seed, O.TAGS["FFCLAIM"], level, 0, 1, v, u)
+        k = h >> 32
+        if k in seen and seen[k][1] > h:
+            return seen[k][0], u
+        seen.setdefault(k, (u, h))
+    return None
+
+
+def test_fire_claim_ties_go_to_the_smaller_node():
+    # start s burns u1 and u2 (p = 0: no break), both draw v in frontier 1
+    # with equal claim keys; the burn goes to the smaller id
+    level, n = 2, 1 << 17
+    for seed in range(20):
+        s = (O.H(seed, O.TAGS["FFSTART"], level, 0) * n) >> 64
+        v = 0 if s != 0 else 1
+        pair = _claim_collision(seed, level, n, v, {s, v})
+        if pair:
+            break
+    assert pair, "no 32-bit claim collision found"
+    u1, u2 = pair
+    g = T.from_edges(n, sorted(tuple(sorted(e)) for e in [(s, u1), (s, u2), (u1, v), (u2, v)]))
+    sc, st = O.fire_scores(g, seed, level, False, (0, 1), (1, 1 << 30))
+    assert st["fires"] == 1
+    xadj = g.xadj.astype(np.int64)
+
+    def score(a, b):
+        row = g.adjncy[xadj[a]:xadj[a + 1]]
+        return int(sc[xadj[a] + int(np.searchsorted(row, b))])
+
+    assert score(u1, v) == 1 and score(u2, v) == 0
+    want, _, _ = _fire_bruteforce(g, seed, level, False, (0, 1), (1, 1 << 30))
+    assert np.array_equal(sc, want)
