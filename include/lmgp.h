@@ -91,7 +91,12 @@ typedef struct {
                                   * 3 = weighted threshold sampling with each edge of
                                   * weight omega_t kept with probability
                                   * (m_hat - |E'^>|)/|E'^=|.  Coins are
-                                  * H(seed, SPARS, level, a, b) as 64-bit fractions. */
+                                  * H(seed, SPARS, level, a, b) as 64-bit fractions.
+                                  * 4 / 5 = threshold sampling (as 0) on Forest Fire
+                                  * / Weighted Forest Fire burn scores instead of
+                                  * weights (Sec. 4.2, the appendix's WFF algorithm;
+                                  * see lmgp_fire_scores); the sampled levels are
+                                  * stored with sorted rows.                          */
   uint32_t clim;                 /* C = 160: U = c(V)/(C k), stop at C k nodes     */
   uint32_t shrink_num, shrink_den; /* node reduction cap 5/2 = 2.5x (Sec. 4.3)     */
   uint32_t lp_rounds;            /* LP clustering rounds, 5                        */
@@ -122,6 +127,11 @@ typedef struct {
                                   * device when at least 16 graphs of a batch share their
                                   * coarsest level, else on the host.  Same result
                                   * either way.                                       */
+  uint32_t ff_p_num, ff_p_den;   /* samplers 4, 5: a node reached by a fire stops
+                                  * drawing after each draw with probability
+                                  * p = 3/5                                          */
+  uint32_t ff_nu_num, ff_nu_den; /* samplers 4, 5: burn ratio nu = 1/2; fires are
+                                  * started while the burns so far are <= nu |E|     */
 } lmgp_params;
 
 #define LMGP_IP_HOST 0u
@@ -247,6 +257,28 @@ lmgp_status lmgp_partition(lmgp_graph *g, uint32_t k, double eps, uint64_t seed,
 lmgp_status lmgp_partition_noalloc(lmgp_graph *g, uint32_t k, double eps, uint64_t seed,
                                    const lmgp_params *params, void *stream, uint32_t *block_out,
                                    uint32_t block_on_device, lmgp_result *res);
+
+/* (Weighted) Forest Fire burn scores (Sec. 4.2; the appendix's WFF
+ * algorithm), as samplers 4 (weighted = 0) and 5 (weighted = 1) compute them
+ * on a coarse level whose hash index is `level`.  Fires start at node
+ * floor(H(seed, FFSTART, level, f) n / 2^64) while the burns so far are at
+ * most nu |E| (nu from params, NULL = defaults).  A fire spreads one frontier
+ * at a time: each frontier node u draws, without replacement, among the
+ * neighbours not visited when the frontier began, its j-th draw taking the
+ * first entry of its row (ascending) at which the summed weight (1 per entry
+ * when weighted = 0) of the remaining candidates exceeds
+ * floor(H(seed, FFDRAW, level, f, l, u, j) W / 2^64), W their total; it stops
+ * after a draw iff p >= 1 or H(seed, FFBREAK, level, f, l, u, j) <
+ * floor(p 2^64).  A node drawn by several frontier nodes is burned by the
+ * draw with the smallest (H(seed, FFCLAIM, level, f, l, v, u) >> 32, u); it
+ * is then visited and in the next frontier.  score_out[e] (nnz entries,
+ * device memory if out_on_device = 1, else host) receives the burns of entry
+ * e's undirected edge; stats_out (3 entries, may be NULL) receives the
+ * number of fires, burns and frontier steps.  The graph's rows must be
+ * sorted (LMGP_EINVAL otherwise). */
+lmgp_status lmgp_fire_scores(const lmgp_graph *g, uint64_t seed, uint64_t level, uint32_t weighted,
+                             const lmgp_params *params, void *stream, uint32_t *score_out,
+                             uint32_t out_on_device, uint64_t *stats_out);
 
 /* Partitions `count` graphs as one batched run: every kernel launch covers
  * all graphs of the batch.  Outputs are identical to `count` separate

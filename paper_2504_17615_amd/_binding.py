@@ -31,7 +31,8 @@ class Params(ctypes.Structure):
     _fields_ = [(nm, ctypes.c_uint32) for nm in (
         "tau_e_num", "tau_e_den", "tau_d_num", "tau_d_den", "rho_num", "rho_den", "sampler",
         "clim", "shrink_num", "shrink_den", "lp_rounds", "ref_rounds", "subrounds",
-        "max_levels", "stop_num", "stop_den", "tune", "graph_rounds", "ip_device")]
+        "max_levels", "stop_num", "stop_den", "tune", "graph_rounds", "ip_device",
+        "ff_p_num", "ff_p_den", "ff_nu_num", "ff_nu_den")]
 
 
 class CsrView(ctypes.Structure):
@@ -104,6 +105,9 @@ _SIGS = {
     "lmgp_partition_noalloc": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_double,
                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int),
+    "lmgp_fire_scores": ([ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                          ctypes.c_void_p], ctypes.c_int),
     "lmgp_partition_batch": ([ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_void_p,
                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                              ctypes.c_void_p], ctypes.c_int),
@@ -300,6 +304,27 @@ class DeviceGraph:
         _check(fn(self._h, k, eps, seed, ctypes.byref(params) if params is not None else None,
                   _stream_ptr(stream), ptr, on_dev, ctypes.byref(res)))
         return blocks, res.as_dict()
+
+    def fire_scores(self, seed: int, level: int, weighted: bool = True,
+                    params: Optional[Params] = None, stream=None, out=None,
+                    host_out: bool = False):
+        """(Weighted) Forest Fire burn score of every entry (lmgp_fire_scores).
+        Returns (scores, dict(fires=, burns=, steps=)); scores is an int32
+        torch tensor on the device (bit pattern of the uint32 scores) or a
+        numpy uint32 array if host_out."""
+        if host_out:
+            sc = np.empty(max(self.nnz, 1), np.uint32)
+            ptr, on_dev = sc.ctypes.data, 0
+        else:
+            torch = _torch()
+            sc = out if out is not None else torch.empty(max(self.nnz, 1), dtype=torch.int32,
+                                                         device="cuda")
+            ptr, on_dev = sc.data_ptr(), 1
+        st = (ctypes.c_uint64 * 3)()
+        _check(library().lmgp_fire_scores(self._h, seed, level, int(bool(weighted)),
+                                          ctypes.byref(params) if params is not None else None,
+                                          _stream_ptr(stream), ptr, on_dev, st))
+        return sc[:self.nnz], dict(fires=int(st[0]), burns=int(st[1]), steps=int(st[2]))
 
     def coarsen(self, k: int, seed: int = 1, params: Optional[Params] = None, stream=None):
         h = ctypes.c_void_p()

@@ -512,6 +512,57 @@ lmgp_status lmgp_partition(lmgp_graph* g, uint32_t k, double eps, uint64_t seed,
   });
 }
 
+lmgp_status lmgp_fire_scores(const lmgp_graph* g, uint64_t seed, uint64_t level, uint32_t weighted,
+                             const lmgp_params* params, void* stream, uint32_t* score_out,
+                             uint32_t out_on_device, uint64_t* stats_out) {
+  return guard([&] {
+    if (!g) throw InvalidArg("NULL graph");
+    if (!score_out && g->g.nnz) throw InvalidArg("score_out is NULL");
+    if (!g->g.rows_sorted) throw InvalidArg("fire scores need a graph with sorted rows");
+    const lmgp_params p = params ? *params : default_params();
+    check_params(p);
+    const InputGraph& ig = g->g;
+    const hipStream_t s = (hipStream_t)stream;
+    Pool& pool = *ig.pool;
+    FireLevel fl;
+    fl.n = ig.n;
+    fl.nnz = ig.nnz;
+    fl.xadj = ig.xadj.get();
+    fl.adj = ig.adj.get();
+    fl.ew = ig.ew();
+    fl.ew_kind = ig.ew_kind;
+    fl.src = ig.src.get();
+    fl.weighted = weighted != 0;
+    fl.p_num = p.ff_p_num, fl.p_den = p.ff_p_den;
+    fl.nu_num = p.ff_nu_num, fl.nu_den = p.ff_nu_den;
+    std::vector<FireGraph> fg(1);
+    fg[0].node_base = 0;
+    fg[0].n = ig.n;
+    fg[0].e0 = 0;
+    fg[0].e1 = ig.nnz;
+    auto pre = [&](uint64_t tag) { return hash_add(hash_prefix(seed, tag), level); };
+    fg[0].pre_start = pre(TAG_FFSTART);
+    fg[0].pre_draw = pre(TAG_FFDRAW);
+    fg[0].pre_break = pre(TAG_FFBREAK);
+    fg[0].pre_claim = pre(TAG_FFCLAIM);
+    DBuf<uint32_t> tmp;
+    uint32_t* dst = score_out;
+    if (!out_on_device) {
+      tmp.reset(&pool, s, ig.nnz ? ig.nnz : 1);
+      dst = tmp.get();
+    }
+    fire_scores(fl, fg, dst, pool, s);
+    if (!out_on_device && ig.nnz)
+      HIP_CHECK(hipMemcpyAsync(score_out, dst, ig.nnz * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (stats_out) {
+      stats_out[0] = fg[0].fires;
+      stats_out[1] = fg[0].burns;
+      stats_out[2] = fg[0].steps;
+    }
+  });
+}
+
 lmgp_status lmgp_partition_batch(lmgp_graph* const* graphs, const uint32_t* k, const double* eps,
                                  const uint64_t* seed, uint32_t count, const lmgp_params* params,
                                  void* stream, uint32_t* const* block_out, uint32_t block_on_device,

@@ -57,7 +57,11 @@ enum HashTag : uint64_t {
   TAG_IP = 7,      // initial bipartitioning start nodes
   TAG_RSUB = 8,    // refinement sub-round
   TAG_RTIE = 9,    // refinement tie-break
-  TAG_RADM = 10    // refinement admission order
+  TAG_RADM = 10,   // refinement admission order
+  TAG_FFSTART = 11,  // (Weighted) Forest Fire: start node of a fire
+  TAG_FFDRAW = 12,   // a frontier node's draw among its unvisited neighbours
+  TAG_FFBREAK = 13,  // whether the node stops drawing after a draw
+  TAG_FFCLAIM = 14   // which of several draws of one node burns it
 };
 
 // Sub-round of a node: floor(hi32(h) * S / 2^32).

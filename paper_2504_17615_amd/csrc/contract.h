@@ -72,7 +72,8 @@ struct SparsGraph {
   uint64_t e0 = 0, e1 = 0;   // entry range of the graph
   uint64_t m_hat = 0;
   bool triggered = false;
-  uint32_t sampler = 0;      // 0 exact-size threshold, 1 uniform, 3 threshold with coins
+  uint32_t sampler = 0;      // 0 exact-size threshold, 1 uniform, 3 threshold with
+                             // coins, 4 / 5 exact-size threshold on fire scores
   uint64_t pre = 0;          // H(seed, SPARS, level) prefix
   // outputs
   int64_t w_t = 0;
@@ -91,9 +92,39 @@ struct SparsOut {
 
 // Sparsify the triggered graphs of a union level in place of a new CSR.  The
 // weights are int64 (ew_kind EW_I64) or int32 (EW_I32) and keep their width.
+// Threshold sampling selects on the weights, or on `score` (one per entry,
+// symmetric) when it is given.
 void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
                     const void* ew, int ew_kind, const uint32_t* src, const uint32_t* gid,
-                    std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s);
+                    const uint32_t* score, std::vector<SparsGraph>& graphs, SparsOut& out,
+                    Pool& pool, hipStream_t s);
+
+// ------------------------------------------------ (Weighted) Forest Fire --
+// A union level with sorted rows, and the fire parameters: break probability
+// p = p_num / p_den, burn ratio nu = nu_num / nu_den.
+struct FireLevel {
+  uint64_t n = 0, nnz = 0;
+  const uint64_t* xadj = nullptr;
+  const uint32_t* adj = nullptr;
+  const void* ew = nullptr;
+  int ew_kind = EW_UNIT;
+  const uint32_t* src = nullptr;
+  bool weighted = true;  // Weighted Forest Fire (draws by edge weight), else Forest Fire
+  uint32_t p_num = 3, p_den = 5, nu_num = 1, nu_den = 2;
+};
+struct FireGraph {
+  uint64_t node_base = 0, n = 0;
+  uint64_t e0 = 0, e1 = 0;  // entry range of the graph
+  // H(seed, tag, level) prefixes of the four fire hashes
+  uint64_t pre_start = 0, pre_draw = 0, pre_break = 0, pre_claim = 0;
+  bool active = true;
+  // outputs
+  uint64_t fires = 0, burns = 0, steps = 0;
+};
+// Burn scores of every entry of the active graphs (score[e] = burns of e's
+// undirected edge; entries of inactive graphs are zero).
+void fire_scores(const FireLevel& lv, std::vector<FireGraph>& graphs, uint32_t* score, Pool& pool,
+                 hipStream_t s);
 
 // --------------------------------------------------------------- refinement --
 void project_blocks(const uint32_t* map, const uint32_t* cblock, uint64_t n, uint32_t* block,

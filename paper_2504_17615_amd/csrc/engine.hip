@@ -556,13 +556,17 @@ lmgp_params default_params() {
   p.tune = LMGP_TUNE_OFF;
   p.graph_rounds = 0;
   p.ip_device = LMGP_IP_AUTO;
+  p.ff_p_num = 3, p.ff_p_den = 5;
+  p.ff_nu_num = 1, p.ff_nu_den = 2;
   return p;
 }
 
 void check_params(const lmgp_params& p) {
   if (!p.tau_e_den || !p.tau_d_den || !p.rho_den) throw InvalidArg("zero denominator in params");
-  if (p.sampler > 3)
-    throw InvalidArg("sampler must be 0 (threshold), 1 (uniform), 2 (off) or 3 (threshold, coins)");
+  if (p.sampler > 5)
+    throw InvalidArg("sampler must be 0 (threshold), 1 (uniform), 2 (off), 3 (threshold, coins), "
+                     "4 (threshold on Forest Fire scores) or 5 (on Weighted Forest Fire scores)");
+  if (!p.ff_p_den || !p.ff_nu_den) throw InvalidArg("zero denominator in the fire parameters");
   if (!p.clim) throw InvalidArg("clim must be positive");
   if (!p.shrink_num) throw InvalidArg("shrink_num must be positive");
   if (!p.subrounds || p.subrounds > 32) throw InvalidArg("subrounds must be in [1, 32]");
@@ -1608,10 +1612,58 @@ void Engine::coarsen(std::vector<Job>& jobs) {
       any_trig |= trig;
       ++c;
     }
+    // fire samplers: the draws scan rows in ascending order, so the coarse
+    // rows are sorted first (and the level keeps them sorted)
+    const bool fire = any_trig && (p_.sampler == 4 || p_.sampler == 5);
     if (any_trig) {
+      const uint32_t* sadj = co.adj.get();
+      const void* sew = co.weights();
+      int sewk = co.ew_kind;
+      const uint32_t* ssrc = co.src.get();
+      DBuf<uint32_t> f_adj, f_src, score;
+      DBuf<int64_t> f_ew;
+      if (fire) {
+        sort_rows(co.nc, co.nnz, co.xadj.get(), co.adj.get(), co.weights(), co.ew_kind,
+                  packed_ ? 1 : 0, f_adj, f_ew, f_src, pool_, s_);
+        sadj = f_adj.get();
+        sew = f_ew.get();
+        sewk = EW_I64;
+        ssrc = f_src.get();
+        FireLevel fl;
+        fl.n = co.nc;
+        fl.nnz = co.nnz;
+        fl.xadj = co.xadj.get();
+        fl.adj = sadj;
+        fl.ew = sew;
+        fl.ew_kind = sewk;
+        fl.src = ssrc;
+        fl.weighted = p_.sampler == 5;
+        fl.p_num = p_.ff_p_num, fl.p_den = p_.ff_p_den;
+        fl.nu_num = p_.ff_nu_num, fl.nu_den = p_.ff_nu_den;
+        std::vector<FireGraph> fg(BC);
+        for (uint32_t c = 0, b = 0; b < B; ++b) {
+          if (!keep[b]) continue;
+          const Job& jb = jobs[L.graphs[b]];
+          const uint64_t lv = depth + 1 - jb.d0;  // the level being created
+          FireGraph& g = fg[c];
+          g.node_base = C->nbase[c];
+          g.n = C->nbase[c + 1] - C->nbase[c];
+          g.e0 = C->ebase[c];
+          g.e1 = C->ebase[c + 1];
+          g.pre_start = chain(jb.seed, TAG_FFSTART, {lv});
+          g.pre_draw = chain(jb.seed, TAG_FFDRAW, {lv});
+          g.pre_break = chain(jb.seed, TAG_FFBREAK, {lv});
+          g.pre_claim = chain(jb.seed, TAG_FFCLAIM, {lv});
+          g.active = sgs[c].triggered;
+          ++c;
+        }
+        score.reset(&pool_, s_, co.nnz ? co.nnz : 1);
+        fire_scores(fl, fg, score.get(), pool_, s_);
+      }
       SparsOut so;
-      sparsify_level(co.nc, co.nnz, co.xadj.get(), co.adj.get(), co.weights(), co.ew_kind,
-                     co.src.get(), BC > 1 ? co.gid.get() : nullptr, sgs, so, pool_, s_);
+      sparsify_level(co.nc, co.nnz, co.xadj.get(), sadj, sew, sewk, ssrc,
+                     BC > 1 ? co.gid.get() : nullptr, fire ? score.get() : nullptr, sgs, so,
+                     pool_, s_);
       C->nnz = so.nnz;
       C->o_xadj = std::move(so.xadj);
       C->o_adj = std::move(so.adj);
@@ -1630,7 +1682,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     }
     C->o_nw = std::move(co.nw);
     if (BC > 1) C->o_gid = std::move(co.gid);
-    C->sorted = false;
+    C->sorted = fire;
     C->xadj = C->o_xadj.get();
     C->adj = C->o_adj.get();
     C->ew = C->ew_kind == EW_I32 ? (const void*)C->o_ew32.get() : (const void*)C->o_ew.get();

@@ -1,4 +1,5 @@
-// Weighted threshold sampling (Sec. 4.2).  omega_t is the weight of the
+// Weighted threshold sampling (Sec. 4.2), on the edge weights or on
+// (Weighted) Forest Fire scores.  omega_t is the weight (score) of the
 // m_hat-th heaviest coarse edge; heavier edges are kept, lighter ones
 // dropped, and among the edges of weight omega_t exactly r = m_hat - |E^>|
 // are kept: those with the smallest (H(seed, SPARS, level, a, b), a, b),
@@ -18,14 +19,14 @@ namespace lmgp {
 
 namespace {
 
-template <typename WT>
-__global__ __launch_bounds__(256) void k_wmax(const WT* ew, uint64_t e0, uint64_t e1,
+template <typename KT>
+__global__ __launch_bounds__(256) void k_wmax(const KT* key, uint64_t e0, uint64_t e1,
                                               unsigned long long* out) {
   __shared__ int64_t sm[NWAVE];
   int64_t m = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride)
-    m = (int64_t)ew[e] > m ? (int64_t)ew[e] : m;
+    m = (int64_t)key[e] > m ? (int64_t)key[e] : m;
   m = wave_reduce_max(m);
   if (lane_id() == 0) sm[threadIdx.x / WAVE] = m;
   __syncthreads();
@@ -35,8 +36,8 @@ __global__ __launch_bounds__(256) void k_wmax(const WT* ew, uint64_t e0, uint64_
   }
 }
 
-template <typename WT>
-__global__ __launch_bounds__(256) void k_whist(const WT* ew, uint64_t e0, uint64_t e1,
+template <typename KT>
+__global__ __launch_bounds__(256) void k_whist(const KT* key, uint64_t e0, uint64_t e1,
                                                int shift, uint64_t prefix,
                                                unsigned long long* hist) {
   // a block counts fewer than 2^32 entries; the device-wide bins are 64-bit
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_whist(const WT* ew, uint64_t e0, uint64
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const int hs = shift + 8;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
-    const uint64_t w = (uint64_t)(int64_t)ew[e];
+    const uint64_t w = (uint64_t)(int64_t)key[e];
     const bool match = hs >= 64 || (w >> hs) == (prefix >> hs);
     if (match) atomicAdd(&h[(w >> shift) & 0xFF], 1u);
   }
@@ -59,9 +60,9 @@ LMGP_D uint64_t edge_key(uint64_t pre, uint64_t a, uint64_t b) {
 }
 
 // 12-bit histogram of the top bits of the keys of E^= (a < b entries only).
-template <typename WT>
+template <typename KT>
 __global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32_t* adj,
-                                               const WT* ew, uint64_t e0, uint64_t e1,
+                                               const KT* key, uint64_t e0, uint64_t e1,
                                                int64_t w_t, uint64_t base, uint64_t pre,
                                                unsigned long long* hist) {
   __shared__ uint32_t h[4096];
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(256) void k_khist(const uint32_t* src, const uint32
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
     const uint32_t a = src[e], b = adj[e];
-    if (a < b && (int64_t)ew[e] == w_t)
+    if (a < b && (int64_t)key[e] == w_t)
       atomicAdd(&h[edge_key(pre, a - base, b - base) >> 52], 1u);
   }
   __syncthreads();
@@ -83,16 +84,16 @@ struct EqEntry {
   uint32_t a, b;  // local ids
 };
 
-template <typename WT>
+template <typename KT>
 __global__ __launch_bounds__(256) void k_kgather(const uint32_t* src, const uint32_t* adj,
-                                                 const WT* ew, uint64_t e0, uint64_t e1,
+                                                 const KT* key, uint64_t e0, uint64_t e1,
                                                  int64_t w_t, uint64_t base, uint64_t pre,
                                                  uint32_t bucket, EqEntry* out,
                                                  unsigned long long* cnt, uint64_t cap) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
     const uint32_t a = src[e], b = adj[e];
-    if (a < b && (int64_t)ew[e] == w_t) {
+    if (a < b && (int64_t)key[e] == w_t) {
       const uint64_t k = edge_key(pre, a - base, b - base);
       if ((k >> 52) == bucket) {
         const uint64_t p = atomicAdd(cnt, 1ull);
@@ -116,8 +117,8 @@ struct SparsDesc {
   uint64_t coin_n, coin_r;
 };
 
-template <typename WT>
-__global__ void k_keep(const uint32_t* src, const uint32_t* adj, const WT* ew,
+template <typename KT>
+__global__ void k_keep(const uint32_t* src, const uint32_t* adj, const KT* keyv,
                        const uint32_t* gid, const SparsDesc* sd, uint64_t nnz, uint8_t* keep) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
@@ -129,7 +130,7 @@ __global__ void k_keep(const uint32_t* src, const uint32_t* adj, const WT* ew,
   if (d.mode == 3) {
     k = __umul64hi(edge_key(d.pre, a, b), d.coin_n) < d.coin_r;
   } else if (d.mode != 0) {
-    const int64_t w = (int64_t)ew[e];
+    const int64_t w = (int64_t)keyv[e];
     if (w > d.w_t) k = 1;
     else if (w < d.w_t) k = 0;
     else if (d.mode == 1) k = 1;
@@ -175,9 +176,10 @@ unsigned sweep_grid(uint64_t cnt) {
 
 namespace {
 
-template <typename WT>
+// Selection on `key` (the weights, or the fire scores), output weights `ew`.
+template <typename WT, typename KT>
 void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
-                const WT* ew, const uint32_t* src, const uint32_t* gid,
+                const WT* ew, const KT* key, const uint32_t* src, const uint32_t* gid,
                 std::vector<SparsGraph>& graphs, SparsOut& out, WT* (*alloc_w)(SparsOut&, uint64_t, Pool&, hipStream_t),
                 Pool& pool, hipStream_t s) {
   const size_t B = graphs.size();
@@ -205,7 +207,7 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
     }
     const uint64_t e0 = sg.e0, e1 = sg.e1;
     dmax.zero();
-    k_wmax<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, dmax.get());
+    k_wmax<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(key, e0, e1, dmax.get());
     LAUNCH_CHECK();
     unsigned long long wmax = 0;
     read_now(&wmax, dmax.get(), sizeof(wmax), s);
@@ -213,13 +215,13 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
     while (top < 64 && (wmax >> top) != 0) top += 8;
     // the weight of every entry per 8-bit digit pass, with the host's digit
     // choice between passes
-    ProfScope prof_sel("sp:select", sizeof(WT) * (e1 - e0) * (top / 8), s);
+    ProfScope prof_sel("sp:select", sizeof(KT) * (e1 - e0) * (top / 8), s);
     // (2 m_hat)-th largest directed weight
     uint64_t R = 2 * sg.m_hat, gt = 0, eq = 0, prefix = 0;
     std::vector<unsigned long long> h(256);
     for (int shift = top - 8; shift >= 0; shift -= 8) {
       hist.zero();
-      k_whist<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(ew, e0, e1, shift, prefix, hist.get());
+      k_whist<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(key, e0, e1, shift, prefix, hist.get());
       LAUNCH_CHECK();
       read_now(h.data(), hist.get(), 256 * sizeof(unsigned long long), s);
       uint64_t cum = 0;
@@ -254,9 +256,9 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
     }
     // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t:
     // row, neighbour and weight of every entry in two passes
-    ProfScope prof_hs("sp:hash_select", 2 * (8 + sizeof(WT)) * (e1 - e0), s);
+    ProfScope prof_hs("sp:hash_select", 2 * (8 + sizeof(KT)) * (e1 - e0), s);
     hist.zero();
-    k_khist<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
+    k_khist<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, key, e0, e1, sg.w_t, sg.node_base,
                                                  sg.pre, hist.get());
     LAUNCH_CHECK();
     std::vector<unsigned long long> kh(4096);
@@ -274,7 +276,7 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
     const uint64_t bsz = kh[bucket];
     DBuf<EqEntry> buf(&pool, s, bsz ? bsz : 1);
     cnt.zero();
-    k_kgather<WT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, ew, e0, e1, sg.w_t, sg.node_base,
+    k_kgather<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, key, e0, e1, sg.w_t, sg.node_base,
                                                    sg.pre, bucket, buf.get(), cnt.get(), bsz);
     LAUNCH_CHECK();
     std::vector<EqEntry> hb(bsz);
@@ -295,13 +297,13 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
   // weight) and flagged, positions scanned, the kept ones written
   uint64_t kept_est = 0;
   for (const SparsGraph& sg : graphs) kept_est += sg.triggered ? 2 * sg.m_hat : sg.e1 - sg.e0;
-  ProfScope prof_cp("sp:compact", (8 + sizeof(WT) + 1 + 8) * nnz + (8 + sizeof(WT)) * kept_est +
+  ProfScope prof_cp("sp:compact", (8 + sizeof(KT) + 1 + 8) * nnz + (8 + sizeof(WT)) * kept_est +
                                       16 * (n + 1), s);
   DBuf<SparsDesc> dd(&pool, s, B);
   HIP_CHECK(hipMemcpyAsync(dd.get(), desc.data(), B * sizeof(SparsDesc), hipMemcpyHostToDevice, s));
   DBuf<uint8_t> keep(&pool, s, nnz ? nnz : 1);
   if (nnz) {
-    k_keep<WT><<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, ew, gid, dd.get(), nnz, keep.get());
+    k_keep<KT><<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, key, gid, dd.get(), nnz, keep.get());
     LAUNCH_CHECK();
   }
   DBuf<uint64_t> pos(&pool, s, nnz + 1);
@@ -338,15 +340,27 @@ int32_t* alloc_w32(SparsOut& o, uint64_t n, Pool& pool, hipStream_t s) {
 
 void sparsify_level(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* adj,
                     const void* ew, int ew_kind, const uint32_t* src, const uint32_t* gid,
-                    std::vector<SparsGraph>& graphs, SparsOut& out, Pool& pool, hipStream_t s) {
-  if (ew_kind == EW_I32)
-    sparsify_t<int32_t>(n, nnz, xadj, adj, (const int32_t*)ew, src, gid, graphs, out, alloc_w32,
-                        pool, s);
-  else if (ew_kind == EW_I64)
-    sparsify_t<int64_t>(n, nnz, xadj, adj, (const int64_t*)ew, src, gid, graphs, out, alloc_w64,
-                        pool, s);
-  else
+                    const uint32_t* score, std::vector<SparsGraph>& graphs, SparsOut& out,
+                    Pool& pool, hipStream_t s) {
+  if (ew_kind == EW_I32) {
+    const int32_t* w = (const int32_t*)ew;
+    if (score)
+      sparsify_t<int32_t, uint32_t>(n, nnz, xadj, adj, w, score, src, gid, graphs, out, alloc_w32,
+                                    pool, s);
+    else
+      sparsify_t<int32_t, int32_t>(n, nnz, xadj, adj, w, w, src, gid, graphs, out, alloc_w32, pool,
+                                   s);
+  } else if (ew_kind == EW_I64) {
+    const int64_t* w = (const int64_t*)ew;
+    if (score)
+      sparsify_t<int64_t, uint32_t>(n, nnz, xadj, adj, w, score, src, gid, graphs, out, alloc_w64,
+                                    pool, s);
+    else
+      sparsify_t<int64_t, int64_t>(n, nnz, xadj, adj, w, w, src, gid, graphs, out, alloc_w64, pool,
+                                   s);
+  } else {
     throw InvalidArg("sparsification needs stored edge weights");
+  }
 }
 
 }  // namespace lmgp
