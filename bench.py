@@ -420,6 +420,9 @@ ABLATION_SETTINGS = [
     ("UR", dict(sampler=1)),
     ("UR tau_e=1/4 tau_d=1 rho=2", dict(sampler=1, tau_e_num=1, tau_e_den=4, tau_d_num=1,
                                         tau_d_den=1, rho_num=2)),
+    # threshold sampling on Weighted / plain Forest Fire scores, p = 0.6, nu = 0.5
+    ("T-WFF", dict(sampler=5)),
+    ("T-FF", dict(sampler=4)),
 ]
 
 

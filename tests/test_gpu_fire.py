@@ -40,8 +40,10 @@ def _with_isolated(g_base, extra):
 
 def _graph(name):
     rng = np.random.default_rng(7)
-    if name == "star1000":
+    if name == "star1000":  # hub row in the register-mask range (256 < deg <= 4096)
         return _star(1000, rng)
+    if name == "star5000":  # hub row beyond it (flags in device memory)
+        return _star(5000, rng)
     if name == "rgg14":
         return gg.rgg(1 << 14, seed=3)
     if name == "er12_iso":
@@ -62,6 +64,8 @@ CASES = [
     ("grid64", False, (0, 1), (1, 4)),
     ("star1000", True, (1, 5), (2, 1)),
     ("star1000", False, (0, 1), (5, 1)),
+    ("star5000", True, (1, 10), (1, 1)),
+    ("star5000", False, (0, 1), (2, 1)),
 ]
 
 
