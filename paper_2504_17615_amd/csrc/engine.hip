@@ -863,7 +863,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   const uint64_t bmin = bmin_env ? std::strtoull(bmin_env, nullptr, 10) : BOUNDARY_MIN_NODES;
   if (spec.refine && n >= bmin && L.nnz && !(p_.graph_rounds && n <= REPLAY_MAX_NODES)) {
     ProfScope prof("rf:boundary", (8 + (label8.get() ? 2 : 8)) * L.nnz + 2 * n, s_);
-    bflag.reset(&pool_, s_, n);
+    bflag.reset(&pool_, s_, (n + 7) / 8 * 8);  // zero-padded to whole 8-byte words
     bflag.zero();
     k_boundary<<<grid_for(L.nnz, 256), 256, 0, s_>>>(L.src, L.adj, L.nnz, label, label8.get(),
                                                       bflag.get());
@@ -877,6 +877,14 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     read_now(&nb, bcount.get(), sizeof(nb), s_);
     bmode = 2 * nb <= n;
     if (!bmode) bflag.clear();
+  }
+  // boundary mode: each sub-round's flagged nodes, listed before bucketing
+  DBuf<uint32_t> subids, subcnt;
+  DBuf<unsigned long long> nsub;
+  if (bmode) {
+    subids.reset(&pool_, s_, n);
+    subcnt.reset(&pool_, s_, SUB_LIST_BLOCKS);
+    nsub.reset(&pool_, s_, 1);
   }
   const std::vector<CutPreset>& presets = cut_presets(dense);
   int preset = p_.tune >= LMGP_TUNE_FORCE ? (int)((p_.tune - LMGP_TUNE_FORCE) % presets.size()) : 0;
@@ -925,6 +933,24 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.cuts = presets[preset].cuts;
   ba.only = bmode ? bflag.get() : nullptr;
   ba.only_sub = 0;
+  // the three bucket passes: over all nodes, or (boundary mode) over the list
+  // of the flagged nodes of sub-round ba.only_sub
+  auto bucket_passes = [&](hipStream_t st) {
+    if (!bmode) {
+      launch_bucket_count(ba, st);
+      launch_bucket_offsets(ba, st);
+      launch_bucket_scatter(ba, st);
+      return;
+    }
+    launch_sub_list(ba, bflag.get(), subcnt.get(), subids.get(), nsub.get(), st);
+    BucketArgs bl = ba;
+    bl.only = nullptr;
+    bl.ids = subids.get();
+    bl.nids = nsub.get();
+    launch_bucket_count(bl, st);
+    launch_bucket_offsets(bl, st);
+    launch_bucket_scatter(bl, st);
+  };
   // Stop decisions (node-reduction cap after a sub-round, no moves in a
   // round) are taken on the device; the host reads the active flags together
   // with the next round's bucket counts, in one copy per round.
@@ -935,11 +961,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       ProfScope prof(spec.refine ? "rf:bucket" : "cl:bucket", 52 * n, s_);
       k_lp_round<<<1, 256, 0, s_>>>(ctl, r, nullptr);  // also clears the bucket counters
       LAUNCH_CHECK();
-      launch_bucket_count(ba, s_);
-      launch_bucket_offsets(ba, s_);
       // the lists too, before the host waits: the scatter needs only the
       // device's offsets, and the first rating launch then follows the wait
-      launch_bucket_scatter(ba, s_);
+      bucket_passes(s_);
     }
     d2h(hstate, rstate.get(), nstate, s_);
     sync(s_);
@@ -952,12 +976,12 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   // moves of the sub-rounds before it (flags have grown since)
   auto begin_sub = [&](uint32_t sr) {
     {
-      ProfScope prof("rf:bucket", 2 * n + 52 * (uint64_t)L.nnz / 8, s_);
+      // the flags (8 per word) and, per listed node, its list slot written
+      // and read and its bucket pass bytes (an eighth of the nodes, say)
+      ProfScope prof("rf:bucket", n + 60 * (n / 8), s_);
       device_zero(rstate.get(), 2 * NB * sizeof(unsigned long long), s_);
       ba.only_sub = sr;
-      launch_bucket_count(ba, s_);
-      launch_bucket_offsets(ba, s_);
-      launch_bucket_scatter(ba, s_);
+      bucket_passes(s_);
     }
     d2h(hstate, rstate.get(), 2 * NB, s_);
     sync(s_);

@@ -1399,7 +1399,9 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
   }
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < a.n; u += stride) {
+  const uint64_t cnt = a.ids ? *a.nids : a.n;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+    const uint64_t u = a.ids ? a.ids[i] : i;
     int b = bucket_of(a, u);
     if (b >= 0) {
       atomicAdd(&h[b], 1u);
@@ -1466,26 +1468,101 @@ constexpr int BK_ITEMS = 8;
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
   __shared__ uint32_t cnt[MAX_BUCKETS], base[MAX_BUCKETS];
-  for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256) cnt[i] = 0;
-  __syncthreads();
-  const uint64_t b0 = (uint64_t)blockIdx.x * 256 * BK_ITEMS;
-  int bk[BK_ITEMS];
-  uint32_t lp[BK_ITEMS];
+  // node range: one tile per block; node list: tiles grid-strided over its
+  // device-side length
+  const uint64_t total = a.ids ? *a.nids : a.n;
+  const uint64_t tile = 256 * BK_ITEMS;
+  const uint64_t step = a.ids ? (uint64_t)gridDim.x * tile : total + tile;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * tile; b0 < total; b0 += step) {
+    for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256) cnt[i] = 0;
+    __syncthreads();
+    int bk[BK_ITEMS];
+    uint32_t lp[BK_ITEMS], uu[BK_ITEMS];
 #pragma unroll
-  for (int j = 0; j < BK_ITEMS; ++j) {
-    const uint64_t u = b0 + (uint64_t)j * 256 + threadIdx.x;
-    bk[j] = u < a.n ? bucket_of(a, u) : -1;
-    lp[j] = bk[j] >= 0 ? atomicAdd(&cnt[bk[j]], 1u) : 0u;
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256)
-    if (cnt[i]) base[i] = atomicAdd(&a.fill[i], cnt[i]);
-  __syncthreads();
+    for (int j = 0; j < BK_ITEMS; ++j) {
+      const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
+      uu[j] = i < total ? (a.ids ? a.ids[i] : (uint32_t)i) : 0u;
+      bk[j] = i < total ? bucket_of(a, uu[j]) : -1;
+      lp[j] = bk[j] >= 0 ? atomicAdd(&cnt[bk[j]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256)
+      if (cnt[i]) base[i] = atomicAdd(&a.fill[i], cnt[i]);
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < BK_ITEMS; ++j) {
-    const uint64_t u = b0 + (uint64_t)j * 256 + threadIdx.x;
-    if (bk[j] >= 0) a.list[a.offs[bk[j]] + base[bk[j]] + lp[j]] = (uint32_t)u;
+    for (int j = 0; j < BK_ITEMS; ++j)
+      if (bk[j] >= 0) a.list[a.offs[bk[j]] + base[bk[j]] + lp[j]] = uu[j];
+    __syncthreads();  // cnt and base are rewritten by the next tile
   }
+}
+
+// The flagged nodes of sub-round only_sub, listed in ascending order (the
+// rating kernels read the rows of nearby nodes together): block b takes a
+// contiguous chunk of 8-byte flag words (most words of a boundary are zero
+// and cost one load), k_sub_count counts its nodes, k_sub_write adds the
+// counts of the blocks before it and writes them.
+constexpr unsigned SUB_BLOCKS = SUB_LIST_BLOCKS;
+
+// bit i: node w * 8 + i is flagged and in sub-round only_sub
+LMGP_D uint32_t sub_select(const BucketArgs& a, const uint8_t* flag, uint64_t w) {
+  uint64_t bits = ((const uint64_t*)flag)[w];
+  uint32_t sel = 0;
+  while (bits) {
+    const int byte = __builtin_ctzll(bits) >> 3;
+    bits &= ~(0xFFull << (byte * 8));
+    const uint64_t u = w * 8 + (uint64_t)byte;
+    if (u >= a.n) break;
+    const GraphDesc& gd = a.gd[graph_of(a.gid, u)];
+    if (subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds) == a.only_sub)
+      sel |= 1u << byte;
+  }
+  return sel;
+}
+
+// words [w0, w1) of block b, split into 256 contiguous runs
+LMGP_D void sub_chunk(uint64_t words, uint64_t& w0, uint64_t& w1) {
+  const uint64_t per = (words + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = b0 + per < words ? b0 + per : words;
+  const uint64_t tper = (per + 255) / 256;
+  w0 = b0 + (uint64_t)threadIdx.x * tper;
+  w1 = w0 + tper;
+  if (w0 > b1) w0 = b1;
+  if (w1 > b1) w1 = b1;
+}
+
+__global__ __launch_bounds__(256) void k_sub_count(BucketArgs a, const uint8_t* flag,
+                                                   uint32_t* block_cnt) {
+  __shared__ uint32_t sm[NWAVE];
+  uint64_t w0, w1;
+  sub_chunk((a.n + 7) / 8, w0, w1);
+  uint32_t c = 0;
+  for (uint64_t w = w0; w < w1; ++w) c += (uint32_t)__popc(sub_select(a, flag, w));
+  const uint32_t tot = block_reduce_sum(c, sm);
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_sub_write(BucketArgs a, const uint8_t* flag,
+                                                   const uint32_t* block_cnt, uint32_t* ids,
+                                                   unsigned long long* nids) {
+  __shared__ uint32_t sm[NWAVE];
+  uint32_t before = 0;
+  for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) before += block_cnt[b];
+  before = block_reduce_sum(before, sm);
+  uint64_t w0, w1;
+  sub_chunk((a.n + 7) / 8, w0, w1);
+  uint32_t c = 0;
+  for (uint64_t w = w0; w < w1; ++w) c += (uint32_t)__popc(sub_select(a, flag, w));
+  uint32_t tot;
+  uint64_t at = before + block_exclusive_scan(c, sm, tot);
+  for (uint64_t w = w0; w < w1; ++w) {
+    uint32_t sel = sub_select(a, flag, w);
+    while (sel) {
+      const int byte = __builtin_ctz(sel);
+      sel &= sel - 1;
+      ids[at++] = (uint32_t)(w * 8 + (uint64_t)byte);
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *nids = before + tot;
 }
 
 // ------------------------------------------------------------- admission --
@@ -1952,7 +2029,19 @@ void launch_lp_plan(const unsigned long long* counts, const uint32_t* offs, uint
 
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s) {
   if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
-  k_bucket_scatter<<<grid_for(a.n, 256 * BK_ITEMS), 256, 0, s>>>(a);
+  unsigned g = grid_for(a.n, 256 * BK_ITEMS);
+  if (a.ids && g > 1024) g = 1024;  // tiles strided over the list's length
+  k_bucket_scatter<<<g, 256, 0, s>>>(a);
+  LAUNCH_CHECK();
+}
+
+void launch_sub_list(const BucketArgs& a, const uint8_t* flag, uint32_t* block_cnt,
+                     uint32_t* ids, unsigned long long* nids, hipStream_t s) {
+  unsigned g = grid_for((a.n + 7) / 8, 256);
+  if (g > SUB_BLOCKS) g = SUB_BLOCKS;
+  k_sub_count<<<g, 256, 0, s>>>(a, flag, block_cnt);
+  LAUNCH_CHECK();
+  k_sub_write<<<g, 256, 0, s>>>(a, flag, block_cnt, ids, nids);
   LAUNCH_CHECK();
 }
 
