@@ -87,9 +87,9 @@ __global__ void k_copy_i64(int64_t* d, const int64_t* s, uint64_t n) {
 struct LpCtl {
   GraphDesc* gd;
   uint32_t B;
-  unsigned long long* moves;        // moves of the current sub-round (admission output)
-  unsigned long long* delta;        // cluster-count change of the sub-round (two's complement)
-  unsigned long long* round_moves;  // moves of the current round
+  unsigned long long* moves;        // 1 if the current sub-round moved a node (admission output)
+  unsigned long long* delta;        // non-empty clusters after the sub-round (counted from W)
+  unsigned long long* round_moves;  // sub-rounds of the current round that moved a node
   unsigned long long* ncl;          // cluster count (clustering) or NULL
   uint32_t* rounds_run;             // rounds in which the graph was active
   unsigned long long* rstate;       // [2 nb] bucket counters, then [B] active flags,
@@ -108,7 +108,7 @@ __global__ void k_lp_after_sub(LpCtl c) {
     if (g.active) {
       c.round_moves[b] += c.moves[b];
       if (c.ncl) {
-        c.ncl[b] += c.delta[b];
+        c.ncl[b] = c.delta[b];  // counted from the cluster weights
         if ((u128)c.shrink_num * c.ncl[b] <= (u128)c.shrink_den * g.nodes) g.active = 0;
       }
     }
@@ -1088,7 +1088,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.seg = seg.get();
     aa.csize = csize;
     aa.moves = (uint64_t*)dmoves.get();
-    aa.ncl_delta = ncl ? (int64_t*)ddelta.get() : nullptr;
+    aa.ncl_count = ncl ? (int64_t*)ddelta.get() : nullptr;
+    aa.nlabels = nlabels;
     aa.few = few;
     aa.label8 = label8.get();
     return aa;

@@ -215,8 +215,11 @@ struct AdmitArgs {
   uint32_t* cpos;
   uint32_t* seg;
   uint32_t* csize;         // member counts (clustering) or NULL
-  uint64_t* moves;         // per graph
-  int64_t* ncl_delta;      // per graph (clustering) or NULL
+  uint64_t* moves;         // per graph: set to 1 when the sub-round moved a node
+  int64_t* ncl_count;      // per graph (clustering): non-empty clusters after the
+                           // sub-round, counted from Wmut over nlabels labels
+                           // (zero before); NULL in refinement
+  uint64_t nlabels;
   uint32_t few;            // labels < few <= FEW_LABELS (see RateArgs), else 0
   const SubPlan* plan;     // planned launch: max_cands is an upper bound, the
                            // slot count is plan->total

@@ -1568,6 +1568,15 @@ __global__ __launch_bounds__(256) void k_sub_write(BucketArgs a, const uint8_t* 
 // ------------------------------------------------------------- admission --
 LMGP_D uint32_t cand_graph(const AdmitArgs& a, uint32_t u) { return graph_of(a.gid, u); }
 
+// A graph's sub-round made a move: only "any move" is read (a round without
+// moves ends the graph's LP), so the counter is a flag.  One add per wave on
+// a single address would serialise (tens of thousands per launch); a load
+// that already sees the flag skips the store.
+LMGP_D void mark_moved(const AdmitArgs& a, uint32_t g) {
+  if (__hip_atomic_load(&a.moves[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    __hip_atomic_store(&a.moves[g], (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Few labels (refinement): per-target demand and candidate count from
 // block-privatised LDS histograms, one global atomic per block and target.
 constexpr int ADM_ITEMS = 8;
@@ -1670,7 +1679,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
       if (a.label8) a.label8[c.u] = (uint8_t)c.tgt;
       atomicAdd((unsigned long long*)&dw[c.tgt], (unsigned long long)cu);
       atomicAdd((unsigned long long*)&dw[own], (unsigned long long)(-cu));
-      if (a.gid) atomicAdd((unsigned long long*)&a.moves[a.gid[c.u]], 1ull);
+      if (a.gid) mark_moved(a, a.gid[c.u]);
       else ++mv;
     }
   }
@@ -1680,7 +1689,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
   if (!a.gid) {
     uint64_t tot;
     (void)block_exclusive_scan(mv, smv, tot);
-    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&a.moves[0], (unsigned long long)tot);
+    if (threadIdx.x == 0 && tot) mark_moved(a, 0);
   }
 }
 
@@ -1932,7 +1941,6 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
   const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t mv = 0;
-  int64_t dl = 0;
   if (i < nc && a.adm[i]) {
     const Cand c = a.cands[i];
     const uint32_t t = c.tgt;
@@ -1940,22 +1948,16 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
     const int64_t cu = a.nw[c.u];
     a.label[c.u] = t;
     if (a.label8) a.label8[c.u] = (uint8_t)t;
-    const int64_t old_t = (int64_t)atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
-    const int64_t old_o =
-        (int64_t)atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
-    // clusters that become non-empty / empty; the sum over all moves is order
-    // independent because W never goes negative
+    // no return values needed: the clusters that became empty or non-empty
+    // are counted from W afterwards (k_count_clusters)
+    atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
+    atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
     mv = 1;
-    dl = (old_t == 0 ? 1 : 0) - (old_o == cu ? 1 : 0);
     if (a.csize) {
       atomicAdd(&a.csize[t], 1u);
       atomicSub(&a.csize[own], 1u);
     }
-    if (a.gid) {
-      const uint32_t g = a.gid[c.u];
-      atomicAdd((unsigned long long*)&a.moves[g], 1ull);
-      if (a.ncl_delta && dl) atomicAdd((unsigned long long*)&a.ncl_delta[g], (unsigned long long)dl);
-    }
+    if (a.gid) mark_moved(a, a.gid[c.u]);
   }
   // clear the per-target scratch for the next sub-round (no kernel of this
   // admission reads it any more)
@@ -1967,14 +1969,42 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
       a.fill[t] = 0;
     }
   }
-  if (!a.gid) {  // one graph: one atomic per wave
-    mv = wave_reduce_sum(mv);
-    dl = wave_reduce_sum(dl);
-    if (lane_id() == 0) {
-      if (mv) atomicAdd((unsigned long long*)&a.moves[0], (unsigned long long)mv);
-      if (a.ncl_delta && dl) atomicAdd((unsigned long long*)&a.ncl_delta[0], (unsigned long long)dl);
-    }
+  if (!a.gid && __ballot(mv != 0) && lane_id() == 0) mark_moved(a, 0);
+}
+
+// Non-empty clusters per graph after the moves.  Labels of one graph are
+// contiguous, so a block's chunk spans few graphs: counts of the chunk's
+// first graph stay in registers, the others go to LDS counters, and the
+// block adds one total per graph (one counter per graph takes every block's
+// add, so per-label or per-wave global atomics would serialise).
+constexpr unsigned COUNT_BLOCKS = 1024;
+constexpr uint32_t COUNT_SPAN = 256;
+
+__global__ __launch_bounds__(256) void k_count_clusters(AdmitArgs a) {
+  __shared__ uint32_t cnt[COUNT_SPAN];
+  __shared__ uint32_t sm[NWAVE];
+  const uint64_t n = a.nlabels;
+  const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t k0 = (uint64_t)blockIdx.x * chunk;
+  const uint64_t k1 = k0 + chunk < n ? k0 + chunk : n;
+  if (k0 >= k1) return;
+  const uint32_t g0 = graph_of(a.gid, k0);
+  const uint32_t span = graph_of(a.gid, k1 - 1) - g0 + 1;
+  for (uint32_t i = threadIdx.x; i < COUNT_SPAN; i += 256) cnt[i] = 0;
+  __syncthreads();
+  uint32_t mine = 0;  // labels of graph g0
+  for (uint64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+    if (a.Wmut[k] <= 0) continue;
+    const uint32_t g = graph_of(a.gid, k);
+    if (g == g0) ++mine;
+    else if (span <= COUNT_SPAN) atomicAdd(&cnt[g - g0], 1u);
+    else atomicAdd((unsigned long long*)&a.ncl_count[g], 1ull);
   }
+  mine = block_reduce_sum(mine, sm);  // contains the barrier before cnt is read
+  if (threadIdx.x == 0) cnt[0] += mine;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < span && i < COUNT_SPAN; i += 256)
+    if (cnt[i]) atomicAdd((unsigned long long*)&a.ncl_count[g0 + i], (unsigned long long)cnt[i]);
 }
 
 
@@ -2049,7 +2079,7 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
   if (a.max_cands == 0) return;
   const unsigned g = grid_for(a.max_cands, 256);
   const bool few = a.few > 0 && a.few <= FEW_LABELS;
-  const bool few_apply = few && !a.csize && !a.ncl_delta;
+  const bool few_apply = few && !a.csize && !a.ncl_count;
   if (a.few > FEW_LABELS) throw InvalidArg("too many labels for the few-label admission");
   if (few) {
     const unsigned gi = grid_for(a.max_cands, 256 * ADM_ITEMS);
@@ -2080,6 +2110,12 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
     }
   }
   LAUNCH_CHECK();
+  if (a.ncl_count && a.nlabels) {
+    unsigned gc = grid_for(a.nlabels, 256 * 16);
+    if (gc > COUNT_BLOCKS) gc = COUNT_BLOCKS;
+    k_count_clusters<<<gc, 256, 0, s>>>(a);
+    LAUNCH_CHECK();
+  }
 }
 
 }  // namespace lmgp
