@@ -163,12 +163,13 @@ __global__ void k_boundary(const uint32_t* src, const uint32_t* adj, uint64_t nn
 
 __global__ __launch_bounds__(256) void k_count_flags(const uint8_t* flag, uint64_t n,
                                                      unsigned long long* count) {
+  __shared__ uint64_t sm[NWAVE];
   uint64_t c = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     c += flag[i] != 0;
-  c = wave_reduce_sum(c);
-  if (lane_id() == 0 && c) atomicAdd(count, (unsigned long long)c);
+  c = block_reduce_sum(c, sm);  // one add per block: a single counter serialises adds
+  if (threadIdx.x == 0 && c) atomicAdd(count, (unsigned long long)c);
 }
 
 // After a sub-round: every neighbour of a node that moved may have become a
@@ -371,9 +372,11 @@ struct StartJoin {
   LMGP_D uint64_t operator()(uint64_t p) const { return mark[p] ? 1ull : (1ull << 32); }
 };
 
-__global__ void k_group_heads(const uint8_t* mark, const uint64_t* sj, uint64_t ns,
-                              const uint32_t* vals, const uint32_t* gid, uint32_t* head,
-                              unsigned long long* joins) {
+__global__ __launch_bounds__(256) void k_group_heads(const uint8_t* mark, const uint64_t* sj,
+                                                     uint64_t ns, const uint32_t* vals,
+                                                     const uint32_t* gid, uint32_t* head,
+                                                     unsigned long long* joins) {
+  __shared__ uint64_t sm[NWAVE];
   const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool join = false;
   if (p < ns) {
@@ -381,9 +384,9 @@ __global__ void k_group_heads(const uint8_t* mark, const uint64_t* sj, uint64_t 
     join = !mark[p];
     if (join && gid) atomicAdd(&joins[gid[vals[p]]], 1ull);
   }
-  if (!gid) {  // one graph: one atomic per wave
-    const uint64_t c = __popcll(__ballot(join));
-    if (lane_id() == 0 && c) atomicAdd(&joins[0], (unsigned long long)c);
+  if (!gid) {  // one graph: one add per block (a single counter serialises adds)
+    const uint64_t c = block_reduce_sum((uint64_t)(join ? 1 : 0), sm);
+    if (threadIdx.x == 0 && c) atomicAdd(&joins[0], (unsigned long long)c);
   }
 }
 

@@ -236,25 +236,48 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   int64_t r_own = 0;
   GraphDesc gd{};
   int64_t cu = 0;
+  // Clustering: the best label ignoring the capacity first (a rated node is
+  // lighter than the cap, so only the labels' weights can exclude one); if
+  // it fits, it is the best of the labels that fit, and the group read one
+  // cluster weight instead of one per label (the random gathers that count
+  // where labels are scattered).  Otherwise, and in refinement (where the
+  // best block is often full), the table is evaluated with every label's
+  // weight.
+  constexpr int SPL = T / G;  // slots per lane
+  uint32_t Ks[SPL];
+  uint64_t pre_u = 0;
+  const bool first = a.mode == MODE_LP && a.phase == 0;
   if (valid) {
     gd = a.gd[graph_of(a.gid, u)];
     cu = a.nw[u];
-    const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
-    constexpr int SPL = T / G;  // slots per lane
-    uint32_t Ks[SPL];
-    int64_t wk[SPL];
+    pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
 #pragma unroll
     for (int j = 0; j < SPL; ++j) Ks[j] = key[gl + j * G];
+    if (first || a.mode != MODE_LP) {
+#pragma unroll
+      for (int j = 0; j < SPL; ++j)
+        if (Ks[j] != EMPTY_KEY)
+          consider_w1(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, 0, pre_u,
+                      gd.label_base, best, r_own);
+    }
+  }
+  if (first || a.mode != MODE_LP) reduce_best<G>(best, r_own);
+  // the whole group holds the same best: the check and the evaluation with
+  // weights are uniform within it
+  if (valid && a.mode == MODE_LP &&
+      (!first || (best.r > 0 && a.W[best.K] + cu > gd.cap))) {
+    best = Best{0, 0, 0};
+    int64_t wk[SPL];
 #pragma unroll
     for (int j = 0; j < SPL; ++j)
-      wk[j] = (Ks[j] != EMPTY_KEY && Ks[j] != own && a.mode == MODE_LP) ? a.W[Ks[j]] : 0;
+      wk[j] = (Ks[j] != EMPTY_KEY && Ks[j] != own) ? a.W[Ks[j]] : 0;
 #pragma unroll
     for (int j = 0; j < SPL; ++j)
       if (Ks[j] != EMPTY_KEY)
         consider_w1(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, wk[j], pre_u,
                     gd.label_base, best, r_own);
   }
-  reduce_best<G>(best, r_own);
+  reduce_best<G>(best, r_own);  // idempotent for the groups that kept their best
   if (gl == 0 && idx < a.count) {
     if (valid) emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
     else no_cand(a, (uint32_t)idx);  // graph stopped
