@@ -220,14 +220,6 @@ def copy_calibration(mib: int):
     del src, dst
 
 
-def _hash64(x: int) -> int:
-    """SplitMix64 finaliser, for the seeded request mix of the serving bench."""
-    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
-    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
-    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
-    return x ^ (x >> 31)
-
-
 def bench_batch(args) -> dict:
     """Batched path: B 128x128 grids (the small configuration's shape) with
     seeds 1..B, k=4, partitioned by one lmgp_partition_batch call per step;
@@ -309,103 +301,113 @@ def bench_batch(args) -> dict:
     }
 
 
-def _request_mix(n_req: int, lo_exp: float, hi_exp: float):
-    """Seeded request mix: n = floor(10^(lo + (hi-lo) u)) nodes, a third each
-    grid / R-MAT (edge factor 16, scale round(log2 n)) / Erdos-Renyi G(n, 16n),
-    k = 2 (1 + H mod 128), eps 0.03, seed = request index."""
-    from paper_2504_17615_amd import graphgen as gg
-
-    reqs = []
-    for i in range(n_req):
-        u = (_hash64(3 * i) >> 11) / float(1 << 53)
-        n = int(10 ** (lo_exp + (hi_exp - lo_exp) * u))
-        kind = _hash64(3 * i + 1) % 3
-        k = 2 * (1 + _hash64(3 * i + 2) % 128)
-        if kind == 0:
-            rows = max(2, int(n ** 0.5))
-            g = gg.grid(rows, -(-n // rows))
-        elif kind == 1:
-            g = gg.rmat(max(4, round(np.log2(n))), seed=i + 1)
-        else:
-            g = gg.er(n, 16 * n, seed=i + 1)
-        reqs.append((g, min(k, g.n), 0.03, i + 1))
-    return reqs
-
-
 def bench_serve(args) -> dict:
-    """Serving loop: requests arrive as a Poisson process at `load` x the plain
-    path's measured capacity; latency = completion - arrival.  The plain path
-    is the same request sequence served one call at a time, FIFO, with the
-    service times measured here."""
+    """Serving loop: requests (the graphgen serving mix) arrive as a Poisson
+    process at `load` x the plain path's measured capacity; latency =
+    completion - arrival.  The plain path serves the same arrivals one call at
+    a time, FIFO, on one stream (run, not simulated); the server takes them
+    through lmgp_server on `streams` streams."""
     import threading
 
     import torch
 
     import paper_2504_17615_amd as L
+    from paper_2504_17615_amd import graphgen as gg
+
+    def note(msg):
+        print(f"serve: {msg}", file=sys.stderr, flush=True)
 
     L.library()
     t_gen = time.perf_counter()
-    reqs = _request_mix(args.requests, 3.0, args.max_exp)
+    threads = max(1, min(args.gen_threads, os.cpu_count() or 1))
+    dgs, meta = [], []  # device graphs; (n, m, k, eps, seed)
+    chunk = 64
+    for c0 in range(0, args.requests, chunk):
+        part = gg.request_mix(min(chunk, args.requests - c0), 3.0, args.max_exp, threads, first=c0)
+        for g, k, eps, seed in part:
+            dgs.append(L.create_graph(g))
+            meta.append((g.n, g.m, k, eps, seed))
+        del part
+        note(f"generated and uploaded {len(dgs)} / {args.requests} requests "
+             f"({time.perf_counter() - t_gen:.0f} s)")
     t_gen = time.perf_counter() - t_gen
-    dgs = [L.create_graph(g) for g, _, _, _ in reqs]
-    m_tot = sum(g.m for g, _, _, _ in reqs)
+    m_tot = sum(x[1] for x in meta)
     prm = L.default_params(ip_device=args.ip_device)
-    for i in range(min(8, len(reqs))):
-        dgs[i].partition(reqs[i][1], reqs[i][2], reqs[i][3], prm, host_out=True)
+    for i in range(min(8, len(dgs))):
+        dgs[i].partition(meta[i][2], meta[i][3], meta[i][4], prm, host_out=True)
     torch.cuda.synchronize()
     # plain capacity: per-request service times on one stream
-    svc = []
-    for dg, (g, k, eps, seed) in zip(dgs, reqs):
+    svc, t_last = [], time.perf_counter()
+    for i, dg in enumerate(dgs):
         t0 = time.perf_counter()
-        dg.partition(k, eps, seed, prm, host_out=True)
+        dg.partition(meta[i][2], meta[i][3], meta[i][4], prm, host_out=True)
         svc.append(time.perf_counter() - t0)
-    mu = len(reqs) / sum(svc)
+        if time.perf_counter() - t_last > 20:
+            note(f"capacity pass {i + 1} / {len(dgs)}")
+            t_last = time.perf_counter()
+    mu = len(dgs) / sum(svc)
     lam = args.load * mu
     rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
-    # plain FIFO under the same arrivals
-    fin, plain_lat = 0.0, []
-    for a, s in zip(arrivals, svc):
-        fin = max(fin, a) + s
-        plain_lat.append(fin - a)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(dgs)))
+    note(f"plain capacity {mu:.1f} requests/s, offering {lam:.1f}/s")
+    # plain FIFO under these arrivals, run: one call at a time in arrival order
+    done = np.zeros(len(dgs))
+    start, t_last = time.perf_counter() + 0.05, time.perf_counter()
+    for i, dg in enumerate(dgs):
+        dt = start + arrivals[i] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        dg.partition(meta[i][2], meta[i][3], meta[i][4], prm, host_out=True)
+        done[i] = time.perf_counter() - start
+        if time.perf_counter() - t_last > 20:
+            note(f"plain FIFO run {i + 1} / {len(dgs)}")
+            t_last = time.perf_counter()
+    plain_lat = done - arrivals
+    plain_span = done[-1] - arrivals[0]
     srv = L.Server(ip_device=args.ip_device, hbm_budget_bytes=args.hbm_budget_gib << 30,
-                   max_slots=args.slots,
-                   max_batch=args.max_batch, streams=args.streams)
-    tickets = [None] * len(reqs)
-    done = [0.0] * len(reqs)
+                   max_slots=args.slots, max_batch=args.max_batch, streams=args.streams)
+    tickets = [None] * len(dgs)
+    done = np.zeros(len(dgs))
     start = time.perf_counter() + 0.05
 
     def submitter():
-        for i, (dg, (g, k, eps, seed)) in enumerate(zip(dgs, reqs)):
+        for i, dg in enumerate(dgs):
             dt = start + arrivals[i] - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
-            tickets[i] = srv.submit(dg, k, eps, seed)
+            tickets[i] = srv.submit(dg, meta[i][2], meta[i][3], meta[i][4])
 
     th = threading.Thread(target=submitter)
     th.start()
-    for i in range(len(reqs)):
+    t_last = time.perf_counter()
+    for i in range(len(dgs)):
         while tickets[i] is None:
             time.sleep(0.0002)
         srv.wait(tickets[i])
         done[i] = time.perf_counter() - start
+        if time.perf_counter() - t_last > 20:
+            note(f"server run {i + 1} / {len(dgs)}")
+            t_last = time.perf_counter()
     th.join()
+    stats = srv.stats()
     srv.close()
-    lat = np.array(done) - arrivals
+    lat = done - arrivals
     makespan = done[-1] - arrivals[0]
+    ns = np.array([x[0] for x in meta])
     return {
         "metric": "serving latency and throughput", "value": float(np.percentile(lat, 99) * 1e3),
         "unit": "ms p99", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-        "config": {"workload": f"request mix x {len(reqs)}",
-                   "description": _request_mix.__doc__.split("\n")[0] + " ...",
+        "config": {"workload": f"request mix x {len(dgs)}",
+                   "description": gg.request_spec.__doc__.split(";")[0] + " ...",
                    "n_range": [1000, int(10 ** args.max_exp)], "load": args.load,
-                   "requests": len(reqs), "m_total": m_tot, "slots": args.slots,
-                   "max_batch": args.max_batch, "streams": args.streams},
+                   "requests": len(dgs), "m_total": m_tot, "n_mean": float(ns.mean()),
+                   "slots": args.slots, "max_batch": args.max_batch, "streams": args.streams},
         "server": {"p50_ms": float(np.percentile(lat, 50) * 1e3),
                    "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                   "graphs_per_s": len(reqs) / makespan},
+                   "graphs_per_s": len(dgs) / makespan, "stats": stats},
         "plain_fifo": {"p50_ms": float(np.percentile(plain_lat, 50) * 1e3),
                        "p99_ms": float(np.percentile(plain_lat, 99) * 1e3),
+                       "graphs_per_s": len(dgs) / plain_span,
                        "capacity_graphs_per_s": mu},
         "arrival_rate_per_s": lam, "gen_s": round(t_gen, 2),
     }
@@ -517,6 +519,8 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-prefix", type=int, default=256)
     ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--gen-threads", type=int, default=4,
+                    help="threads generating the serving mix (each generator is parallel too)")
     ap.add_argument("--max-exp", type=float, default=5.0, help="request sizes up to 10^max_exp")
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--slots", type=int, default=16)

@@ -158,3 +158,49 @@ def workload(name: str):
         s = int(name[4:])
         return grid(s, s), 4, 0.03, 1
     raise KeyError(name)
+
+
+def _mix64(x: int) -> int:
+    """SplitMix64 step (Steele, Lea, Flood, OOPSLA 2014): the request mix's
+    counter-based draws."""
+    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return x ^ (x >> 31)
+
+
+def request_spec(i: int, lo_exp: float, hi_exp: float):
+    """Request i of the serving mix: (kind, n, k) with n = floor(10^(lo + (hi -
+    lo) u)) nodes (u uniform), kind 0 grid (rows = floor(sqrt n), cols = ceil(n /
+    rows)), 1 R-MAT (edge factor 16, scale round(log2 n)), 2 Erdos-Renyi
+    G(n, 16n); k = 2 (1 + H mod 128); eps 0.03 and seed i + 1 go with it."""
+    u = (_mix64(3 * i) >> 11) / float(1 << 53)
+    n = int(10 ** (lo_exp + (hi_exp - lo_exp) * u))
+    kind = _mix64(3 * i + 1) % 3
+    k = 2 * (1 + _mix64(3 * i + 2) % 128)
+    return kind, n, k
+
+
+def request_graph(i: int, lo_exp: float, hi_exp: float):
+    """(graph, k, eps, seed) of request i of the serving mix."""
+    kind, n, k = request_spec(i, lo_exp, hi_exp)
+    if kind == 0:
+        rows = max(2, int(n ** 0.5))
+        g = grid(rows, -(-n // rows))
+    elif kind == 1:
+        g = rmat(max(4, int(round(float(np.log2(n))))), seed=i + 1)
+    else:
+        g = er(n, 16 * n, seed=i + 1)
+    return g, min(k, g.n), 0.03, i + 1
+
+
+def request_mix(n_req: int, lo_exp: float, hi_exp: float, threads: int = 1, first: int = 0):
+    """Requests first .. first + n_req - 1 of the serving mix, generated on
+    `threads` threads (the generator releases the interpreter lock)."""
+    ids = range(first, first + n_req)
+    if threads <= 1:
+        return [request_graph(i, lo_exp, hi_exp) for i in ids]
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda i: request_graph(i, lo_exp, hi_exp), ids))

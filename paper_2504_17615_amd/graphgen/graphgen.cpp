@@ -33,6 +33,7 @@
 //           probability proportional to w (inverse CDF on the prefix sums);
 //           self-loops dropped, symmetrised, deduplicated.
 #include <algorithm>
+#include <parallel/algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -222,7 +223,8 @@ void gen_er(uint64_t n, uint64_t m, uint64_t seed, Csr& out) {
     }
     kv.resize(D);
     for (uint64_t e = 0; e < D; ++e) kv[e] = {key[e], e};
-    std::sort(kv.begin(), kv.end());
+    // (key, draw index) pairs are distinct: any sort gives this order
+    __gnu_parallel::sort(kv.begin(), kv.end());
     size_t k = 0;
     for (size_t i = 0; i < kv.size(); ++i) {
       if (kv[i].first == UINT64_MAX) break;

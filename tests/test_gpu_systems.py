@@ -220,3 +220,26 @@ def test_batch_with_many_labels_equals_solo(lib):
         assert _same(res[i], r), (i, res[i], r)
     ob, ores, _ = O.partition(graphs[3], 64, 0.03, 3)
     assert np.array_equal(outs[3].cpu().numpy().view(np.uint32), ob)
+
+
+def test_server_request_mix_matches_oracle(lib):
+    # the serving mix's recipe (grid / R-MAT / Erdos-Renyi, n log-uniform in
+    # [10^3, 2 * 10^4], k = 2 (1 + H mod 128)) through the server on 4
+    # streams with runs joined in flight: every result is the oracle's
+    import math
+
+    reqs = gg.request_mix(36, 3.0, math.log10(2e4), threads=4)
+    assert max(g.n for g, _, _, _ in reqs) <= 20000 + 200
+    dgs = [lib.create_graph(g) for g, _, _, _ in reqs]
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=32, max_batch=8, streams=4)
+    print("server: request mix against the oracle", flush=True)
+    tickets = [srv.submit(dg, k, eps, seed) for dg, (_, k, eps, seed) in zip(dgs, reqs)]
+    got = [srv.wait(t) for t in tickets]
+    srv.close()
+    for i, ((g, k, eps, seed), (out, res)) in enumerate(zip(reqs, got)):
+        ob, ores, _ = O.partition(g, k, eps, seed)
+        assert res["cut"] == ores["cut"], (i, g.n, k, res["cut"], ores["cut"])
+        assert res["max_block_weight"] == ores["max_block_weight"], i
+        assert np.array_equal(out, ob), i
+    for dg in dgs:
+        dg.close()
