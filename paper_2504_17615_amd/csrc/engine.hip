@@ -148,6 +148,32 @@ __global__ void k_lp_peek(LpCtl c) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+// Member count of every label (csize zeroed before): a block counts a
+// contiguous chunk of nodes, and a run of equal labels within a wave adds
+// once, from its last lane.
+__global__ __launch_bounds__(256) void k_label_sizes(const uint32_t* label, uint64_t n,
+                                                     uint32_t* csize) {
+  const uint64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t u0 = (uint64_t)blockIdx.x * chunk;
+  const uint64_t u1 = u0 + chunk < n ? u0 + chunk : n;
+  const int lane = lane_id();
+  for (uint64_t b = u0; b < u1; b += 256) {
+    const uint64_t u = b + threadIdx.x;
+    const bool valid = u < u1;  // the valid lanes of a wave are a prefix
+    const uint32_t l = valid ? label[u] : 0u;
+    const uint32_t prev = __shfl_up(l, 1);
+    const bool head = valid && (lane == 0 || prev != l);
+    const uint64_t heads = __ballot(head), vmask = __ballot(valid);
+    const bool next_head = lane < WAVE - 1 && ((heads >> (lane + 1)) & 1);
+    const bool next_valid = lane < WAVE - 1 && ((vmask >> (lane + 1)) & 1);
+    if (valid && (next_head || !next_valid)) {
+      const uint64_t upto = heads & ((2ull << lane) - 1);  // heads at lanes <= lane
+      const int start = 63 - __builtin_clzll(upto);
+      atomicAdd(&csize[l], (uint32_t)(lane - start + 1));
+    }
+  }
+}
+
 // Refinement: a node whose neighbours all share its block has no other block
 // with a positive rating, so it can produce no move.  flag[u] = 1 for the
 // other nodes (flag zeroed before), from the entries; `count` gets the number
@@ -1441,14 +1467,21 @@ void Engine::cluster(Level& L, std::vector<Job>& jobs, std::vector<uint8_t>& act
     LAUNCH_CHECK();
     k_copy_i64<<<grid_for(n, 256), 256, 0, s_>>>(W.get(), L.nw, n);
     LAUNCH_CHECK();
-    device_fill_u32(csize.get(), 1u, n, s_);
   }
   ncl.resize(B);
   for (uint32_t b = 0; b < B; ++b) ncl[b] = L.nbase[b + 1] - L.nbase[b];
   std::vector<uint8_t> act = active;
   std::vector<uint32_t> rounds;
   LpSpec spec{false, level, p_.lp_rounds};
-  run_lp(L, jobs, spec, act, label.get(), W.get(), n, csize.get(), L.nbase, &ncl, rounds);
+  // member counts are read only after LP (2-hop, contraction): counted once
+  // from the labels instead of two atomics per move
+  run_lp(L, jobs, spec, act, label.get(), W.get(), n, nullptr, L.nbase, &ncl, rounds);
+  if (n) {
+    device_zero(csize.get(), n * sizeof(uint32_t), s_);
+    unsigned g = grid_for(n, 256 * 16);
+    k_label_sizes<<<g > 2048 ? 2048 : g, 256, 0, s_>>>(label.get(), n, csize.get());
+    LAUNCH_CHECK();
+  }
   stats.assign(B, lmgp_level_info{});
   std::vector<uint8_t> which(B, 0);
   bool any = false;
