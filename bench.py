@@ -195,6 +195,7 @@ def phase_figures(bd: dict, wall: float) -> dict:
     tot_ns = sum(v["total_ns"] for v in fam.values())
     tot_b = sum(v["bytes"] for v in fam.values())
     syncs = bd.get("host:stream_syncs", {}).get("launches")
+    launches = bd.get("host:kernel_launches", {}).get("launches")
     return {
         "coarsen_dominant": best(lambda ph: ph in COARSEN_PHASES),
         "refine_dominant": best(lambda ph: ph == "rf"),
@@ -203,6 +204,7 @@ def phase_figures(bd: dict, wall: float) -> dict:
                              "covered_ms": round(tot_ns / 1e6, 3),
                              "share_of_step": round(tot_ns / 1e9 / wall, 3)},
         "host_syncs_per_call": syncs,
+        "kernel_launches_per_call": launches,
     }
 
 

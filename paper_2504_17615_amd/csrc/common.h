@@ -32,7 +32,15 @@ struct OutOfMemory : std::runtime_error {
                                      __FILE__ + ":" + std::to_string(__LINE__));          \
   } while (0)
 
-#define LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+// Counts a kernel launch for the profiler (a relaxed atomic add while it
+// records, nothing otherwise).
+void note_launch();
+
+#define LAUNCH_CHECK()                 \
+  do {                                 \
+    HIP_CHECK(hipGetLastError());      \
+    ::lmgp::note_launch();             \
+  } while (0)
 
 // ------------------------------------------------------------------ hashing --
 // Counter-based hash: H(seed, tag, x1..xj) = mix(..mix(mix(mix(seed) ^ tag) ^ x1)..^ xj)

@@ -40,6 +40,10 @@ class Profiler {
   // Counts an event of the host (e.g. a stream synchronisation) under `name`:
   // launches = count, no time or bytes.
   void count(const char* name);
+  // Kernel launches while recording (reported as "host:kernel_launches").
+  void count_launch() {
+    if (on()) launches_.fetch_add(1, std::memory_order_relaxed);
+  }
   // Resolve recorded events (synchronises them) and accumulate.
   void collect();
   std::map<std::string, KernelStat> read(bool reset);
@@ -53,6 +57,7 @@ class Profiler {
   };
   hipEvent_t take_event();
   std::atomic<bool> on_{false};
+  std::atomic<uint64_t> launches_{0};
   std::mutex mu_;
   std::vector<Rec> pending_;
   std::vector<hipEvent_t> free_;

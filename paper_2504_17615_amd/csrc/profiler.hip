@@ -78,6 +78,8 @@ std::map<std::string, KernelStat> Profiler::read(bool reset) {
   collect();
   std::lock_guard<std::mutex> g(mu_);
   auto out = stats_;
+  const uint64_t nl = reset ? launches_.exchange(0) : launches_.load();
+  if (nl) out["host:kernel_launches"].launches = nl;
   if (reset) stats_.clear();
   return out;
 }
@@ -86,7 +88,10 @@ void Profiler::reset() {
   collect();
   std::lock_guard<std::mutex> g(mu_);
   stats_.clear();
+  launches_.store(0);
 }
+
+void note_launch() { Profiler::get().count_launch(); }
 
 void Profiler::set_filter(const std::string& kernel) {
   std::lock_guard<std::mutex> g(mu_);
