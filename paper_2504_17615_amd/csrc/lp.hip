@@ -50,6 +50,21 @@ LMGP_D void reduce_best(Best& b, int64_t& r_own) {
   }
 }
 
+// As reduce_best for a group whose own-label rating is already known to every
+// lane; with r32 (every rating below 2^32) the ratings cross lanes as 32-bit
+// words.
+template <int WIDTH>
+LMGP_D void reduce_best_only(Best& b, bool r32) {
+#pragma unroll
+  for (int d = WIDTH / 2; d > 0; d >>= 1) {
+    const int64_t orr = r32 ? (int64_t)(uint32_t)__shfl_xor((uint32_t)b.r, d, WIDTH)
+                            : __shfl_xor(b.r, d, WIDTH);
+    const uint64_t oh = __shfl_xor(b.h, d, WIDTH);
+    const uint32_t oK = __shfl_xor(b.K, d, WIDTH);
+    if (better(orr, oh, oK, b)) b = Best{orr, oh, oK};
+  }
+}
+
 // Consider table slot (K, r) for node u.
 LMGP_D void consider(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, int64_t cu,
                      int64_t cap, uint64_t pre_u, uint64_t label_base, Best& best,
@@ -261,11 +276,15 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
                       gd.label_base, best, r_own);
     }
   }
-  if (first || a.mode != MODE_LP) reduce_best<G>(best, r_own);
+  // the own label's rating is the group's summed own-label weight (inserted
+  // above when positive), known to every lane: only the best crosses lanes
+  r_own = acc;
+  if (first || a.mode != MODE_LP) reduce_best_only<G>(best, a.packed != 0);
   // the whole group holds the same best: the check and the evaluation with
   // weights are uniform within it
-  if (valid && a.mode == MODE_LP &&
-      (!first || (best.r > 0 && a.W[best.K] + cu > gd.cap))) {
+  const bool redo = valid && a.mode == MODE_LP &&
+                    (!first || (best.r > 0 && a.W[best.K] + cu > gd.cap));
+  if (redo) {
     best = Best{0, 0, 0};
     int64_t wk[SPL];
 #pragma unroll
@@ -277,7 +296,10 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
         consider_w1(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, wk[j], pre_u,
                     gd.label_base, best, r_own);
   }
-  reduce_best<G>(best, r_own);  // idempotent for the groups that kept their best
+  // (idempotent for the groups that kept their best: skipped when no group of
+  // the wavefront evaluated again)
+  if (__ballot(redo)) reduce_best_only<G>(best, a.packed != 0);
+  r_own = acc;
   if (gl == 0 && idx < a.count) {
     if (valid) emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
     else no_cand(a, (uint32_t)idx);  // graph stopped
