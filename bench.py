@@ -320,6 +320,8 @@ def bench_serve(args) -> dict:
         print(f"serve: {msg}", file=sys.stderr, flush=True)
 
     L.library()
+    torch.cuda.init()
+    free0 = torch.cuda.mem_get_info()[0]
     t_gen = time.perf_counter()
     threads = max(1, min(args.gen_threads, os.cpu_count() or 1))
     dgs, meta = [], []  # device graphs; (n, m, k, eps, seed)
@@ -330,8 +332,10 @@ def bench_serve(args) -> dict:
             dgs.append(L.create_graph(g))
             meta.append((g.n, g.m, k, eps, seed))
         del part
-        note(f"generated and uploaded {len(dgs)} / {args.requests} requests "
-             f"({time.perf_counter() - t_gen:.0f} s)")
+        if len(dgs) % 512 < chunk or len(dgs) == args.requests:
+            used = (free0 - torch.cuda.mem_get_info()[0]) / 2**30
+            note(f"generated and uploaded {len(dgs)} / {args.requests} requests "
+                 f"({time.perf_counter() - t_gen:.0f} s, {used:.1f} GiB of device memory)")
     t_gen = time.perf_counter() - t_gen
     m_tot = sum(x[1] for x in meta)
     prm = L.default_params(ip_device=args.ip_device)

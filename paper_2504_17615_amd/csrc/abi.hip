@@ -190,10 +190,23 @@ void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
   if (v.vwgt && v.vwgt_bits != 32 && v.vwgt_bits != 64) throw InvalidArg("vwgt_bits must be 32 or 64");
   if (v.adjwgt && v.adjwgt_bits != 32 && v.adjwgt_bits != 64)
     throw InvalidArg("adjwgt_bits must be 32 or 64");
-  Pool& pool = *g.pool;
   g.stream = s;
   g.n = v.n;
   g.nnz = v.nnz;
+  // One device allocation holds every array of the graph (offsets,
+  // neighbours, weights, node weights, entry rows and the checks' words): a
+  // process holds a bounded number of device mappings, and a server keeping
+  // thousands of graphs resident would otherwise use six per graph.
+  {
+    auto al = [](uint64_t b) { return (b + 255) / 256 * 256; };
+    const uint64_t e1 = v.nnz ? v.nnz : 1;
+    uint64_t need = al(8 * (v.n + 1)) + 2 * al(4 * e1) + al(8 * v.n) + 2 * al(16);
+    if (v.adjwgt) need += al((uint64_t)(v.adjwgt_bits / 8) * e1);
+    if (v.vwgt && !v.on_device) need += al((uint64_t)(v.vwgt_bits / 8) * v.n);
+    g.storage.reset(g.pool, s, need);
+    g.arena = std::make_shared<Pool>(g.storage.get(), need);
+  }
+  Pool& pool = *g.arena;
   const hipMemcpyKind kind = v.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   g.xadj.reset(&pool, s, v.n + 1);
   HIP_CHECK(hipMemcpyAsync(g.xadj.get(), v.xadj, (v.n + 1) * sizeof(uint64_t), kind, s));

@@ -11,8 +11,12 @@ namespace lmgp {
 
 // A validated input graph in device memory (what lmgp_graph owns).
 struct InputGraph {
-  Pool* pool = nullptr;
+  Pool* pool = nullptr;  // the graph's work memory (caching pool)
   std::shared_ptr<Pool> own_pool;
+  // the block holding the arrays below and the arena handing them out
+  // (declared before the arrays: released after them)
+  DBuf<uint8_t> storage;
+  std::shared_ptr<Pool> arena;
   hipStream_t stream = nullptr;
   uint64_t n = 0, nnz = 0;
   int ew_kind = EW_UNIT;

@@ -188,10 +188,15 @@ class Pool {
     size_t sz;
     bool operator<(const Key& o) const { return s != o.s ? s < o.s : sz < o.sz; }
   };
+  // Size classes of the free lists: powers of two up to 1 MiB, then
+  // sixteenths of the next power of two (at most 1/8 more than asked for a
+  // large array, rather than up to twice as much).
   static size_t round_up(size_t b) {
     size_t r = 512;
     while (r < b) r <<= 1;
-    return r;
+    if (r <= (1u << 20)) return r;
+    const size_t step = r >> 4;
+    return (b + step - 1) / step * step;
   }
   bool have_user_ = false;
   lmgp_allocator user_{};
