@@ -308,7 +308,9 @@ def bench_serve(args) -> dict:
     process at `load` x the plain path's measured capacity; latency =
     completion - arrival.  The plain path serves the same arrivals one call at
     a time, FIFO, on one stream (run, not simulated); the server takes them
-    through lmgp_server on `streams` streams."""
+    through lmgp_server on `streams` streams.  At most `resident` distinct
+    graphs are generated and kept on the device: request i partitions graph
+    i mod resident (its kind, n and k) with its own seed i + 1."""
     import threading
 
     import torch
@@ -324,97 +326,136 @@ def bench_serve(args) -> dict:
     free0 = torch.cuda.mem_get_info()[0]
     t_gen = time.perf_counter()
     threads = max(1, min(args.gen_threads, os.cpu_count() or 1))
-    dgs, meta = [], []  # device graphs; (n, m, k, eps, seed)
+    G = min(args.requests, args.resident)
+    dgs, gmeta = [], []  # device graphs; (n, m, k, eps)
     chunk = 64
-    for c0 in range(0, args.requests, chunk):
-        part = gg.request_mix(min(chunk, args.requests - c0), 3.0, args.max_exp, threads, first=c0)
-        for g, k, eps, seed in part:
+    for c0 in range(0, G, chunk):
+        part = gg.request_mix(min(chunk, G - c0), 3.0, args.max_exp, threads, first=c0)
+        for g, k, eps, _ in part:
             dgs.append(L.create_graph(g))
-            meta.append((g.n, g.m, k, eps, seed))
+            gmeta.append((g.n, g.m, k, eps))
         del part
-        if len(dgs) % 512 < chunk or len(dgs) == args.requests:
+        if len(dgs) % 512 < chunk or len(dgs) == G:
             used = (free0 - torch.cuda.mem_get_info()[0]) / 2**30
-            note(f"generated and uploaded {len(dgs)} / {args.requests} requests "
+            note(f"generated and uploaded {len(dgs)} / {G} graphs "
                  f"({time.perf_counter() - t_gen:.0f} s, {used:.1f} GiB of device memory)")
     t_gen = time.perf_counter() - t_gen
-    m_tot = sum(x[1] for x in meta)
+    R = args.requests
+    # request i: (graph, n, m, k, eps, seed)
+    req = [(i % G,) + gmeta[i % G] + (i + 1,) for i in range(R)]
+    m_tot = sum(r[2] for r in req)
     prm = L.default_params(ip_device=args.ip_device)
-    for i in range(min(8, len(dgs))):
-        dgs[i].partition(meta[i][2], meta[i][3], meta[i][4], prm, host_out=True)
+
+    def call(r):
+        dgs[r[0]].partition(r[3], r[4], r[5], prm, host_out=True)
+
+    for i in range(min(8, R)):
+        call(req[i])
     torch.cuda.synchronize()
     # plain capacity: per-request service times on one stream
     svc, t_last = [], time.perf_counter()
-    for i, dg in enumerate(dgs):
+    for i in range(R):
         t0 = time.perf_counter()
-        dg.partition(meta[i][2], meta[i][3], meta[i][4], prm, host_out=True)
+        call(req[i])
         svc.append(time.perf_counter() - t0)
         if time.perf_counter() - t_last > 20:
-            note(f"capacity pass {i + 1} / {len(dgs)}")
+            note(f"capacity pass {i + 1} / {R}")
             t_last = time.perf_counter()
-    mu = len(dgs) / sum(svc)
+    mu = R / sum(svc)
     lam = args.load * mu
     rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(dgs)))
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=R))
     note(f"plain capacity {mu:.1f} requests/s, offering {lam:.1f}/s")
     # plain FIFO under these arrivals, run: one call at a time in arrival order
-    done = np.zeros(len(dgs))
+    done = np.zeros(R)
     start, t_last = time.perf_counter() + 0.05, time.perf_counter()
-    for i, dg in enumerate(dgs):
+    for i in range(R):
         dt = start + arrivals[i] - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        dg.partition(meta[i][2], meta[i][3], meta[i][4], prm, host_out=True)
+        call(req[i])
         done[i] = time.perf_counter() - start
         if time.perf_counter() - t_last > 20:
-            note(f"plain FIFO run {i + 1} / {len(dgs)}")
+            note(f"plain FIFO run {i + 1} / {R}")
             t_last = time.perf_counter()
     plain_lat = done - arrivals
     plain_span = done[-1] - arrivals[0]
-    srv = L.Server(ip_device=args.ip_device, hbm_budget_bytes=args.hbm_budget_gib << 30,
-                   max_slots=args.slots, max_batch=args.max_batch, streams=args.streams)
-    tickets = [None] * len(dgs)
-    done = np.zeros(len(dgs))
-    start = time.perf_counter() + 0.05
+    def serve(at, label):
+        """Every request through a fresh server, request i submitted at
+        at[i] s after the start (all at once when at is None); returns each
+        request's submit and completion times and the server's statistics."""
+        srv = L.Server(ip_device=args.ip_device, hbm_budget_bytes=args.hbm_budget_gib << 30,
+                       max_slots=args.slots, max_batch=args.max_batch, streams=args.streams,
+                       join_runs=bool(args.join_runs))
+        tickets = [None] * R
+        submitted = np.zeros(R)
+        start = time.perf_counter() + 0.05
 
-    def submitter():
-        for i, dg in enumerate(dgs):
-            dt = start + arrivals[i] - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            tickets[i] = srv.submit(dg, meta[i][2], meta[i][3], meta[i][4])
+        def submitter():
+            for i, r in enumerate(req):
+                if at is not None:
+                    dt = start + at[i] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                submitted[i] = time.perf_counter() - start
+                tickets[i] = srv.submit(dgs[r[0]], r[3], r[4], r[5])
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    t_last = time.perf_counter()
-    for i in range(len(dgs)):
-        while tickets[i] is None:
-            time.sleep(0.0002)
-        srv.wait(tickets[i])
-        done[i] = time.perf_counter() - start
-        if time.perf_counter() - t_last > 20:
-            note(f"server run {i + 1} / {len(dgs)}")
-            t_last = time.perf_counter()
-    th.join()
-    stats = srv.stats()
-    srv.close()
-    lat = done - arrivals
-    makespan = done[-1] - arrivals[0]
-    ns = np.array([x[0] for x in meta])
+        th = threading.Thread(target=submitter)
+        th.start()
+        # each request's completion is the server's own submit-to-completion
+        # time (the run that held it ended then), not when this loop gets to it
+        service = np.zeros(R)
+        t_last = time.perf_counter()
+        for i in range(R):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            _, res = srv.wait(tickets[i])
+            service[i] = res["t_total_ns"] * 1e-9
+            if time.perf_counter() - t_last > 20:
+                note(f"server {label} {i + 1} / {R}")
+                t_last = time.perf_counter()
+        th.join()
+        stats = srv.stats()
+        srv.close()
+        return submitted, submitted + service, stats
+
+    # closed loop: every request queued at once, the server's throughput
+    _, sat_end, sat_stats = serve(None, "closed loop")
+    sat_thr = R / float(np.max(sat_end))
+    note(f"server closed loop {sat_thr:.1f} requests/s")
+    submitted, end, stats = serve(arrivals, "run")
+    lat = end - arrivals
+    makespan = float(np.max(end)) - arrivals[0]
+    ns = np.array([r[1] for r in req])
+
+    def pct(x):
+        return {"p50_ms": round(float(np.percentile(x, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(x, 99)) * 1e3, 3),
+                "max_ms": round(float(np.max(x)) * 1e3, 3)}
+
+    def by_size(x):
+        out = {}
+        for name, lo, hi in (("n<1e4", 0, 10**4), ("1e4<=n<1e5", 10**4, 10**5),
+                             ("n>=1e5", 10**5, 1 << 62)):
+            sel = (ns >= lo) & (ns < hi)
+            if sel.any():
+                out[name] = dict(requests=int(sel.sum()), **pct(x[sel]))
+        return out
+
     return {
         "metric": "serving latency and throughput", "value": float(np.percentile(lat, 99) * 1e3),
         "unit": "ms p99", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-        "config": {"workload": f"request mix x {len(dgs)}",
+        "config": {"workload": f"request mix x {R}",
                    "description": gg.request_spec.__doc__.split(";")[0] + " ...",
                    "n_range": [1000, int(10 ** args.max_exp)], "load": args.load,
-                   "requests": len(dgs), "m_total": m_tot, "n_mean": float(ns.mean()),
-                   "slots": args.slots, "max_batch": args.max_batch, "streams": args.streams},
-        "server": {"p50_ms": float(np.percentile(lat, 50) * 1e3),
-                   "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                   "graphs_per_s": len(dgs) / makespan, "stats": stats},
-        "plain_fifo": {"p50_ms": float(np.percentile(plain_lat, 50) * 1e3),
-                       "p99_ms": float(np.percentile(plain_lat, 99) * 1e3),
-                       "graphs_per_s": len(dgs) / plain_span,
-                       "capacity_graphs_per_s": mu},
+                   "requests": R, "resident_graphs": G, "m_total": m_tot,
+                   "n_mean": float(ns.mean()), "slots": args.slots,
+                   "max_batch": args.max_batch, "streams": args.streams,
+                   "join_runs": bool(args.join_runs)},
+        "server": dict(pct(lat), graphs_per_s=R / makespan, by_size=by_size(lat), stats=stats,
+                       closed_loop_graphs_per_s=sat_thr, closed_loop_stats=sat_stats),
+        "plain_fifo": dict(pct(plain_lat), graphs_per_s=R / plain_span,
+                           capacity_graphs_per_s=mu, by_size=by_size(plain_lat)),
         "arrival_rate_per_s": lam, "gen_s": round(t_gen, 2),
     }
 
@@ -525,6 +566,8 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-prefix", type=int, default=256)
     ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--resident", type=int, default=5000,
+                    help="serve: distinct graphs kept on the device (request i uses i mod this)")
     ap.add_argument("--gen-threads", type=int, default=4,
                     help="threads generating the serving mix (each generator is parallel too)")
     ap.add_argument("--max-exp", type=float, default=5.0, help="request sizes up to 10^max_exp")
@@ -532,6 +575,8 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--join-runs", type=int, default=0, choices=[0, 1],
+                    help="serve: requests that find every stream busy join a run in flight")
     ap.add_argument("--hbm-budget-gib", type=int, default=64)
     ap.add_argument("--tune", default="off",
                     help="rating class tables: off (default table), auto (autotuned, "

@@ -52,7 +52,9 @@ typedef enum {
 /* Optional device allocator.  alloc returns device memory of at least
  * `bytes` bytes usable in stream order on `stream` (NULL on failure); free
  * releases it in stream order.  When no allocator is given the library uses
- * its own stream-ordered caching pool of hipMalloc'd memory. */
+ * a stream-ordered caching pool of hipMalloc'd memory, one per device, shared
+ * by every graph created there without an allocator (and by the calls on
+ * them); its cached blocks go back to the device when a hipMalloc fails. */
 typedef struct {
   void *ctx;
   void *(*alloc)(void *ctx, size_t bytes, void *stream);
@@ -183,7 +185,10 @@ typedef struct {
   uint32_t ip_device;         /* lmgp_params.ip_device of every batched run          */
   uint32_t join_runs;         /* 1: a request that finds every stream busy joins a
                                  run still coarsening at its next level (requests
-                                 with sorted rows and the run's parameters)        */
+                                 with sorted rows and the run's parameters).  A
+                                 run ends with its last request, so under steady
+                                 arrivals joined runs grow long and every request
+                                 in them waits: 0 serves a steady stream better */
 } lmgp_server_cfg;
 
 void lmgp_default_params(lmgp_params *out);

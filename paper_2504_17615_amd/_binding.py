@@ -443,7 +443,7 @@ class Server:
     """Serving loop: submit partition requests, poll or wait for results."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, max_batch: int = 32,
-                 streams: int = 4, ip_device: int = 2, join_runs: bool = True):
+                 streams: int = 4, ip_device: int = 2, join_runs: bool = False):
         cfg = ServerConfig(hbm_budget_bytes, max_slots, max_batch, streams, ip_device,
                            1 if join_runs else 0)
         h = ctypes.c_void_p()

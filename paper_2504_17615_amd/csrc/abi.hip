@@ -180,7 +180,8 @@ Job make_job(const InputGraph* g, uint32_t k, double eps, uint64_t seed, const l
 
 }  // namespace
 
-void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
+// The host-side checks of a view (before any device work).
+void check_view(const lmgp_csr_view& v) {
   if (v.n == 0) throw InvalidArg("graph must have at least one node");
   if (v.n >= (1ull << 31)) throw InvalidArg("n must be < 2^31");
   if (v.nnz >= (1ull << 40)) throw InvalidArg("nnz must be < 2^40");
@@ -190,6 +191,10 @@ void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
   if (v.vwgt && v.vwgt_bits != 32 && v.vwgt_bits != 64) throw InvalidArg("vwgt_bits must be 32 or 64");
   if (v.adjwgt && v.adjwgt_bits != 32 && v.adjwgt_bits != 64)
     throw InvalidArg("adjwgt_bits must be 32 or 64");
+}
+
+void create_input_graph(const lmgp_csr_view& v, InputGraph& g, hipStream_t s) {
+  check_view(v);
   g.stream = s;
   g.n = v.n;
   g.nnz = v.nnz;
@@ -401,8 +406,9 @@ lmgp_status lmgp_graph_create(const lmgp_csr_view* view, const lmgp_allocator* a
                               lmgp_graph** out) {
   return guard([&] {
     if (!view || !out) throw InvalidArg("NULL argument");
+    check_view(*view);
     auto h = std::make_unique<lmgp_graph>();
-    h->g.own_pool = std::make_shared<Pool>(alloc);
+    h->g.own_pool = alloc ? std::make_shared<Pool>(alloc) : device_pool();
     h->g.pool = h->g.own_pool.get();
     create_input_graph(*view, h->g, (hipStream_t)stream);
     *out = h.release();

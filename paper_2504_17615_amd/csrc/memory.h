@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <iterator>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -205,6 +206,13 @@ class Pool {
   std::map<void*, size_t> sizes_;
   std::vector<void*> owned_;
 };
+
+// The caching pool of the current device that every graph created without a
+// caller allocator works from, so that blocks one graph's call returns serve
+// the next call on any graph (per-graph pools would each keep their own
+// working set cached, and a process holding thousands of graphs would fill
+// the device with them).  Created on first use, kept until the process ends.
+std::shared_ptr<Pool> device_pool();
 
 // Owning device buffer bound to a pool and a stream.
 template <class T>

@@ -172,6 +172,19 @@ Stage& stage() {
 }
 }  // namespace
 
+std::shared_ptr<Pool> device_pool() {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  static std::mutex mu;
+  // never destroyed: freeing device memory while the runtime shuts down at
+  // process exit is not safe
+  static auto* pools = new std::map<int, std::shared_ptr<Pool>>();
+  std::lock_guard<std::mutex> g(mu);
+  auto& p = (*pools)[dev];
+  if (!p) p = std::make_shared<Pool>(nullptr);
+  return p;
+}
+
 bool& no_alloc_mode() {
   static thread_local bool on = false;
   return on;

@@ -78,11 +78,12 @@ def test_batch_of_one_equals_plain(lib, solo):
     assert np.array_equal(outs[0].cpu().numpy().view(np.uint32), b)
 
 
-@pytest.mark.parametrize("budget_mib,slots,batch,streams", [(4096, 16, 8, 2), (64, 8, 4, 2),
-                                                            (4096, 4, 1, 1), (4096, 16, 8, 4)])
-def test_server_results_equal_solo(lib, solo, budget_mib, slots, batch, streams):
+@pytest.mark.parametrize("budget_mib,slots,batch,streams,join", [
+    (4096, 16, 8, 2, True), (64, 8, 4, 2, True), (4096, 4, 1, 1, False), (4096, 16, 8, 4, False),
+    (4096, 16, 8, 4, True)])
+def test_server_results_equal_solo(lib, solo, budget_mib, slots, batch, streams, join):
     srv = lib.Server(hbm_budget_bytes=budget_mib << 20, max_slots=slots, max_batch=batch,
-                     streams=streams)
+                     streams=streams, join_runs=join)
     tickets = []
     for rep in range(2):
         for i, (dg, k, eps, seed, b, r) in enumerate(solo):
@@ -131,7 +132,8 @@ def test_server_joins_run_in_flight(lib, solo):
     g = gg.rmat(17)
     big = lib.create_graph(g)
     bb, br = big.partition(16, 0.03, 11, host_out=True)
-    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=32, max_batch=8, streams=1)
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=32, max_batch=8, streams=1,
+                     join_runs=True)
     print("server: requests joining a run in flight", flush=True)
     tickets = [(-1, srv.submit(big, 16, 0.03, 11))]
     t0 = time.perf_counter()
@@ -231,7 +233,8 @@ def test_server_request_mix_matches_oracle(lib):
     reqs = gg.request_mix(36, 3.0, math.log10(2e4), threads=4)
     assert max(g.n for g, _, _, _ in reqs) <= 20000 + 200
     dgs = [lib.create_graph(g) for g, _, _, _ in reqs]
-    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=32, max_batch=8, streams=4)
+    srv = lib.Server(hbm_budget_bytes=8192 << 20, max_slots=32, max_batch=8, streams=4,
+                     join_runs=True)
     print("server: request mix against the oracle", flush=True)
     tickets = [srv.submit(dg, k, eps, seed) for dg, (_, k, eps, seed) in zip(dgs, reqs)]
     got = [srv.wait(t) for t in tickets]
