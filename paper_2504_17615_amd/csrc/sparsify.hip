@@ -9,8 +9,11 @@
 // omega_t: MSB-first radix select with 8-bit digits over the weights of the
 // directed entries (every edge counted twice, so the (2 m_hat)-th largest
 // entry).  The r-th smallest hash among E^=: one 12-bit histogram pass, then
-// the entries of the selected bucket are gathered and ranked exactly.
+// the entries of the selected bucket are gathered and ranked exactly, all on
+// the device (the host learns omega_t, |E^>| and |E^=| from the weight
+// passes; the rank decides only which of the E^= edges are kept).
 #include <algorithm>
+#include <cstdlib>
 
 #include "contract.h"
 #include "profiler.h"
@@ -84,12 +87,41 @@ struct EqEntry {
   uint32_t a, b;  // local ids
 };
 
+// The rank of the wanted entry, found on the device: sel[0] the 12-bit bucket
+// holding the r-th smallest key, sel[1] its rank inside the bucket (1-based),
+// sel[2] the bucket's size.  One 1024-thread block, four bins per thread.
+constexpr int PICK_NT = 1024;
+__global__ __launch_bounds__(PICK_NT) void k_eq_pick(const unsigned long long* hist, uint64_t r,
+                                                      unsigned long long* sel) {
+  __shared__ unsigned long long sm[PICK_NT / WAVE];
+  const int t = threadIdx.x;
+  unsigned long long h[4], loc = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) loc += (h[i] = hist[4 * t + i]);
+  unsigned long long tot;
+  unsigned long long cum = block_exclusive_scan<unsigned long long, PICK_NT / WAVE>(loc, sm, tot);
+  // 1 <= r <= the number of keys, so exactly one bin qualifies
+  if (cum < r && r <= cum + loc) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (cum + h[i] >= r) {
+        sel[0] = (unsigned long long)(4 * t + i);
+        sel[1] = r - cum;
+        sel[2] = h[i];
+        break;
+      }
+      cum += h[i];
+    }
+  }
+}
+
 template <typename KT>
 __global__ __launch_bounds__(256) void k_kgather(const uint32_t* src, const uint32_t* adj,
                                                  const KT* key, uint64_t e0, uint64_t e1,
                                                  int64_t w_t, uint64_t base, uint64_t pre,
-                                                 uint32_t bucket, EqEntry* out,
+                                                 const unsigned long long* sel, EqEntry* out,
                                                  unsigned long long* cnt, uint64_t cap) {
+  const uint64_t bucket = sel[0];
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t e = e0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride) {
     const uint32_t a = src[e], b = adj[e];
@@ -116,6 +148,101 @@ struct SparsDesc {
   uint32_t pad;
   uint64_t coin_n, coin_r;
 };
+
+// The rin-th smallest (key, a, b) of the selected bucket, written into the
+// graph's descriptor.  One block, MSB-first radix select over the 128-bit
+// composite (key, a, b) in 8-bit digits: each pass counts the digit of every
+// candidate that matches the digits chosen so far and picks the digit holding
+// the wanted rank; once one candidate is left it is found by one more pass.
+// Candidates: the gathered entries, or, if the gather overflowed its buffer,
+// the E^= entries of the edge range whose key lies in the bucket.
+constexpr int RANK_NT = 1024;
+
+LMGP_D uint32_t eq_digit(uint64_t key, uint32_t a, uint32_t b, int pos) {
+  // digit 15 is the top byte of key, digit 0 the low byte of b
+  const uint64_t w = pos >= 8 ? key : ((uint64_t)a << 32 | b);
+  return (uint32_t)(w >> (8 * (pos & 7))) & 0xFF;
+}
+
+template <typename KT>
+struct EqSource {
+  const EqEntry* buf;  // gathered entries, or NULL: scan the edge range
+  uint64_t cnt;
+  const uint32_t* src;
+  const uint32_t* adj;
+  const KT* key;
+  uint64_t e0, e1, base, pre, bucket;
+  int64_t w_t;
+  // f(key, a, b) for every candidate, the block's threads striding over them
+  template <class F>
+  LMGP_D void each(F&& f) const {
+    if (buf) {
+      for (uint64_t i = threadIdx.x; i < cnt; i += RANK_NT) f(buf[i].key, buf[i].a, buf[i].b);
+      return;
+    }
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += RANK_NT) {
+      const uint32_t a = src[e], b = adj[e];
+      if (a < b && (int64_t)key[e] == w_t) {
+        const uint64_t k = edge_key(pre, a - base, b - base);
+        if ((k >> 52) == bucket) f(k, a - (uint32_t)base, b - (uint32_t)base);
+      }
+    }
+  }
+};
+
+template <typename KT>
+__global__ __launch_bounds__(RANK_NT) void k_eq_rank(EqSource<KT> in, const unsigned long long* cnt,
+                                                     uint64_t cap, const unsigned long long* sel,
+                                                     SparsDesc* d) {
+  __shared__ uint32_t h[256];
+  __shared__ uint32_t s_digit, s_left;
+  __shared__ uint64_t s_rank;
+  __shared__ EqEntry s_out;
+  in.bucket = sel[0];
+  in.cnt = *cnt;
+  if (in.cnt > cap) in.buf = nullptr;
+  uint64_t rank = sel[1];
+  // chosen digits so far: composite bits above `pos` (hi: key, lo: a << 32 | b)
+  uint64_t phi = 0, plo = 0, mhi = 0, mlo = 0;
+  auto matches = [&](uint64_t k, uint32_t a, uint32_t b) {
+    return (k & mhi) == phi && (((uint64_t)a << 32 | b) & mlo) == plo;
+  };
+  int pos = 15;
+  for (; pos >= 0; --pos) {
+    for (int i = threadIdx.x; i < 256; i += RANK_NT) h[i] = 0;
+    __syncthreads();
+    in.each([&](uint64_t k, uint32_t a, uint32_t b) {
+      if (matches(k, a, b)) atomicAdd(&h[eq_digit(k, a, b, pos)], 1u);
+    });
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t cum = 0;
+      int dg = 0;
+      for (; dg < 255 && cum + h[dg] < rank; ++dg) cum += h[dg];
+      s_digit = (uint32_t)dg;
+      s_left = h[dg];
+      s_rank = rank - cum;
+    }
+    __syncthreads();
+    const uint64_t dm = 0xFFull << (8 * (pos & 7)), dv = (uint64_t)s_digit << (8 * (pos & 7));
+    if (pos >= 8) mhi |= dm, phi |= dv;
+    else mlo |= dm, plo |= dv;
+    rank = s_rank;
+    const uint32_t left = s_left;
+    __syncthreads();
+    if (left == 1) break;  // (keys are distinct: at the last digit one is left)
+  }
+  // the one candidate matching every chosen digit
+  in.each([&](uint64_t k, uint32_t a, uint32_t b) {
+    if (matches(k, a, b)) s_out = EqEntry{k, a, b};
+  });
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d->tkey = s_out.key;
+    d->ta = s_out.a;
+    d->tb = s_out.b;
+  }
+}
 
 template <typename KT>
 __global__ void k_keep(const uint32_t* src, const uint32_t* adj, const KT* keyv,
@@ -184,6 +311,12 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
                 Pool& pool, hipStream_t s) {
   const size_t B = graphs.size();
   std::vector<SparsDesc> desc(B);
+  struct EqRank {
+    size_t g;       // graph
+    uint64_t r;     // rank of the last kept edge of weight w_t (1-based)
+    uint64_t n_eq;  // edges of weight w_t
+  };
+  std::vector<EqRank> eq_rank;
   DBuf<unsigned long long> dmax(&pool, s, 1);
   DBuf<unsigned long long> hist(&pool, s, 4096), cnt(&pool, s, 1);
   for (size_t g = 0; g < B; ++g) {
@@ -254,44 +387,52 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
       d.coin_r = r;
       continue;
     }
-    // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t:
-    // row, neighbour and weight of every entry in two passes
-    ProfScope prof_hs("sp:hash_select", 2 * (8 + sizeof(KT)) * (e1 - e0), s);
-    hist.zero();
-    k_khist<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, key, e0, e1, sg.w_t, sg.node_base,
-                                                 sg.pre, hist.get());
-    LAUNCH_CHECK();
-    std::vector<unsigned long long> kh(4096);
-    read_now(kh.data(), hist.get(), 4096 * sizeof(unsigned long long), s);
-    uint64_t cum = 0;
-    uint32_t bucket = 0;
-    for (uint32_t i = 0; i < 4096; ++i) {
-      if (cum + kh[i] >= r) {
-        bucket = i;
-        break;
-      }
-      cum += kh[i];
-    }
-    const uint64_t rin = r - cum;  // rank inside the bucket (1-based)
-    const uint64_t bsz = kh[bucket];
-    DBuf<EqEntry> buf(&pool, s, bsz ? bsz : 1);
-    cnt.zero();
-    k_kgather<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, key, e0, e1, sg.w_t, sg.node_base,
-                                                   sg.pre, bucket, buf.get(), cnt.get(), bsz);
-    LAUNCH_CHECK();
-    std::vector<EqEntry> hb(bsz);
-    read_now(hb.data(), buf.get(), bsz * sizeof(EqEntry), s);
-    auto less = [](const EqEntry& x, const EqEntry& y) {
-      if (x.key != y.key) return x.key < y.key;
-      if (x.a != y.a) return x.a < y.a;
-      return x.b < y.b;
-    };
-    std::nth_element(hb.begin(), hb.begin() + (rin - 1), hb.end(), less);
-    const EqEntry t = hb[rin - 1];
+    // r-th smallest (key, a, b) among the n_eq undirected edges of weight w_t
+    // (1 <= r < n_eq: fewer than 2 m_hat entries are heavier than w_t and at
+    // least 2 m_hat weigh at least w_t): ranked on the device below
     d.mode = 2;
-    d.tkey = t.key;
-    d.ta = t.a;
-    d.tb = t.b;
+    eq_rank.push_back(EqRank{g, r, sg.n_eq});
+  }
+  DBuf<SparsDesc> dd(&pool, s, B);
+  HIP_CHECK(hipMemcpyAsync(dd.get(), desc.data(), B * sizeof(SparsDesc), hipMemcpyHostToDevice, s));
+  if (!eq_rank.empty()) {
+    // the bucket of the r-th key from a 12-bit histogram, its entries
+    // gathered, the rank inside it by radix select, all on the device.  The
+    // gather buffer holds 4x a bucket's mean size plus 4096 entries (a bucket
+    // larger than that has vanishing probability under a 64-bit hash; the
+    // rank kernel then scans the edge range itself).  LMGP_EQ_GATHER_CAP
+    // lowers the capacity (tests use it to take the scanning path).
+    const char* cap_env = std::getenv("LMGP_EQ_GATHER_CAP");
+    const uint64_t cap_max = cap_env ? std::strtoull(cap_env, nullptr, 10) : ~0ull;
+    auto cap_of = [&](const EqRank& q) {
+      const uint64_t c = std::min<uint64_t>(q.n_eq, 4 * ((q.n_eq + 4095) / 4096) + 4096);
+      return std::max<uint64_t>(1, std::min(c, cap_max));
+    };
+    uint64_t buf_cap = 1;
+    for (const EqRank& q : eq_rank) buf_cap = std::max(buf_cap, cap_of(q));
+    DBuf<EqEntry> buf(&pool, s, buf_cap);
+    DBuf<unsigned long long> sel(&pool, s, 3);
+    for (const EqRank& q : eq_rank) {
+      const SparsGraph& sg = graphs[q.g];
+      const uint64_t e0 = sg.e0, e1 = sg.e1;
+      // row, neighbour and weight of every entry in two passes
+      ProfScope prof_hs("sp:hash_select", 2 * (8 + sizeof(KT)) * (e1 - e0), s);
+      hist.zero();
+      k_khist<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, key, e0, e1, sg.w_t,
+                                                   sg.node_base, sg.pre, hist.get());
+      LAUNCH_CHECK();
+      k_eq_pick<<<1, PICK_NT, 0, s>>>(hist.get(), q.r, sel.get());
+      LAUNCH_CHECK();
+      cnt.zero();
+      const uint64_t cap = cap_of(q);
+      k_kgather<KT><<<sweep_grid(e1 - e0), 256, 0, s>>>(src, adj, key, e0, e1, sg.w_t,
+                                                     sg.node_base, sg.pre, sel.get(), buf.get(),
+                                                     cnt.get(), cap);
+      LAUNCH_CHECK();
+      EqSource<KT> in{buf.get(), 0, src, adj, key, e0, e1, sg.node_base, sg.pre, 0, sg.w_t};
+      k_eq_rank<KT><<<1, RANK_NT, 0, s>>>(in, cnt.get(), cap, sel.get(), dd.get() + q.g);
+      LAUNCH_CHECK();
+    }
   }
   // keep flags, positions, compaction: every entry read (row, neighbour,
   // weight) and flagged, positions scanned, the kept ones written
@@ -299,8 +440,6 @@ void sparsify_t(uint64_t n, uint64_t nnz, const uint64_t* xadj, const uint32_t* 
   for (const SparsGraph& sg : graphs) kept_est += sg.triggered ? 2 * sg.m_hat : sg.e1 - sg.e0;
   ProfScope prof_cp("sp:compact", (8 + sizeof(KT) + 1 + 8) * nnz + (8 + sizeof(WT)) * kept_est +
                                       16 * (n + 1), s);
-  DBuf<SparsDesc> dd(&pool, s, B);
-  HIP_CHECK(hipMemcpyAsync(dd.get(), desc.data(), B * sizeof(SparsDesc), hipMemcpyHostToDevice, s));
   DBuf<uint8_t> keep(&pool, s, nnz ? nnz : 1);
   if (nnz) {
     k_keep<KT><<<grid_for(nnz, 256), 256, 0, s>>>(src, adj, key, gid, dd.get(), nnz, keep.get());

@@ -116,6 +116,19 @@ def test_sparsification_samplers(lib, name, sampler):
     check_partition(lib, g, k, eps, seed, sampler=sampler)
 
 
+@pytest.mark.parametrize("cap", ["1", "64"])
+@pytest.mark.parametrize("name", ["er14", "rmat14"])
+def test_eq_rank_scan_path(lib, name, cap, monkeypatch):
+    # the rank inside E^= with a gather buffer too small for the selected
+    # bucket: the rank kernel scans the edge range itself (same result)
+    g, k, eps, seed = gg.workload(name)
+    monkeypatch.setenv("LMGP_EQ_GATHER_CAP", cap)
+    oh = check_hierarchy(lib, g, 16, seed, sampler=0)
+    ranked = [i for i in oh.info if i["triggered"] and i["m_hat"] - i["n_gt"] != i["n_eq"]]
+    assert ranked, "no level ranks inside E^="
+    check_partition(lib, g, k, eps, seed, sampler=0)
+
+
 def test_sparsification_off(lib):
     g, k, eps, seed = gg.workload("er14")
     check_hierarchy(lib, g, 16, seed, sampler=2)
