@@ -850,8 +850,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<unsigned long long> dmoves(&pool_, s_, B), ddelta(&pool_, s_, B);
   DBuf<Cand> cands(&pool_, s_, n);
   DBuf<uint32_t> list(&pool_, s_, n);
-  DBuf<int64_t> demand(&pool_, s_, nlabels);
-  DBuf<uint32_t> ntgt(&pool_, s_, nlabels), fill(&pool_, s_, nlabels), segbase(&pool_, s_, nlabels);
+  DBuf<LabelTally> tally(&pool_, s_, nlabels);
+  DBuf<uint32_t> segbase(&pool_, s_, nlabels);
   DBuf<uint32_t> ovtotal(&pool_, s_, 2), ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
   DBuf<uint8_t> adm(&pool_, s_, n);
   DBuf<uint32_t> boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
@@ -861,9 +861,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   const size_t nstate = 2 * NB + B;
   unsigned long long* hstate = pinned_state(nstate);
   std::memset(hstate, 0, nstate * sizeof(unsigned long long));
-  demand.zero();
-  ntgt.zero();
-  fill.zero();
+  tally.zero();
   std::vector<uint32_t> cnt(NB), offs(NB);
   std::vector<unsigned long long> degs(NB);
   // refinement with few labels: demand and segment slots from block-privatised
@@ -1040,8 +1038,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     ra.phase = spec.refine ? 1 : 0;
     ra.packed = packed_ ? 1 : 0;
     ra.few = few;
-    ra.demand = demand.get();
-    ra.ntgt = ntgt.get();
+    ra.tally = tally.get();
     ra.list = list.get() + offs[sr * NCLASS];
     ra.cands = cands.get();
     ra.label8 = label8.get();
@@ -1105,9 +1102,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.label = label;
     aa.gid = L.gid;
     aa.gd = dgd.get();
-    aa.demand = demand.get();
-    aa.ntgt = ntgt.get();
-    aa.fill = fill.get();
+    aa.tally = tally.get();
     aa.segbase = segbase.get();
     aa.ovtotal = ovtotal.get();
     aa.ovcount = ovtotal.get() + 1;

@@ -75,6 +75,16 @@ constexpr uint32_t MAX_BUCKETS = 512;
 
 enum RateMode : int { MODE_LP = 0, MODE_FAV = 1 };
 
+// Per-label tallies of one LP sub-round, one 16-byte record per label so that
+// a target's tallies share a cache line (and are cleared by one store):
+// summed weight of the candidates targeting the label, their number, and
+// the admission's slot counter of an overfull target.
+struct alignas(16) LabelTally {
+  int64_t demand;
+  uint32_t ntgt;
+  uint32_t fill;
+};
+
 struct RateArgs {
   const uint64_t* xadj;
   const uint32_t* adj;
@@ -91,8 +101,7 @@ struct RateArgs {
   int mode;
   // MODE_LP outputs
   Cand* cands;             // slot i belongs to list[i]; tgt = EMPTY_KEY: no move
-  int64_t* demand;         // per label: summed weight of candidates targeting it
-  uint32_t* ntgt;          // per label: number of candidates targeting it
+  LabelTally* tally;       // per label: demand and ntgt of the candidates targeting it
   // MODE_FAV output
   uint32_t* fav;
   // global-table class
@@ -101,9 +110,9 @@ struct RateArgs {
   const uint64_t* goff;    // table offset of each listed node (class 7 only)
   unsigned long long* gtab;  // packed (label << 32 | rating) slots
   int packed;              // every rating fits in 32 bits: use gtab
-  uint32_t few;            // labels < few <= FEW_LABELS: demand and ntgt are counted
+  uint32_t few;            // labels < few <= FEW_LABELS: the tallies are counted
                            // by the admission (block-privatised), not here
-  uint32_t trial;          // timing trial: candidates are written, demand and ntgt
+  uint32_t trial;          // timing trial: candidates are written, the tallies
                            // are not counted
   // Planned launch (rounds replayed from a HIP graph): the grid is an upper
   // bound and the kernel takes its node count and list range from the
@@ -204,9 +213,7 @@ struct AdmitArgs {
   uint32_t* label;
   const uint32_t* gid;
   const GraphDesc* gd;
-  int64_t* demand;
-  uint32_t* ntgt;
-  uint32_t* fill;
+  LabelTally* tally;       // per label (cleared for the next sub-round by the apply)
   uint32_t* segbase;
   uint32_t* ovtotal;       // [1]
   uint32_t* ovcount;       // [1]

@@ -94,20 +94,6 @@ LMGP_D void consider_w(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, i
   if (better(r, h, K, best)) best = Best{r, h, K};
 }
 
-// As consider_w with a single branch (around the tie hash of a candidate that
-// can still win); the lane-group kernels, whose lanes hold few slots each,
-// issue fewer instructions with it.
-LMGP_D void consider_w1(const RateArgs& a, uint32_t K, int64_t r, uint32_t own, int64_t cu,
-                        int64_t cap, int64_t wk, uint64_t pre_u, uint64_t label_base, Best& best,
-                        int64_t& r_own) {
-  r_own = K == own ? r : r_own;
-  const bool cand = K != own && (a.mode != MODE_LP || wk + cu <= cap) && r >= best.r;
-  if (cand) {
-    const uint64_t h = hash_add(pre_u, (uint64_t)K - label_base);
-    if (better(r, h, K, best)) best = Best{r, h, K};
-  }
-}
-
 // Candidate slots are dense: the node at position idx of the rated list owns
 // slot idx and marks it empty (tgt = EMPTY_KEY) when it proposes no move, so
 // that no global counter is needed.
@@ -133,8 +119,8 @@ LMGP_D void emit(const RateArgs& a, uint32_t idx, uint32_t u, const GraphDesc& g
     c.gain = best.r - r_own;
     a.cands[i] = c;
     if (!a.few && !a.trial) {
-      atomicAdd((unsigned long long*)&a.demand[best.K], (unsigned long long)cu);
-      atomicAdd(&a.ntgt[best.K], 1u);
+      atomicAdd((unsigned long long*)&a.tally[best.K].demand, (unsigned long long)cu);
+      atomicAdd(&a.tally[best.K].ntgt, 1u);
     }
   }
 }
@@ -201,6 +187,35 @@ LMGP_D void resolve_plan(RateArgs& r) {
   if (r.cands) r.cands = r.cands + p.off[r.plan_c0];
 }
 
+// The best of a lane group's eligible slots (el: label, rating), as the
+// lexicographic order of `better` picks it: the group's highest rating
+// first, then the smallest (tie hash, label) among the slots that reach it.
+// Only those slots hash their label (a slot below the maximum cannot win,
+// whatever its hash).  {0, 0, 0} when no slot is eligible.  Every lane of the
+// wave takes part (shuffles).
+template <int G, int SPL>
+LMGP_D Best group_best(const bool* el, const uint32_t* Ks, const int64_t* rs, uint64_t pre_u,
+                       uint64_t label_base, bool r32) {
+  int64_t rm = 0;
+#pragma unroll
+  for (int j = 0; j < SPL; ++j) rm = el[j] && rs[j] > rm ? rs[j] : rm;
+#pragma unroll
+  for (int d = G / 2; d > 0; d >>= 1) {
+    const int64_t o = r32 ? (int64_t)(uint32_t)__shfl_xor((uint32_t)rm, d, G) : __shfl_xor(rm, d, G);
+    rm = o > rm ? o : rm;
+  }
+  Best b{0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < SPL; ++j) {
+    if (el[j] && rs[j] == rm) {
+      const uint64_t h = hash_add(pre_u, (uint64_t)Ks[j] - label_base);
+      if (b.r == 0 || h < b.h || (h == b.h && Ks[j] < b.K)) b = Best{rm, h, Ks[j]};
+    }
+  }
+  reduce_best_only<G>(b, r32);
+  return b;
+}
+
 template <int G, int EWK>
 LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sval,
                        uint64_t blk) {
@@ -247,7 +262,6 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   acc = group_sum<G>(acc);
   if (gl == 0 && acc > 0) lds_insert<T>(key, val, own, (uint64_t)acc);
   wave_sync();
-  Best best{0, 0, 0};
   int64_t r_own = 0;
   GraphDesc gd{};
   int64_t cu = 0;
@@ -260,45 +274,45 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   // weight.
   constexpr int SPL = T / G;  // slots per lane
   uint32_t Ks[SPL];
+  int64_t rs[SPL];
+  bool el[SPL];
+#pragma unroll
+  for (int j = 0; j < SPL; ++j) Ks[j] = EMPTY_KEY, rs[j] = 0;
   uint64_t pre_u = 0;
   const bool first = a.mode == MODE_LP && a.phase == 0;
+  const bool r32 = a.packed != 0;
   if (valid) {
     gd = a.gd[graph_of(a.gid, u)];
     cu = a.nw[u];
     pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
 #pragma unroll
-    for (int j = 0; j < SPL; ++j) Ks[j] = key[gl + j * G];
-    if (first || a.mode != MODE_LP) {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j)
-        if (Ks[j] != EMPTY_KEY)
-          consider_w1(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, 0, pre_u,
-                      gd.label_base, best, r_own);
+    for (int j = 0; j < SPL; ++j) {
+      Ks[j] = key[gl + j * G];
+      rs[j] = (int64_t)val[gl + j * G];
     }
   }
-  // the own label's rating is the group's summed own-label weight (inserted
-  // above when positive), known to every lane: only the best crosses lanes
-  r_own = acc;
-  if (first || a.mode != MODE_LP) reduce_best_only<G>(best, a.packed != 0);
+  Best best{0, 0, 0};
+  if (first || a.mode != MODE_LP) {
+    const bool fits = valid && (a.mode != MODE_LP || cu <= gd.cap);
+#pragma unroll
+    for (int j = 0; j < SPL; ++j) el[j] = fits && Ks[j] != EMPTY_KEY && Ks[j] != own;
+    best = group_best<G, SPL>(el, Ks, rs, pre_u, gd.label_base, r32);
+  }
   // the whole group holds the same best: the check and the evaluation with
   // weights are uniform within it
   const bool redo = valid && a.mode == MODE_LP &&
                     (!first || (best.r > 0 && a.W[best.K] + cu > gd.cap));
-  if (redo) {
-    best = Best{0, 0, 0};
+  if (__ballot(redo)) {
     int64_t wk[SPL];
 #pragma unroll
     for (int j = 0; j < SPL; ++j)
-      wk[j] = (Ks[j] != EMPTY_KEY && Ks[j] != own) ? a.W[Ks[j]] : 0;
+      wk[j] = (redo && Ks[j] != EMPTY_KEY && Ks[j] != own) ? a.W[Ks[j]] : 0;
 #pragma unroll
     for (int j = 0; j < SPL; ++j)
-      if (Ks[j] != EMPTY_KEY)
-        consider_w1(a, Ks[j], (int64_t)val[gl + j * G], own, cu, gd.cap, wk[j], pre_u,
-                    gd.label_base, best, r_own);
+      el[j] = redo && Ks[j] != EMPTY_KEY && Ks[j] != own && wk[j] + cu <= gd.cap;
+    const Best nb = group_best<G, SPL>(el, Ks, rs, pre_u, gd.label_base, r32);
+    if (redo) best = nb;
   }
-  // (idempotent for the groups that kept their best: skipped when no group of
-  // the wavefront evaluated again)
-  if (__ballot(redo)) reduce_best_only<G>(best, a.packed != 0);
   r_own = acc;
   if (gl == 0 && idx < a.count) {
     if (valid) emit(a, (uint32_t)idx, u, gd, best, r_own, cu);
@@ -1648,8 +1662,8 @@ __global__ __launch_bounds__(256) void k_adm_count_few(AdmitArgs a) {
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < a.few; t += 256)
     if (sn[t]) {
-      atomicAdd((unsigned long long*)&a.demand[t], sd[t]);
-      atomicAdd(&a.ntgt[t], sn[t]);
+      atomicAdd((unsigned long long*)&a.tally[t].demand, sd[t]);
+      atomicAdd(&a.tally[t].ntgt, sn[t]);
     }
 }
 
@@ -1671,7 +1685,7 @@ __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
     } else if (i < nc) {
       const Cand c = a.cands[i];
       const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
-      if (a.W[c.tgt] + a.demand[c.tgt] <= cap) {
+      if (a.W[c.tgt] + a.tally[c.tgt].demand <= cap) {
         a.adm[i] = 1;
       } else {
         a.adm[i] = 0;
@@ -1683,10 +1697,10 @@ __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < a.few; t += 256)
     if (cnt[t]) {
-      const uint32_t p = atomicAdd(&a.fill[t], cnt[t]);
+      const uint32_t p = atomicAdd(&a.tally[t].fill, cnt[t]);
       base[t] = p;
       if (p == 0) {
-        a.segbase[t] = atomicAdd(a.ovtotal, a.ntgt[t]);
+        a.segbase[t] = atomicAdd(a.ovtotal, a.tally[t].ntgt);
         a.ovtgts[atomicAdd(a.ovcount, 1u)] = t;
       }
     }
@@ -1704,9 +1718,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
   for (uint32_t t = threadIdx.x; t < a.few; t += 256) {
     dw[t] = 0;
     if (blockIdx.x == 0) {  // per-target scratch for the next sub-round
-      a.demand[t] = 0;
-      a.ntgt[t] = 0;
-      a.fill[t] = 0;
+      a.tally[t] = LabelTally{0, 0, 0};
     }
   }
   __syncthreads();
@@ -1740,9 +1752,7 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
 
 __global__ void k_adm_reset_few(AdmitArgs a) {
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < a.few; t += gridDim.x * blockDim.x) {
-    a.demand[t] = 0;
-    a.ntgt[t] = 0;
-    a.fill[t] = 0;
+    a.tally[t] = LabelTally{0, 0, 0};
   }
 }
 
@@ -1757,15 +1767,16 @@ __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
   }
   const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
   const uint32_t t = c.tgt;
-  if (a.W[t] + a.demand[t] <= cap) {
+  const LabelTally tl = a.tally[t];
+  if (a.W[t] + tl.demand <= cap) {
     a.adm[i] = 1;  // everything aimed at t fits
     return;
   }
   a.adm[i] = 0;
-  const uint32_t p = atomicAdd(&a.fill[t], 1u);
+  const uint32_t p = atomicAdd(&a.tally[t].fill, 1u);
   a.cpos[i] = p;
   if (p == 0) {
-    a.segbase[t] = atomicAdd(a.ovtotal, a.ntgt[t]);
+    a.segbase[t] = atomicAdd(a.ovtotal, tl.ntgt);
     a.ovtgts[atomicAdd(a.ovcount, 1u)] = t;
   }
 }
@@ -1793,7 +1804,7 @@ LMGP_D void seg_waves(const AdmitArgs& a, uint32_t wid, uint32_t waves) {
   const int l = lane_id();
   for (uint32_t j = wid; j < nt; j += waves) {
     const uint32_t t = a.ovtgts[j];
-    const uint32_t size = a.ntgt[t];
+    const uint32_t size = a.tally[t].ntgt;
     if (size > WAVE) continue;
     const uint32_t base = a.segbase[t];
     const bool valid = (uint32_t)l < size;
@@ -1879,7 +1890,7 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
   const uint32_t nt = *a.ovcount;
   for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
     const uint32_t t = a.ovtgts[j];
-    const uint32_t size = a.ntgt[t];
+    const uint32_t size = a.tally[t].ntgt;
     if (size <= WAVE) continue;
     const uint32_t base = a.segbase[t];
     uint32_t* in = a.seg + base;
@@ -2009,9 +2020,7 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
   if (i < nc && !a.few) {
     const uint32_t t = a.cands[i].tgt;
     if (t != EMPTY_KEY) {
-      a.demand[t] = 0;
-      a.ntgt[t] = 0;
-      a.fill[t] = 0;
+      a.tally[t] = LabelTally{0, 0, 0};
     }
   }
   if (!a.gid && __ballot(mv != 0) && lane_id() == 0) mark_moved(a, 0);
