@@ -1024,7 +1024,13 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   // graph boundaries of the coarse union
   const size_t nbnd = in.bounds.size();
   out.cid_at_bounds.resize(nbnd);
-  if (nbnd) {  // one gather and one read, whatever the number of graphs
+  // bounds at 0 and n map to 0 and nc (a single graph has no other)
+  bool interior = false;
+  for (size_t i = 0; i < nbnd; ++i) {
+    interior |= in.bounds[i] != 0 && in.bounds[i] != n;
+    out.cid_at_bounds[i] = in.bounds[i] == 0 ? 0u : (uint32_t)nc;
+  }
+  if (interior) {  // one gather and one read, whatever the number of graphs
     DBuf<uint64_t> dbnd(&pool, s, nbnd);
     DBuf<uint32_t> dval(&pool, s, nbnd);
     HIP_CHECK(hipMemcpyAsync(dbnd.get(), in.bounds.data(), nbnd * sizeof(uint64_t),

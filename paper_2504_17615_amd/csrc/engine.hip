@@ -1613,8 +1613,14 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     C->nbase.push_back(co.nc);
     const uint32_t BC = nkeep;
     C->ebase.resize(BC + 1);
-    // entry offsets of the graphs: one gather and one read
-    auto read_ebase = [&](const uint64_t* xadj) {
+    // entry offsets of the graphs: one gather and one read (a single graph's
+    // are 0 and the level's entry count)
+    auto read_ebase = [&](const uint64_t* xadj, uint64_t total) {
+      if (BC == 1) {
+        C->ebase[0] = 0;
+        C->ebase[1] = total;
+        return;
+      }
       DBuf<uint64_t> didx(&pool_, s_, BC + 1), dval(&pool_, s_, BC + 1);
       h2d(didx.get(), C->nbase.data(), BC + 1, s_);
       k_gather_u64<<<grid_for(BC + 1, 256), 256, 0, s_>>>(xadj, didx.get(), BC + 1, dval.get());
@@ -1622,7 +1628,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
       d2h(C->ebase.data(), dval.get(), BC + 1, s_);
       sync(s_);
     };
-    read_ebase(co.xadj.get());
+    read_ebase(co.xadj.get(), co.nnz);
     // remap coarse graph ids to positions in the coarse union
     if (BC > 1) {
       std::vector<uint32_t> remap(B);
@@ -1727,7 +1733,7 @@ void Engine::coarsen(std::vector<Job>& jobs) {
       C->o_ew32 = std::move(so.ew32);
       C->ew_kind = so.ew_kind;
       C->o_src = std::move(so.src);
-      read_ebase(C->o_xadj.get());
+      read_ebase(C->o_xadj.get(), C->nnz);
     } else {
       C->o_xadj = std::move(co.xadj);
       C->o_adj = std::move(co.adj);
