@@ -52,9 +52,9 @@ struct ContractArgs {
   const uint32_t* members;
   const unsigned long long* degsum;
   const uint64_t* tmpoff;
-  uint32_t* tkey;
-  int64_t* tw;
-  uint32_t* tsrc;
+  uint32_t* tkey;   // scratch rows: row x's distinct neighbours at tmpoff[x] ..
+  int64_t* tw;      //   tmpoff[x] + ndist[x] - 1, their summed weights
+  uint32_t* tsrc;   //   and their row (written only when not NULL)
   uint32_t* ndist;
 };
 

@@ -18,6 +18,8 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <type_traits>
+
 #include "contract.h"
 #include "profiler.h"
 
@@ -205,15 +207,13 @@ __global__ __launch_bounds__(256) void k_rows_wave(ContractArgs a, const uint32_
   const bool tail = valid && (l == WAVE - 1 || next != key);
   const uint64_t tmask = __ballot(tail);
   const uint64_t base = a.tmpoff[x];
-  const uint64_t deg = a.degsum[x];
   if (tail) {
     const uint64_t o = base + (uint64_t)__popcll(tmask & lanemask_lt());
     a.tkey[o] = key;
     a.tw[o] = s;
-    a.tsrc[o] = x;
+    if (a.tsrc) a.tsrc[o] = x;
   }
   const uint32_t nd = (uint32_t)__popcll(tmask);
-  for (uint64_t i = nd + l; i < deg; i += WAVE) a.tkey[base + i] = EMPTY_KEY;
   if (l == 0) a.ndist[x] = nd;
 }
 
@@ -315,11 +315,9 @@ __global__ __launch_bounds__(256) void k_rows_group(ContractArgs a, const uint32
     if (kk[j] != EMPTY_KEY) {
       a.tkey[o] = kk[j];
       a.tw[o] = (int64_t)val[gl * SPL + j];
-      a.tsrc[o] = x;
+      if (a.tsrc) a.tsrc[o] = x;
       ++o;
     }
-  const uint64_t deg = a.degsum[x];
-  for (uint64_t i = (uint64_t)nd + gl; i < deg; i += G) a.tkey[base + i] = EMPTY_KEY;
   if (gl == 0) a.ndist[x] = (uint32_t)nd;
 }
 
@@ -407,11 +405,10 @@ __global__ __launch_bounds__(256) void k_rows_block(ContractArgs a, const uint32
       const uint64_t o = base + carry + ex;
       a.tkey[o] = sk[i];
       a.tw[o] = s;
-      a.tsrc[o] = x;
+      if (a.tsrc) a.tsrc[o] = x;
     }
     carry += tot;
   }
-  for (uint64_t i = carry + threadIdx.x; i < deg; i += 256) a.tkey[base + i] = EMPTY_KEY;
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)carry;
 }
 
@@ -499,11 +496,10 @@ __global__ __launch_bounds__(1024) void k_rows_big(ContractArgs a, const uint32_
       const uint64_t o = base + carry + ex;
       a.tkey[o] = key;
       a.tw[o] = sum;
-      a.tsrc[o] = x;
+      if (a.tsrc) a.tsrc[o] = x;
     }
     carry += tot;
   }
-  for (uint64_t i = carry + threadIdx.x; i < deg; i += NT) a.tkey[base + i] = EMPTY_KEY;
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)carry;
 }
 
@@ -555,7 +551,6 @@ __global__ __launch_bounds__(NT) void k_rows_hash(ContractArgs a, const uint32_t
   if (r >= nrows) return;
   const uint32_t x = rows[r];
   const uint64_t m0 = a.mstart[x], m1 = a.mstart[x + 1];
-  const uint64_t deg = a.degsum[x];
   for (int i = threadIdx.x; i < T; i += NT) {
     if (PACK) {
       tab[i] = ~0ull;
@@ -636,10 +631,9 @@ __global__ __launch_bounds__(NT) void k_rows_hash(ContractArgs a, const uint32_t
     }
     a.tkey[o] = k;
     a.tw[o] = w;
-    a.tsrc[o] = x;
+    if (a.tsrc) a.tsrc[o] = x;
     ++o;
   }
-  for (uint64_t i = tot + threadIdx.x; i < deg; i += NT) a.tkey[a.tmpoff[x] + i] = EMPTY_KEY;
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)tot;
 }
 
@@ -781,7 +775,7 @@ __global__ __launch_bounds__(1024) void k_rows_range(ContractArgs a, const uint3
     if (v == ~0ull) continue;
     a.tkey[o] = (uint32_t)(v >> 32);
     a.tw[o] = (int64_t)(v & 0xFFFFFFFFull);
-    a.tsrc[o] = x;
+    if (a.tsrc) a.tsrc[o] = x;
     ++o;
   }
 }
@@ -790,8 +784,6 @@ __global__ void k_rows_range_finish(ContractArgs a, const uint32_t* rows, const 
   const uint32_t r = blockIdx.x;
   const uint32_t x = rows[r];
   const uint64_t nd = rowfill[r];
-  const uint64_t deg = a.degsum[x];
-  for (uint64_t i = nd + threadIdx.x; i < deg; i += blockDim.x) a.tkey[a.tmpoff[x] + i] = EMPTY_KEY;
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)nd;
 }
 
@@ -819,7 +811,7 @@ __global__ void k_rows_reduce(ContractArgs a, const uint32_t* rows, uint32_t nro
   const uint64_t o = a.tmpoff[x] + (hpos[i] - hpos[goff[r]]);
   a.tkey[o] = (uint32_t)k;
   a.tw[o] = s;
-  a.tsrc[o] = x;
+  if (a.tsrc) a.tsrc[o] = x;
 }
 
 __global__ void k_rows_finish(ContractArgs a, const uint32_t* rows, uint32_t nrows,
@@ -828,24 +820,62 @@ __global__ void k_rows_finish(ContractArgs a, const uint32_t* rows, uint32_t nro
   if (r >= nrows) return;
   const uint32_t x = rows[r];
   const uint64_t nd = hpos[goff[r + 1]] - hpos[goff[r]];
-  const uint64_t deg = a.degsum[x];
-  for (uint64_t i = nd + threadIdx.x; i < deg; i += blockDim.x) a.tkey[a.tmpoff[x] + i] = EMPTY_KEY;
   if (threadIdx.x == 0) a.ndist[x] = (uint32_t)nd;
 }
 
 // Compact the scratch rows into the coarse CSR (weights stored as WT).
+// Compact the scratch rows into the coarse CSR (weights stored as WT): row x's
+// distinct entries sit at the front of its scratch range, ndist[x] of them.
+// A group of G lanes per row (G chosen per level from the mean row length);
+// rows above 32 G entries are listed, one atomic per block, for one block
+// each (k_rows_copy_big).
+constexpr uint32_t COPY_ITERS = 32;
+
 template <typename WT>
-__global__ void k_rows_copy(ContractArgs a, uint64_t total, uint32_t* cadj, WT* cew,
-                            uint32_t* csrc, const uint64_t* cxadj) {
-  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  const uint32_t k = a.tkey[e];
-  if (k == EMPTY_KEY) return;
-  const uint32_t x = a.tsrc[e];
-  const uint64_t d = cxadj[x] + (e - a.tmpoff[x]);
-  cadj[d] = k;
-  cew[d] = (WT)a.tw[e];
-  csrc[d] = x;
+LMGP_D void copy_row(const ContractArgs& a, uint32_t x, uint32_t i0, uint32_t step, uint32_t* cadj,
+                     WT* cew, uint32_t* csrc, const uint64_t* cxadj) {
+  const uint32_t nd = a.ndist[x];
+  const uint64_t from = a.tmpoff[x], to = cxadj[x];
+  for (uint32_t i = i0; i < nd; i += step) {
+    cadj[to + i] = a.tkey[from + i];
+    cew[to + i] = (WT)a.tw[from + i];
+    csrc[to + i] = x;
+  }
+}
+
+template <typename WT, int G>
+__global__ __launch_bounds__(256) void k_rows_copy(ContractArgs a, uint64_t nc, uint32_t* cadj,
+                                                   WT* cew, uint32_t* csrc, const uint64_t* cxadj,
+                                                   uint32_t* big, unsigned long long* nbig) {
+  __shared__ uint32_t s_cnt;
+  __shared__ unsigned long long s_base;
+  const uint64_t x = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / G;
+  const uint32_t gl = threadIdx.x % G;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint32_t nd = x < nc ? a.ndist[x] : 0u;
+  const bool listed = nd > COPY_ITERS * G;
+  uint32_t pos = 0;
+  if (listed && gl == 0) pos = atomicAdd(&s_cnt, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(nbig, (unsigned long long)s_cnt);
+  __syncthreads();
+  if (x >= nc) return;
+  if (listed) {
+    if (gl == 0) big[s_base + pos] = (uint32_t)x;
+    return;
+  }
+  copy_row<WT>(a, (uint32_t)x, gl, G, cadj, cew, csrc, cxadj);
+}
+
+template <typename WT>
+__global__ __launch_bounds__(256) void k_rows_copy_big(ContractArgs a, const uint32_t* rows,
+                                                       const unsigned long long* nrows,
+                                                       uint32_t* cadj, WT* cew, uint32_t* csrc,
+                                                       const uint64_t* cxadj) {
+  const unsigned long long nr = *nrows;
+  for (unsigned long long j = blockIdx.x; j < nr; j += gridDim.x)
+    copy_row<WT>(a, rows[j], threadIdx.x, 256u, cadj, cew, csrc, cxadj);
 }
 
 struct FlagUsed {
@@ -1061,7 +1091,7 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   exclusive_scan(ArrayU64{(const uint64_t*)degsum.get()}, nc, tmpoff.get(), true, pool, s);
   uint64_t mt = 0;
   read_now(&mt, tmpoff.get() + nc, sizeof(uint64_t), s);
-  DBuf<uint32_t> tkey(&pool, s, mt ? mt : 1), tsrc(&pool, s, mt ? mt : 1), ndist(&pool, s, nc + 1);
+  DBuf<uint32_t> tkey(&pool, s, mt ? mt : 1), ndist(&pool, s, nc + 1);
   DBuf<int64_t> tw(&pool, s, mt ? mt : 1);
   ContractArgs a{};
   a.xadj = in.xadj;
@@ -1074,11 +1104,11 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   a.tmpoff = tmpoff.get();
   a.tkey = tkey.get();
   a.tw = tw.get();
-  a.tsrc = tsrc.get();
+  a.tsrc = nullptr;  // the copy writes each entry's row
   a.ndist = ndist.get();
   prof_members.end();
   // rows: every member entry's neighbour, its map entry and weight read; the
-  // distinct neighbours written to scratch (id, weight, row) and counted
+  // distinct neighbours written to scratch (id, weight) and counted
   const uint64_t fine_entries = mt;
   ProfScope prof_rows("ct:rows", (8 + bw) * fine_entries + 8 * n + 16 * nc, s);
   build_rows(a, nc, in.packed, in.sorted, in.ew_kind, pool, s);
@@ -1088,24 +1118,40 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   uint64_t mc = 0;
   read_now(&mc, out.xadj.get() + nc, sizeof(uint64_t), s);
   out.nnz = mc;
-  prof_rows.add_bytes(16 * mc);
+  prof_rows.add_bytes(12 * mc);
   prof_rows.end();
-  // copy: scratch entries read (id, weight, row), coarse adjacency, weight and
-  // row written
-  ProfScope prof_copy("ct:copy", (16 + 8 + (in.narrow ? 4 : 8)) * mc + 8 * nc, s);
+  // copy: scratch entries read (id, weight), coarse adjacency, weight and row
+  // written; per coarse node its count and two offsets
+  ProfScope prof_copy("ct:copy", (12 + 8 + (in.narrow ? 4 : 8)) * mc + 20 * nc, s);
   out.adj.reset(&pool, s, mc ? mc : 1);
   out.src.reset(&pool, s, mc ? mc : 1);
   out.ew_kind = in.narrow ? EW_I32 : EW_I64;
   if (in.narrow) out.ew32.reset(&pool, s, mc ? mc : 1);
   else out.ew.reset(&pool, s, mc ? mc : 1);
-  if (mt) {
-    if (in.narrow)
-      k_rows_copy<int32_t><<<grid_for(mt, 256), 256, 0, s>>>(a, mt, out.adj.get(), out.ew32.get(),
-                                                             out.src.get(), out.xadj.get());
-    else
-      k_rows_copy<int64_t><<<grid_for(mt, 256), 256, 0, s>>>(a, mt, out.adj.get(), out.ew.get(),
-                                                             out.src.get(), out.xadj.get());
-    LAUNCH_CHECK();
+  if (mc) {
+    // G: the power of two nearest half the mean row length, in [4, 64]
+    int G = 4;
+    while (G < 64 && (uint64_t)G * 2 * nc < mc) G *= 2;
+    // listed rows have more than COPY_ITERS * G entries
+    const uint64_t big_max = mc / (COPY_ITERS * G + 1) + 1;
+    DBuf<uint32_t> big(&pool, s, big_max);
+    DBuf<unsigned long long> nbig(&pool, s, 1);
+    nbig.zero();
+    const unsigned gc = grid_for(nc * (uint64_t)G, 256);
+    const unsigned gb = (unsigned)std::min<uint64_t>(big_max, 1024);
+    auto copy = [&](auto* cew) {
+      using WT = std::remove_pointer_t<decltype(cew)>;
+      auto* k = G == 4 ? k_rows_copy<WT, 4> : G == 8 ? k_rows_copy<WT, 8>
+              : G == 16 ? k_rows_copy<WT, 16> : G == 32 ? k_rows_copy<WT, 32> : k_rows_copy<WT, 64>;
+      k<<<gc, 256, 0, s>>>(a, nc, out.adj.get(), cew, out.src.get(), out.xadj.get(), big.get(),
+                           nbig.get());
+      LAUNCH_CHECK();
+      k_rows_copy_big<WT><<<gb, 256, 0, s>>>(a, big.get(), nbig.get(), out.adj.get(), cew,
+                                             out.src.get(), out.xadj.get());
+      LAUNCH_CHECK();
+    };
+    if (in.narrow) copy(out.ew32.get());
+    else copy(out.ew.get());
   }
   // no wait here: scratch freed on return goes back to a stream-ordered pool
   // (reused only by later work on this stream)
