@@ -95,16 +95,39 @@ __global__ void k_coarse_nodes(const int64_t* W, const uint32_t* lcount, const u
   }
 }
 
-__global__ void k_members(const uint64_t* xadj, const uint32_t* map, uint64_t n,
-                          const uint64_t* mstart, uint32_t* mfill, uint32_t* members,
-                          unsigned long long* degsum) {
-  uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  const uint32_t x = map[u];
-  if (x == EMPTY_KEY) return;
-  members[mstart[x] + atomicAdd(&mfill[x], 1u)] = (uint32_t)u;
-  const uint64_t d = xadj[u + 1] - xadj[u];
-  if (d) atomicAdd(&degsum[x], (unsigned long long)d);
+// Members of each coarse node (in any order: every consumer is order
+// independent) and the summed degree of each.  Lanes holding consecutive
+// nodes of one coarse node form a run; the run's last lane takes the slots
+// and adds the degrees for the whole run (one pair of atomics per run).
+__global__ __launch_bounds__(256) void k_members(const uint64_t* xadj, const uint32_t* map,
+                                                 uint64_t n, const uint64_t* mstart, uint32_t* mfill,
+                                                 uint32_t* members, unsigned long long* degsum) {
+  const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = lane_id();
+  const uint32_t x = u < n ? map[u] : EMPTY_KEY;
+  const uint64_t d = u < n && x != EMPTY_KEY ? xadj[u + 1] - xadj[u] : 0;
+  const uint32_t xp = __shfl_up(x, 1);
+  const uint32_t xn = __shfl_down(x, 1);
+  const uint64_t heads = __ballot(l == 0 || xp != x);
+  const bool tail = l == WAVE - 1 || xn != x;
+  // the run [h, t] holding this lane
+  const uint64_t below = heads & ((2ull << l) - 1);  // heads at lanes <= l (l's own included)
+  const int h = 63 - __clzll(below);
+  const uint64_t above = heads & ~((2ull << l) - 1);
+  const int t = above ? __ffsll((long long)above) - 2 : WAVE - 1;
+  const uint64_t incl = wave_inclusive_scan(d);
+  // every lane takes part in the shuffle (a lane left out of it would read 0
+  // from a source lane that is)
+  const uint64_t at_prev = __shfl(incl, h > 0 ? h - 1 : 0);
+  const uint64_t before = h > 0 ? at_prev : 0;
+  uint32_t base = 0;
+  if (tail && x != EMPTY_KEY) {
+    base = atomicAdd(&mfill[x], (uint32_t)(t - h + 1));
+    const uint64_t run_deg = incl - before;
+    if (run_deg) atomicAdd(&degsum[x], (unsigned long long)run_deg);
+  }
+  base = __shfl(base, t);
+  if (x != EMPTY_KEY) members[mstart[x] + base + (uint32_t)(l - h)] = (uint32_t)u;
 }
 
 // Row size classes (see row_class), counted per block and listed.
