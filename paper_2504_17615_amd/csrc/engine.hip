@@ -954,6 +954,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.nbuckets = NB;
   ba.counts = rstate.get();
   ba.degs = rstate.get() + NB;
+  ba.degs_all = Profiler::get().on() || p_.tune || p_.graph_rounds;
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();
@@ -1318,6 +1319,7 @@ void Engine::two_hop(Level& L, std::vector<Job>& jobs, const std::vector<uint8_t
   ba.nbuckets = NCLASS;
   ba.counts = bcount.get();
   ba.degs = bcount.get() + NCLASS;
+  ba.degs_all = Profiler::get().on() || p_.tune;
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();

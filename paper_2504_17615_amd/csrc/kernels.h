@@ -178,7 +178,11 @@ struct BucketArgs {
   const int64_t* nw;       // node weights
   uint32_t nbuckets;
   unsigned long long* counts;  // [nbuckets]
-  unsigned long long* degs;  // [nbuckets] summed degrees (count pass)
+  unsigned long long* degs;  // [nbuckets] summed degrees (count pass): of every bucket
+                             // when degs_all, else of the hub class only (its
+                             // launches are sized by them; the others serve
+                             // measurement and the autotuner)
+  uint32_t degs_all;
   uint32_t* offs;          // [nbuckets] (offsets pass writes, scatter pass reads)
   uint32_t* fill;          // [nbuckets] (scatter pass)
   uint32_t* list;          // output

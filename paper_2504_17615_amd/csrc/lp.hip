@@ -1464,7 +1464,8 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
     int b = bucket_of(a, u);
     if (b >= 0) {
       atomicAdd(&h[b], 1u);
-      atomicAdd(&hd[b], (unsigned long long)(a.xadj[u + 1] - a.xadj[u]));
+      if (a.degs_all || b % NCLASS == CLASS_GLOBAL)
+        atomicAdd(&hd[b], (unsigned long long)(a.xadj[u + 1] - a.xadj[u]));
     }
   }
   __syncthreads();
