@@ -932,6 +932,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     }
   DBuf<uint64_t> dpre(&pool_, s_, pre.size() ? pre.size() : 1);
   DBuf<unsigned long long> dround(&pool_, s_, B), dncl(&pool_, s_, B);
+  // one graph's cluster-count changes, one per admission apply block
+  DBuf<int64_t> nclpart;
+  if (ncl && B == 1 && !L.gid) nclpart.reset(&pool_, s_, grid_for(n ? n : 1, 256));
   DBuf<uint32_t> drounds(&pool_, s_, B);
   h2d(dpre.get(), pre.data(), pre.size(), s_);
   h2d(dgd.get(), gd.data(), B, s_);
@@ -1115,6 +1118,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.moves = (uint64_t*)dmoves.get();
     aa.ncl_count = ncl ? (int64_t*)ddelta.get() : nullptr;
     aa.nlabels = nlabels;
+    aa.ncl_part = ncl && B == 1 && !L.gid ? nclpart.get() : nullptr;
+    aa.ncl_prev = dncl.get();
     aa.few = few;
     aa.label8 = label8.get();
     return aa;

@@ -1995,9 +1995,11 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
+  __shared__ int64_t sm[NWAVE];
   const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t mv = 0;
+  int64_t dn = 0;  // change of the non-empty cluster count by this move
   if (i < nc && a.adm[i]) {
     const Cand c = a.cands[i];
     const uint32_t t = c.tgt;
@@ -2005,10 +2007,20 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
     const int64_t cu = a.nw[c.u];
     a.label[c.u] = t;
     if (a.label8) a.label8[c.u] = (uint8_t)t;
-    // no return values needed: the clusters that became empty or non-empty
-    // are counted from W afterwards (k_count_clusters)
-    atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
-    atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
+    if (a.ncl_part) {
+      // weights are positive and only members leave, so a weight never drops
+      // below zero: the target becomes non-empty iff it weighed 0 before this
+      // add, the own cluster becomes empty iff it weighed exactly cu
+      const int64_t ot =
+          (int64_t)atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
+      const int64_t oo =
+          (int64_t)atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
+      dn = (ot == 0 ? 1 : 0) - (oo == cu ? 1 : 0);
+    } else {
+      // a batch counts its clusters from W afterwards (k_count_clusters)
+      atomicAdd((unsigned long long*)&a.Wmut[t], (unsigned long long)cu);
+      atomicAdd((unsigned long long*)&a.Wmut[own], (unsigned long long)(-cu));
+    }
     mv = 1;
     if (a.csize) {
       atomicAdd(&a.csize[t], 1u);
@@ -2025,6 +2037,20 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
     }
   }
   if (!a.gid && __ballot(mv != 0) && lane_id() == 0) mark_moved(a, 0);
+  if (a.ncl_part) {
+    const int64_t tot = block_reduce_sum(dn, sm);
+    if (threadIdx.x == 0) a.ncl_part[blockIdx.x] = tot;
+  }
+}
+
+// One graph: its cluster count after the sub-round, the count before plus the
+// apply blocks' changes (one block).
+__global__ __launch_bounds__(256) void k_ncl_sum(AdmitArgs a, uint32_t parts) {
+  __shared__ int64_t sm[NWAVE];
+  int64_t v = 0;
+  for (uint32_t j = threadIdx.x; j < parts; j += 256) v += a.ncl_part[j];
+  const int64_t tot = block_reduce_sum(v, sm);
+  if (threadIdx.x == 0) a.ncl_count[0] = (int64_t)a.ncl_prev[0] + tot;
 }
 
 // Non-empty clusters per graph after the moves.  Labels of one graph are
@@ -2165,7 +2191,11 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
     }
   }
   LAUNCH_CHECK();
-  if (a.ncl_count && a.nlabels) {
+  if (a.ncl_count && a.ncl_part) {
+    if (few_apply) throw InvalidArg("cluster-count changes need the general apply");
+    k_ncl_sum<<<1, 256, 0, s>>>(a, g);
+    LAUNCH_CHECK();
+  } else if (a.ncl_count && a.nlabels) {
     unsigned gc = grid_for(a.nlabels, 256 * 16);
     if (gc > COUNT_BLOCKS) gc = COUNT_BLOCKS;
     k_count_clusters<<<gc, 256, 0, s>>>(a);
