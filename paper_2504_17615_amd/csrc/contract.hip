@@ -849,56 +849,51 @@ __global__ void k_rows_finish(ContractArgs a, const uint32_t* rows, uint32_t nro
 // Compact the scratch rows into the coarse CSR (weights stored as WT).
 // Compact the scratch rows into the coarse CSR (weights stored as WT): row x's
 // distinct entries sit at the front of its scratch range, ndist[x] of them.
-// A group of G lanes per row (G chosen per level from the mean row length);
-// rows above 32 G entries are listed, one atomic per block, for one block
-// each (k_rows_copy_big).
-constexpr uint32_t COPY_ITERS = 32;
+// Balanced over the output: block b writes coarse entries [b C, (b + 1) C)
+// (C = COPY_TILE); the rows they fall in are found by binary search over the
+// coarse offsets, staged in LDS when the tile spans at most COPY_ROWS rows.
+constexpr uint32_t COPY_TILE = 2048;
+constexpr uint32_t COPY_ROWS = 2048;
 
-template <typename WT>
-LMGP_D void copy_row(const ContractArgs& a, uint32_t x, uint32_t i0, uint32_t step, uint32_t* cadj,
-                     WT* cew, uint32_t* csrc, const uint64_t* cxadj) {
-  const uint32_t nd = a.ndist[x];
-  const uint64_t from = a.tmpoff[x], to = cxadj[x];
-  for (uint32_t i = i0; i < nd; i += step) {
-    cadj[to + i] = a.tkey[from + i];
-    cew[to + i] = (WT)a.tw[from + i];
-    csrc[to + i] = x;
+// last row x in [lo, hi] with off[x] <= d (off ascending, off[lo] <= d)
+template <class Off>
+LMGP_D uint64_t row_of(const Off& off, uint64_t lo, uint64_t hi, uint64_t d) {
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (off(mid) <= d) lo = mid;
+    else hi = mid - 1;
   }
-}
-
-template <typename WT, int G>
-__global__ __launch_bounds__(256) void k_rows_copy(ContractArgs a, uint64_t nc, uint32_t* cadj,
-                                                   WT* cew, uint32_t* csrc, const uint64_t* cxadj,
-                                                   uint32_t* big, unsigned long long* nbig) {
-  __shared__ uint32_t s_cnt;
-  __shared__ unsigned long long s_base;
-  const uint64_t x = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / G;
-  const uint32_t gl = threadIdx.x % G;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  const uint32_t nd = x < nc ? a.ndist[x] : 0u;
-  const bool listed = nd > COPY_ITERS * G;
-  uint32_t pos = 0;
-  if (listed && gl == 0) pos = atomicAdd(&s_cnt, 1u);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(nbig, (unsigned long long)s_cnt);
-  __syncthreads();
-  if (x >= nc) return;
-  if (listed) {
-    if (gl == 0) big[s_base + pos] = (uint32_t)x;
-    return;
-  }
-  copy_row<WT>(a, (uint32_t)x, gl, G, cadj, cew, csrc, cxadj);
+  return lo;
 }
 
 template <typename WT>
-__global__ __launch_bounds__(256) void k_rows_copy_big(ContractArgs a, const uint32_t* rows,
-                                                       const unsigned long long* nrows,
-                                                       uint32_t* cadj, WT* cew, uint32_t* csrc,
-                                                       const uint64_t* cxadj) {
-  const unsigned long long nr = *nrows;
-  for (unsigned long long j = blockIdx.x; j < nr; j += gridDim.x)
-    copy_row<WT>(a, rows[j], threadIdx.x, 256u, cadj, cew, csrc, cxadj);
+__global__ __launch_bounds__(256) void k_rows_copy(ContractArgs a, uint64_t nc, uint64_t mc,
+                                                   uint32_t* cadj, WT* cew, uint32_t* csrc,
+                                                   const uint64_t* cxadj) {
+  __shared__ uint64_t soff[COPY_ROWS + 1];
+  __shared__ uint64_t s_x0, s_x1;
+  const uint64_t d0 = (uint64_t)blockIdx.x * COPY_TILE;
+  const uint64_t d1 = d0 + COPY_TILE < mc ? d0 + COPY_TILE : mc;
+  auto goff = [&](uint64_t x) { return cxadj[x]; };
+  if (threadIdx.x == 0) {
+    // rows holding the tile's first and last entry (cxadj[nc] = mc > d)
+    s_x0 = row_of(goff, 0, nc - 1, d0);
+    s_x1 = row_of(goff, s_x0, nc - 1, d1 - 1);
+  }
+  __syncthreads();
+  const uint64_t x0 = s_x0, x1 = s_x1;
+  const bool staged = x1 - x0 < COPY_ROWS;
+  if (staged)
+    for (uint64_t j = threadIdx.x; j <= x1 - x0; j += 256) soff[j] = cxadj[x0 + j];
+  __syncthreads();
+  auto loff = [&](uint64_t x) { return soff[x - x0]; };
+  for (uint64_t d = d0 + threadIdx.x; d < d1; d += 256) {
+    const uint64_t x = staged ? row_of(loff, x0, x1, d) : row_of(goff, x0, x1, d);
+    const uint64_t from = a.tmpoff[x] + (d - (staged ? loff(x) : goff(x)));
+    cadj[d] = a.tkey[from];
+    cew[d] = (WT)a.tw[from];
+    csrc[d] = (uint32_t)x;
+  }
 }
 
 struct FlagUsed {
@@ -1143,38 +1138,23 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   out.nnz = mc;
   prof_rows.add_bytes(12 * mc);
   prof_rows.end();
-  // copy: scratch entries read (id, weight), coarse adjacency, weight and row
-  // written; per coarse node its count and two offsets
-  ProfScope prof_copy("ct:copy", (12 + 8 + (in.narrow ? 4 : 8)) * mc + 20 * nc, s);
+  // copy: scratch entries read (id, weight) with their row's two offsets,
+  // coarse adjacency, weight and row written; the coarse offsets staged
+  ProfScope prof_copy("ct:copy", (12 + 8 + 8 + (in.narrow ? 4 : 8)) * mc + 8 * nc, s);
   out.adj.reset(&pool, s, mc ? mc : 1);
   out.src.reset(&pool, s, mc ? mc : 1);
   out.ew_kind = in.narrow ? EW_I32 : EW_I64;
   if (in.narrow) out.ew32.reset(&pool, s, mc ? mc : 1);
   else out.ew.reset(&pool, s, mc ? mc : 1);
   if (mc) {
-    // G: the power of two nearest half the mean row length, in [4, 64]
-    int G = 4;
-    while (G < 64 && (uint64_t)G * 2 * nc < mc) G *= 2;
-    // listed rows have more than COPY_ITERS * G entries
-    const uint64_t big_max = mc / (COPY_ITERS * G + 1) + 1;
-    DBuf<uint32_t> big(&pool, s, big_max);
-    DBuf<unsigned long long> nbig(&pool, s, 1);
-    nbig.zero();
-    const unsigned gc = grid_for(nc * (uint64_t)G, 256);
-    const unsigned gb = (unsigned)std::min<uint64_t>(big_max, 1024);
-    auto copy = [&](auto* cew) {
-      using WT = std::remove_pointer_t<decltype(cew)>;
-      auto* k = G == 4 ? k_rows_copy<WT, 4> : G == 8 ? k_rows_copy<WT, 8>
-              : G == 16 ? k_rows_copy<WT, 16> : G == 32 ? k_rows_copy<WT, 32> : k_rows_copy<WT, 64>;
-      k<<<gc, 256, 0, s>>>(a, nc, out.adj.get(), cew, out.src.get(), out.xadj.get(), big.get(),
-                           nbig.get());
-      LAUNCH_CHECK();
-      k_rows_copy_big<WT><<<gb, 256, 0, s>>>(a, big.get(), nbig.get(), out.adj.get(), cew,
-                                             out.src.get(), out.xadj.get());
-      LAUNCH_CHECK();
-    };
-    if (in.narrow) copy(out.ew32.get());
-    else copy(out.ew.get());
+    const unsigned gc = (unsigned)((mc + COPY_TILE - 1) / COPY_TILE);
+    if (in.narrow)
+      k_rows_copy<int32_t><<<gc, 256, 0, s>>>(a, nc, mc, out.adj.get(), out.ew32.get(),
+                                              out.src.get(), out.xadj.get());
+    else
+      k_rows_copy<int64_t><<<gc, 256, 0, s>>>(a, nc, mc, out.adj.get(), out.ew.get(),
+                                              out.src.get(), out.xadj.get());
+    LAUNCH_CHECK();
   }
   // no wait here: scratch freed on return goes back to a stream-ordered pool
   // (reused only by later work on this stream)
