@@ -1115,7 +1115,10 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.cpos = cpos.get();
     aa.seg = seg.get();
     aa.csize = csize;
-    aa.moves = (uint64_t*)dmoves.get();
+    // refinement: no control kernel after a sub-round (its graphs change only
+    // at round starts), the moves mark the round directly
+    aa.moves = (uint64_t*)(ncl ? dmoves.get() : dround.get());
+    aa.clear_ov = ncl ? 0 : 1;
     aa.ncl_count = ncl ? (int64_t*)ddelta.get() : nullptr;
     aa.nlabels = nlabels;
     aa.ncl_part = ncl && B == 1 && !L.gid ? nclpart.get() : nullptr;
@@ -1189,7 +1192,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
         aa.plan = dplan.get() + sr;
         aa.max_cands = (uint32_t)umax;
         launch_admit(aa, cs);
-        k_lp_after_sub<<<1, 256, 0, cs>>>(ctl);
+        if (ncl) k_lp_after_sub<<<1, 256, 0, cs>>>(ctl);
         LAUNCH_CHECK();
       }
     } catch (...) {
@@ -1237,8 +1240,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
             // per candidate slot: the slot (24 B) read by classification,
             // scatter and apply, its target's demand and weight (16 B)
             ProfScope prof(spec.refine ? "rf:admission" : "cl:admission", 88ull * total, s_);
-            launch_admit(aa, s_);  // ovtotal was cleared by the control kernel
-            k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+            launch_admit(aa, s_);  // ovtotal was cleared by the control kernel or the apply
+            if (ncl) k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
             LAUNCH_CHECK();
           }
           if (bmode) {  // the next sub-round (or round) buckets from the grown flags

@@ -227,6 +227,8 @@ struct AdmitArgs {
   uint32_t* seg;
   uint32_t* csize;         // member counts (clustering) or NULL
   uint64_t* moves;         // per graph: set to 1 when the sub-round moved a node
+  uint32_t clear_ov;       // the apply clears ovtotal and ovcount (no control
+                           // kernel runs after this admission)
   int64_t* ncl_count;      // per graph (clustering): non-empty clusters after the
                            // sub-round, counted from Wmut over nlabels labels
                            // (zero before); NULL in refinement

@@ -1749,6 +1749,8 @@ __global__ __launch_bounds__(256) void k_adm_apply_few(AdmitArgs a) {
     (void)block_exclusive_scan(mv, smv, tot);
     if (threadIdx.x == 0 && tot) mark_moved(a, 0);
   }
+  // every kernel of this admission that reads the overflow counters has run
+  if (a.clear_ov && blockIdx.x == 0 && threadIdx.x == 0) a.ovtotal[0] = 0, a.ovcount[0] = 0;
 }
 
 __global__ void k_adm_reset_few(AdmitArgs a) {
@@ -2037,6 +2039,8 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
     }
   }
   if (!a.gid && __ballot(mv != 0) && lane_id() == 0) mark_moved(a, 0);
+  // every kernel of this admission that reads the overflow counters has run
+  if (a.clear_ov && blockIdx.x == 0 && threadIdx.x == 0) a.ovtotal[0] = 0, a.ovcount[0] = 0;
   if (a.ncl_part) {
     const int64_t tot = block_reduce_sum(dn, sm);
     if (threadIdx.x == 0) a.ncl_part[blockIdx.x] = tot;
