@@ -102,7 +102,18 @@ struct LpCtl {
 
 // After a sub-round: count its moves; in clustering apply the cluster-count
 // change and stop a graph once shrink_num * |C| <= shrink_den * n.
-__global__ void k_lp_after_sub(LpCtl c) {
+// One graph (parts != NULL): the count is its count before the sub-round plus
+// the admission apply blocks' changes, summed here first.
+__global__ __launch_bounds__(256) void k_lp_after_sub(LpCtl c, const int64_t* parts,
+                                                      uint32_t nparts) {
+  if (parts) {
+    __shared__ int64_t sm[NWAVE];
+    int64_t v = 0;
+    for (uint32_t j = threadIdx.x; j < nparts; j += 256) v += parts[j];
+    const int64_t tot = block_reduce_sum(v, sm);
+    if (threadIdx.x == 0) c.delta[0] = (unsigned long long)((int64_t)c.ncl[0] + tot);
+    __syncthreads();
+  }
   for (uint32_t b = threadIdx.x; b < c.B; b += blockDim.x) {
     GraphDesc& g = c.gd[b];
     if (g.active) {
@@ -1122,7 +1133,6 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.ncl_count = ncl ? (int64_t*)ddelta.get() : nullptr;
     aa.nlabels = nlabels;
     aa.ncl_part = ncl && B == 1 && !L.gid ? nclpart.get() : nullptr;
-    aa.ncl_prev = dncl.get();
     aa.few = few;
     aa.label8 = label8.get();
     return aa;
@@ -1192,7 +1202,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
         aa.plan = dplan.get() + sr;
         aa.max_cands = (uint32_t)umax;
         launch_admit(aa, cs);
-        if (ncl) k_lp_after_sub<<<1, 256, 0, cs>>>(ctl);
+        if (ncl)
+          k_lp_after_sub<<<1, 256, 0, cs>>>(ctl, aa.ncl_part, grid_for(aa.max_cands, 256));
         LAUNCH_CHECK();
       }
     } catch (...) {
@@ -1241,7 +1252,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
             // scatter and apply, its target's demand and weight (16 B)
             ProfScope prof(spec.refine ? "rf:admission" : "cl:admission", 88ull * total, s_);
             launch_admit(aa, s_);  // ovtotal was cleared by the control kernel or the apply
-            if (ncl) k_lp_after_sub<<<1, 256, 0, s_>>>(ctl);
+            if (ncl)
+              k_lp_after_sub<<<1, 256, 0, s_>>>(ctl, aa.ncl_part, grid_for(total, 256));
             LAUNCH_CHECK();
           }
           if (bmode) {  // the next sub-round (or round) buckets from the grown flags

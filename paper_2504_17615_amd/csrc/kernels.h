@@ -235,10 +235,9 @@ struct AdmitArgs {
   uint64_t nlabels;
   // one graph: the apply kernel takes the count from the cluster weights'
   // transitions instead (returned by its atomics), one change per apply block
-  // into ncl_part, added to ncl_prev (the count before the sub-round); NULL
-  // for a batch (counted from Wmut)
+  // (grid_for(max_cands, 256) of them) into ncl_part, which the caller adds to
+  // the count before the sub-round; NULL for a batch (counted from Wmut)
   int64_t* ncl_part;
-  const unsigned long long* ncl_prev;
   uint32_t few;            // labels < few <= FEW_LABELS (see RateArgs), else 0
   const SubPlan* plan;     // planned launch: max_cands is an upper bound, the
                            // slot count is plan->total

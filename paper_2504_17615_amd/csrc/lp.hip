@@ -2047,15 +2047,6 @@ __global__ __launch_bounds__(256) void k_adm_apply(AdmitArgs a) {
   }
 }
 
-// One graph: its cluster count after the sub-round, the count before plus the
-// apply blocks' changes (one block).
-__global__ __launch_bounds__(256) void k_ncl_sum(AdmitArgs a, uint32_t parts) {
-  __shared__ int64_t sm[NWAVE];
-  int64_t v = 0;
-  for (uint32_t j = threadIdx.x; j < parts; j += 256) v += a.ncl_part[j];
-  const int64_t tot = block_reduce_sum(v, sm);
-  if (threadIdx.x == 0) a.ncl_count[0] = (int64_t)a.ncl_prev[0] + tot;
-}
 
 // Non-empty clusters per graph after the moves.  Labels of one graph are
 // contiguous, so a block's chunk spans few graphs: counts of the chunk's
@@ -2196,9 +2187,8 @@ void launch_admit(const AdmitArgs& a, hipStream_t s) {
   }
   LAUNCH_CHECK();
   if (a.ncl_count && a.ncl_part) {
+    // the caller's control kernel adds the apply blocks' changes
     if (few_apply) throw InvalidArg("cluster-count changes need the general apply");
-    k_ncl_sum<<<1, 256, 0, s>>>(a, g);
-    LAUNCH_CHECK();
   } else if (a.ncl_count && a.nlabels) {
     unsigned gc = grid_for(a.nlabels, 256 * 16);
     if (gc > COUNT_BLOCKS) gc = COUNT_BLOCKS;
