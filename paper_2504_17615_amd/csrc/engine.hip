@@ -857,13 +857,11 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     gd[b].subrounds = S;
     gd[b].active = active[b];
   }
-  DBuf<GraphDesc> dgd(&pool_, s_, B);
-  DBuf<unsigned long long> dmoves(&pool_, s_, B), ddelta(&pool_, s_, B);
   DBuf<Cand> cands(&pool_, s_, n);
   DBuf<uint32_t> list(&pool_, s_, n);
   DBuf<LabelTally> tally(&pool_, s_, nlabels);
   DBuf<uint32_t> segbase(&pool_, s_, nlabels);
-  DBuf<uint32_t> ovtotal(&pool_, s_, 2), ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
+  DBuf<uint32_t> ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
   DBuf<uint8_t> adm(&pool_, s_, n);
   DBuf<uint32_t> boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
   // per-round state read by the host in one copy: bucket counts, bucket
@@ -941,27 +939,36 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       q[1] = chain(jb.seed, ttie, {lv, r});
       q[2] = chain(jb.seed, tadm, {lv, r});
     }
-  DBuf<uint64_t> dpre(&pool_, s_, pre.size() ? pre.size() : 1);
-  DBuf<unsigned long long> dround(&pool_, s_, B), dncl(&pool_, s_, B);
+  // the graphs' control state (zero: moves, cluster-count changes, round
+  // moves, rounds run, admission overflow counters), their cluster counts,
+  // graph table and the hash prefixes of every round: one block, one upload
+  const size_t o_delta = 8 * (size_t)B, o_round = 16 * (size_t)B, o_rounds = 24 * (size_t)B;
+  const size_t o_ov = o_rounds + 8 * (((size_t)B + 1) / 2), o_ncl = o_ov + 8;
+  const size_t o_gd = o_ncl + 8 * (size_t)B, o_pre = o_gd + sizeof(GraphDesc) * B;
+  const size_t ctl_bytes = o_pre + 8 * pre.size();
+  std::vector<uint8_t> hctl(ctl_bytes, 0);
+  if (ncl) std::memcpy(&hctl[o_ncl], ncl->data(), 8 * (size_t)B);
+  std::memcpy(&hctl[o_gd], gd.data(), sizeof(GraphDesc) * B);
+  if (!pre.empty()) std::memcpy(&hctl[o_pre], pre.data(), 8 * pre.size());
+  DBuf<uint8_t> dctl(&pool_, s_, ctl_bytes);
+  h2d(dctl.get(), hctl.data(), ctl_bytes, s_);
+  unsigned long long* const dmoves = (unsigned long long*)dctl.get();
+  unsigned long long* const ddelta = (unsigned long long*)(dctl.get() + o_delta);
+  unsigned long long* const dround = (unsigned long long*)(dctl.get() + o_round);
+  uint32_t* const drounds = (uint32_t*)(dctl.get() + o_rounds);
+  uint32_t* const ovtotal = (uint32_t*)(dctl.get() + o_ov);
+  unsigned long long* const dncl = (unsigned long long*)(dctl.get() + o_ncl);
+  GraphDesc* const dgd = (GraphDesc*)(dctl.get() + o_gd);
+  const uint64_t* const dpre = (const uint64_t*)(dctl.get() + o_pre);
   // one graph's cluster-count changes, one per admission apply block
   DBuf<int64_t> nclpart;
   if (ncl && B == 1 && !L.gid) nclpart.reset(&pool_, s_, grid_for(n ? n : 1, 256));
-  DBuf<uint32_t> drounds(&pool_, s_, B);
-  h2d(dpre.get(), pre.data(), pre.size(), s_);
-  h2d(dgd.get(), gd.data(), B, s_);
-  if (ncl) h2d(dncl.get(), (const unsigned long long*)ncl->data(), B, s_);
-  dmoves.zero();
-  ddelta.zero();
-  dround.zero();
-  drounds.zero();
-  ovtotal.zero();
-  LpCtl ctl{dgd.get(), B, dmoves.get(), ddelta.get(), dround.get(), ncl ? dncl.get() : nullptr,
-            drounds.get(), rstate.get(), NB, ovtotal.get(), dpre.get(), p_.shrink_num,
-            p_.shrink_den};
+  LpCtl ctl{dgd, B, dmoves, ddelta, dround, ncl ? dncl : nullptr, drounds, rstate.get(), NB,
+            ovtotal, dpre, p_.shrink_num, p_.shrink_den};
   BucketArgs ba{};
   ba.xadj = L.xadj;
   ba.gid = L.gid;
-  ba.gd = dgd.get();
+  ba.gd = dgd;
   ba.n = n;
   ba.nw = L.nw;
   ba.mode = 0;
@@ -1048,7 +1055,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     ra.label = label;
     ra.W = W;
     ra.gid = L.gid;
-    ra.gd = dgd.get();
+    ra.gd = dgd;
     ra.mode = MODE_LP;
     ra.phase = spec.refine ? 1 : 0;
     ra.packed = packed_ ? 1 : 0;
@@ -1116,11 +1123,11 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.nw = L.nw;
     aa.label = label;
     aa.gid = L.gid;
-    aa.gd = dgd.get();
+    aa.gd = dgd;
     aa.tally = tally.get();
     aa.segbase = segbase.get();
-    aa.ovtotal = ovtotal.get();
-    aa.ovcount = ovtotal.get() + 1;
+    aa.ovtotal = ovtotal;
+    aa.ovcount = ovtotal + 1;
     aa.ovtgts = ovtgts.get();
     aa.adm = adm.get();
     aa.cpos = cpos.get();
@@ -1128,9 +1135,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.csize = csize;
     // refinement: no control kernel after a sub-round (its graphs change only
     // at round starts), the moves mark the round directly
-    aa.moves = (uint64_t*)(ncl ? dmoves.get() : dround.get());
+    aa.moves = (uint64_t*)(ncl ? dmoves : dround);
     aa.clear_ov = ncl ? 0 : 1;
-    aa.ncl_count = ncl ? (int64_t*)ddelta.get() : nullptr;
+    aa.ncl_count = ncl ? (int64_t*)ddelta : nullptr;
     aa.nlabels = nlabels;
     aa.ncl_part = ncl && B == 1 && !L.gid ? nclpart.get() : nullptr;
     aa.few = few;
@@ -1290,8 +1297,8 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     throw;
   }
   std::vector<unsigned long long> hncl(B);
-  d2h(rounds_run.data(), drounds.get(), B, s_);
-  if (ncl) d2h(hncl.data(), dncl.get(), B, s_);
+  d2h(rounds_run.data(), drounds, B, s_);
+  if (ncl) d2h(hncl.data(), dncl, B, s_);
   if (replay && !flags_from_peek) d2h(hflags.data(), rstate.get() + 2 * NB, B, s_);
   sync(s_);
   if (gexec) HIP_CHECK(hipGraphExecDestroy(gexec));
