@@ -26,6 +26,10 @@ struct ContractIn {
   // int32 (ew32, ew_kind EW_I32) instead of int64
   bool narrow = false;
   std::vector<uint64_t> bounds;     // node boundaries of the graphs (B + 1 values)
+  // every graph is kept: every node is mapped, so the summed member degree
+  // is the level's entry count, entries (no read back)
+  bool all_kept = false;
+  uint64_t entries = 0;
 };
 
 struct ContractOut {

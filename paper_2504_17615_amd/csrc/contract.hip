@@ -1107,8 +1107,8 @@ void contract_level(const ContractIn& in, ContractOut& out, Pool& pool, hipStrea
   mfill.clear();
   DBuf<uint64_t> tmpoff(&pool, s, nc + 1);
   exclusive_scan(ArrayU64{(const uint64_t*)degsum.get()}, nc, tmpoff.get(), true, pool, s);
-  uint64_t mt = 0;
-  read_now(&mt, tmpoff.get() + nc, sizeof(uint64_t), s);
+  uint64_t mt = in.entries;
+  if (!in.all_kept) read_now(&mt, tmpoff.get() + nc, sizeof(uint64_t), s);
   DBuf<uint32_t> tkey(&pool, s, mt ? mt : 1), ndist(&pool, s, nc + 1);
   DBuf<int64_t> tw(&pool, s, mt ? mt : 1);
   ContractArgs a{};

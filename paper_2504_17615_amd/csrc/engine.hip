@@ -1623,6 +1623,8 @@ void Engine::coarsen(std::vector<Job>& jobs) {
     ci.gid = L.gid;
     ci.keep = dkeep.get();
     ci.bounds = L.nbase;
+    ci.all_kept = nkeep == B;
+    ci.entries = L.nnz;
     ci.packed = packed_;
     ci.sorted = false;
     ContractOut co;
