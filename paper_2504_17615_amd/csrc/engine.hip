@@ -863,6 +863,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<uint32_t> segbase(&pool_, s_, nlabels);
   DBuf<uint32_t> ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
   DBuf<uint8_t> adm(&pool_, s_, n);
+  // each node's bucket from the count pass for the scatter (ids fit a byte)
+  DBuf<uint8_t> bkt;
+  if (NB <= 255) bkt.reset(&pool_, s_, n);
   DBuf<uint32_t> boffs(&pool_, s_, NB), bfill(&pool_, s_, NB);
   // per-round state read by the host in one copy: bucket counts, bucket
   // degree sums, active flags
@@ -979,6 +982,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   ba.offs = boffs.get();
   ba.fill = bfill.get();
   ba.list = list.get();
+  ba.bkt = NB <= 255 ? bkt.get() : nullptr;
   ba.cuts = presets[preset].cuts;
   ba.only = bmode ? bflag.get() : nullptr;
   ba.only_sub = 0;

@@ -186,6 +186,8 @@ struct BucketArgs {
   uint32_t* offs;          // [nbuckets] (offsets pass writes, scatter pass reads)
   uint32_t* fill;          // [nbuckets] (scatter pass)
   uint32_t* list;          // output
+  uint8_t* bkt;            // per node: its bucket, written by the count pass and read
+                           // by the scatter (0xFF: none), or NULL (recomputed)
   ClassCuts cuts;          // degree -> class (non-decreasing bounds)
   // mode 0, refinement of boundary nodes only: when `only` is set, a node is
   // bucketed only if only[u] != 0 and its sub-round is only_sub

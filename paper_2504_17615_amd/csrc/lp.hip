@@ -1462,6 +1462,7 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
     const uint64_t u = a.ids ? a.ids[i] : i;
     int b = bucket_of(a, u);
+    if (a.bkt) a.bkt[u] = b >= 0 ? (uint8_t)b : (uint8_t)0xFF;
     if (b >= 0) {
       atomicAdd(&h[b], 1u);
       if (a.degs_all || b % NCLASS == CLASS_GLOBAL)
@@ -1542,7 +1543,12 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
     for (int j = 0; j < BK_ITEMS; ++j) {
       const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
       uu[j] = i < total ? (a.ids ? a.ids[i] : (uint32_t)i) : 0u;
-      bk[j] = i < total ? bucket_of(a, uu[j]) : -1;
+      if (a.bkt) {
+        const uint8_t v = i < total ? a.bkt[uu[j]] : (uint8_t)0xFF;
+        bk[j] = v == 0xFF ? -1 : (int)v;
+      } else {
+        bk[j] = i < total ? bucket_of(a, uu[j]) : -1;
+      }
       lp[j] = bk[j] >= 0 ? atomicAdd(&cnt[bk[j]], 1u) : 0u;
     }
     __syncthreads();
@@ -2113,6 +2119,7 @@ void launch_rate(int cls, int ew_kind, const RateArgs& a, hipStream_t s) {
 }
 
 void launch_bucket_count(const BucketArgs& a, hipStream_t s) {
+  if (a.bkt && a.nbuckets > 255) throw InvalidArg("bucket ids do not fit a byte");
   if (a.nbuckets > MAX_BUCKETS) throw InvalidArg("too many sub-round buckets");
   unsigned g = grid_for(a.n, 256);
   if (g > 2048) g = 2048;
