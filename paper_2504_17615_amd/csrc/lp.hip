@@ -50,11 +50,47 @@ LMGP_D void reduce_best(Best& b, int64_t& r_own) {
   }
 }
 
+// Lane groups of at most 16 lanes reduce with DPP moves inside a 16-lane row
+// instead of LDS-routed shuffles.  Stage s pairs each lane with a partner in
+// the other half of its 2^(s+1)-lane block: stages 0 and 1 are the quad
+// permutes i^1 and i^2, stage 2 the half-row mirror (i <-> 7 - i), stage 3 the
+// row mirror (i <-> 15 - i).  The halves agree after the earlier stages, so
+// after stages 0 .. log2(G) - 1 of an all-reduce (an associative, commutative
+// operation) every lane of an aligned G-lane group holds the group's result.
+// Every lane of the wave must take part.
+template <int S>
+LMGP_D uint32_t dpp_partner(uint32_t v) {
+  constexpr int ctrl = S == 0 ? 0xB1 : S == 1 ? 0x4E : S == 2 ? 0x141 : 0x140;
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
+}
+template <int S>
+LMGP_D uint64_t dpp_partner64(uint64_t v) {
+  return (uint64_t)dpp_partner<S>((uint32_t)v) | ((uint64_t)dpp_partner<S>((uint32_t)(v >> 32)) << 32);
+}
+
+template <int S, int G>
+LMGP_D void dpp_best_stage(Best& b, bool r32) {
+  if constexpr ((1 << S) < G) {
+    const int64_t orr = r32 ? (int64_t)dpp_partner<S>((uint32_t)b.r)
+                            : (int64_t)dpp_partner64<S>((uint64_t)b.r);
+    const uint64_t oh = dpp_partner64<S>(b.h);
+    const uint32_t oK = dpp_partner<S>(b.K);
+    if (better(orr, oh, oK, b)) b = Best{orr, oh, oK};
+  }
+}
+
 // As reduce_best for a group whose own-label rating is already known to every
 // lane; with r32 (every rating below 2^32) the ratings cross lanes as 32-bit
 // words.
 template <int WIDTH>
 LMGP_D void reduce_best_only(Best& b, bool r32) {
+  if constexpr (WIDTH <= 16) {
+    dpp_best_stage<0, WIDTH>(b, r32);
+    dpp_best_stage<1, WIDTH>(b, r32);
+    dpp_best_stage<2, WIDTH>(b, r32);
+    dpp_best_stage<3, WIDTH>(b, r32);
+    return;
+  }
 #pragma unroll
   for (int d = WIDTH / 2; d > 0; d >>= 1) {
     const int64_t orr = r32 ? (int64_t)(uint32_t)__shfl_xor((uint32_t)b.r, d, WIDTH)
@@ -157,6 +193,13 @@ LMGP_D void lds_insert_n(uint32_t* key, unsigned long long* val, uint32_t K, uin
 
 template <int G>
 LMGP_D int64_t group_sum(int64_t v) {
+  if constexpr (G <= 16) {
+    if constexpr (G > 1) v += (int64_t)dpp_partner64<0>((uint64_t)v);
+    if constexpr (G > 2) v += (int64_t)dpp_partner64<1>((uint64_t)v);
+    if constexpr (G > 4) v += (int64_t)dpp_partner64<2>((uint64_t)v);
+    if constexpr (G > 8) v += (int64_t)dpp_partner64<3>((uint64_t)v);
+    return v;
+  }
 #pragma unroll
   for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
   return v;
@@ -199,10 +242,26 @@ LMGP_D Best group_best(const bool* el, const uint32_t* Ks, const int64_t* rs, ui
   int64_t rm = 0;
 #pragma unroll
   for (int j = 0; j < SPL; ++j) rm = el[j] && rs[j] > rm ? rs[j] : rm;
+  if constexpr (G <= 16) {
+    auto stage = [&](auto sc) {
+      constexpr int S = decltype(sc)::value;
+      if constexpr ((1 << S) < G) {
+        const int64_t o = r32 ? (int64_t)dpp_partner<S>((uint32_t)rm)
+                              : (int64_t)dpp_partner64<S>((uint64_t)rm);
+        rm = o > rm ? o : rm;
+      }
+    };
+    stage(std::integral_constant<int, 0>());
+    stage(std::integral_constant<int, 1>());
+    stage(std::integral_constant<int, 2>());
+    stage(std::integral_constant<int, 3>());
+  } else {
 #pragma unroll
-  for (int d = G / 2; d > 0; d >>= 1) {
-    const int64_t o = r32 ? (int64_t)(uint32_t)__shfl_xor((uint32_t)rm, d, G) : __shfl_xor(rm, d, G);
-    rm = o > rm ? o : rm;
+    for (int d = G / 2; d > 0; d >>= 1) {
+      const int64_t o =
+          r32 ? (int64_t)(uint32_t)__shfl_xor((uint32_t)rm, d, G) : __shfl_xor(rm, d, G);
+      rm = o > rm ? o : rm;
+    }
   }
   Best b{0, 0, 0};
 #pragma unroll
