@@ -862,6 +862,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   DBuf<LabelTally> tally(&pool_, s_, nlabels);
   DBuf<uint32_t> segbase(&pool_, s_, nlabels);
   DBuf<uint32_t> ovtgts(&pool_, s_, n), cpos(&pool_, s_, n), seg(&pool_, s_, n);
+  DBuf<SegRec> segrec(&pool_, s_, n);
   DBuf<uint8_t> adm(&pool_, s_, n);
   // each node's bucket from the count pass for the scatter (ids fit a byte)
   DBuf<uint8_t> bkt;
@@ -1136,6 +1137,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
     aa.adm = adm.get();
     aa.cpos = cpos.get();
     aa.seg = seg.get();
+    aa.rec = segrec.get();
     aa.csize = csize;
     // refinement: no control kernel after a sub-round (its graphs change only
     // at round starts), the moves mark the round directly

@@ -209,6 +209,14 @@ void launch_sub_list(const BucketArgs& a, const uint8_t* flag, uint32_t* block_c
 void launch_bucket_offsets(const BucketArgs& a, hipStream_t s);
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s);
 
+// A candidate of an overfull target's segment as the segment select reads it:
+// its admission key (hi, lo), node weight and slot.
+struct SegRec {
+  uint64_t hi, lo;
+  int64_t w;
+  uint32_t ci, pad;
+};
+
 // Admission of LP candidates and application of moves.
 struct AdmitArgs {
   Cand* cands;             // dense slots, tgt = EMPTY_KEY for no candidate
@@ -227,6 +235,7 @@ struct AdmitArgs {
   uint8_t* adm;
   uint32_t* cpos;
   uint32_t* seg;
+  SegRec* rec;             // [max_cands] records of the segments (beside seg)
   uint32_t* csize;         // member counts (clustering) or NULL
   uint64_t* moves;         // per graph: set to 1 when the sub-round moved a node
   uint32_t clear_ov;       // the apply clears ovtotal and ovcount (no control

@@ -1961,8 +1961,13 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
     const uint32_t size = a.tally[t].ntgt;
     if (size <= WAVE) continue;
     const uint32_t base = a.segbase[t];
+    // the segment's candidates as records (key, weight, slot) beside their
+    // slots, written by the first pass; the digit passes read records, the
+    // survivors as indices into them, ping-ponged between the segment's
+    // slots (free once copied) and cpos (free once the segments are scattered)
+    SegRec* rec = a.rec + base;
     uint32_t* in = a.seg + base;
-    uint32_t* out = a.cpos + base;  // cpos is free once the segments are scattered
+    uint32_t* out = a.cpos + base;
     const uint32_t u0 = a.cands[in[0]].u;
     const int64_t room = a.gd[cand_graph(a, u0)].cap - a.W[t];
     // range of the keys: digits above the highest differing bit are shared
@@ -1975,8 +1980,10 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         if (ci[q] == ~0u) continue;
+        const Cand c = a.cands[ci[q]];
         uint64_t h, l;
-        cand_key(a.cands[ci[q]], h, l);
+        cand_key(c, h, l);
+        rec[i0 + q * SEG_NT] = SegRec{h, l, a.nw[c.u], ci[q], 0};
         mnh = h < mnh ? h : mnh;
         mxh = h > mxh ? h : mxh;
         mnl = l < mnl ? l : mnl;
@@ -1993,28 +2000,28 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
     else top = mnl != mxl ? (63 - __clzll(mnl ^ mxl)) / 8 : -1;
     int64_t rem = room;  // weight still admissible below the threshold
     uint32_t cur = size;  // candidates sharing the threshold's digits so far
+    bool all = true;      // the survivors are every record (no index list yet)
     for (int pos = top; pos >= 0 && cur > 0; --pos) {
       for (int i = threadIdx.x; i < 256; i += SEG_NT) whist[i] = 0;
       if (threadIdx.x == 0) s_cnt = 0;
-      __syncthreads();
+      __syncthreads();  // (also makes the first pass's records visible)
       const int sh = 8 * (pos & 7);
       for (uint32_t i0 = threadIdx.x; i0 < cur; i0 += U * SEG_NT) {
-        uint32_t ci[U], d[U];
+        uint32_t d[U];
         int64_t w[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) ci[q] = i0 + q * SEG_NT < cur ? in[i0 + q * SEG_NT] : ~0u;
+        bool v[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-          if (ci[q] == ~0u) continue;
-          const Cand c = a.cands[ci[q]];
-          uint64_t h, l;
-          cand_key(c, h, l);
-          d[q] = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
-          w[q] = a.nw[c.u];
+          const uint32_t i = i0 + q * SEG_NT;
+          v[q] = i < cur;
+          if (!v[q]) continue;
+          const SegRec r = rec[all ? i : in[i]];
+          d[q] = (uint32_t)(((pos >= 8) ? r.hi : r.lo) >> sh) & 0xFF;
+          w[q] = r.w;
         }
 #pragma unroll
         for (int q = 0; q < U; ++q)
-          if (ci[q] != ~0u) atomicAdd(&whist[d[q]], (unsigned long long)w[q]);
+          if (v[q]) atomicAdd(&whist[d[q]], (unsigned long long)w[q]);
       }
       __syncthreads();
       {
@@ -2032,26 +2039,21 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
       __syncthreads();
       const uint32_t dsel = (uint32_t)s_digit;
       for (uint32_t i0 = threadIdx.x; i0 < cur; i0 += U * SEG_NT) {
-        uint32_t ci[U], d[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) ci[q] = i0 + q * SEG_NT < cur ? in[i0 + q * SEG_NT] : ~0u;
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-          if (ci[q] == ~0u) continue;
-          uint64_t h, l;
-          cand_key(a.cands[ci[q]], h, l);
-          d[q] = (uint32_t)(((pos >= 8) ? h : l) >> sh) & 0xFF;
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          if (ci[q] == ~0u) continue;
-          if (d[q] < dsel) a.adm[ci[q]] = 1;
-          else if (d[q] == dsel) out[atomicAdd(&s_cnt, 1u)] = ci[q];
+          const uint32_t i = i0 + q * SEG_NT;
+          if (i >= cur) continue;
+          const uint32_t j = all ? i : in[i];
+          const SegRec r = rec[j];
+          const uint32_t dg = (uint32_t)(((pos >= 8) ? r.hi : r.lo) >> sh) & 0xFF;
+          if (dg < dsel) a.adm[r.ci] = 1;
+          else if (dg == dsel) out[atomicAdd(&s_cnt, 1u)] = j;
         }
       }
       __syncthreads();
       rem = s_rem;
       cur = s_cnt;
+      all = false;
       uint32_t* tmp = in;
       in = out;
       out = tmp;
