@@ -1261,9 +1261,9 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
           AdmitArgs aa = admit_args();
           aa.max_cands = total;
           {
-            // per candidate slot: the slot (24 B) read by classification,
+            // per candidate slot: the slot (16 B) read by classification,
             // scatter and apply, its target's demand and weight (16 B)
-            ProfScope prof(spec.refine ? "rf:admission" : "cl:admission", 88ull * total, s_);
+            ProfScope prof(spec.refine ? "rf:admission" : "cl:admission", 64ull * total, s_);
             launch_admit(aa, s_);  // ovtotal was cleared by the control kernel or the apply
             if (ncl)
               k_lp_after_sub<<<1, 256, 0, s_>>>(ctl, aa.ncl_part, grid_for(total, 256));

@@ -26,12 +26,11 @@ struct GraphDesc {
 
 LMGP_D uint32_t graph_of(const uint32_t* gid, uint64_t u) { return gid ? gid[u] : 0u; }
 
-// An LP move candidate.
+// An LP move candidate (its admission-order hash is computed from u where a
+// segment of an overfull target needs it).
 struct Cand {
   uint32_t u;     // node
   uint32_t tgt;   // target cluster / block (global label)
-  uint32_t hadm;  // admission-order hash (upper 32 bits)
-  uint32_t pad;
   int64_t gain;   // r(target) - r(own)
 };
 

@@ -150,8 +150,6 @@ LMGP_D void emit(const RateArgs& a, uint32_t idx, uint32_t u, const GraphDesc& g
     Cand c;
     c.u = u;
     c.tgt = best.K;
-    c.hadm = (uint32_t)(hash_add(gd.pre_adm, (uint64_t)u - gd.node_base) >> 32);
-    c.pad = 0;
     c.gain = best.r - r_own;
     a.cands[i] = c;
     if (!a.few && !a.trial) {
@@ -1857,10 +1855,13 @@ __global__ __launch_bounds__(256) void k_adm_scatter(AdmitArgs a) {
   if (t != EMPTY_KEY) a.seg[a.segbase[t] + a.cpos[i]] = i;
 }
 
-// Admission order key: (gain desc, hadm asc, u asc) as two uint64 words.
-LMGP_D void cand_key(const Cand& c, uint64_t& hi, uint64_t& lo) {
+// Admission order key: (gain desc, hadm asc, u asc) as two uint64 words, hadm
+// the upper 32 bits of H(seed, ADM|RADM, level, round, u).
+LMGP_D void cand_key(const AdmitArgs& a, const Cand& c, uint64_t& hi, uint64_t& lo) {
+  const GraphDesc& gd = a.gd[graph_of(a.gid, c.u)];
+  const uint32_t hadm = (uint32_t)(hash_add(gd.pre_adm, (uint64_t)c.u - gd.node_base) >> 32);
   hi = (uint64_t)INT64_MAX - (uint64_t)c.gain;
-  lo = ((uint64_t)c.hadm << 32) | c.u;
+  lo = ((uint64_t)hadm << 32) | c.u;
 }
 LMGP_D bool key_less(uint64_t ahi, uint64_t alo, uint64_t bhi, uint64_t blo) {
   return ahi < bhi || (ahi == bhi && alo < blo);
@@ -1881,7 +1882,7 @@ LMGP_D void seg_waves(const AdmitArgs& a, uint32_t wid, uint32_t waves) {
     int64_t w = 0;
     if (valid) {
       Cand c = a.cands[ci];
-      cand_key(c, khi, klo);
+      cand_key(a, c, khi, klo);
       w = a.nw[c.u];
     }
     for (int k = 2; k <= WAVE; k <<= 1) {
@@ -1982,7 +1983,7 @@ __global__ __launch_bounds__(SEG_NT) void k_adm_seg(AdmitArgs a) {
         if (ci[q] == ~0u) continue;
         const Cand c = a.cands[ci[q]];
         uint64_t h, l;
-        cand_key(c, h, l);
+        cand_key(a, c, h, l);
         rec[i0 + q * SEG_NT] = SegRec{h, l, a.nw[c.u], ci[q], 0};
         mnh = h < mnh ? h : mnh;
         mxh = h > mxh ? h : mxh;
