@@ -240,8 +240,9 @@ struct AdmitArgs {
   uint32_t clear_ov;       // the apply clears ovtotal and ovcount (no control
                            // kernel runs after this admission)
   int64_t* ncl_count;      // per graph (clustering): non-empty clusters after the
-                           // sub-round, counted from Wmut over nlabels labels
-                           // (zero before); NULL in refinement
+                           // sub-round; a batch counts them from Wmut over nlabels
+                           // labels (zero before), one graph through ncl_part;
+                           // NULL in refinement
   uint64_t nlabels;
   // one graph: the apply kernel takes the count from the cluster weights'
   // transitions instead (returned by its atomics), one change per apply block
