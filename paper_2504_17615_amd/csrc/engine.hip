@@ -921,10 +921,12 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
   // boundary mode: each sub-round's flagged nodes, listed before bucketing
   DBuf<uint32_t> subids, subcnt;
   DBuf<unsigned long long> nsub;
+  DBuf<uint8_t> subsel;  // each flag word's selection of the sub-round
   if (bmode) {
     subids.reset(&pool_, s_, n);
     subcnt.reset(&pool_, s_, SUB_LIST_BLOCKS);
     nsub.reset(&pool_, s_, 1);
+    subsel.reset(&pool_, s_, (n + 7) / 8);
   }
   const std::vector<CutPreset>& presets = cut_presets(dense);
   int preset = p_.tune >= LMGP_TUNE_FORCE ? (int)((p_.tune - LMGP_TUNE_FORCE) % presets.size()) : 0;
@@ -996,7 +998,7 @@ void Engine::run_lp(Level& L, std::vector<Job>& jobs, const LpSpec& spec,
       launch_bucket_scatter(ba, st);
       return;
     }
-    launch_sub_list(ba, bflag.get(), subcnt.get(), subids.get(), nsub.get(), st);
+    launch_sub_list(ba, bflag.get(), subcnt.get(), subsel.get(), subids.get(), nsub.get(), st);
     BucketArgs bl = ba;
     bl.only = nullptr;
     bl.ids = subids.get();

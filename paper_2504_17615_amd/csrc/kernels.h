@@ -200,10 +200,10 @@ void launch_bucket_count(const BucketArgs& a, hipStream_t s);
 // The nodes u with flag[u] != 0 whose sub-round (mode 0 hash) is a.only_sub,
 // written to ids in ascending order, *nids their count.  flag holds n bytes
 // padded with zeros to a multiple of 8; block_cnt holds SUB_LIST_BLOCKS
-// counters of scratch.
+// counters and wsel one byte per 8-byte flag word of scratch.
 constexpr unsigned SUB_LIST_BLOCKS = 2048;
 void launch_sub_list(const BucketArgs& a, const uint8_t* flag, uint32_t* block_cnt,
-                     uint32_t* ids, unsigned long long* nids, hipStream_t s);
+                     uint8_t* wsel, uint32_t* ids, unsigned long long* nids, hipStream_t s);
 // offs = exclusive prefix of counts, fill = 0 (one small block on the device).
 void launch_bucket_offsets(const BucketArgs& a, hipStream_t s);
 void launch_bucket_scatter(const BucketArgs& a, hipStream_t s);

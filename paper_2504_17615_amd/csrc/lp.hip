@@ -1654,17 +1654,21 @@ LMGP_D void sub_chunk(uint64_t words, uint64_t& w0, uint64_t& w1) {
 }
 
 __global__ __launch_bounds__(256) void k_sub_count(BucketArgs a, const uint8_t* flag,
-                                                   uint32_t* block_cnt) {
+                                                   uint32_t* block_cnt, uint8_t* wsel) {
   __shared__ uint32_t sm[NWAVE];
   uint64_t w0, w1;
   sub_chunk((a.n + 7) / 8, w0, w1);
   uint32_t c = 0;
-  for (uint64_t w = w0; w < w1; ++w) c += (uint32_t)__popc(sub_select(a, flag, w));
+  for (uint64_t w = w0; w < w1; ++w) {
+    const uint32_t sel = sub_select(a, flag, w);
+    wsel[w] = (uint8_t)sel;  // read back by k_sub_write
+    c += (uint32_t)__popc(sel);
+  }
   const uint32_t tot = block_reduce_sum(c, sm);
   if (threadIdx.x == 0) block_cnt[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_sub_write(BucketArgs a, const uint8_t* flag,
+__global__ __launch_bounds__(256) void k_sub_write(BucketArgs a, const uint8_t* wsel,
                                                    const uint32_t* block_cnt, uint32_t* ids,
                                                    unsigned long long* nids) {
   __shared__ uint32_t sm[NWAVE];
@@ -1674,11 +1678,11 @@ __global__ __launch_bounds__(256) void k_sub_write(BucketArgs a, const uint8_t* 
   uint64_t w0, w1;
   sub_chunk((a.n + 7) / 8, w0, w1);
   uint32_t c = 0;
-  for (uint64_t w = w0; w < w1; ++w) c += (uint32_t)__popc(sub_select(a, flag, w));
+  for (uint64_t w = w0; w < w1; ++w) c += (uint32_t)__popc(wsel[w]);
   uint32_t tot;
   uint64_t at = before + block_exclusive_scan(c, sm, tot);
   for (uint64_t w = w0; w < w1; ++w) {
-    uint32_t sel = sub_select(a, flag, w);
+    uint32_t sel = wsel[w];
     while (sel) {
       const int byte = __builtin_ctz(sel);
       sel &= sel - 1;
@@ -2211,12 +2215,12 @@ void launch_bucket_scatter(const BucketArgs& a, hipStream_t s) {
 }
 
 void launch_sub_list(const BucketArgs& a, const uint8_t* flag, uint32_t* block_cnt,
-                     uint32_t* ids, unsigned long long* nids, hipStream_t s) {
+                     uint8_t* wsel, uint32_t* ids, unsigned long long* nids, hipStream_t s) {
   unsigned g = grid_for((a.n + 7) / 8, 256);
   if (g > SUB_BLOCKS) g = SUB_BLOCKS;
-  k_sub_count<<<g, 256, 0, s>>>(a, flag, block_cnt);
+  k_sub_count<<<g, 256, 0, s>>>(a, flag, block_cnt, wsel);
   LAUNCH_CHECK();
-  k_sub_write<<<g, 256, 0, s>>>(a, flag, block_cnt, ids, nids);
+  k_sub_write<<<g, 256, 0, s>>>(a, wsel, block_cnt, ids, nids);
   LAUNCH_CHECK();
 }
 
