@@ -1496,7 +1496,9 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
     // a node at least as heavy as the capacity can join no label (every
     // adjacent label weighs at least one), so rating it cannot produce a move
     if (a.nw[u] >= gd.cap) return -1;
-    uint32_t sr = subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds);
+    // listed nodes (ids) are those of sub-round only_sub already
+    const uint32_t sr =
+        a.ids ? a.only_sub : subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds);
     if (a.only && sr != a.only_sub) return -1;
     return (int)(sr * NCLASS + class_of(d, a.cuts));
   }
