@@ -273,7 +273,14 @@ LMGP_D Best group_best(const bool* el, const uint32_t* Ks, const int64_t* rs, ui
   return b;
 }
 
-template <int G, int EWK>
+// Graph of node u; ONE: a single graph (index 0), so that its descriptor is
+// read with scalar loads.
+template <bool ONE>
+LMGP_D uint32_t graph_at(const uint32_t* gid, uint64_t u) {
+  return ONE ? 0u : graph_of(gid, u);
+}
+
+template <int G, int EWK, bool ONE>
 LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sval,
                        uint64_t blk) {
   constexpr int T = 4 * G;
@@ -286,7 +293,7 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   bool valid = idx < a.count;
   const uint32_t u = valid ? a.list[idx] : 0u;
   // a graph may stop in the middle of a round (its flag is cleared on the device)
-  if (valid && !a.gd[graph_of(a.gid, u)].active) valid = false;
+  if (valid && !a.gd[graph_at<ONE>(a.gid, u)].active) valid = false;
 #pragma unroll
   for (int s = gl; s < T; s += G) {
     key[s] = EMPTY_KEY;
@@ -339,7 +346,7 @@ LMGP_D void rate_group(const RateArgs& a, uint32_t* skey, unsigned long long* sv
   const bool first = a.mode == MODE_LP && a.phase == 0;
   const bool r32 = a.packed != 0;
   if (valid) {
-    gd = a.gd[graph_of(a.gid, u)];
+    gd = a.gd[graph_at<ONE>(a.gid, u)];
     cu = a.nw[u];
     pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
 #pragma unroll
@@ -386,7 +393,7 @@ struct BlockScratch {
   int64_t sm[NWAVE];
 };
 
-template <int EWK, int LOGT>
+template <int EWK, int LOGT, bool ONE>
 LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val,
                        BlockScratch& bs, uint64_t idx) {
   constexpr int T = 1 << LOGT;
@@ -396,7 +403,7 @@ LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val
   int64_t* sm = bs.sm;
   if (idx >= a.count) return;
   const uint32_t u = a.list[idx];
-  if (!a.gd[graph_of(a.gid, u)].active) {
+  if (!a.gd[graph_at<ONE>(a.gid, u)].active) {
     if (threadIdx.x == 0) no_cand(a, (uint32_t)idx);
     return;
   }
@@ -431,7 +438,7 @@ LMGP_D void rate_block(const RateArgs& a, uint32_t* key, unsigned long long* val
   (void)block_exclusive_scan(acc, sm, acc_tot);
   if (threadIdx.x == 0 && acc_tot > 0) lds_insert_n(key, val, own, (uint64_t)acc_tot, logt);
   __syncthreads();
-  const GraphDesc gd = a.gd[graph_of(a.gid, u)];
+  const GraphDesc gd = a.gd[graph_at<ONE>(a.gid, u)];
   const int64_t cu = a.nw[u];
   const uint64_t pre_u = hash_add(gd.pre_tie, (uint64_t)u - gd.node_base);
   Best best{0, 0, 0};
@@ -474,7 +481,7 @@ __global__ __launch_bounds__(256) void k_rate_block(RateArgs a0) {
   __shared__ BlockScratch bs;
   RateArgs a = a0;
   resolve_plan(a);
-  rate_block<EWK, LOGT>(a, key, val, bs, blockIdx.x);
+  rate_block<EWK, LOGT, false>(a, key, val, bs, blockIdx.x);
 }
 
 // The classes 0..7 in one launch: block b belongs to the class c
@@ -499,16 +506,22 @@ __global__ __launch_bounds__(256) void k_rate_groups(RateArgs a, GroupSplit spli
   if (a.mode == MODE_LP) r.cands = a.cands + sp.off[c];
   r.count = sp.count[c];
   const uint64_t blk = b - sp.bstart[c];
-  switch (c) {
-    case 0: rate_group<2, EWK>(r, skey, sval, blk); break;
-    case 1: rate_group<4, EWK>(r, skey, sval, blk); break;
-    case 2: rate_group<8, EWK>(r, skey, sval, blk); break;
-    case 3: rate_group<16, EWK>(r, skey, sval, blk); break;
-    case 4: rate_group<32, EWK>(r, skey, sval, blk); break;
-    case 5: rate_group<64, EWK>(r, skey, sval, blk); break;
-    case 6: rate_block<EWK, 9>(r, skey, sval, bs, blk); break;  // whole block per node
-    default: rate_block<EWK, 10>(r, skey, sval, bs, blk); break;
-  }
+  // one graph (uniform over the launch): its descriptor at a constant index
+  auto classes = [&](auto one) {
+    constexpr bool ONE = decltype(one)::value;
+    switch (c) {
+      case 0: rate_group<2, EWK, ONE>(r, skey, sval, blk); break;
+      case 1: rate_group<4, EWK, ONE>(r, skey, sval, blk); break;
+      case 2: rate_group<8, EWK, ONE>(r, skey, sval, blk); break;
+      case 3: rate_group<16, EWK, ONE>(r, skey, sval, blk); break;
+      case 4: rate_group<32, EWK, ONE>(r, skey, sval, blk); break;
+      case 5: rate_group<64, EWK, ONE>(r, skey, sval, blk); break;
+      case 6: rate_block<EWK, 9, ONE>(r, skey, sval, bs, blk); break;  // whole block per node
+      default: rate_block<EWK, 10, ONE>(r, skey, sval, bs, blk); break;
+    }
+  };
+  if (a.gid) classes(std::false_type());
+  else classes(std::true_type());
 }
 
 constexpr unsigned long long EMPTY_SLOT = ~0ull;  // packed slot: label EMPTY_KEY
