@@ -1497,11 +1497,24 @@ void launch_hubs_t(const RateArgs& ra, Pool& pool, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- bucketing --
-LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
+// The descriptor fields bucketing reads.  A single graph's (gid NULL) are
+// loaded once per thread, with scalar loads; a union reads its graph's.
+struct BucketGd {
+  uint64_t node_base, pre_sub;
+  int64_t cap;
+  uint32_t active, subrounds;
+};
+LMGP_D BucketGd bucket_gd(const GraphDesc& d) {
+  return BucketGd{d.node_base, d.pre_sub, d.cap, d.active, d.subrounds};
+}
+LMGP_D BucketGd bucket_gd0(const BucketArgs& a) {
+  return a.gid ? BucketGd{0, 0, 0, 0, 1} : bucket_gd(a.gd[0]);
+}
+
+LMGP_D int bucket_of(const BucketArgs& a, uint64_t u, const BucketGd& g0) {
   // boundary refinement: interior nodes cost one byte
   if (a.mode == 0 && a.only && !a.only[u]) return -1;
-  const uint32_t g = graph_of(a.gid, u);
-  const GraphDesc& gd = a.gd[g];
+  const BucketGd gd = a.gid ? bucket_gd(a.gd[a.gid[u]]) : g0;
   if (!gd.active) return -1;
   const uint64_t d = a.xadj[u + 1] - a.xadj[u];
   if (d == 0) return -1;
@@ -1522,6 +1535,7 @@ LMGP_D int bucket_of(const BucketArgs& a, uint64_t u) {
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
+  const BucketGd g0 = bucket_gd0(a);
   __shared__ uint32_t h[MAX_BUCKETS];
   __shared__ unsigned long long hd[MAX_BUCKETS];
   for (uint32_t i = threadIdx.x; i < a.nbuckets; i += 256) {
@@ -1533,7 +1547,7 @@ __global__ __launch_bounds__(256) void k_bucket_count(BucketArgs a) {
   const uint64_t cnt = a.ids ? *a.nids : a.n;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
     const uint64_t u = a.ids ? a.ids[i] : i;
-    int b = bucket_of(a, u);
+    int b = bucket_of(a, u, g0);
     if (a.bkt) a.bkt[u] = b >= 0 ? (uint8_t)b : (uint8_t)0xFF;
     if (b >= 0) {
       atomicAdd(&h[b], 1u);
@@ -1600,6 +1614,7 @@ __global__ void k_lp_plan(const unsigned long long* counts, const uint32_t* offs
 constexpr int BK_ITEMS = 8;
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
+  const BucketGd g0 = bucket_gd0(a);
   __shared__ uint32_t cnt[MAX_BUCKETS], base[MAX_BUCKETS];
   // node range: one tile per block; node list: tiles grid-strided over its
   // device-side length
@@ -1619,7 +1634,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
         const uint8_t v = i < total ? a.bkt[uu[j]] : (uint8_t)0xFF;
         bk[j] = v == 0xFF ? -1 : (int)v;
       } else {
-        bk[j] = i < total ? bucket_of(a, uu[j]) : -1;
+        bk[j] = i < total ? bucket_of(a, uu[j], g0) : -1;
       }
       lp[j] = bk[j] >= 0 ? atomicAdd(&cnt[bk[j]], 1u) : 0u;
     }
@@ -1642,7 +1657,8 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(BucketArgs a) {
 constexpr unsigned SUB_BLOCKS = SUB_LIST_BLOCKS;
 
 // bit i: node w * 8 + i is flagged and in sub-round only_sub
-LMGP_D uint32_t sub_select(const BucketArgs& a, const uint8_t* flag, uint64_t w) {
+LMGP_D uint32_t sub_select(const BucketArgs& a, const uint8_t* flag, uint64_t w,
+                           const BucketGd& g0) {
   uint64_t bits = ((const uint64_t*)flag)[w];
   uint32_t sel = 0;
   while (bits) {
@@ -1650,7 +1666,7 @@ LMGP_D uint32_t sub_select(const BucketArgs& a, const uint8_t* flag, uint64_t w)
     bits &= ~(0xFFull << (byte * 8));
     const uint64_t u = w * 8 + (uint64_t)byte;
     if (u >= a.n) break;
-    const GraphDesc& gd = a.gd[graph_of(a.gid, u)];
+    const BucketGd gd = a.gid ? bucket_gd(a.gd[a.gid[u]]) : g0;
     if (subround_of(hash_add(gd.pre_sub, u - gd.node_base), gd.subrounds) == a.only_sub)
       sel |= 1u << byte;
   }
@@ -1674,8 +1690,9 @@ __global__ __launch_bounds__(256) void k_sub_count(BucketArgs a, const uint8_t* 
   uint64_t w0, w1;
   sub_chunk((a.n + 7) / 8, w0, w1);
   uint32_t c = 0;
+  const BucketGd g0 = bucket_gd0(a);
   for (uint64_t w = w0; w < w1; ++w) {
-    const uint32_t sel = sub_select(a, flag, w);
+    const uint32_t sel = sub_select(a, flag, w, g0);
     wsel[w] = (uint8_t)sel;  // read back by k_sub_write
     c += (uint32_t)__popc(sel);
   }
@@ -1754,6 +1771,7 @@ __global__ __launch_bounds__(256) void k_adm_count_few(AdmitArgs a) {
 // overflowing candidates reserved by one atomic per block and target.
 __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
   __shared__ uint32_t cnt[FEW_LABELS], base[FEW_LABELS];
+  const int64_t cap0 = a.gid ? 0 : a.gd[0].cap;  // a single graph's, one scalar load
   for (uint32_t t = threadIdx.x; t < a.few; t += 256) cnt[t] = 0;
   __syncthreads();
   const uint32_t nc = a.plan ? a.plan->total : a.max_cands;
@@ -1767,7 +1785,7 @@ __global__ __launch_bounds__(256) void k_adm_classify_few(AdmitArgs a) {
       a.adm[i] = 0;
     } else if (i < nc) {
       const Cand c = a.cands[i];
-      const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
+      const int64_t cap = a.gid ? a.gd[a.gid[c.u]].cap : cap0;
       if (a.W[c.tgt] + a.tally[c.tgt].demand <= cap) {
         a.adm[i] = 1;
       } else {
@@ -1850,7 +1868,7 @@ __global__ __launch_bounds__(256) void k_adm_classify(AdmitArgs a) {
     a.adm[i] = 0;
     return;
   }
-  const int64_t cap = a.gd[cand_graph(a, c.u)].cap;
+  const int64_t cap = a.gid ? a.gd[a.gid[c.u]].cap : a.gd[0].cap;
   const uint32_t t = c.tgt;
   const LabelTally tl = a.tally[t];
   if (a.W[t] + tl.demand <= cap) {
