@@ -253,16 +253,23 @@ LMGP_D T group_inclusive_scan(T v) {
 
 // Rows with at most 2G fine entries (unsorted output): a group of G lanes
 // per row, 256 / G rows per block, an LDS hash table of 4G slots per row;
-// the distinct entries are written in slot order.
+// the distinct entries are written in slot order.  Entry positions: every
+// member with entries marks its first position in the group's bit mask and
+// stores (row start - position) there, so the entry at position t belongs
+// to the highest mark at or below t.
 template <int EWK, int G>
 __global__ __launch_bounds__(256) void k_rows_group(ContractArgs a, const uint32_t* rows,
                                                     uint32_t nrows) {
-  constexpr int T = 4 * G, GPB = 256 / G;
+  constexpr int T = 4 * G, GPB = 256 / G, P = 2 * G, MW = (P + 63) / 64;
   __shared__ uint32_t skey[GPB * T];
   __shared__ unsigned long long sval[GPB * T];
+  __shared__ uint64_t sbase[GPB * P];
+  __shared__ unsigned long long smask[GPB * MW];
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   uint32_t* key = skey + grp * T;
   unsigned long long* val = sval + grp * T;
+  uint64_t* mbase = sbase + grp * P;
+  unsigned long long* mask = smask + grp * MW;
   const uint32_t r = blockIdx.x * GPB + grp;
   const bool valid = r < nrows;
 #pragma unroll
@@ -270,7 +277,6 @@ __global__ __launch_bounds__(256) void k_rows_group(ContractArgs a, const uint32
     key[i] = EMPTY_KEY;
     val[i] = 0;
   }
-  wave_sync();
   uint32_t x = 0;
   uint64_t m0 = 0, m1 = 0;
   if (valid) {
@@ -278,34 +284,47 @@ __global__ __launch_bounds__(256) void k_rows_group(ContractArgs a, const uint32
     m0 = a.mstart[x];
     m1 = a.mstart[x + 1];
   }
-  // members in chunks of G: lane l takes entries l and l + G of the chunk
+  // members in chunks of G (the row's entries, and so each chunk's, number
+  // at most P = 2G): lane l takes positions l and l + G of the chunk
   for (uint64_t mb = m0; mb < m1; mb += G) {
+    if (gl < MW) mask[gl] = 0;
+    wave_sync();
     const uint64_t mi = mb + gl;
-    uint64_t beg = 0, d = 0;
+    uint64_t beg = 0;
+    uint32_t d = 0;
     if (mi < m1) {
       const uint32_t u = a.members[mi];
       beg = a.xadj[u];
-      d = a.xadj[u + 1] - beg;
+      d = (uint32_t)(a.xadj[u + 1] - beg);
     }
-    const uint64_t incl = group_inclusive_scan<G>(d);
-    const uint64_t excl = incl - d;
-    const uint64_t tot = __shfl(incl, G - 1, G);
+    const uint32_t incl = group_inclusive_scan<G>(d);
+    const uint32_t excl = incl - d;
+    const uint32_t tot = __shfl(incl, G - 1, G);
+    if (d) {  // excl + d <= tot <= P, so excl < P
+      mbase[excl] = beg - excl;
+      atomicOr(&mask[excl >> 6], 1ull << (excl & 63));
+    }
+    wave_sync();
+    unsigned long long mk[MW];
+#pragma unroll
+    for (int q = 0; q < MW; ++q) mk[q] = mask[q];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const uint64_t t = (uint64_t)gl + (uint64_t)h * G;
-      // owner: the last member whose exclusive offset is <= t
-      int lo = 0;
-#pragma unroll
-      for (int step = G / 2; step > 0; step >>= 1) {
-        const int c = lo + step;
-        const uint64_t ex = __shfl(excl, c, G);
-        if (mb + (uint64_t)c < m1 && t >= ex) lo = c;
-      }
-      const uint64_t obeg = __shfl(beg, lo, G);
-      const uint64_t oex = __shfl(excl, lo, G);
+      const uint32_t t = (uint32_t)gl + (uint32_t)h * G;
       uint32_t k = EMPTY_KEY;
       int64_t w = 0;
-      if (t < tot) load_entry<EWK>(a, obeg + (t - oex), x, k, w);
+      if (t < tot) {
+        // the first member with entries starts at 0, so a mark <= t exists
+        uint32_t st;
+        if (MW == 1 || t < 64) {
+          const unsigned long long below = mk[0] & (~0ull >> (63 - (t & 63)));
+          st = 63u - (uint32_t)__clzll(below);
+        } else {
+          const unsigned long long hi = mk[MW - 1] & (~0ull >> (63 - (t & 63)));
+          st = hi ? 127u - (uint32_t)__clzll(hi) : 63u - (uint32_t)__clzll(mk[0]);
+        }
+        load_entry<EWK>(a, mbase[st] + t, x, k, w);
+      }
       if (k != EMPTY_KEY) {
         uint32_t sl = (k * 0x9E3779B1u) >> (32 - __builtin_ctz(T));
         bool hit;
@@ -317,6 +336,7 @@ __global__ __launch_bounds__(256) void k_rows_group(ContractArgs a, const uint32
         atomicAdd(&val[sl], (unsigned long long)w);
       }
     }
+    wave_sync();
   }
   wave_sync();
   if (!valid) return;
